@@ -1,0 +1,125 @@
+/* psb -- parallel sparse-blossom decoding on MI355X (gfx950).
+ *
+ * C ABI of the decoder library (libpsb.so).  The calls follow the decoding
+ * task of the paper "Sparse-Blossom Decoding in o(1) Time" (Mikami &
+ * Yamasaki): a detector graph with positive integer edge weights and a set of
+ * active detectors go in; the minimum-weight embedded matching (MWEM: odd
+ * degree at active detectors, even degree at the other detectors, any degree
+ * at boundary vertices -- Results, "Decoding task"), its weight and the
+ * predicted observable flips come out (Methods, Algorithm "Parallel sparse
+ * blossom", last two steps).
+ *
+ * Conventions for every call:
+ *   * return value 0 = PSB_OK, negative = error (PSB_E_*); psb_last_error()
+ *     returns a thread-local message describing the last failure;
+ *   * no call takes ownership of caller memory; objects created by the
+ *     library are released by the matching *_destroy call;
+ *   * a psb_decoder may be used by one host thread / one stream at a time.
+ */
+#ifndef PSB_H
+#define PSB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSB_OK 0
+#define PSB_E_INVALID (-1)      /* bad argument: ids out of range, w <= 0, sizes */
+#define PSB_E_NOMEM (-2)        /* host or device allocation failed */
+#define PSB_E_DEVICE (-3)       /* HIP runtime error (launch, copy) */
+#define PSB_E_UNSUPPORTED (-4)  /* graph/schedule combination outside the kernel's limits */
+
+/* Per-shot status codes written by psb_decode_batch. */
+#define PSB_S_OK 0
+#define PSB_S_CAPACITY 1        /* a per-shot workspace bound was exceeded; outputs invalid */
+#define PSB_S_INFEASIBLE 2      /* odd number of active detectors in a component with no boundary */
+#define PSB_S_EDGES_TRUNCATED 3 /* weight/obs valid, edge list cut at edges_per_shot */
+#define PSB_S_INTERNAL 4        /* an internal consistency check failed */
+
+#define PSB_BOUNDARY (-1)
+
+typedef struct psb_graph psb_graph;
+typedef struct psb_decoder psb_decoder;
+
+/* Detector graph (Results, "Decoding task"): vertices are detectors
+ * 0..num_detectors-1 plus boundary vertices; edge i joins u[i] and v[i], or
+ * u[i] and its own fresh boundary vertex when v[i] == PSB_BOUNDARY.
+ * All pointers are HOST pointers, read during psb_graph_create only. */
+typedef struct {
+  int32_t num_detectors;
+  int64_t num_edges;
+  const int32_t* u;          /* [num_edges], 0 <= u < num_detectors */
+  const int32_t* v;          /* [num_edges], PSB_BOUNDARY or 0 <= v < num_detectors, v != u */
+  const int32_t* w;          /* [num_edges], > 0 */
+  const uint64_t* obs_mask;  /* [num_edges], bit j = the edge flips observable j */
+} psb_graph_desc;
+
+/* Creates a device-resident copy of the graph (fixed-width adjacency).
+ * Errors: PSB_E_INVALID (ids out of range, w <= 0, self loop, more than
+ * 2^23 edges, a detector of degree > 16), PSB_E_NOMEM, PSB_E_DEVICE. */
+int32_t psb_graph_create(const psb_graph_desc* desc, psb_graph** out);
+int32_t psb_graph_destroy(psb_graph* g);
+
+typedef struct {
+  /* Finite-size parameter schedule (Methods, Algorithm "Parameter schedule"):
+   * q = q_num/q_den and phi_min = phi_min_num/phi_min_den, both in (0, 1).
+   * Zeros select the paper's numerical choice q = 1/10, phi_min = 1/100. */
+  int64_t q_num, q_den, phi_min_num, phi_min_den;
+  /* Tie-break seed: every weight is replaced by the even integer
+   * 2*w*2^64 + 2*h(e), h(e) = (SplitMix64 output e+1 for this seed) >> 24,
+   * so that the MWEM is unique with overwhelming probability. */
+  uint64_t tiebreak_seed;
+  /* 0 = partition-and-fuse (hierarchical execution over processing clusters,
+   *     Methods, Algorithms "Clustering" and "Parallel sparse blossom");
+   * 1 = global sparse blossom (every active detector in one execution). */
+  int32_t mode;
+  /* Boundary reading of the parity condition for odd clusters:
+   * 0 = a boundary vertex lies within d_k of every member (default);
+   * 1 = some member's exploring region of radius b_k/2 reaches the boundary. */
+  int32_t boundary_reading;
+  int32_t max_defects_per_shot;   /* 0 = choose from the graph */
+  int32_t edges_per_shot;         /* output stride of psb_decode_batch; 0 = max_defects_per_shot*8 */
+  int32_t num_slots;              /* concurrent shots on the device; 0 = 2048 */
+} psb_decoder_opts;
+
+/* Builds the decoder: tie-broken weights, level parameters d_k, b_k (exact
+ * rational arithmetic) and per-slot device workspaces.
+ * Errors: PSB_E_INVALID, PSB_E_NOMEM, PSB_E_DEVICE, PSB_E_UNSUPPORTED. */
+int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts* opts, psb_decoder** out);
+int32_t psb_decoder_destroy(psb_decoder* d);
+
+/* Level parameters in tie-broken weight units, each as two int64 halves
+ * (value = hi * 2^64 + lo).  final_level[k] != 0 marks a level whose b_k
+ * exceeds the graph's diameter bound, where every remaining detection event
+ * forms the final clusters.  Returns the number of levels written. */
+int32_t psb_decoder_levels(const psb_decoder* d, int32_t max_levels, int64_t* d_hi, uint64_t* d_lo,
+                           int64_t* b_hi, uint64_t* b_lo, int32_t* final_level);
+
+/* Decodes n shots in one persistent launch, asynchronously on `stream`
+ * (a hipStream_t; NULL = the default stream).  All array arguments are
+ * DEVICE pointers owned by the caller:
+ *   syndromes  [n][ceil(num_detectors/8)] uint8, detector j = bit (j&7) of byte (j>>3);
+ *   edges      [n][edges_per_shot] int32, MWEM edge ids in ascending order;
+ *   n_edges    [n] int32;  weight [n] int64 (sum of caller weights);
+ *   obs        [n] uint64 (XOR of observable masks);  status [n] int32 (PSB_S_*);
+ *   levels     [n][max_defects_per_shot] int8 or NULL: processing-cluster level of
+ *              each active detector in ascending detector order (0 = global mode);
+ *   t_done     [n] uint64 or NULL: device clock (100 MHz) when the shot finished.
+ * Errors: PSB_E_INVALID, PSB_E_DEVICE. */
+int32_t psb_decode_batch(psb_decoder* d, const uint8_t* syndromes, int64_t n, int32_t* edges,
+                         int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
+                         int8_t* levels, uint64_t* t_done, void* stream);
+
+/* Sizes the caller needs to allocate outputs. */
+int32_t psb_decoder_edges_per_shot(const psb_decoder* d);
+int32_t psb_decoder_max_defects(const psb_decoder* d);
+int32_t psb_graph_syndrome_bytes(const psb_graph* g);
+
+const char* psb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSB_H */

@@ -1,0 +1,1180 @@
+// Per-shot decoding engine: one wavefront decodes one shot.
+//
+// Steps (paper: "Sparse-Blossom Decoding in o(1) Time", Mikami & Yamasaki):
+//   1. syndrome intake: packed detector bits -> sorted detection events;
+//   2. processing-cluster hierarchy (Methods, Algorithm "Clustering");
+//   3. hierarchical execution (Methods, hierarchical execution rule and
+//      Algorithm "Parallel sparse blossom"): level by level, the detection
+//      events of that level seed growing regions at t = 0 while every stopped
+//      lower-level configuration stays in place; a lower-level configuration
+//      that a collision touches joins the running dynamics;
+//   4. sparse blossom itself (Supplementary S1): graph-fill regions with
+//      growth rate +1/0/-1, flooder events ARRIVE / LEAVE / COLLIDE /
+//      IMPLODE and matcher events (a)-(g) on matches, alternating trees and
+//      blossoms;
+//   5. fuse: expand blossoms of the terminal configuration into matched
+//      pairs, trace their paths through the arrival log, XOR them into the
+//      edge set, and sum weights / XOR observable masks.
+//
+// All arithmetic is integer.  Times and radii are 128-bit integers in units
+// of the tie-broken even weights, so every event happens at an integer time.
+//
+// Code style: every function is executed by all lanes of the wavefront with
+// identical (uniform) values except inside the lane-parallel loops
+// `for (i = lane(); i < n; i += PSB_WAVE)`.  Uniform stores of the same value
+// by all lanes are intentional.
+#pragma once
+
+namespace psb {
+
+constexpr int K_NONE = -1;
+constexpr int K_LEAVE = 1000;
+constexpr int NB_BOUNDARY = -1;
+constexpr int NB_PAD = -2;
+constexpr int MATE_BOUNDARY = -2;
+constexpr int CHUNK = 64;
+constexpr int MAXH = 6;           // deepest path enumeration used by clustering
+constexpr int S_OK = 0, S_CAPACITY = 1, S_INFEASIBLE = 2, S_TRUNC = 3, S_INTERNAL = 4;
+
+#define T_INF (((i128)1) << 124)
+
+// LDS scalars of one wavefront.
+struct Lds {
+  int dblk_n;           // dirty event blocks pending refresh
+  int x_n;              // explored-node count (lane-parallel appends)
+  int fin_n;            // final compressed edges
+  int stk_n;            // expansion stack
+  int lnk_n;
+  int pad[3];
+  int dblk[512];        // dirty block ids
+  unsigned dmask[512];  // dirty block bitmap (up to 16384 blocks)
+};
+
+struct Ctx {
+  const Params* P;
+  Lds* S;
+  // graph
+  const int32_t* nbr; const int32_t* eid; const i128* wt; const int32_t* w; const uint64_t* obs;
+  int deg, n_det;
+  // nodes
+  int32_t *n_top, *n_reg, *n_src, *n_eix, *n_rec, *n_pos, *n_did; i128* n_wr;
+  // explored
+  int32_t* x_node; i128* x_ev; i128* blk_min; int32_t* blk_arg;
+  // regions
+  i128* r_base; int32_t* r_f; int rcap;
+  // chunks
+  int32_t *ck_next, *ck_prev, *ck_nodes;
+  // pools
+  int32_t *ce, *bc, *lg;
+  int32_t *defects, *uf, *cl_a, *cl_b, *cl_c, *cl_d, *bdl, *hit;
+  int8_t* level;
+  int32_t *shr, *chg, *stk, *fin; uint32_t* ebits;
+  // uniform scalars
+  int nd, n_regions, n_ce, n_bc, n_log, n_ck, ck_free, n_shr, n_chg, stamp, status;
+  i128 now;
+  int64_t n_ev;
+};
+
+#define RF(c, r, f) ((c).r_f[(int64_t)(f) * (c).rcap + (r)])
+#define CEF(c, i, f) ((c).ce[(int64_t)(i) * CE_COUNT + (f)])
+
+PSB_DEV i128 yrad(const Ctx& c, int r, i128 t) { return c.r_base[r] + (i128)RF(c, r, RF_RATE) * t; }
+
+// ---------------------------------------------------------------------------
+// event cache (explored nodes, 64-entry blocks with cached minima)
+// ---------------------------------------------------------------------------
+PSB_DEV void mark_block(Ctx& c, int b) {
+  unsigned bit = 1u << (b & 31);
+  unsigned old = (unsigned)atom_or((int*)&c.S->dmask[b >> 5], (int)bit);
+  if (!(old & bit)) {
+    int k = atom_add(&c.S->dblk_n, 1);
+    if (k < 512) c.S->dblk[k] = b;
+  }
+}
+
+PSB_DEV void refresh_blocks(Ctx& c) {
+  wave_sync();
+  int nb = c.S->dblk_n;
+  const int xn = c.S->x_n;
+  if (nb > 512) {  // list overflowed: refresh every block
+    nb = (xn + CHUNK - 1) / CHUNK;
+    for (int b = 0; b < nb; ++b) {
+      i128 key = T_INF; int arg = 0x7fffffff;
+      for (int j = lane(); j < CHUNK; j += PSB_WAVE) {
+        int ix = b * CHUNK + j;
+        if (ix < xn) { i128 k = c.x_ev[ix]; if (k < key) { key = k; arg = ix; } }
+      }
+      wave_argmin(key, arg);
+      c.blk_min[b] = key; c.blk_arg[b] = arg;
+    }
+    for (int i = lane(); i < 512; i += PSB_WAVE) c.S->dmask[i] = 0;
+  } else {
+    for (int i = 0; i < nb; ++i) {
+      int b = c.S->dblk[i];
+      i128 key = T_INF; int arg = 0x7fffffff;
+      for (int j = lane(); j < CHUNK; j += PSB_WAVE) {
+        int ix = b * CHUNK + j;
+        if (ix < xn) { i128 k = c.x_ev[ix]; if (k < key) { key = k; arg = ix; } }
+      }
+      wave_argmin(key, arg);
+      c.blk_min[b] = key; c.blk_arg[b] = arg;
+      c.S->dmask[b >> 5] = 0;   // whole word cleared: other bits of it are refreshed in this loop too
+    }
+    // clearing whole words may drop marks of blocks not in this list only if
+    // they share a word with a listed block; those are listed as well, since
+    // every set bit has a list entry.
+  }
+  c.S->dblk_n = 0;
+  wave_sync();
+}
+
+PSB_DEV void set_event(Ctx& c, int ix, i128 t) {
+  c.x_ev[ix] = t;
+  mark_block(c, ix / CHUNK);
+}
+
+// Next event among explored nodes: (time, explored index).
+PSB_DEV void node_min(Ctx& c, i128& t, int& ix) {
+  refresh_blocks(c);
+  const int nb = (c.S->x_n + CHUNK - 1) / CHUNK;
+  i128 key = T_INF; int arg = 0x7fffffff;
+  for (int b = lane(); b < nb; b += PSB_WAVE) {
+    i128 k = c.blk_min[b]; int a = c.blk_arg[b];
+    if (k < key || (k == key && a < arg)) { key = k; arg = a; }
+  }
+  wave_argmin(key, arg);
+  t = key; ix = arg;
+}
+
+// ---------------------------------------------------------------------------
+// node-level events (flooder): ARRIVE / COLLIDE / LEAVE times at node u
+// ---------------------------------------------------------------------------
+PSB_DEV bool is_source_of(const Ctx& c, int u, int r) { return r < c.nd && c.defects[r] == u; }
+
+// Earliest event seen from node u: returns time (T_INF = none) and kind
+// (edge slot 0..deg-1 or K_LEAVE).  The local radius of an owned node is
+// l_u(t) = y_top(t) + wr_u; an edge (u, v) of weight W is reached by u's fill
+// when l_u = W (ARRIVE at an empty v, COLLIDE with the boundary) and two
+// fills meet when l_u + l_v = W, provided their rates add up to > 0.
+PSB_DEV void node_event(const Ctx& c, int u, i128& tbest, int& kbest) {
+  tbest = T_INF; kbest = K_NONE;
+  const int top = c.n_top[u];
+  if (top < 0) return;
+  const int ra = RF(c, top, RF_RATE);
+  const i128 bu = c.r_base[top] + c.n_wr[u];      // l_u(t) = bu + ra * t
+  if (ra < 0) {
+    if (c.n_reg[u] == top && !is_source_of(c, u, top)) { tbest = bu; kbest = K_LEAVE; }
+    return;   // a shrinking fill cannot gain on any neighbour
+  }
+  const int deg = c.deg;
+  for (int j = 0; j < deg; ++j) {
+    const int v = c.nbr[(int64_t)u * deg + j];
+    if (v == NB_PAD) break;
+    const i128 W = c.wt[c.eid[(int64_t)u * deg + j]];
+    i128 t;
+    if (v == NB_BOUNDARY) {
+      if (ra <= 0) continue;
+      t = W - bu;
+    } else {
+      const int vt = c.n_top[v];
+      if (vt < 0) {
+        if (ra <= 0) continue;
+        t = W - bu;                                   // ARRIVE
+      } else {
+        if (vt == top) continue;
+        const int rb = RF(c, vt, RF_RATE);
+        const int rs = ra + rb;
+        if (rs <= 0) continue;
+        const i128 num = W - bu - (c.r_base[vt] + c.n_wr[v]);
+        t = (rs == 1) ? num : (num >> 1);             // COLLIDE (num even when rs == 2)
+      }
+    }
+    if (t < tbest) { tbest = t; kbest = j; }
+  }
+}
+
+// Lane-parallel refresh of node v and all of its neighbours.
+PSB_DEV void refresh_star(Ctx& c, int v) {
+  wave_sync();
+  const int deg = c.deg;
+  for (int j = lane(); j <= deg; j += PSB_WAVE) {
+    int x = v;
+    if (j < deg) {
+      x = c.nbr[(int64_t)v * deg + j];
+      if (x < 0) continue;
+    }
+    const int ix = c.n_eix[x];
+    if (ix < 0) continue;
+    i128 t; int k;
+    node_event(c, x, t, k);
+    set_event(c, ix, t);
+  }
+  wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// shells: the nodes that arrived while a region was top level, kept as a
+// chunked array with O(1) insert and swap-remove
+// ---------------------------------------------------------------------------
+PSB_DEV int chunk_alloc(Ctx& c) {
+  if (c.ck_free >= 0) { int k = c.ck_free; c.ck_free = c.ck_next[k]; return k; }
+  if (c.n_ck >= c.P->ckcap) { c.status = S_CAPACITY; return -1; }
+  return c.n_ck++;
+}
+
+PSB_DEV void shell_push(Ctx& c, int r, int v) {
+  const int cnt = RF(c, r, RF_CNT);
+  const int idx = cnt % CHUNK;
+  int tail = RF(c, r, RF_CKT);
+  if (idx == 0) {
+    const int k = chunk_alloc(c);
+    if (k < 0) return;
+    c.ck_next[k] = -1; c.ck_prev[k] = tail;
+    if (tail >= 0) c.ck_next[tail] = k; else RF(c, r, RF_CKH) = k;
+    RF(c, r, RF_CKT) = k;
+    tail = k;
+  }
+  c.ck_nodes[(int64_t)tail * CHUNK + idx] = v;
+  c.n_pos[v] = tail * CHUNK + idx;
+  RF(c, r, RF_CNT) = cnt + 1;
+}
+
+PSB_DEV void shell_remove(Ctx& c, int r, int v) {
+  int cnt = RF(c, r, RF_CNT);
+  const int tail = RF(c, r, RF_CKT);
+  const int lp = tail * CHUNK + (cnt - 1) % CHUNK;
+  const int p = c.n_pos[v];
+  const int last = c.ck_nodes[lp];
+  c.ck_nodes[p] = last;
+  c.n_pos[last] = p;
+  --cnt;
+  RF(c, r, RF_CNT) = cnt;
+  if (cnt % CHUNK == 0) {
+    const int prev = c.ck_prev[tail];
+    if (prev >= 0) c.ck_next[prev] = -1; else RF(c, r, RF_CKH) = -1;
+    RF(c, r, RF_CKT) = prev;
+    c.ck_next[tail] = c.ck_free;
+    c.ck_free = tail;
+  }
+}
+
+// Collect region r and all its blossom descendants into stk[base..); returns count.
+PSB_DEV int collect_descendants(Ctx& c, int r, int base) {
+  int n = 0, head = 0;
+  if (base + 1 > c.P->stkcap) { c.status = S_CAPACITY; return 0; }
+  c.stk[base + n++] = r;
+  while (head < n) {
+    const int x = c.stk[base + head++];
+    const int bn = RF(c, x, RF_BCN);
+    const int bo = RF(c, x, RF_BCO);
+    if (base + n + bn > c.P->stkcap) { c.status = S_CAPACITY; return n; }
+    for (int i = 0; i < bn; ++i) c.stk[base + n++] = c.bc[2 * (bo + i)];
+  }
+  return n;
+}
+
+// Operation applied lane-parallel to every node of a region's total area.
+enum AreaOp { OP_REFRESH = 0, OP_SET_TOP_ADD_WR = 2 };
+
+PSB_DEV void area_apply(Ctx& c, int r, int op, int new_top, i128 add_wr, int base) {
+  const int nreg = collect_descendants(c, r, base);
+  wave_sync();
+  for (int q = 0; q < nreg; ++q) {
+    const int x = c.stk[base + q];
+    int ck = RF(c, x, RF_CKH);
+    int remaining = RF(c, x, RF_CNT);
+    while (ck >= 0 && remaining > 0) {
+      const int m = remaining < CHUNK ? remaining : CHUNK;
+      for (int i = lane(); i < m; i += PSB_WAVE) {
+        const int v = c.ck_nodes[(int64_t)ck * CHUNK + i];
+        if (op == OP_REFRESH) {
+          const int ix = c.n_eix[v];
+          if (ix >= 0) { i128 t; int k; node_event(c, v, t, k); set_event(c, ix, t); }
+        } else {
+          c.n_top[v] = new_top;
+          if (op == OP_SET_TOP_ADD_WR) c.n_wr[v] = c.n_wr[v] + add_wr;
+        }
+      }
+      remaining -= m;
+      ck = c.ck_next[ck];
+    }
+  }
+  wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// regions, compressed edges, tree bookkeeping
+// ---------------------------------------------------------------------------
+PSB_DEV void region_init(Ctx& c, int r, int rate, i128 base, int tid) {
+  c.r_base[r] = base;
+  RF(c, r, RF_RATE) = rate; RF(c, r, RF_BPAR) = -1; RF(c, r, RF_TPAR) = -1; RF(c, r, RF_TPE) = -1;
+  RF(c, r, RF_TID) = tid; RF(c, r, RF_MATE) = -1; RF(c, r, RF_ME) = -1; RF(c, r, RF_BCO) = 0;
+  RF(c, r, RF_BCN) = 0; RF(c, r, RF_ALIVE) = 1; RF(c, r, RF_CKH) = -1; RF(c, r, RF_CKT) = -1;
+  RF(c, r, RF_CNT) = 0; RF(c, r, RF_MARK) = 0; RF(c, r, RF_INSHR) = 0; RF(c, r, RF_CHGM) = 0;
+}
+
+PSB_DEV void note_change(Ctx& c, int r) {
+  if (RF(c, r, RF_CHGM) == c.stamp) return;
+  RF(c, r, RF_CHGM) = c.stamp;
+  if (c.n_chg >= c.P->rcap) { c.status = S_CAPACITY; return; }
+  c.chg[c.n_chg++] = r;
+}
+
+PSB_DEV void set_rate(Ctx& c, int r, int rate) {
+  const i128 y = yrad(c, r, c.now);
+  c.r_base[r] = y - (i128)rate * c.now;
+  RF(c, r, RF_RATE) = rate;
+  if (rate < 0 && !RF(c, r, RF_INSHR)) {
+    if (c.n_shr >= c.P->shrcap) { c.status = S_CAPACITY; return; }
+    RF(c, r, RF_INSHR) = 1;
+    c.shr[c.n_shr++] = r;
+  }
+  note_change(c, r);
+}
+
+PSB_DEV int ce_leaf(Ctx& c, int e, int rec_a, int rec_b, int sa, int sb) {
+  if (c.n_ce >= c.P->cecap) { c.status = S_CAPACITY; return -1; }
+  const int i = c.n_ce++;
+  CEF(c, i, CE_E) = e; CEF(c, i, CE_A) = rec_a; CEF(c, i, CE_B) = rec_b;
+  CEF(c, i, CE_SA) = sa; CEF(c, i, CE_SB) = sb;
+  return i;
+}
+
+PSB_DEV int ce_concat(Ctx& c, int a, int b, int sa, int sb) {
+  if (c.n_ce >= c.P->cecap) { c.status = S_CAPACITY; return -1; }
+  const int i = c.n_ce++;
+  CEF(c, i, CE_E) = -1; CEF(c, i, CE_A) = a; CEF(c, i, CE_B) = b;
+  CEF(c, i, CE_SA) = sa; CEF(c, i, CE_SB) = sb;
+  return i;
+}
+
+// The end of compressed edge `ce` that is not detection event `s`.
+PSB_DEV int ce_other(const Ctx& c, int ce, int s) {
+  return CEF(c, ce, CE_SA) == s ? CEF(c, ce, CE_SB) : CEF(c, ce, CE_SA);
+}
+
+// Child of blossom `b` (or b itself when b is top level) containing detection event s.
+PSB_DEV int child_containing(const Ctx& c, int s, int b) {
+  int x = s;
+  while (x >= 0 && RF(c, x, RF_BPAR) != b) x = RF(c, x, RF_BPAR);
+  return x;
+}
+
+// Is detection event s inside region r (r itself or a descendant)?
+PSB_DEV bool inside(const Ctx& c, int s, int r) {
+  int x = s;
+  while (x >= 0) { if (x == r) return true; x = RF(c, x, RF_BPAR); }
+  return false;
+}
+
+// Augment from outer region x up to its tree root: every inner region on the
+// path is re-matched to its tree parent (Supplementary S1: AUGMENT).
+PSB_DEV void augment_to_root(Ctx& c, int x) {
+  int cur = x;
+  int guard = 0;
+  while (RF(c, cur, RF_TPAR) >= 0) {
+    const int in = RF(c, cur, RF_TPAR);
+    const int out = RF(c, in, RF_TPAR);
+    const int e = RF(c, in, RF_TPE);
+    RF(c, in, RF_MATE) = out; RF(c, in, RF_ME) = e;
+    RF(c, out, RF_MATE) = in; RF(c, out, RF_ME) = e;
+    cur = out;
+    if (++guard > c.n_regions) { c.status = S_INTERNAL; return; }
+  }
+}
+
+// All regions of tree `tid` become frozen and leave the tree.
+PSB_DEV void dissolve_tree(Ctx& c, int tid) {
+  const int nr = c.n_regions;
+  int n = 0;
+  wave_sync();
+  for (int i0 = 0; i0 < nr; i0 += PSB_WAVE) {
+    const int r = i0 + lane();
+    const int take = (r < nr && RF(c, r, RF_ALIVE) && RF(c, r, RF_BPAR) < 0 && RF(c, r, RF_TID) == tid) ? 1 : 0;
+    const uint64_t mask = ballot(take);
+    if (take) c.stk[n + __builtin_popcountll(mask & lanemask_lt())] = r;
+    n += __builtin_popcountll(mask);
+  }
+  wave_sync();
+  for (int q = 0; q < n; ++q) {
+    const int r = c.stk[q];
+    RF(c, r, RF_TID) = -1;
+    RF(c, r, RF_TPAR) = -1;
+    set_rate(c, r, 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// matcher events
+// ---------------------------------------------------------------------------
+
+// (c) tree hits itself / (e) after an implode: outer regions a and b of the
+// same tree touch through compressed edge ce -> blossom (SHRINK).
+PSB_DEV void form_blossom(Ctx& c, int a, int b, int ce) {
+  // lowest common outer ancestor
+  ++c.stamp;
+  const int st = c.stamp;
+  int x = a, guard = 0;
+  RF(c, x, RF_MARK) = st;
+  while (RF(c, x, RF_TPAR) >= 0) {
+    x = RF(c, RF(c, x, RF_TPAR), RF_TPAR);
+    RF(c, x, RF_MARK) = st;
+    if (++guard > c.n_regions) { c.status = S_INTERNAL; return; }
+  }
+  int y = b; guard = 0;
+  while (RF(c, y, RF_MARK) != st) {
+    if (RF(c, y, RF_TPAR) < 0) { c.status = S_INTERNAL; return; }
+    y = RF(c, RF(c, y, RF_TPAR), RF_TPAR);
+    if (++guard > c.n_regions) { c.status = S_INTERNAL; return; }
+  }
+  const int lca = y;
+  ++c.stamp;   // fresh stamp for cycle membership
+  const int cs = c.stamp;
+  // cycle = [lca] + reverse(path a->lca) + path b->lca  (paths exclude lca)
+  // build in the stack scratch: path_a at [0..ma), path_b at [ma..ma+mb)
+  int ma = 0, mb = 0;
+  const int cap = c.P->stkcap;
+  for (x = a; x != lca; x = RF(c, RF(c, x, RF_TPAR), RF_TPAR)) {
+    if (ma + 2 > cap) { c.status = S_CAPACITY; return; }
+    c.stk[ma++] = x; c.stk[ma++] = RF(c, x, RF_TPAR);
+  }
+  for (x = b; x != lca; x = RF(c, RF(c, x, RF_TPAR), RF_TPAR)) {
+    if (ma + mb + 2 > cap) { c.status = S_CAPACITY; return; }
+    c.stk[ma + mb++] = x; c.stk[ma + mb++] = RF(c, x, RF_TPAR);
+  }
+  const int m = 1 + ma + mb;
+  if (c.n_bc + m > c.P->bccap || c.n_regions >= c.P->rcap) { c.status = S_CAPACITY; return; }
+  const int bo = c.n_bc;
+  c.n_bc += m;
+  int* cyc = c.bc + 2 * bo;   // pairs (child, edge to next)
+  cyc[0] = lca;
+  for (int i = 0; i < ma; ++i) cyc[2 * (1 + i)] = c.stk[ma - 1 - i];
+  for (int i = 0; i < mb; ++i) cyc[2 * (1 + ma + i)] = c.stk[ma + i];
+  for (int i = 0; i < m; ++i) {
+    int e;
+    if (i < ma) e = RF(c, cyc[2 * (i + 1)], RF_TPE);       // parent -> child: child's tree edge
+    else if (i == ma) e = ce;                              // a -> b
+    else e = RF(c, cyc[2 * i], RF_TPE);                    // child -> parent
+    cyc[2 * i + 1] = e;
+  }
+  // new blossom region
+  const int X = c.n_regions++;
+  const int tid = RF(c, lca, RF_TID);
+  region_init(c, X, 1, -c.now, tid);
+  RF(c, X, RF_TPAR) = RF(c, lca, RF_TPAR);
+  RF(c, X, RF_TPE) = RF(c, lca, RF_TPE);
+  RF(c, X, RF_MATE) = RF(c, lca, RF_MATE);
+  RF(c, X, RF_ME) = RF(c, lca, RF_ME);
+  RF(c, X, RF_BCO) = bo; RF(c, X, RF_BCN) = m;
+  if (RF(c, lca, RF_TPAR) >= 0) RF(c, RF(c, lca, RF_TPAR), RF_MATE) = X;
+  for (int i = 0; i < m; ++i) RF(c, cyc[2 * i], RF_MARK) = cs;
+  // tree children of cycle members that are not on the cycle hang from X
+  wave_sync();
+  for (int r = lane(); r < c.n_regions; r += PSB_WAVE) {
+    if (r == X || !RF(c, r, RF_ALIVE) || RF(c, r, RF_BPAR) >= 0 || RF(c, r, RF_TID) != tid) continue;
+    if (RF(c, r, RF_MARK) == cs) continue;
+    const int p = RF(c, r, RF_TPAR);
+    if (p >= 0 && RF(c, p, RF_MARK) == cs) RF(c, r, RF_TPAR) = X;
+  }
+  wave_sync();
+  // freeze the cycle members inside X; their nodes now belong to X's area
+  for (int i = 0; i < m; ++i) {
+    const int ch = cyc[2 * i];
+    const i128 y_ch = yrad(c, ch, c.now);
+    c.r_base[ch] = y_ch;
+    RF(c, ch, RF_RATE) = 0;
+    RF(c, ch, RF_BPAR) = X;
+    RF(c, ch, RF_TID) = -1; RF(c, ch, RF_TPAR) = -1; RF(c, ch, RF_MATE) = -1;
+    area_apply(c, ch, OP_SET_TOP_ADD_WR, X, y_ch, c.P->stkcap / 2);
+  }
+  note_change(c, X);
+}
+
+// (d) an inner blossom's radius reaches zero: it shatters (EXPAND).
+PSB_DEV void shatter(Ctx& c, int B) {
+  const int m = RF(c, B, RF_BCN);
+  const int bo = RF(c, B, RF_BCO);
+  const int* cyc = c.bc + 2 * bo;
+  const int P_ = RF(c, B, RF_TPAR);
+  const int ce_p = RF(c, B, RF_TPE);
+  const int C = RF(c, B, RF_MATE);
+  const int ce_c = RF(c, B, RF_ME);
+  const int tid = RF(c, B, RF_TID);
+  if (P_ < 0 || C < 0) { c.status = S_INTERNAL; return; }
+  const int s_in = inside(c, CEF(c, ce_p, CE_SA), B) ? CEF(c, ce_p, CE_SA) : CEF(c, ce_p, CE_SB);
+  const int s_out = inside(c, CEF(c, ce_c, CE_SA), B) ? CEF(c, ce_c, CE_SA) : CEF(c, ce_c, CE_SB);
+  const int c_in = child_containing(c, s_in, B), c_out = child_containing(c, s_out, B);
+  int i_in = -1, i_out = -1;
+  for (int i = 0; i < m; ++i) { if (cyc[2 * i] == c_in) i_in = i; if (cyc[2 * i] == c_out) i_out = i; }
+  if (i_in < 0 || i_out < 0) { c.status = S_INTERNAL; return; }
+  const int fwd = ((i_out - i_in) % m + m) % m;
+  const int dir = (fwd % 2 == 0) ? 1 : -1;
+  const int L = (dir == 1) ? fwd : m - fwd;
+  // children become top level again
+  for (int i = 0; i < m; ++i) {
+    const int ch = cyc[2 * i];
+    RF(c, ch, RF_BPAR) = -1;
+    // while inside B, l_v = y_B + wr_v with the child's frozen radius folded
+    // into wr_v; y_B = 0 now, so l_v = y_child + (wr_v - y_child)
+    area_apply(c, ch, OP_SET_TOP_ADD_WR, ch, -c.r_base[ch], c.P->stkcap / 2);
+  }
+  // the even path from c_in to c_out stays in the tree
+  int prev = P_;
+  int prev_edge = ce_p;
+  for (int j = 0; j <= L; ++j) {
+    const int idx = ((i_in + dir * j) % m + m) % m;
+    const int ch = cyc[2 * idx];
+    int e;
+    if (j == 0) e = prev_edge;
+    else {
+      const int pidx = ((i_in + dir * (j - 1)) % m + m) % m;
+      e = (dir == 1) ? cyc[2 * pidx + 1] : cyc[2 * idx + 1];
+    }
+    RF(c, ch, RF_TID) = tid;
+    RF(c, ch, RF_TPAR) = prev;
+    RF(c, ch, RF_TPE) = e;
+    if (j % 2 == 1) {        // outer: matched to the inner before it
+      RF(c, ch, RF_MATE) = prev; RF(c, ch, RF_ME) = e;
+      RF(c, prev, RF_MATE) = ch; RF(c, prev, RF_ME) = e;
+      set_rate(c, ch, 1);
+    } else {
+      set_rate(c, ch, -1);
+    }
+    prev = ch;
+  }
+  RF(c, prev, RF_MATE) = C; RF(c, prev, RF_ME) = ce_c;
+  RF(c, C, RF_TPAR) = prev; RF(c, C, RF_MATE) = prev;
+  // the remaining arc pairs up along the cycle
+  const int rest = m - L - 1;
+  for (int j = 1; j <= rest; j += 2) {
+    const int ia = ((i_out + dir * j) % m + m) % m;
+    const int ib = ((i_out + dir * (j + 1)) % m + m) % m;
+    const int ca = cyc[2 * ia], cb = cyc[2 * ib];
+    const int e = (dir == 1) ? cyc[2 * ia + 1] : cyc[2 * ib + 1];
+    RF(c, ca, RF_MATE) = cb; RF(c, ca, RF_ME) = e; RF(c, ca, RF_TID) = -1; RF(c, ca, RF_TPAR) = -1;
+    RF(c, cb, RF_MATE) = ca; RF(c, cb, RF_ME) = e; RF(c, cb, RF_TID) = -1; RF(c, cb, RF_TPAR) = -1;
+    set_rate(c, ca, 0); set_rate(c, cb, 0);
+  }
+  // nodes still in B's own shell sit exactly on its boundary: release them
+  while (RF(c, B, RF_CNT) > 0) {
+    const int ck = RF(c, B, RF_CKT);
+    const int v = c.ck_nodes[(int64_t)ck * CHUNK + (RF(c, B, RF_CNT) - 1) % CHUNK];
+    shell_remove(c, B, v);
+    c.n_top[v] = -1; c.n_reg[v] = -1; c.n_src[v] = -1; c.n_rec[v] = -1;
+    if (c.n_eix[v] >= 0) set_event(c, c.n_eix[v], T_INF);
+    refresh_star(c, v);
+  }
+  RF(c, B, RF_ALIVE) = 0;
+  RF(c, B, RF_TID) = -1;
+}
+
+// (e) an inner detector region shrinks to radius zero: its tree parent and
+// child touch at its detection event and form a blossom with it.
+PSB_DEV void implode(Ctx& c, int s) {
+  const int P_ = RF(c, s, RF_TPAR), C = RF(c, s, RF_MATE);
+  if (P_ < 0 || C < 0) { c.status = S_INTERNAL; return; }
+  const int e_c = RF(c, s, RF_ME), e_p = RF(c, s, RF_TPE);
+  const int ce = ce_concat(c, e_c, e_p, ce_other(c, e_c, s), ce_other(c, e_p, s));
+  if (ce < 0) return;
+  form_blossom(c, C, P_, ce);
+}
+
+// Growing region a (tree) touches region b (or the boundary when b < 0).
+PSB_DEV void collide(Ctx& c, int a, int b, int ce) {
+  const int ta = RF(c, a, RF_TID);
+  if (RF(c, a, RF_RATE) != 1 || ta < 0) { c.status = S_INTERNAL; return; }
+  if (b < 0) {                                     // (f) tree hits boundary
+    augment_to_root(c, a);
+    RF(c, a, RF_MATE) = MATE_BOUNDARY; RF(c, a, RF_ME) = ce;
+    dissolve_tree(c, ta);
+    return;
+  }
+  const int rb = RF(c, b, RF_RATE);
+  if (rb == 1) {
+    const int tb = RF(c, b, RF_TID);
+    if (tb == ta) { form_blossom(c, a, b, ce); return; }   // (c)
+    augment_to_root(c, a);                                   // (b) tree hits tree
+    augment_to_root(c, b);
+    RF(c, a, RF_MATE) = b; RF(c, a, RF_ME) = ce;
+    RF(c, b, RF_MATE) = a; RF(c, b, RF_ME) = ce;
+    dissolve_tree(c, ta);
+    dissolve_tree(c, tb);
+    return;
+  }
+  if (rb != 0) { c.status = S_INTERNAL; return; }
+  const int mb = RF(c, b, RF_MATE);
+  if (mb == MATE_BOUNDARY) {                                 // (g) tree hits boundary match
+    augment_to_root(c, a);
+    RF(c, a, RF_MATE) = b; RF(c, a, RF_ME) = ce;
+    RF(c, b, RF_MATE) = a; RF(c, b, RF_ME) = ce;
+    dissolve_tree(c, ta);
+    return;
+  }
+  if (mb < 0) { c.status = S_INTERNAL; return; }
+  // (a) tree hits match: b joins as inner, its partner as outer (GROW)
+  RF(c, b, RF_TID) = ta; RF(c, b, RF_TPAR) = a; RF(c, b, RF_TPE) = ce;
+  RF(c, mb, RF_TID) = ta; RF(c, mb, RF_TPAR) = b; RF(c, mb, RF_TPE) = RF(c, b, RF_ME);
+  set_rate(c, b, -1);
+  set_rate(c, mb, 1);
+}
+
+// ---------------------------------------------------------------------------
+// flooder events
+// ---------------------------------------------------------------------------
+PSB_DEV void add_explored(Ctx& c, int v) {
+  if (c.n_eix[v] >= 0) return;
+  const int ix = c.S->x_n;
+  c.x_node[ix] = v; c.x_ev[ix] = T_INF; c.n_eix[v] = ix;
+  wave_sync();
+  c.S->x_n = ix + 1;
+  wave_sync();
+}
+
+PSB_DEV void arrive(Ctx& c, int u, int v, int e) {
+  if (c.n_did[v] >= 0) { c.status = S_INTERNAL; return; }   // an unseeded detection event was reached
+  const int a = c.n_top[u];
+  if (c.n_log >= c.P->lcap) { c.status = S_CAPACITY; return; }
+  const int rec = c.n_log++;
+  c.lg[3 * rec] = v; c.lg[3 * rec + 1] = c.n_rec[u]; c.lg[3 * rec + 2] = e;
+  c.n_top[v] = a; c.n_reg[v] = a; c.n_src[v] = c.n_src[u]; c.n_wr[v] = -yrad(c, a, c.now);
+  c.n_rec[v] = rec;
+  add_explored(c, v);
+  shell_push(c, a, v);
+  refresh_star(c, v);
+}
+
+PSB_DEV void leave(Ctx& c, int u) {
+  const int a = c.n_top[u];
+  shell_remove(c, a, u);
+  c.n_top[u] = -1; c.n_reg[u] = -1; c.n_src[u] = -1; c.n_rec[u] = -1;
+  refresh_star(c, u);
+}
+
+// Refresh every node of every region recorded in the change list.
+PSB_DEV void flush_changes(Ctx& c) {
+  for (int i = 0; i < c.n_chg; ++i) {
+    const int r = c.chg[i];
+    if (!RF(c, r, RF_ALIVE)) continue;
+    area_apply(c, r, OP_REFRESH, 0, 0, c.P->stkcap / 2);
+  }
+  c.n_chg = 0;
+  ++c.stamp;
+}
+
+PSB_DEV void node_event_apply(Ctx& c, int u, int kind) {
+  if (kind == K_LEAVE) { leave(c, u); return; }
+  const int deg = c.deg;
+  const int v = c.nbr[(int64_t)u * deg + kind];
+  const int e = c.eid[(int64_t)u * deg + kind];
+  const int a = c.n_top[u];
+  if (v == NB_BOUNDARY) {
+    const int ce = ce_leaf(c, e, c.n_rec[u], -1, c.n_src[u], -1);
+    if (ce < 0) return;
+    collide(c, a, -1, ce);
+  } else if (c.n_top[v] < 0) {
+    arrive(c, u, v, e);
+  } else {
+    const int b = c.n_top[v];
+    int ce;
+    if (RF(c, a, RF_RATE) >= RF(c, b, RF_RATE)) {
+      ce = ce_leaf(c, e, c.n_rec[u], c.n_rec[v], c.n_src[u], c.n_src[v]);
+      if (ce < 0) return;
+      collide(c, a, b, ce);
+    } else {
+      ce = ce_leaf(c, e, c.n_rec[v], c.n_rec[u], c.n_src[v], c.n_src[u]);
+      if (ce < 0) return;
+      collide(c, b, a, ce);
+    }
+  }
+  flush_changes(c);
+}
+
+// Earliest region-level event: an inner (shrinking) top-level region whose
+// radius y(t) = base - t reaches zero at t = base.
+PSB_DEV void region_min(Ctx& c, i128& t, int& r) {
+  i128 key = T_INF; int arg = 0x7fffffff;
+  wave_sync();
+  for (int i = lane(); i < c.n_shr; i += PSB_WAVE) {
+    const int x = c.shr[i];
+    if (RF(c, x, RF_ALIVE) && RF(c, x, RF_BPAR) < 0 && RF(c, x, RF_RATE) < 0) {
+      const i128 k = c.r_base[x];
+      if (k < key || (k == key && x < arg)) { key = k; arg = x; }
+    }
+  }
+  wave_argmin(key, arg);
+  t = key; r = arg;
+}
+
+// Run the dynamics until no alternating tree is left.
+PSB_DEV void run_dynamics(Ctx& c) {
+  const int64_t max_ev = c.P->max_events;
+  for (;;) {
+    if (c.status) return;
+    if (++c.n_ev > max_ev) { c.status = S_INTERNAL; return; }
+    i128 tn, tr; int ix, r;
+    node_min(c, tn, ix);
+    region_min(c, tr, r);
+    if (tr < T_INF && tr <= tn) {
+      if (tr < c.now) { c.status = S_INTERNAL; return; }
+      c.now = tr;
+      if (RF(c, r, RF_BCN) > 0) shatter(c, r); else implode(c, r);
+      if (c.status) return;
+      flush_changes(c);
+      continue;
+    }
+    if (tn >= T_INF) return;
+    const int u = c.x_node[ix];
+    i128 tf; int kf;
+    node_event(c, u, tf, kf);
+    if (tf != tn) { wave_sync(); c.x_ev[ix] = tf; mark_block(c, ix / CHUNK); continue; }
+    if (tf < c.now) { c.status = S_INTERNAL; return; }
+    c.now = tf;
+    node_event_apply(c, u, kf);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// syndrome intake
+// ---------------------------------------------------------------------------
+PSB_DEV void load_defects(Ctx& c, const uint8_t* row) {
+  const int nb = c.P->nbytes;
+  int total = 0;
+  for (int b0 = 0; b0 < nb; b0 += PSB_WAVE) {
+    int cnt = 0, byte = 0;
+    for (int i = b0 + lane(); i < b0 + PSB_WAVE && i < nb; i += PSB_WAVE) { byte = row[i]; cnt = __builtin_popcount(byte); }
+    const int off = wave_prefix(cnt);
+    int pos = total + off;
+    for (int k = 0; k < 8; ++k) if (byte >> k & 1) {
+      const int d = 8 * (b0 + lane()) + k;
+      if (d < c.n_det && pos < c.P->dcap) c.defects[pos] = d;
+      ++pos;
+    }
+    total += wave_sum(cnt);
+  }
+  wave_sync();
+  c.nd = total;
+  if (total > c.P->dcap) { c.status = S_CAPACITY; return; }
+  for (int i = lane(); i < total; i += PSB_WAVE) {
+    c.n_did[c.defects[i]] = i;
+    c.level[i] = 0;
+  }
+  wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// processing-cluster hierarchy (Methods, Algorithm "Clustering")
+// ---------------------------------------------------------------------------
+PSB_DEV int uf_find(Ctx& c, int x) {
+  while (true) { const int p = atom_load(&c.uf[x]); if (p == x) return x; x = p; }
+}
+
+PSB_DEV void uf_union(Ctx& c, int a, int b) {
+  for (int guard = 0; guard < 1 << 20; ++guard) {
+    a = uf_find(c, a); b = uf_find(c, b);
+    if (a == b) return;
+    if (a < b) { const int t = a; a = b; b = t; }
+    if (atom_cas(&c.uf[a], a, b) == a) return;
+  }
+}
+
+// Level of every detection event.  For each level k with b_k below the graph's
+// diameter bound, the exploring region of radius b_k/2 around event u touches
+// that of event v iff d(u, v) <= b_k; all such pairs are found by enumerating
+// paths of at most H_k = floor(b_k / w_min) edges.  A component is accepted if
+// every pair in it is within d_k (its diameter) and it has an even number of
+// events or satisfies the boundary condition.  At the first level whose b_k
+// exceeds the diameter bound, every remaining event is in the component of
+// its connected part of the graph: these form the final clusters.
+PSB_DEV void cluster(Ctx& c) {
+  const int nd = c.nd;
+  const int deg = c.deg;
+  const int hitcap = c.P->hitcap, bdc = c.P->bdc;
+  int32_t* close_cnt = c.cl_a;   // per event: close partners with larger index
+  int32_t* bcount = c.cl_b;      // per event: boundary edges within d_k (or loose flag bit 30)
+  int32_t* csize = c.cl_c;       // per root: size
+  int32_t* cclose = c.cl_d;      // per root: close pairs
+  for (int k = 0; k < c.P->n_levels; ++k) {
+    // residual count
+    int nres = 0;
+    for (int i = lane(); i < nd; i += PSB_WAVE) nres += (c.level[i] == 0);
+    nres = wave_sum(nres);
+    if (nres == 0) return;
+    if (c.P->shmax[k] < 0) {
+      for (int i = lane(); i < nd; i += PSB_WAVE) if (c.level[i] == 0) c.level[i] = (int8_t)(k + 1);
+      wave_sync();
+      return;
+    }
+    const i128 bk = c.P->sb[k], dk = c.P->sd[k];
+    const int H = c.P->shmax[k];
+    for (int i = lane(); i < nd; i += PSB_WAVE) { c.uf[i] = i; close_cnt[i] = 0; bcount[i] = 0; csize[i] = 0; cclose[i] = 0; }
+    wave_sync();
+    for (int i = lane(); i < nd; i += PSB_WAVE) {
+      if (c.level[i] != 0) continue;
+      const int u = c.defects[i];
+      int32_t* hits = c.hit + (int64_t)(lane() % PSB_WAVE) * hitcap * 2;
+      int nh = 0, nbd = 0, loose = 0, overflow = 0;
+      int st_node[MAXH + 1], st_slot[MAXH + 1];
+      i128 st_dist[MAXH + 1];
+      int dep = 0;
+      st_node[0] = u; st_slot[0] = 0; st_dist[0] = 0;
+      while (dep >= 0) {
+        if (st_slot[dep] >= deg || dep >= H) { --dep; continue; }
+        const int x = st_node[dep];
+        const int j = st_slot[dep]++;
+        const int y = c.nbr[(int64_t)x * deg + j];
+        if (y == NB_PAD) { st_slot[dep] = deg; continue; }
+        const i128 nd_ = st_dist[dep] + c.wt[c.eid[(int64_t)x * deg + j]];
+        if (nd_ > bk) continue;
+        if (y == NB_BOUNDARY) {
+          const int e = c.eid[(int64_t)x * deg + j];
+          if (nd_ <= dk) {
+            bool dup = false;
+            for (int q = 0; q < nbd && q < bdc; ++q) dup |= (c.bdl[(int64_t)i * bdc + q] == e);
+            if (!dup) { if (nbd < bdc) c.bdl[(int64_t)i * bdc + nbd] = e; ++nbd; }
+          }
+          if (2 * nd_ <= bk) loose = 1;
+          continue;
+        }
+        if (y != u) {
+          const int rj = c.n_did[y];
+          if (rj >= 0 && c.level[rj] == 0) {
+            const int cl = (nd_ <= dk) ? 1 : 0;
+            int q = 0;
+            for (; q < nh; ++q) if (hits[2 * q] == rj) { hits[2 * q + 1] |= cl; break; }
+            if (q == nh) { if (nh < hitcap) { hits[2 * nh] = rj; hits[2 * nh + 1] = cl; ++nh; } else overflow = 1; }
+          }
+        }
+        if (dep + 1 < H) { ++dep; st_node[dep] = y; st_slot[dep] = 0; st_dist[dep] = nd_; }
+      }
+      int cc = 0;
+      for (int q = 0; q < nh; ++q) {
+        const int rj = hits[2 * q];
+        uf_union(c, i, rj);
+        if (rj > i && hits[2 * q + 1]) ++cc;
+      }
+      close_cnt[i] = overflow ? -(1 << 20) : cc;
+      bcount[i] = (nbd > bdc ? bdc + 1 : nbd) | (loose << 30);
+    }
+    wave_sync();
+    for (int i = lane(); i < nd; i += PSB_WAVE) {
+      if (c.level[i] != 0) continue;
+      const int r = uf_find(c, i);
+      atom_add(&csize[r], 1);
+      atom_add(&cclose[r], close_cnt[i]);
+    }
+    wave_sync();
+    // acceptance, root by root
+    for (int i = lane(); i < nd; i += PSB_WAVE) {
+      if (c.level[i] != 0 || atom_load(&c.uf[i]) != i) continue;
+      const int s = atom_load(&csize[i]);
+      bool ok = (int64_t)atom_load(&cclose[i]) == (int64_t)s * (s - 1) / 2;
+      if (ok && (s & 1)) {
+        if (c.P->reading == 1) {
+          int lo = 0;
+          for (int j = 0; j < nd; ++j) if (c.level[j] == 0 && uf_find(c, j) == i) lo |= (bcount[j] >> 30) & 1;
+          ok = lo != 0;
+        } else if (s == 1) {
+          ok = (bcount[i] & 0x3fffffff) > 0;
+        } else {
+          // some boundary edge (vertex) within d_k of every member
+          bool any = false;
+          const int nb0 = bcount[i] & 0x3fffffff;
+          for (int q = 0; q < nb0 && q < bdc && !any; ++q) {
+            const int e = c.bdl[(int64_t)i * bdc + q];
+            bool all = true;
+            for (int j = 0; j < nd && all; ++j) {
+              if (c.level[j] != 0 || uf_find(c, j) != i || j == i) continue;
+              const int nbj = bcount[j] & 0x3fffffff;
+              bool has = false;
+              for (int t2 = 0; t2 < nbj && t2 < bdc; ++t2) has |= (c.bdl[(int64_t)j * bdc + t2] == e);
+              all = has;
+            }
+            any = all;
+          }
+          ok = any;
+        }
+      }
+      atom_xchg((unsigned*)&csize[i], ok ? 0xffffffffu : 0u);   // reuse as accept flag
+    }
+    wave_sync();
+    for (int i = lane(); i < nd; i += PSB_WAVE)
+      if (c.level[i] == 0 && atom_load(&csize[atom_load(&c.uf[i])]) == -1) c.level[i] = (int8_t)(k + 1);
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fuse: terminal configuration -> edges, weight, observables
+// ---------------------------------------------------------------------------
+PSB_DEV void push_expand(Ctx& c, int region, int s) {
+  if (RF(c, region, RF_BCN) == 0) return;
+  if (c.S->stk_n + 2 > c.P->stkcap) { c.status = S_CAPACITY; return; }
+  c.stk[c.S->stk_n] = region; c.stk[c.S->stk_n + 1] = s;
+  c.S->stk_n += 2;
+}
+
+PSB_DEV void add_fin(Ctx& c, int ce) {
+  if (c.S->fin_n >= c.P->fincap) { c.status = S_CAPACITY; return; }
+  c.fin[c.S->fin_n] = ce;
+  c.S->fin_n += 1;
+}
+
+PSB_DEV void collect_final(Ctx& c) {
+  c.S->fin_n = 0; c.S->stk_n = 0;
+  wave_sync();
+  int bad = 0;
+  for (int r = lane(); r < c.n_regions; r += PSB_WAVE) {
+    if (!RF(c, r, RF_ALIVE) || RF(c, r, RF_BPAR) >= 0) continue;
+    const int mt = RF(c, r, RF_MATE);
+    const int ce = RF(c, r, RF_ME);
+    if (mt == -1 || ce < 0) { bad |= 1; continue; }
+    if (mt != MATE_BOUNDARY && mt < r) continue;   // each pair once, from the smaller id
+    const int k = atom_add(&c.S->fin_n, 1);
+    if (k < c.P->fincap) c.fin[k] = ce; else bad |= 2;
+    const int sa = CEF(c, ce, CE_SA), sb = CEF(c, ce, CE_SB);
+    const int s_r = inside(c, sa, r) ? sa : sb;
+    if (RF(c, r, RF_BCN) > 0) {
+      const int q = atom_add(&c.S->stk_n, 2);
+      if (q + 2 <= c.P->stkcap) { c.stk[q] = r; c.stk[q + 1] = s_r; } else bad |= 2;
+    }
+    if (mt != MATE_BOUNDARY && RF(c, mt, RF_BCN) > 0) {
+      const int q = atom_add(&c.S->stk_n, 2);
+      if (q + 2 <= c.P->stkcap) { c.stk[q] = mt; c.stk[q + 1] = (s_r == sa ? sb : sa); } else bad |= 2;
+    }
+  }
+  bad = wave_or(bad);
+  wave_sync();
+  if (bad & 1) { c.status = S_INFEASIBLE; return; }
+  if (bad & 2) { c.status = S_CAPACITY; return; }
+  if (c.S->fin_n > c.P->fincap) { c.status = S_CAPACITY; return; }
+  while (c.S->stk_n > 0 && !c.status) {
+    c.S->stk_n -= 2;
+    const int X = c.stk[c.S->stk_n], s = c.stk[c.S->stk_n + 1];
+    const int m = RF(c, X, RF_BCN), bo = RF(c, X, RF_BCO);
+    const int* cyc = c.bc + 2 * bo;
+    const int ch = child_containing(c, s, X);
+    int p = -1;
+    for (int i = 0; i < m; ++i) if (cyc[2 * i] == ch) p = i;
+    if (p < 0) { c.status = S_INTERNAL; return; }
+    push_expand(c, ch, s);
+    for (int j = 1; j < m; j += 2) {
+      const int ia = (p + j) % m, ib = (p + j + 1) % m;
+      const int ca = cyc[2 * ia], cb = cyc[2 * ib];
+      const int ce = cyc[2 * ia + 1];
+      add_fin(c, ce);
+      const int sa = CEF(c, ce, CE_SA), sb = CEF(c, ce, CE_SB);
+      const bool a_has_sa = inside(c, sa, ca);
+      push_expand(c, ca, a_has_sa ? sa : sb);
+      push_expand(c, cb, a_has_sa ? sb : sa);
+    }
+  }
+}
+
+PSB_DEV void fuse_and_write(Ctx& c, int64_t shot) {
+  collect_final(c);
+  wave_sync();
+  const int nf = c.S->fin_n;
+  // lane-parallel tracing; each lane flattens its compressed edges with a private stack
+  int bad = 0;
+  for (int i = lane(); i < nf; i += PSB_WAVE) {
+    int* st = c.hit + (int64_t)(lane() % PSB_WAVE) * c.P->hitcap * 2;
+    const int cap = c.P->hitcap * 2;
+    int n = 0;
+    st[n++] = c.fin[i];
+    while (n > 0) {
+      const int ce = st[--n];
+      const int e = CEF(c, ce, CE_E);
+      if (e >= 0) {
+        atom_xor(&c.ebits[e >> 5], 1u << (e & 31));
+        const int ra = CEF(c, ce, CE_A), rb = CEF(c, ce, CE_B);
+        int rec = ra, guard = 0;
+        while (rec >= 0) {
+          const int ee = c.lg[3 * rec + 2];
+          if (ee >= 0) atom_xor(&c.ebits[ee >> 5], 1u << (ee & 31));
+          rec = c.lg[3 * rec + 1];
+          if (++guard > c.n_det + 1) { bad = 1; break; }
+        }
+        rec = rb; guard = 0;
+        while (rec >= 0) {
+          const int ee = c.lg[3 * rec + 2];
+          if (ee >= 0) atom_xor(&c.ebits[ee >> 5], 1u << (ee & 31));
+          rec = c.lg[3 * rec + 1];
+          if (++guard > c.n_det + 1) { bad = 1; break; }
+        }
+      } else {
+        if (n + 2 > cap) { bad = 1; break; }
+        st[n++] = CEF(c, ce, CE_A);
+        st[n++] = CEF(c, ce, CE_B);
+      }
+    }
+  }
+  if (wave_or(bad)) c.status = S_INTERNAL;
+  wave_sync();
+  // scan the edge bitmap in ascending order
+  const int64_t nwords = (c.P->n_edges + 31) / 32;
+  int32_t* out = c.P->out_edges + shot * (int64_t)c.P->edge_stride;
+  const int stride = c.P->edge_stride;
+  int64_t wsum = 0; uint64_t ob = 0;
+  int count = 0;
+  for (int64_t w0 = 0; w0 < nwords; w0 += PSB_WAVE) {
+    unsigned bits = 0;
+    int64_t wi = w0 + lane();
+    if (wi < nwords) bits = atom_xchg(&c.ebits[wi], 0u);
+    const int pc = __builtin_popcount(bits);
+    int pos = count + wave_prefix(pc);
+    for (int k = 0; k < 32; ++k) if (bits >> k & 1) {
+      const int e = (int)(wi * 32 + k);
+      if (pos < stride) out[pos] = e;
+      ++pos; wsum += c.w[e]; ob ^= c.obs[e];
+    }
+    count += wave_sum(pc);
+  }
+  // reduce weight / obs across lanes
+  for (int m = PSB_WAVE / 2; m >= 1; m >>= 1) {
+    const int lo = shfl_xor_i32((int)(uint32_t)(wsum & 0xffffffff), m);
+    const int hi = shfl_xor_i32((int)(wsum >> 32), m);
+    wsum += ((int64_t)hi << 32) | (uint32_t)lo;
+    const int olo = shfl_xor_i32((int)(uint32_t)(ob & 0xffffffff), m);
+    const int ohi = shfl_xor_i32((int)(ob >> 32), m);
+    ob ^= ((uint64_t)(uint32_t)ohi << 32) | (uint32_t)olo;
+  }
+  if (c.status == S_OK && count > stride) c.status = S_TRUNC;
+  if (lane() == 0) {
+    c.P->out_nedges[shot] = count < stride ? count : stride;
+    c.P->out_weight[shot] = wsum;
+    c.P->out_obs[shot] = ob;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one shot
+// ---------------------------------------------------------------------------
+PSB_DEV void seed_level(Ctx& c, int lvl) {
+  // detector regions of this level start growing at t = 0 (one tree each)
+  for (int i = lane(); i < c.nd; i += PSB_WAVE) {
+    if (c.level[i] != lvl) continue;
+    const int u = c.defects[i];
+    c.lg[3 * i] = u; c.lg[3 * i + 1] = -1; c.lg[3 * i + 2] = -1;
+    c.n_top[u] = i; c.n_reg[u] = i; c.n_src[u] = i; c.n_wr[u] = 0; c.n_rec[u] = i;
+    c.n_did[u] = -1;    // seeded: arrivals are no longer an error
+    // shell: the reserved chunk i holds the detection event itself
+    c.ck_nodes[(int64_t)i * CHUNK] = u; c.ck_next[i] = -1; c.ck_prev[i] = -1;
+    c.n_pos[u] = i * CHUNK;
+    RF(c, i, RF_RATE) = 1; c.r_base[i] = 0; RF(c, i, RF_TID) = i;
+    RF(c, i, RF_CKH) = i; RF(c, i, RF_CKT) = i; RF(c, i, RF_CNT) = 1;
+    const int ix = atom_add(&c.S->x_n, 1);
+    c.x_node[ix] = u; c.x_ev[ix] = T_INF; c.n_eix[u] = ix;
+  }
+  wave_sync();
+  for (int i = lane(); i < c.nd; i += PSB_WAVE) {
+    if (c.level[i] != lvl) continue;
+    const int u = c.defects[i];
+    i128 t; int k;
+    node_event(c, u, t, k);
+    set_event(c, c.n_eix[u], t);
+  }
+  wave_sync();
+}
+
+PSB_DEV void write_empty(Ctx& c, int64_t shot, int status) {
+  if (lane() == 0) {
+    c.P->out_nedges[shot] = 0; c.P->out_weight[shot] = 0; c.P->out_obs[shot] = 0;
+    c.P->out_status[shot] = status;
+  }
+}
+
+PSB_DEV void cleanup(Ctx& c) {
+  wave_sync();
+  const int xn = c.S->x_n;
+  for (int i = lane(); i < xn; i += PSB_WAVE) {
+    const int v = c.x_node[i];
+    c.n_top[v] = -1; c.n_reg[v] = -1; c.n_src[v] = -1; c.n_eix[v] = -1; c.n_rec[v] = -1;
+  }
+  const int nd = c.nd < c.P->dcap ? c.nd : c.P->dcap;
+  for (int i = lane(); i < nd; i += PSB_WAVE) {
+    const int u = c.defects[i];
+    c.n_did[u] = -1; c.n_top[u] = -1; c.n_reg[u] = -1; c.n_src[u] = -1; c.n_eix[u] = -1; c.n_rec[u] = -1;
+  }
+  const int64_t nwords = (c.P->n_edges + 31) / 32;
+  if (c.status) for (int64_t i = lane(); i < nwords; i += PSB_WAVE) c.ebits[i] = 0;
+  for (int i = lane(); i < 512; i += PSB_WAVE) c.S->dmask[i] = 0;
+  wave_sync();
+  c.S->x_n = 0; c.S->dblk_n = 0; c.S->fin_n = 0; c.S->stk_n = 0;
+  wave_sync();
+}
+
+PSB_DEV void decode_shot(Ctx& c, int64_t shot) {
+  c.status = S_OK; c.n_ce = 0; c.n_bc = 0; c.n_shr = 0; c.n_chg = 0; c.stamp = 1; c.n_ev = 0;
+  c.ck_free = -1; c.now = 0;
+  const uint8_t* row = c.P->synd + shot * (int64_t)c.P->nbytes;
+  load_defects(c, row);
+  const int nd = c.nd;
+  if (c.status) { write_empty(c, shot, c.status); cleanup(c); return; }
+  if (nd == 0) { write_empty(c, shot, S_OK); cleanup(c); return; }
+  if (nd > c.rcap) { write_empty(c, shot, S_CAPACITY); cleanup(c); return; }
+  c.n_regions = nd; c.n_log = nd; c.n_ck = nd;
+  for (int i = lane(); i < nd; i += PSB_WAVE) region_init(c, i, 0, 0, -1);
+  wave_sync();
+  int max_level = 1;
+  if (c.P->mode == 1) {
+    for (int i = lane(); i < nd; i += PSB_WAVE) c.level[i] = 1;
+    wave_sync();
+  } else {
+    cluster(c);
+    int mx = 0, miss = 0;
+    for (int i = lane(); i < nd; i += PSB_WAVE) { mx = c.level[i] > mx ? c.level[i] : mx; miss |= (c.level[i] == 0); }
+    max_level = wave_max(mx);
+    if (wave_or(miss)) c.status = S_INTERNAL;
+  }
+  for (int lvl = 1; lvl <= max_level && !c.status; ++lvl) {
+    int present = 0;
+    for (int i = lane(); i < nd; i += PSB_WAVE) present |= (c.level[i] == lvl);
+    if (!wave_or(present)) continue;
+    c.now = 0;       // every level starts its clock at zero; stopped regions are frozen
+    seed_level(c, lvl);
+    run_dynamics(c);
+    if (!c.status) {
+      // every tree must have dissolved
+      int open = 0;
+      for (int r = lane(); r < c.n_regions; r += PSB_WAVE)
+        open |= (RF(c, r, RF_ALIVE) && RF(c, r, RF_BPAR) < 0 && RF(c, r, RF_TID) >= 0 &&
+                 (r >= nd || c.level[r] <= lvl));
+      if (wave_or(open)) c.status = S_INFEASIBLE;
+    }
+  }
+  if (c.P->out_levels && lane() == 0) {
+    int8_t* lv = c.P->out_levels + shot * (int64_t)c.P->dcap;
+    for (int i = 0; i < nd; ++i) lv[i] = (c.P->mode == 1) ? 0 : c.level[i];
+  }
+  if (c.status) { write_empty(c, shot, c.status); cleanup(c); return; }
+  fuse_and_write(c, shot);
+  if (lane() == 0) c.P->out_status[shot] = c.status;
+  cleanup(c);
+}
+
+// Workspace pointers of slot `slot`.
+PSB_DEV void ctx_init(Ctx& c, const Params* P, Lds* S, int64_t slot) {
+  c.P = P; c.S = S;
+  c.nbr = P->nbr; c.eid = P->eid; c.wt = P->wt; c.w = P->w; c.obs = P->obs;
+  c.deg = P->deg; c.n_det = P->n_det; c.rcap = P->rcap;
+  char* base = P->ws + slot * P->L.total;
+  const WsLayout& L = P->L;
+  c.n_top = (int32_t*)(base + L.n_top); c.n_reg = (int32_t*)(base + L.n_reg);
+  c.n_src = (int32_t*)(base + L.n_src); c.n_eix = (int32_t*)(base + L.n_eix);
+  c.n_rec = (int32_t*)(base + L.n_rec); c.n_pos = (int32_t*)(base + L.n_pos);
+  c.n_did = (int32_t*)(base + L.n_did); c.n_wr = (i128*)(base + L.n_wr);
+  c.x_node = (int32_t*)(base + L.x_node); c.x_ev = (i128*)(base + L.x_ev);
+  c.blk_min = (i128*)(base + L.blk_min); c.blk_arg = (int32_t*)(base + L.blk_arg);
+  c.r_base = (i128*)(base + L.r_base); c.r_f = (int32_t*)(base + L.r_f);
+  c.ck_next = (int32_t*)(base + L.ck_next); c.ck_prev = (int32_t*)(base + L.ck_prev);
+  c.ck_nodes = (int32_t*)(base + L.ck_nodes);
+  c.ce = (int32_t*)(base + L.ce); c.bc = (int32_t*)(base + L.bc); c.lg = (int32_t*)(base + L.lg);
+  c.defects = (int32_t*)(base + L.defects); c.level = (int8_t*)(base + L.level);
+  c.uf = (int32_t*)(base + L.uf); c.cl_a = (int32_t*)(base + L.cl_a); c.cl_b = (int32_t*)(base + L.cl_b);
+  c.cl_c = (int32_t*)(base + L.cl_c); c.cl_d = (int32_t*)(base + L.cl_d);
+  c.bdl = (int32_t*)(base + L.bdl); c.hit = (int32_t*)(base + L.hit);
+  c.shr = (int32_t*)(base + L.shr); c.chg = (int32_t*)(base + L.chg); c.stk = (int32_t*)(base + L.stk);
+  c.fin = (int32_t*)(base + L.fin); c.ebits = (uint32_t*)(base + L.ebits);
+}
+
+}  // namespace psb

@@ -1,0 +1,237 @@
+// Host-side setup shared by the HIP library and tooling: exact level
+// schedule (big-integer rationals), tie-broken weights, diameter bound and
+// the per-slot workspace layout.  Plain C++ (no HIP).
+#pragma once
+#include <stdint.h>
+#include <algorithm>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "../../include/psb.h"
+#include "psb_types.h"
+
+namespace psb_host {
+typedef unsigned __int128 u128;
+using psb::WsLayout;
+using psb::Params;
+
+// Provided by the including translation unit.
+int32_t fail(int32_t code, const std::string& msg);
+
+// Graph topology in fixed-width adjacency form.
+struct Ell {
+  int32_t n_det = 0, deg = 0;
+  int64_t n_edges = 0;
+  std::vector<int32_t> nbr, eid;
+};
+
+// ---------------------------------------------------------------------------
+// exact level schedule (Methods, Algorithm "Parameter schedule"), unsigned
+// big integers so that the rationals phi_k are handled without rounding
+// ---------------------------------------------------------------------------
+struct Big {
+  std::vector<uint32_t> d;  // little endian, no leading zeros
+  static Big of(u128 x) { Big b; while (x) { b.d.push_back((uint32_t)x); x >>= 32; } return b; }
+  void trim() { while (!d.empty() && d.back() == 0) d.pop_back(); }
+};
+static Big badd(const Big& a, const Big& b) {
+  Big r; r.d.resize(std::max(a.d.size(), b.d.size()) + 1, 0);
+  uint64_t carry = 0;
+  for (size_t i = 0; i < r.d.size(); ++i) {
+    uint64_t s = carry + (i < a.d.size() ? a.d[i] : 0) + (i < b.d.size() ? b.d[i] : 0);
+    r.d[i] = (uint32_t)s; carry = s >> 32;
+  }
+  r.trim(); return r;
+}
+static Big bsub(const Big& a, const Big& b) {   // requires a >= b
+  Big r; r.d.resize(a.d.size(), 0);
+  int64_t borrow = 0;
+  for (size_t i = 0; i < a.d.size(); ++i) {
+    int64_t s = (int64_t)a.d[i] - borrow - (i < b.d.size() ? b.d[i] : 0);
+    borrow = s < 0; if (s < 0) s += (1LL << 32);
+    r.d[i] = (uint32_t)s;
+  }
+  r.trim(); return r;
+}
+static Big bmul(const Big& a, const Big& b) {
+  Big r; if (a.d.empty() || b.d.empty()) return r;
+  std::vector<uint64_t> t(a.d.size() + b.d.size() + 1, 0);
+  for (size_t i = 0; i < a.d.size(); ++i) {
+    uint64_t carry = 0;
+    for (size_t j = 0; j < b.d.size(); ++j) {
+      uint64_t cur = t[i + j] + (uint64_t)a.d[i] * b.d[j] + carry;
+      t[i + j] = cur & 0xffffffffu; carry = cur >> 32;
+    }
+    size_t k = i + b.d.size();
+    while (carry) { uint64_t cur = t[k] + carry; t[k] = cur & 0xffffffffu; carry = cur >> 32; ++k; }
+  }
+  r.d.resize(t.size()); for (size_t i = 0; i < t.size(); ++i) r.d[i] = (uint32_t)t[i];
+  r.trim(); return r;
+}
+static int bcmp(const Big& a, const Big& b) {
+  if (a.d.size() != b.d.size()) return a.d.size() < b.d.size() ? -1 : 1;
+  for (size_t i = a.d.size(); i-- > 0;) if (a.d[i] != b.d[i]) return a.d[i] < b.d[i] ? -1 : 1;
+  return 0;
+}
+
+struct LevelSchedule { std::vector<u128> d, b; std::vector<int> final_level; };
+
+// phi = n/m; target = P/Q; admissibility of an integer b (Algorithm "Parameter schedule"):
+// b >= d, phi > 2 d / b, Phi_{k+1}(b) = phi - (phi+2) d / ((phi+1) d + phi b) >= target.
+static bool admissible(u128 b, u128 d, const Big& n, const Big& m, const Big& P, const Big& Q) {
+  if (b < d) return false;
+  const Big B = Big::of(b), D_ = Big::of(d);
+  if (bcmp(bmul(n, B), bmul(Big::of(2), bmul(D_, m))) <= 0) return false;
+  const Big Dn = badd(bmul(badd(n, m), D_), bmul(n, B));               // (n+m) d + n b
+  const Big lhs = bmul(bmul(n, Dn), Q);
+  const Big rhs = badd(bmul(bmul(P, m), Dn), bmul(bmul(m, badd(n, bmul(Big::of(2), m))), bmul(D_, Q)));
+  return bcmp(lhs, rhs) >= 0;
+}
+
+static int32_t build_schedule(u128 wmax, u128 diam, int64_t qn, int64_t qd, int64_t pn, int64_t pd,
+                              LevelSchedule& out) {
+  const u128 LIM = ((u128)1) << 123;
+  u128 d = wmax + 1;
+  Big n = Big::of(1), m = Big::of(1);
+  Big qn_pow = Big::of(1), qd_pow = Big::of(1);
+  for (int k = 1; k <= 32; ++k) {
+    qn_pow = bmul(qn_pow, Big::of((u128)qn)); qd_pow = bmul(qd_pow, Big::of((u128)qd));
+    // target phi_bar_{k+1} = phi_min + (1 - phi_min) q^k = [pn qd^k + (pd - pn) qn^k] / (pd qd^k)
+    const Big P = badd(bmul(Big::of((u128)pn), qd_pow), bmul(Big::of((u128)(pd - pn)), qn_pow));
+    const Big Q = bmul(Big::of((u128)pd), qd_pow);
+    u128 b;
+    if (admissible(d, d, n, m, P, Q)) b = d;
+    else {
+      u128 lo = d, hi = d * 2;
+      while (!admissible(hi, d, n, m, P, Q)) {
+        if (hi > LIM) return fail(PSB_E_UNSUPPORTED, "level parameters exceed 2^123");
+        lo = hi; hi *= 2;
+      }
+      while (hi - lo > 1) { u128 mid = lo + (hi - lo) / 2; if (admissible(mid, d, n, m, P, Q)) hi = mid; else lo = mid; }
+      b = hi;
+    }
+    out.d.push_back(d); out.b.push_back(b);
+    const bool fin = b >= diam;
+    out.final_level.push_back(fin ? 1 : 0);
+    if (fin) return PSB_OK;
+    // phi_{k+1} = (n Dn - m (n + 2m) d) / (m Dn)
+    const Big D_ = Big::of(d), B = Big::of(b);
+    const Big Dn = badd(bmul(badd(n, m), D_), bmul(n, B));
+    const Big num = bsub(bmul(n, Dn), bmul(bmul(m, badd(n, bmul(Big::of(2), m))), D_));
+    const Big den = bmul(m, Dn);
+    n = num; m = den;
+    const u128 dn = 3 * d + 4 * b + 2 * wmax;
+    if (dn > LIM) return fail(PSB_E_UNSUPPORTED, "level parameters exceed 2^123");
+    d = dn;
+  }
+  return fail(PSB_E_UNSUPPORTED, "schedule did not reach the graph diameter within 32 levels");
+}
+
+static uint64_t lib_splitmix(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + k * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// Upper bound on the tie-broken distance between any two vertices (detectors
+// or boundary vertices) of one connected component: twice the eccentricity
+// of a detector plus the heaviest edge, maximised over components.
+static u128 diameter_bound(const Ell* g, const std::vector<__int128>& wt) {
+  const int32_t n = g->n_det, deg = g->deg;
+  std::vector<__int128> dist(n, -1);
+  __int128 wmax = 0;
+  for (auto x : wt) wmax = std::max(wmax, x);
+  __int128 best = 0;
+  typedef std::pair<__int128, int32_t> item;
+  for (int32_t s = 0; s < n; ++s) {
+    if (dist[s] >= 0) continue;
+    std::priority_queue<item, std::vector<item>, std::greater<item>> pq;
+    dist[s] = 0; pq.push({0, s});
+    __int128 ecc = 0;
+    while (!pq.empty()) {
+      auto [dd, x] = pq.top(); pq.pop();
+      if (dd != dist[x]) continue;
+      ecc = std::max(ecc, dd);
+      for (int j = 0; j < deg; ++j) {
+        const int32_t y = g->nbr[(size_t)x * deg + j];
+        if (y < 0) continue;
+        const __int128 nd = dd + wt[g->eid[(size_t)x * deg + j]];
+        if (dist[y] < 0 || nd < dist[y]) { dist[y] = nd; pq.push({nd, y}); }
+      }
+    }
+    best = std::max(best, 2 * (ecc + wmax));
+  }
+  return (u128)best;
+}
+
+static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+
+// Tie-broken even weights wt(e) = 2 w(e) 2^64 + 2 h(e), h = SplitMix64 output (e+1) >> 24.
+static void tiebroken_weights(const int32_t* w, int64_t m, uint64_t seed, std::vector<__int128>& wt,
+                              __int128& wmax, __int128& wmin) {
+  wt.resize(m);
+  wmax = 0; wmin = 0;
+  for (int64_t e = 0; e < m; ++e) {
+    const uint64_t h = lib_splitmix(seed, (uint64_t)e + 1) >> 24;
+    wt[e] = ((__int128)(2 * (int64_t)w[e]) << 64) + (__int128)(2 * h);
+    wmax = std::max(wmax, wt[e]);
+    wmin = (e == 0) ? wt[e] : std::min(wmin, wt[e]);
+  }
+  if (m == 0) { wmax = 2; wmin = 2; }
+}
+
+
+
+// Capacities and workspace layout for one slot.
+static void plan_workspace(Params& P, int32_t n, int32_t deg, int64_t n_edges, int32_t dcap) {
+  P.n_det = n; P.deg = deg; P.nbytes = (n + 7) / 8; P.n_edges = n_edges;
+  P.dcap = dcap;
+  P.rcap = 4 * dcap + 64;
+  P.cecap = 8 * dcap + 256;
+  P.bccap = 8 * dcap + 256;
+  P.lcap = 2 * n + 4 * dcap + 64;
+  P.ckcap = 3 * dcap + n / psb::CHUNK + 64;
+  P.shrcap = P.rcap;
+  P.stkcap = 4 * P.rcap + 64;
+  P.fincap = 2 * dcap + 64;
+  P.hitcap = 32;
+  P.bdc = 8;
+  P.max_events = (int64_t)64 * ((int64_t)n + 64 * (int64_t)dcap);
+  WsLayout& L = P.L;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) { int64_t o = off; off = align256(off + bytes); return o; };
+  const int64_t nblk = (n + psb::CHUNK - 1) / psb::CHUNK;
+  L.n_top = take(4LL * n); L.n_reg = take(4LL * n); L.n_src = take(4LL * n); L.n_eix = take(4LL * n);
+  L.n_rec = take(4LL * n); L.n_pos = take(4LL * n); L.n_did = take(4LL * n); L.n_wr = take(16LL * n);
+  L.x_node = take(4LL * n); L.x_ev = take(16LL * n); L.blk_min = take(16 * nblk); L.blk_arg = take(4 * nblk);
+  L.r_base = take(16LL * P.rcap); L.r_f = take(4LL * psb::RF_COUNT * P.rcap);
+  L.ck_next = take(4LL * P.ckcap); L.ck_prev = take(4LL * P.ckcap); L.ck_nodes = take(4LL * psb::CHUNK * P.ckcap);
+  L.ce = take(4LL * psb::CE_COUNT * P.cecap); L.bc = take(8LL * P.bccap); L.lg = take(12LL * P.lcap);
+  L.defects = take(4LL * dcap); L.level = take(dcap); L.uf = take(4LL * dcap);
+  L.cl_a = take(4LL * dcap); L.cl_b = take(4LL * dcap); L.cl_c = take(4LL * dcap); L.cl_d = take(4LL * dcap);
+  L.bdl = take(4LL * dcap * P.bdc); L.hit = take(4LL * 64 * P.hitcap * 2);
+  L.shr = take(4LL * P.shrcap); L.chg = take(4LL * P.rcap); L.stk = take(4LL * P.stkcap);
+  L.fin = take(4LL * P.fincap); L.ebits = take(4 * ((n_edges + 31) / 32 + 1));
+  L.total = off;
+}
+
+// Path-enumeration depth per level (-1 = final level); returns false if a
+// level would need deeper enumeration than the clustering kernel supports.
+static bool level_depths(const LevelSchedule& S, __int128 wmin, std::vector<int32_t>& hmax, int& bad_level) {
+  hmax.clear();
+  for (size_t k = 0; k < S.d.size(); ++k) {
+    int h = -1;
+    if (!S.final_level[k]) {
+      const u128 H = S.b[k] / (u128)wmin;
+      if (H > (u128)psb::MAXH) { bad_level = (int)k + 1; return false; }
+      h = (int)H;
+    }
+    hmax.push_back(h);
+  }
+  return true;
+}
+
+}  // namespace psb_host

@@ -1,0 +1,283 @@
+// libpsb: host side of the decoder (graph upload, level schedule, workspace,
+// launch) and the persistent decode kernel.  See include/psb.h for the ABI.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "../../include/psb.h"
+#include "psb_types.h"
+#include "wave.h"
+#include "engine.h"
+#include "host_setup.h"
+
+using namespace psb_host;
+
+using psb::Params;
+using psb::WsLayout;
+typedef unsigned __int128 u128;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+namespace psb_host { int32_t fail(int32_t code, const std::string& msg) { g_err = msg; return code; } }
+using psb_host::fail;
+extern "C" const char* psb_last_error(void) { return g_err.c_str(); }
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess) return fail(PSB_E_DEVICE, std::string(#expr " failed: ") + hipGetErrorString(_e)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+__global__ void psb_zero_kernel(int32_t* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ __launch_bounds__(64) void psb_decode_kernel(Params P) {
+  __shared__ psb::Lds S;
+  for (int i = threadIdx.x; i < 512; i += 64) { S.dmask[i] = 0; S.dblk[i] = 0; }
+  if (threadIdx.x == 0) { S.dblk_n = 0; S.x_n = 0; S.fin_n = 0; S.stk_n = 0; S.lnk_n = 0; }
+  __syncthreads();
+  psb::Ctx c;
+  psb::ctx_init(c, &P, &S, blockIdx.x);
+  for (;;) {
+    int shot = 0;
+    if (threadIdx.x == 0) shot = atomicAdd(P.counter, 1);
+    shot = __shfl(shot, 0, 64);
+    if (shot >= P.n_shots) break;
+    psb::decode_shot(c, shot);
+    if (P.out_tdone && threadIdx.x == 0) P.out_tdone[shot] = wall_clock64();
+  }
+}
+
+// Marks the explored/defect state of fresh workspace slots as empty.
+__global__ void psb_ws_init_kernel(char* ws, int64_t stride, int64_t slots, WsLayout L, int32_t n_det) {
+  const int64_t slot = blockIdx.y;
+  if (slot >= slots) return;
+  char* base = ws + slot * stride;
+  int32_t* arr[7] = {(int32_t*)(base + L.n_top), (int32_t*)(base + L.n_reg), (int32_t*)(base + L.n_src),
+                     (int32_t*)(base + L.n_eix), (int32_t*)(base + L.n_rec), (int32_t*)(base + L.n_pos),
+                     (int32_t*)(base + L.n_did)};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_det; i += (int64_t)gridDim.x * blockDim.x)
+    for (int a = 0; a < 7; ++a) arr[a][i] = -1;
+}
+
+// ---------------------------------------------------------------------------
+// graph
+// ---------------------------------------------------------------------------
+struct psb_graph {
+  int32_t n_det = 0, deg = 0;
+  int64_t n_edges = 0;
+  std::vector<int32_t> u, v, w;
+  std::vector<uint64_t> obs;
+  std::vector<int32_t> nbr, eid;     // host ELL
+  int32_t *d_nbr = nullptr, *d_eid = nullptr, *d_w = nullptr;
+  uint64_t* d_obs = nullptr;
+};
+
+extern "C" int32_t psb_graph_create(const psb_graph_desc* desc, psb_graph** out) {
+  if (!desc || !out) return fail(PSB_E_INVALID, "null argument");
+  *out = nullptr;
+  const int32_t n = desc->num_detectors;
+  const int64_t m = desc->num_edges;
+  if (n <= 0 || m < 0 || m >= (1LL << 23)) return fail(PSB_E_INVALID, "num_detectors must be > 0 and num_edges in [0, 2^23)");
+  if (m > 0 && (!desc->u || !desc->v || !desc->w || !desc->obs_mask)) return fail(PSB_E_INVALID, "null edge array");
+  std::vector<int32_t> degree(n, 0);
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t a = desc->u[e], b = desc->v[e];
+    if (a < 0 || a >= n || b < PSB_BOUNDARY || b >= n || a == b)
+      return fail(PSB_E_INVALID, "edge " + std::to_string(e) + " has an endpoint out of range or is a self loop");
+    if (desc->w[e] <= 0) return fail(PSB_E_INVALID, "edge " + std::to_string(e) + " has a non-positive weight");
+    ++degree[a];
+    if (b >= 0) ++degree[b];
+  }
+  int32_t deg = 1;
+  for (int32_t x : degree) deg = std::max(deg, x);
+  if (deg > 16) return fail(PSB_E_INVALID, "a detector has degree > 16");
+  psb_graph* g = new psb_graph();
+  g->n_det = n; g->n_edges = m; g->deg = deg;
+  g->u.assign(desc->u, desc->u + m); g->v.assign(desc->v, desc->v + m);
+  g->w.assign(desc->w, desc->w + m); g->obs.assign(desc->obs_mask, desc->obs_mask + m);
+  g->nbr.assign((size_t)n * deg, psb::NB_PAD);
+  g->eid.assign((size_t)n * deg, -1);
+  std::vector<int32_t> fill(n, 0);
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t a = g->u[e], b = g->v[e];
+    g->nbr[(size_t)a * deg + fill[a]] = (b >= 0) ? b : psb::NB_BOUNDARY;
+    g->eid[(size_t)a * deg + fill[a]++] = (int32_t)e;
+    if (b >= 0) {
+      g->nbr[(size_t)b * deg + fill[b]] = a;
+      g->eid[(size_t)b * deg + fill[b]++] = (int32_t)e;
+    }
+  }
+  auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(dst, bytes ? bytes : 16);
+    if (e != hipSuccess) return e;
+    return bytes ? hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+  };
+  hipError_t e1 = up((void**)&g->d_nbr, g->nbr.data(), g->nbr.size() * 4);
+  hipError_t e2 = up((void**)&g->d_eid, g->eid.data(), g->eid.size() * 4);
+  hipError_t e3 = up((void**)&g->d_w, g->w.data(), g->w.size() * 4);
+  hipError_t e4 = up((void**)&g->d_obs, g->obs.data(), g->obs.size() * 8);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+    psb_graph_destroy(g);
+    return fail(PSB_E_DEVICE, "graph upload failed");
+  }
+  *out = g;
+  return PSB_OK;
+}
+
+extern "C" int32_t psb_graph_destroy(psb_graph* g) {
+  if (!g) return PSB_OK;
+  if (g->d_nbr) (void)hipFree(g->d_nbr);
+  if (g->d_eid) (void)hipFree(g->d_eid);
+  if (g->d_w) (void)hipFree(g->d_w);
+  if (g->d_obs) (void)hipFree(g->d_obs);
+  delete g;
+  return PSB_OK;
+}
+
+extern "C" int32_t psb_graph_syndrome_bytes(const psb_graph* g) { return g ? (g->n_det + 7) / 8 : -1; }
+
+// ---------------------------------------------------------------------------
+// decoder
+// ---------------------------------------------------------------------------
+struct psb_decoder {
+  const psb_graph* g = nullptr;
+  psb_decoder_opts opts{};
+  int32_t dcap = 0, edge_stride = 0, slots = 0;
+  __int128* d_wt = nullptr;
+  __int128* d_sd = nullptr; __int128* d_sb = nullptr; int32_t* d_shmax = nullptr;
+  int32_t* d_counter = nullptr;
+  char* d_ws = nullptr;
+  WsLayout L{};
+  Params P{};
+  LevelSchedule sched;
+  std::vector<int32_t> hmax;
+};
+
+extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts* o, psb_decoder** out) {
+  if (!g || !out) return fail(PSB_E_INVALID, "null argument");
+  *out = nullptr;
+  psb_decoder_opts opts = o ? *o : psb_decoder_opts{};
+  if (opts.q_num == 0 && opts.q_den == 0) { opts.q_num = 1; opts.q_den = 10; }
+  if (opts.phi_min_num == 0 && opts.phi_min_den == 0) { opts.phi_min_num = 1; opts.phi_min_den = 100; }
+  if (opts.q_num <= 0 || opts.q_den <= opts.q_num || opts.phi_min_num <= 0 || opts.phi_min_den <= opts.phi_min_num)
+    return fail(PSB_E_INVALID, "q and phi_min must lie in (0, 1)");
+  if (opts.mode != 0 && opts.mode != 1) return fail(PSB_E_INVALID, "mode must be 0 or 1");
+  if (opts.boundary_reading != 0 && opts.boundary_reading != 1) return fail(PSB_E_INVALID, "boundary_reading must be 0 or 1");
+  const int32_t n = g->n_det;
+  int32_t dcap = opts.max_defects_per_shot > 0 ? opts.max_defects_per_shot : std::min(n, n > 20000 ? 1024 : 512);
+  if (dcap > n) dcap = n;
+  if (dcap < 1) dcap = 1;
+  const int32_t stride = opts.edges_per_shot > 0 ? opts.edges_per_shot : std::max(64, dcap * 8);
+  const int32_t slots = opts.num_slots > 0 ? opts.num_slots : 2048;
+
+  psb_decoder* D = new psb_decoder();
+  D->g = g; D->opts = opts; D->dcap = dcap; D->edge_stride = stride; D->slots = slots;
+  std::vector<__int128> wt;
+  __int128 wmax, wmin;
+  tiebroken_weights(g->w.data(), g->n_edges, opts.tiebreak_seed, wt, wmax, wmin);
+  Ell ell; ell.n_det = g->n_det; ell.deg = g->deg; ell.n_edges = g->n_edges; ell.nbr = g->nbr; ell.eid = g->eid;
+  const u128 diam = diameter_bound(&ell, wt);
+  int32_t rc = build_schedule((u128)wmax, diam, opts.q_num, opts.q_den, opts.phi_min_num, opts.phi_min_den, D->sched);
+  if (rc != PSB_OK) { delete D; return rc; }
+  int bad_level = 0;
+  if (!level_depths(D->sched, wmin, D->hmax, bad_level)) {
+    delete D;
+    return fail(PSB_E_UNSUPPORTED, "level " + std::to_string(bad_level) + " needs paths of more than " +
+                                       std::to_string(psb::MAXH) + " edges; the clustering kernel enumerates at most that");
+  }
+  Params& P = D->P;
+  plan_workspace(P, n, g->deg, g->n_edges, dcap);
+  P.n_levels = (int32_t)D->sched.d.size(); P.reading = opts.boundary_reading; P.mode = opts.mode;
+  P.edge_stride = stride;
+  const WsLayout& L = P.L;
+  D->L = L;
+  // device buffers
+  auto fail_dev = [&](const char* what) { psb_decoder_destroy(D); return fail(PSB_E_NOMEM, std::string("device allocation failed: ") + what); };
+  if (hipMalloc((void**)&D->d_wt, 16 * std::max<int64_t>(1, g->n_edges)) != hipSuccess) return fail_dev("weights");
+  if (g->n_edges) HIP_TRY(hipMemcpy(D->d_wt, wt.data(), 16 * g->n_edges, hipMemcpyHostToDevice));
+  const size_t nl = D->sched.d.size();
+  std::vector<__int128> sd(nl), sb(nl);
+  for (size_t k = 0; k < nl; ++k) { sd[k] = (__int128)D->sched.d[k]; sb[k] = (__int128)D->sched.b[k]; }
+  if (hipMalloc((void**)&D->d_sd, 16 * nl) != hipSuccess || hipMalloc((void**)&D->d_sb, 16 * nl) != hipSuccess ||
+      hipMalloc((void**)&D->d_shmax, 4 * nl) != hipSuccess || hipMalloc((void**)&D->d_counter, 256) != hipSuccess)
+    return fail_dev("schedule");
+  HIP_TRY(hipMemcpy(D->d_sd, sd.data(), 16 * nl, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(D->d_sb, sb.data(), 16 * nl, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(D->d_shmax, D->hmax.data(), 4 * nl, hipMemcpyHostToDevice));
+  if (hipMalloc((void**)&D->d_ws, (size_t)L.total * slots) != hipSuccess) return fail_dev("workspace");
+  HIP_TRY(hipMemset(D->d_ws, 0, (size_t)L.total * slots));
+  {
+    dim3 grid(64, slots);
+    psb_ws_init_kernel<<<grid, 256>>>(D->d_ws, L.total, slots, L, n);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipDeviceSynchronize());
+  }
+  P.nbr = g->d_nbr; P.eid = g->d_eid; P.wt = D->d_wt; P.w = g->d_w; P.obs = g->d_obs;
+  P.sd = D->d_sd; P.sb = D->d_sb; P.shmax = D->d_shmax;
+  P.counter = D->d_counter; P.ws = D->d_ws;
+  *out = D;
+  return PSB_OK;
+}
+
+extern "C" int32_t psb_decoder_destroy(psb_decoder* D) {
+  if (!D) return PSB_OK;
+  if (D->d_wt) (void)hipFree(D->d_wt);
+  if (D->d_sd) (void)hipFree(D->d_sd);
+  if (D->d_sb) (void)hipFree(D->d_sb);
+  if (D->d_shmax) (void)hipFree(D->d_shmax);
+  if (D->d_counter) (void)hipFree(D->d_counter);
+  if (D->d_ws) (void)hipFree(D->d_ws);
+  delete D;
+  return PSB_OK;
+}
+
+extern "C" int32_t psb_decoder_levels(const psb_decoder* D, int32_t max_levels, int64_t* d_hi, uint64_t* d_lo,
+                                      int64_t* b_hi, uint64_t* b_lo, int32_t* final_level) {
+  if (!D) return fail(PSB_E_INVALID, "null decoder");
+  const int32_t nl = (int32_t)std::min<size_t>(D->sched.d.size(), (size_t)std::max(0, max_levels));
+  for (int32_t k = 0; k < nl; ++k) {
+    if (d_hi) d_hi[k] = (int64_t)(D->sched.d[k] >> 64);
+    if (d_lo) d_lo[k] = (uint64_t)D->sched.d[k];
+    if (b_hi) b_hi[k] = (int64_t)(D->sched.b[k] >> 64);
+    if (b_lo) b_lo[k] = (uint64_t)D->sched.b[k];
+    if (final_level) final_level[k] = D->sched.final_level[k];
+  }
+  return nl;
+}
+
+extern "C" int32_t psb_decoder_edges_per_shot(const psb_decoder* D) { return D ? D->edge_stride : -1; }
+extern "C" int32_t psb_decoder_max_defects(const psb_decoder* D) { return D ? D->dcap : -1; }
+
+extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, int64_t n, int32_t* edges,
+                                    int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
+                                    int8_t* levels, uint64_t* t_done, void* stream) {
+  if (!D) return fail(PSB_E_INVALID, "null decoder");
+  if (n < 0) return fail(PSB_E_INVALID, "negative batch size");
+  if (n == 0) return PSB_OK;
+  if (n > (int64_t)INT32_MAX) return fail(PSB_E_INVALID, "batch too large");
+  if (!syndromes || !edges || !n_edges || !weight || !obs || !status) return fail(PSB_E_INVALID, "null output");
+  hipStream_t s = (hipStream_t)stream;
+  Params P = D->P;
+  P.n_shots = n; P.synd = syndromes; P.out_edges = edges; P.out_nedges = n_edges; P.out_weight = weight;
+  P.out_obs = obs; P.out_status = status; P.out_levels = levels; P.out_tdone = t_done;
+  psb_zero_kernel<<<1, 64, 0, s>>>(D->d_counter, 1);
+  HIP_TRY(hipGetLastError());
+  const int64_t grid = std::min<int64_t>(n, D->slots);
+  psb_decode_kernel<<<(unsigned)grid, 64, 0, s>>>(P);
+  HIP_TRY(hipGetLastError());
+  return PSB_OK;
+}
