@@ -106,11 +106,28 @@ int32_t psb_decoder_levels(const psb_decoder* d, int32_t max_levels, int64_t* d_
  *   obs        [n] uint64 (XOR of observable masks);  status [n] int32 (PSB_S_*);
  *   levels     [n][max_defects_per_shot] int8 or NULL: processing-cluster level of
  *              each active detector in ascending detector order (0 = global mode);
- *   t_done     [n] uint64 or NULL: device clock (100 MHz) when the shot finished.
+ *   t_done     [n+1] uint64 or NULL: device clock (100 MHz) when shot i finished;
+ *              t_done[n] receives the clock when the launch started;
+ *   stats      [n][4] int32 or NULL: per-shot work counters (events processed,
+ *              detectors reached by region growth, nodes visited by the
+ *              clustering search, arrival-log records).
  * Errors: PSB_E_INVALID, PSB_E_DEVICE. */
 int32_t psb_decode_batch(psb_decoder* d, const uint8_t* syndromes, int64_t n, int32_t* edges,
                          int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
-                         int8_t* levels, uint64_t* t_done, void* stream);
+                         int8_t* levels, uint64_t* t_done, int32_t* stats, void* stream);
+
+/* Host-only: the finite-size level schedule of Methods, Algorithm "Parameter
+ * schedule" (Supplementary S11) for maximum edge weight w_max and target
+ * diameter bound diam, both given as (hi, lo) halves of unsigned 128-bit
+ * integers.  d_1 = w_max + 1, phi_1 = 1; b_k is the smallest integer with
+ * b_k >= d_k, phi_k > 2 d_k / b_k and Phi_{k+1}(b_k) >= phi_bar_{k+1};
+ * d_{k+1} = 3 d_k + 4 b_k + 2 w_max.  Generation stops at the first level
+ * with b_k >= diam (marked final).  Exact rational arithmetic.  Returns the
+ * number of levels written (<= max_levels) or a negative error. */
+int32_t psb_schedule_levels(uint64_t wmax_hi, uint64_t wmax_lo, uint64_t diam_hi, uint64_t diam_lo,
+                            int64_t q_num, int64_t q_den, int64_t phi_min_num, int64_t phi_min_den,
+                            int32_t max_levels, uint64_t* d_hi, uint64_t* d_lo, uint64_t* b_hi,
+                            uint64_t* b_lo, int32_t* final_level);
 
 /* Sizes the caller needs to allocate outputs. */
 int32_t psb_decoder_edges_per_shot(const psb_decoder* d);

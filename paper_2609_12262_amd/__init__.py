@@ -1,0 +1,195 @@
+"""Thin Python binding of libpsb (parallel sparse-blossom decoding on MI355X).
+
+Argument marshalling only: every step of decoding runs in the HIP library.
+PyTorch provides device memory and the current stream.  The names follow the
+C ABI in include/psb.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsb.so")
+
+PSB_OK = 0
+PSB_S_OK, PSB_S_CAPACITY, PSB_S_INFEASIBLE, PSB_S_EDGES_TRUNCATED, PSB_S_INTERNAL = 0, 1, 2, 3, 4
+MODE_PARTITION, MODE_GLOBAL = 0, 1
+
+_lib = None
+
+
+class PsbError(RuntimeError):
+    pass
+
+
+class _GraphDesc(ctypes.Structure):
+    _fields_ = [("num_detectors", ctypes.c_int32), ("num_edges", ctypes.c_int64),
+                ("u", ctypes.c_void_p), ("v", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("obs_mask", ctypes.c_void_p)]
+
+
+class _DecoderOpts(ctypes.Structure):
+    _fields_ = [("q_num", ctypes.c_int64), ("q_den", ctypes.c_int64),
+                ("phi_min_num", ctypes.c_int64), ("phi_min_den", ctypes.c_int64),
+                ("tiebreak_seed", ctypes.c_uint64), ("mode", ctypes.c_int32),
+                ("boundary_reading", ctypes.c_int32), ("max_defects_per_shot", ctypes.c_int32),
+                ("edges_per_shot", ctypes.c_int32), ("num_slots", ctypes.c_int32)]
+
+
+def lib():
+    """The loaded libpsb.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PsbError(f"{LIB_PATH} is missing: build it with paper_2609_12262_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.psb_last_error.restype = ctypes.c_char_p
+        for name in ("psb_graph_create", "psb_graph_destroy", "psb_decoder_create", "psb_decoder_destroy",
+                     "psb_decode_batch", "psb_decoder_levels", "psb_decoder_edges_per_shot",
+                     "psb_decoder_max_defects", "psb_graph_syndrome_bytes", "psb_schedule_levels"):
+            getattr(L, name).restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc < 0:
+        raise PsbError(f"{what}: {lib().psb_last_error().decode()} (code {rc})")
+    return rc
+
+
+def schedule_levels(w_max: int, diam: int, q=(1, 10), phi_min=(1, 100), max_levels: int = 16):
+    """Level parameters (d_k, b_k, final) from the library's host-side schedule."""
+    M = (1 << 64) - 1
+    arr = [np.zeros(max_levels, np.uint64) for _ in range(4)]
+    fin = np.zeros(max_levels, np.int32)
+    n = _check(lib().psb_schedule_levels(
+        ctypes.c_uint64(w_max >> 64), ctypes.c_uint64(w_max & M), ctypes.c_uint64(diam >> 64),
+        ctypes.c_uint64(diam & M), ctypes.c_int64(q[0]), ctypes.c_int64(q[1]), ctypes.c_int64(phi_min[0]),
+        ctypes.c_int64(phi_min[1]), ctypes.c_int32(max_levels), *[ctypes.c_void_p(a.ctypes.data) for a in arr],
+        ctypes.c_void_p(fin.ctypes.data)), "psb_schedule_levels")
+    d = [(int(arr[0][k]) << 64) | int(arr[1][k]) for k in range(n)]
+    b = [(int(arr[2][k]) << 64) | int(arr[3][k]) for k in range(n)]
+    return d, b, fin[:n].tolist()
+
+
+class Graph:
+    """Device-resident detector graph (psb_graph_create)."""
+
+    def __init__(self, num_detectors: int, u, v, w, obs_mask):
+        self.u = np.ascontiguousarray(u, np.int32)
+        self.v = np.ascontiguousarray(v, np.int32)
+        self.w = np.ascontiguousarray(w, np.int32)
+        self.obs_mask = np.ascontiguousarray(obs_mask, np.uint64)
+        self.num_detectors = int(num_detectors)
+        desc = _GraphDesc(self.num_detectors, self.u.shape[0], self.u.ctypes.data, self.v.ctypes.data,
+                          self.w.ctypes.data, self.obs_mask.ctypes.data)
+        h = ctypes.c_void_p()
+        _check(lib().psb_graph_create(ctypes.byref(desc), ctypes.byref(h)), "psb_graph_create")
+        self._h = h
+
+    @classmethod
+    def from_synth(cls, g):
+        return cls(g.num_detectors, g.u, g.v, g.w, g.obs_mask)
+
+    @property
+    def syndrome_bytes(self) -> int:
+        return lib().psb_graph_syndrome_bytes(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().psb_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Batch:
+    edges: "object"      # torch int32 [n, edges_per_shot] (device)
+    n_edges: "object"    # torch int32 [n]
+    weight: "object"     # torch int64 [n]
+    obs: "object"        # torch uint64 as int64 view [n]
+    status: "object"     # torch int32 [n]
+    levels: "object"     # torch int8 [n, max_defects] or None
+    t_done: "object"     # torch int64 [n+1] (device clock ticks; [n] = launch start) or None
+    stats: "object"      # torch int32 [n, 4] or None
+
+
+class Decoder:
+    """psb_decoder: schedule, tie-break weights and device workspaces."""
+
+    def __init__(self, graph: Graph, tiebreak_seed: int = 0x5EED, mode: int = MODE_PARTITION,
+                 boundary_reading: int = 0, max_defects: int = 0, edges_per_shot: int = 0,
+                 num_slots: int = 0, q=(1, 10), phi_min=(1, 100)):
+        self.graph = graph
+        opts = _DecoderOpts(q[0], q[1], phi_min[0], phi_min[1], tiebreak_seed & ((1 << 64) - 1), mode,
+                            boundary_reading, max_defects, edges_per_shot, num_slots)
+        h = ctypes.c_void_p()
+        _check(lib().psb_decoder_create(graph._h, ctypes.byref(opts), ctypes.byref(h)), "psb_decoder_create")
+        self._h = h
+        self.edges_per_shot = lib().psb_decoder_edges_per_shot(h)
+        self.max_defects = lib().psb_decoder_max_defects(h)
+
+    def levels(self, max_levels: int = 16):
+        arr = [np.zeros(max_levels, t) for t in (np.int64, np.uint64, np.int64, np.uint64)]
+        fin = np.zeros(max_levels, np.int32)
+        n = _check(lib().psb_decoder_levels(self._h, ctypes.c_int32(max_levels),
+                                            *[ctypes.c_void_p(a.ctypes.data) for a in arr],
+                                            ctypes.c_void_p(fin.ctypes.data)), "psb_decoder_levels")
+        d = [(int(arr[0][k]) << 64) + int(arr[1][k]) for k in range(n)]
+        b = [(int(arr[2][k]) << 64) + int(arr[3][k]) for k in range(n)]
+        return d, b, fin[:n].tolist()
+
+    def alloc(self, n: int, levels: bool = False, timestamps: bool = False, stats: bool = False,
+              device="cuda") -> Batch:
+        import torch
+        return Batch(
+            edges=torch.empty((n, self.edges_per_shot), dtype=torch.int32, device=device),
+            n_edges=torch.empty(n, dtype=torch.int32, device=device),
+            weight=torch.empty(n, dtype=torch.int64, device=device),
+            obs=torch.empty(n, dtype=torch.int64, device=device),
+            status=torch.empty(n, dtype=torch.int32, device=device),
+            levels=torch.zeros((n, self.max_defects), dtype=torch.int8, device=device) if levels else None,
+            t_done=torch.zeros(n + 1, dtype=torch.int64, device=device) if timestamps else None,
+            stats=torch.zeros((n, 4), dtype=torch.int32, device=device) if stats else None)
+
+    def decode_into(self, syndromes, out: Batch, stream=None) -> Batch:
+        """Launch psb_decode_batch on `stream` (default: torch's current stream)."""
+        import torch
+        if not syndromes.is_cuda or syndromes.dtype != torch.uint8 or not syndromes.is_contiguous():
+            raise PsbError("syndromes must be a contiguous uint8 CUDA tensor")
+        n = syndromes.shape[0]
+        if n and syndromes.shape[1] != self.graph.syndrome_bytes:
+            raise PsbError(f"syndrome rows must have {self.graph.syndrome_bytes} bytes")
+        if out.edges.shape[0] < n:
+            raise PsbError("output batch too small")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        P = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+        _check(lib().psb_decode_batch(self._h, P(syndromes), ctypes.c_int64(n), P(out.edges), P(out.n_edges),
+                                      P(out.weight), P(out.obs), P(out.status), P(out.levels), P(out.t_done),
+                                      P(out.stats), ctypes.c_void_p(s.cuda_stream)), "psb_decode_batch")
+        return out
+
+    def decode(self, syndromes, levels: bool = False, timestamps: bool = False, stats: bool = False) -> Batch:
+        out = self.alloc(syndromes.shape[0], levels, timestamps, stats, device=syndromes.device)
+        return self.decode_into(syndromes, out)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().psb_decoder_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

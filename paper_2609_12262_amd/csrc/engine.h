@@ -73,6 +73,7 @@ struct Ctx {
   int nd, n_regions, n_ce, n_bc, n_log, n_ck, ck_free, n_shr, n_chg, stamp, status;
   i128 now;
   int64_t n_ev;
+  int n_visit;      // clustering search visits (statistics)
 };
 
 #define RF(c, r, f) ((c).r_f[(int64_t)(f) * (c).rcap + (r)])
@@ -806,6 +807,7 @@ PSB_DEV void cluster(Ctx& c) {
     }
     const i128 bk = c.P->sb[k], dk = c.P->sd[k];
     const int H = c.P->shmax[k];
+    int visits = 0;
     for (int i = lane(); i < nd; i += PSB_WAVE) { c.uf[i] = i; close_cnt[i] = 0; bcount[i] = 0; csize[i] = 0; cclose[i] = 0; }
     wave_sync();
     for (int i = lane(); i < nd; i += PSB_WAVE) {
@@ -815,7 +817,7 @@ PSB_DEV void cluster(Ctx& c) {
       int nh = 0, nbd = 0, loose = 0, overflow = 0;
       int st_node[MAXH + 1], st_slot[MAXH + 1];
       i128 st_dist[MAXH + 1];
-      int dep = 0;
+      int dep = 0, nvis = 0;
       st_node[0] = u; st_slot[0] = 0; st_dist[0] = 0;
       while (dep >= 0) {
         if (st_slot[dep] >= deg || dep >= H) { --dep; continue; }
@@ -824,6 +826,7 @@ PSB_DEV void cluster(Ctx& c) {
         const int y = c.nbr[(int64_t)x * deg + j];
         if (y == NB_PAD) { st_slot[dep] = deg; continue; }
         const i128 nd_ = st_dist[dep] + c.wt[c.eid[(int64_t)x * deg + j]];
+        ++nvis;
         if (nd_ > bk) continue;
         if (y == NB_BOUNDARY) {
           const int e = c.eid[(int64_t)x * deg + j];
@@ -846,6 +849,7 @@ PSB_DEV void cluster(Ctx& c) {
         }
         if (dep + 1 < H) { ++dep; st_node[dep] = y; st_slot[dep] = 0; st_dist[dep] = nd_; }
       }
+      visits += nvis;
       int cc = 0;
       for (int q = 0; q < nh; ++q) {
         const int rj = hits[2 * q];
@@ -855,6 +859,7 @@ PSB_DEV void cluster(Ctx& c) {
       close_cnt[i] = overflow ? -(1 << 20) : cc;
       bcount[i] = (nbd > bdc ? bdc + 1 : nbd) | (loose << 30);
     }
+    c.n_visit += wave_sum(visits);
     wave_sync();
     for (int i = lane(); i < nd; i += PSB_WAVE) {
       if (c.level[i] != 0) continue;
@@ -1083,8 +1088,12 @@ PSB_DEV void write_empty(Ctx& c, int64_t shot, int status) {
   }
 }
 
-PSB_DEV void cleanup(Ctx& c) {
+PSB_DEV void cleanup(Ctx& c, int64_t shot) {
   wave_sync();
+  if (c.P->out_stats && lane() == 0) {
+    int32_t* st = c.P->out_stats + 4 * shot;
+    st[0] = (int32_t)c.n_ev; st[1] = c.S->x_n; st[2] = c.n_visit; st[3] = c.n_log;
+  }
   const int xn = c.S->x_n;
   for (int i = lane(); i < xn; i += PSB_WAVE) {
     const int v = c.x_node[i];
@@ -1105,13 +1114,13 @@ PSB_DEV void cleanup(Ctx& c) {
 
 PSB_DEV void decode_shot(Ctx& c, int64_t shot) {
   c.status = S_OK; c.n_ce = 0; c.n_bc = 0; c.n_shr = 0; c.n_chg = 0; c.stamp = 1; c.n_ev = 0;
-  c.ck_free = -1; c.now = 0;
+  c.ck_free = -1; c.now = 0; c.n_visit = 0; c.nd = 0; c.n_log = 0;
   const uint8_t* row = c.P->synd + shot * (int64_t)c.P->nbytes;
   load_defects(c, row);
   const int nd = c.nd;
-  if (c.status) { write_empty(c, shot, c.status); cleanup(c); return; }
-  if (nd == 0) { write_empty(c, shot, S_OK); cleanup(c); return; }
-  if (nd > c.rcap) { write_empty(c, shot, S_CAPACITY); cleanup(c); return; }
+  if (c.status) { write_empty(c, shot, c.status); cleanup(c, shot); return; }
+  if (nd == 0) { write_empty(c, shot, S_OK); cleanup(c, shot); return; }
+  if (nd > c.rcap) { write_empty(c, shot, S_CAPACITY); cleanup(c, shot); return; }
   c.n_regions = nd; c.n_log = nd; c.n_ck = nd;
   for (int i = lane(); i < nd; i += PSB_WAVE) region_init(c, i, 0, 0, -1);
   wave_sync();
@@ -1146,10 +1155,10 @@ PSB_DEV void decode_shot(Ctx& c, int64_t shot) {
     int8_t* lv = c.P->out_levels + shot * (int64_t)c.P->dcap;
     for (int i = 0; i < nd; ++i) lv[i] = (c.P->mode == 1) ? 0 : c.level[i];
   }
-  if (c.status) { write_empty(c, shot, c.status); cleanup(c); return; }
+  if (c.status) { write_empty(c, shot, c.status); cleanup(c, shot); return; }
   fuse_and_write(c, shot);
   if (lane() == 0) c.P->out_status[shot] = c.status;
-  cleanup(c);
+  cleanup(c, shot);
 }
 
 // Workspace pointers of slot `slot`.

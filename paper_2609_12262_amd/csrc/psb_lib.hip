@@ -39,9 +39,10 @@ extern "C" const char* psb_last_error(void) { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-__global__ void psb_zero_kernel(int32_t* p, int n) {
+__global__ void psb_zero_kernel(int32_t* p, int n, uint64_t* t_start) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
+  if (i == 0 && t_start) *t_start = wall_clock64();
 }
 
 __global__ __launch_bounds__(64) void psb_decode_kernel(Params P) {
@@ -264,7 +265,7 @@ extern "C" int32_t psb_decoder_max_defects(const psb_decoder* D) { return D ? D-
 
 extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, int64_t n, int32_t* edges,
                                     int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
-                                    int8_t* levels, uint64_t* t_done, void* stream) {
+                                    int8_t* levels, uint64_t* t_done, int32_t* stats, void* stream) {
   if (!D) return fail(PSB_E_INVALID, "null decoder");
   if (n < 0) return fail(PSB_E_INVALID, "negative batch size");
   if (n == 0) return PSB_OK;
@@ -273,11 +274,31 @@ extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, in
   hipStream_t s = (hipStream_t)stream;
   Params P = D->P;
   P.n_shots = n; P.synd = syndromes; P.out_edges = edges; P.out_nedges = n_edges; P.out_weight = weight;
-  P.out_obs = obs; P.out_status = status; P.out_levels = levels; P.out_tdone = t_done;
-  psb_zero_kernel<<<1, 64, 0, s>>>(D->d_counter, 1);
+  P.out_obs = obs; P.out_status = status; P.out_levels = levels; P.out_tdone = t_done; P.out_stats = stats;
+  psb_zero_kernel<<<1, 64, 0, s>>>(D->d_counter, 1, t_done ? t_done + n : nullptr);
   HIP_TRY(hipGetLastError());
   const int64_t grid = std::min<int64_t>(n, D->slots);
   psb_decode_kernel<<<(unsigned)grid, 64, 0, s>>>(P);
   HIP_TRY(hipGetLastError());
   return PSB_OK;
+}
+
+extern "C" int32_t psb_schedule_levels(uint64_t wmax_hi, uint64_t wmax_lo, uint64_t diam_hi, uint64_t diam_lo,
+                                       int64_t q_num, int64_t q_den, int64_t phi_min_num, int64_t phi_min_den,
+                                       int32_t max_levels, uint64_t* d_hi, uint64_t* d_lo, uint64_t* b_hi,
+                                       uint64_t* b_lo, int32_t* final_level) {
+  if (q_num <= 0 || q_den <= q_num || phi_min_num <= 0 || phi_min_den <= phi_min_num)
+    return fail(PSB_E_INVALID, "q and phi_min must lie in (0, 1)");
+  const u128 wmax = ((u128)wmax_hi << 64) | wmax_lo, diam = ((u128)diam_hi << 64) | diam_lo;
+  if (wmax == 0) return fail(PSB_E_INVALID, "w_max must be positive");
+  LevelSchedule S;
+  const int32_t rc = build_schedule(wmax, diam, q_num, q_den, phi_min_num, phi_min_den, S);
+  if (rc != PSB_OK) return rc;
+  const int32_t nl = (int32_t)std::min<size_t>(S.d.size(), (size_t)std::max(0, max_levels));
+  for (int32_t k = 0; k < nl; ++k) {
+    d_hi[k] = (uint64_t)(S.d[k] >> 64); d_lo[k] = (uint64_t)S.d[k];
+    b_hi[k] = (uint64_t)(S.b[k] >> 64); b_lo[k] = (uint64_t)S.b[k];
+    final_level[k] = S.final_level[k];
+  }
+  return nl;
 }

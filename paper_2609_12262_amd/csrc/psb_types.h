@@ -79,6 +79,7 @@ struct Params {
   int32_t* out_status;
   int8_t* out_levels;
   uint64_t* out_tdone;
+  int32_t* out_stats;     // [n][4] or null
   int32_t* counter;       // work queue head
   // workspace
   char* ws;

@@ -1,0 +1,177 @@
+"""GPU parity: the HIP decoder against the oracle, element by element.
+
+Every test goes through the C ABI (psb_decode_batch).  Tolerance: exact --
+edge ids, weights and observable masks are integers."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import SEED, compare, gpu_decode, say, valid_embedded
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_d5_one_shot_config_all_shots(mode):
+    """d=5, 5 rounds, p=q=0.005, 10,000 shots: every shot equals the oracle."""
+    g = synth.rotated_phenom_graph(5, 0.005)
+    s = synth.sample(g, 10000, seed=1)
+    say(f"d5 mode={mode}: decoding 10000 shots")
+    res = gpu_decode(g, s.syndromes, mode=mode)
+    bad = compare(g, s.syndromes, res, range(10000))
+    assert not bad, bad[:5]
+
+
+def test_d11_batched_config_parity():
+    """d=11, p=q=0.003: one persistent launch over 20,000 shots, all compared."""
+    g = synth.rotated_phenom_graph(11, 0.003)
+    s = synth.sample(g, 20000, seed=2)
+    say("d11: decoding 20000 shots")
+    res = gpu_decode(g, s.syndromes, levels=True)
+    bad = compare(g, s.syndromes, res, range(20000))
+    assert not bad, bad[:5]
+
+
+@pytest.mark.parametrize("p,seed", [(0.005, 3), (0.001, 4)])
+def test_d21_full_batch_sampled_parity(p, seed):
+    """d=21 at the benchmark's launch shape (50,000 shots, default slots):
+    150 sampled shots against the oracle, validity on every shot."""
+    g = synth.rotated_phenom_graph(21, p)
+    s = synth.sample(g, 50000, seed=seed)
+    say(f"d21 p={p}: decoding 50000 shots")
+    res = gpu_decode(g, s.syndromes)
+    assert (res["status"] == 0).all(), np.bincount(res["status"])
+    rng = np.random.default_rng(0)
+    idx = sorted(set(rng.integers(0, 50000, 150).tolist()) | {0, 49999})
+    bad = compare(g, s.syndromes, res, idx)
+    assert not bad, bad[:5]
+    assert not valid_embedded(g, s.syndromes, res)
+    assert (res["weight"] <= s.weight).all()
+
+
+def test_partition_equals_global_sparse_blossom():
+    """Theorem 1: partition-and-fuse returns the same correction as global
+    sparse blossom, on every shot of a d=21 batch."""
+    g = synth.rotated_phenom_graph(21, 0.005)
+    s = synth.sample(g, 20000, seed=5)
+    a = gpu_decode(g, s.syndromes, mode=0)
+    b = gpu_decode(g, s.syndromes, mode=1)
+    for k in ("n_edges", "weight", "obs", "status"):
+        assert np.array_equal(a[k], b[k]), k
+    m = np.arange(a["edges"].shape[1])[None, :] < a["n_edges"][:, None]
+    assert np.array_equal(np.where(m, a["edges"], 0), np.where(m, b["edges"], 0))
+
+
+def test_high_error_rate_blossoms():
+    """Dense syndromes (blossoms form and shatter) on d=11 and d=5."""
+    for d, p, n in ((11, 0.03, 400), (5, 0.08, 2000)):
+        g = synth.rotated_phenom_graph(d, p)
+        s = synth.sample(g, n, seed=6)
+        for mode in (0, 1):
+            res = gpu_decode(g, s.syndromes, mode=mode)
+            bad = compare(g, s.syndromes, res, range(n))
+            assert not bad, (d, p, mode, bad[:5])
+
+
+def test_random_and_repetition_graphs():
+    for seed in range(3):
+        g = synth.random_graph(60, 150, 10, 50, 90, seed, p=0.08)
+        s = synth.sample(g, 300, seed=11)
+        for mode, reading in ((0, 0), (1, 0), (0, 1)):
+            res = gpu_decode(g, s.syndromes, mode=mode, reading=reading)
+            bad = compare(g, s.syndromes, res, range(300))
+            assert not bad, (seed, mode, reading, bad[:5])
+    g = synth.repetition_graph(50, 100, 0.1)
+    s = synth.sample(g, 500, seed=12)
+    res = gpu_decode(g, s.syndromes)
+    assert not compare(g, s.syndromes, res, range(500))
+    g = synth.rotated_phenom_graph(9, 0.01, 0.03)      # unequal spatial / time weights
+    s = synth.sample(g, 500, seed=13)
+    res = gpu_decode(g, s.syndromes)
+    assert not compare(g, s.syndromes, res, range(500))
+
+
+def test_cluster_levels_equal_oracle_clustering():
+    """Processing-cluster levels (Methods, Algorithm "Clustering") against the
+    oracle's plain construction: identical below the final level; at the
+    final level every remaining event is placed there (the oracle may assign
+    a later level to the same, single remaining component)."""
+    g = synth.rotated_phenom_graph(11, 0.003)
+    s = synth.sample(g, 300, seed=14)
+    res = gpu_decode(g, s.syndromes, levels=True)
+    og = oracle.Graph(g, SEED)
+    import paper_2609_12262_amd as psb
+    dec = psb.Decoder(psb.Graph.from_synth(g), tiebreak_seed=SEED)
+    d_k, b_k, fin = dec.levels()
+    kf = fin.index(1) + 1
+    od, ob, _ = oracle.schedule(max(og.tiebroken_weights()), levels=max(len(d_k), 4))
+    assert od[: len(d_k)] == d_k and ob[: len(b_k)] == b_k
+    for i in range(300):
+        dd = synth.defects_of(s.syndromes[i], g.num_detectors)
+        if len(dd) == 0:
+            continue
+        D, _ = og.defect_distances(dd)
+        BT = og.boundary_table(dd)
+        lv = oracle.cluster_levels(D, BT, od, ob)
+        got = res["levels"][i, : len(dd)].tolist()
+        for a, b in zip(got, lv):
+            if b < kf:
+                assert a == b, (i, got, lv)
+            else:
+                assert a == kf, (i, got, lv)
+
+
+def test_edge_cases():
+    g = synth.rotated_phenom_graph(5, 0.005)
+    nb = g.nbytes
+    # all-zero syndromes
+    z = np.zeros((100, nb), np.uint8)
+    res = gpu_decode(g, z)
+    assert (res["status"] == 0).all() and (res["n_edges"] == 0).all() and (res["weight"] == 0).all()
+    # single defects everywhere (ragged tail of the detector range)
+    one = np.zeros((g.num_detectors, nb), np.uint8)
+    for j in range(g.num_detectors):
+        one[j, j >> 3] |= 1 << (j & 7)
+    res = gpu_decode(g, one)
+    assert not compare(g, one, res, range(g.num_detectors))
+    # every detector active
+    full = np.zeros((1, nb), np.uint8)
+    for j in range(g.num_detectors):
+        full[0, j >> 3] |= 1 << (j & 7)
+    res = gpu_decode(g, full)
+    assert not compare(g, full, res, [0])
+    # capacity: more defects than the workspace holds -> status, not a wrong answer
+    res = gpu_decode(g, full, max_defects=8)
+    assert res["status"][0] == 1
+    # truncated edge list: weight and obs still exact
+    s = synth.sample(g, 500, seed=21)
+    res = gpu_decode(g, s.syndromes, edges_per_shot=1)
+    og = oracle.Graph(g, SEED)
+    for i in range(500):
+        r = og.mwem(synth.defects_of(s.syndromes[i], g.num_detectors))
+        st = res["status"][i]
+        assert st == (3 if len(r.edges) > 1 else 0)
+        assert res["weight"][i] == r.weight and int(res["obs"][i]) == r.obs
+
+
+def test_infeasible_component():
+    # a triangle without boundary plus a path with a boundary edge
+    g = synth.DetectorGraph(5, np.array([0, 1, 0, 3, 4], np.int32), np.array([1, 2, 2, 4, -1], np.int32),
+                            np.array([3, 3, 3, 5, 5], np.int32), np.zeros(5, np.uint64), np.full(5, .1))
+    rows = np.array([[0b00001], [0b00101], [0b01000], [0b11000]], np.uint8)
+    res = gpu_decode(g, rows)
+    assert res["status"].tolist()[0] == 2
+    assert not compare(g, rows, res, range(4))
+
+
+def test_determinism_and_order_independence():
+    g = synth.rotated_phenom_graph(11, 0.01)
+    s = synth.sample(g, 3000, seed=31)
+    a = gpu_decode(g, s.syndromes)
+    b = gpu_decode(g, s.syndromes)
+    perm = np.random.default_rng(1).permutation(3000)
+    c = gpu_decode(g, s.syndromes[perm])
+    for k in ("n_edges", "weight", "obs", "status"):
+        assert np.array_equal(a[k], b[k])
+        assert np.array_equal(a[k][perm], c[k])
