@@ -161,7 +161,11 @@ def main():
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(avg_launch_s * 1e3, 3),
                      "kernel": "psb_decode_kernel"},
         "work_per_shot": {"events": float(stats[:, 0].mean()), "reached": float(stats[:, 1].mean()),
-                          "cluster_visits": float(stats[:, 2].mean()), "log_records": float(stats[:, 3].mean())},
+                          "cluster_visits": float(stats[:, 2].mean()), "log_records": float(stats[:, 3].mean()),
+                          "us_intake_cluster": float(stats[:, 4].mean()) * 1e6 / DEVICE_CLOCK_HZ,
+                          "us_dynamics": float(stats[:, 5].mean()) * 1e6 / DEVICE_CLOCK_HZ,
+                          "us_fuse": float(stats[:, 6].mean()) * 1e6 / DEVICE_CLOCK_HZ,
+                          "us_shot": float(stats[:, 7].mean()) * 1e6 / DEVICE_CLOCK_HZ},
     }
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         log("cpu baseline (oracle)")

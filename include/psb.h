@@ -81,7 +81,14 @@ typedef struct {
   int32_t boundary_reading;
   int32_t max_defects_per_shot;   /* 0 = choose from the graph */
   int32_t edges_per_shot;         /* output stride of psb_decode_batch; 0 = max_defects_per_shot*8 */
-  int32_t num_slots;              /* concurrent shots on the device; 0 = 2048 */
+  int32_t num_slots;              /* fast-tier shots in flight; 0 = as many as fit the device */
+  /* Fast tier: per-shot state held in LDS, for shots that reach at most
+   * fast_max_nodes detectors and create at most fast_max_regions regions
+   * (0 = 256 / 192; fast_max_nodes < 0 disables the tier).  Shots beyond
+   * these bounds are decoded by the overflow tier (state in global memory,
+   * overflow_slots shots in flight, 0 = chosen from the device) within the
+   * same psb_decode_batch call; results do not depend on the tier. */
+  int32_t fast_max_nodes, fast_max_regions, overflow_slots;
 } psb_decoder_opts;
 
 /* Builds the decoder: tie-broken weights, level parameters d_k, b_k (exact
@@ -108,9 +115,10 @@ int32_t psb_decoder_levels(const psb_decoder* d, int32_t max_levels, int64_t* d_
  *              each active detector in ascending detector order (0 = global mode);
  *   t_done     [n+1] uint64 or NULL: device clock (100 MHz) when shot i finished;
  *              t_done[n] receives the clock when the launch started;
- *   stats      [n][4] int32 or NULL: per-shot work counters (events processed,
+ *   stats      [n][8] int32 or NULL: per-shot work counters (events processed,
  *              detectors reached by region growth, nodes visited by the
- *              clustering search, arrival-log records).
+ *              clustering search, arrival-log records) and device-clock
+ *              durations of clustering, dynamics, fuse and the whole shot.
  * Errors: PSB_E_INVALID, PSB_E_DEVICE. */
 int32_t psb_decode_batch(psb_decoder* d, const uint8_t* syndromes, int64_t n, int32_t* edges,
                          int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
@@ -128,6 +136,14 @@ int32_t psb_schedule_levels(uint64_t wmax_hi, uint64_t wmax_lo, uint64_t diam_hi
                             int64_t q_num, int64_t q_den, int64_t phi_min_num, int64_t phi_min_den,
                             int32_t max_levels, uint64_t* d_hi, uint64_t* d_lo, uint64_t* b_hi,
                             uint64_t* b_lo, int32_t* final_level);
+
+/* Shots in flight per tier and the fast tier's LDS bytes per shot. */
+int32_t psb_decoder_slots(const psb_decoder* d, int32_t* fast_slots, int32_t* overflow_slots,
+                          int32_t* fast_lds_bytes);
+
+/* Number of shots of the most recent psb_decode_batch call that the fast
+ * tier handed to the overflow tier.  Synchronises `stream` first. */
+int32_t psb_decoder_last_overflow(psb_decoder* d, void* stream, int32_t* n_overflow);
 
 /* Sizes the caller needs to allocate outputs. */
 int32_t psb_decoder_edges_per_shot(const psb_decoder* d);

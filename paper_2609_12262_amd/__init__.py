@@ -37,7 +37,9 @@ class _DecoderOpts(ctypes.Structure):
                 ("phi_min_num", ctypes.c_int64), ("phi_min_den", ctypes.c_int64),
                 ("tiebreak_seed", ctypes.c_uint64), ("mode", ctypes.c_int32),
                 ("boundary_reading", ctypes.c_int32), ("max_defects_per_shot", ctypes.c_int32),
-                ("edges_per_shot", ctypes.c_int32), ("num_slots", ctypes.c_int32)]
+                ("edges_per_shot", ctypes.c_int32), ("num_slots", ctypes.c_int32),
+                ("fast_max_nodes", ctypes.c_int32), ("fast_max_regions", ctypes.c_int32),
+                ("overflow_slots", ctypes.c_int32)]
 
 
 def lib():
@@ -50,7 +52,8 @@ def lib():
         L.psb_last_error.restype = ctypes.c_char_p
         for name in ("psb_graph_create", "psb_graph_destroy", "psb_decoder_create", "psb_decoder_destroy",
                      "psb_decode_batch", "psb_decoder_levels", "psb_decoder_edges_per_shot",
-                     "psb_decoder_max_defects", "psb_graph_syndrome_bytes", "psb_schedule_levels"):
+                     "psb_decoder_max_defects", "psb_graph_syndrome_bytes", "psb_schedule_levels",
+                     "psb_decoder_slots", "psb_decoder_last_overflow"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -121,7 +124,7 @@ class Batch:
     status: "object"     # torch int32 [n]
     levels: "object"     # torch int8 [n, max_defects] or None
     t_done: "object"     # torch int64 [n+1] (device clock ticks; [n] = launch start) or None
-    stats: "object"      # torch int32 [n, 4] or None
+    stats: "object"      # torch int32 [n, 8] or None
 
 
 class Decoder:
@@ -129,15 +132,20 @@ class Decoder:
 
     def __init__(self, graph: Graph, tiebreak_seed: int = 0x5EED, mode: int = MODE_PARTITION,
                  boundary_reading: int = 0, max_defects: int = 0, edges_per_shot: int = 0,
-                 num_slots: int = 0, q=(1, 10), phi_min=(1, 100)):
+                 num_slots: int = 0, q=(1, 10), phi_min=(1, 100), fast_max_nodes: int = 0,
+                 fast_max_regions: int = 0, overflow_slots: int = 0):
         self.graph = graph
         opts = _DecoderOpts(q[0], q[1], phi_min[0], phi_min[1], tiebreak_seed & ((1 << 64) - 1), mode,
-                            boundary_reading, max_defects, edges_per_shot, num_slots)
+                            boundary_reading, max_defects, edges_per_shot, num_slots, fast_max_nodes,
+                            fast_max_regions, overflow_slots)
         h = ctypes.c_void_p()
         _check(lib().psb_decoder_create(graph._h, ctypes.byref(opts), ctypes.byref(h)), "psb_decoder_create")
         self._h = h
         self.edges_per_shot = lib().psb_decoder_edges_per_shot(h)
         self.max_defects = lib().psb_decoder_max_defects(h)
+        fs, os_, lds = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().psb_decoder_slots(h, ctypes.byref(fs), ctypes.byref(os_), ctypes.byref(lds)), "psb_decoder_slots")
+        self.fast_slots, self.overflow_slots, self.fast_lds_bytes = fs.value, os_.value, lds.value
 
     def levels(self, max_levels: int = 16):
         arr = [np.zeros(max_levels, t) for t in (np.int64, np.uint64, np.int64, np.uint64)]
@@ -160,7 +168,7 @@ class Decoder:
             status=torch.empty(n, dtype=torch.int32, device=device),
             levels=torch.zeros((n, self.max_defects), dtype=torch.int8, device=device) if levels else None,
             t_done=torch.zeros(n + 1, dtype=torch.int64, device=device) if timestamps else None,
-            stats=torch.zeros((n, 4), dtype=torch.int32, device=device) if stats else None)
+            stats=torch.zeros((n, 8), dtype=torch.int32, device=device) if stats else None)
 
     def decode_into(self, syndromes, out: Batch, stream=None) -> Batch:
         """Launch psb_decode_batch on `stream` (default: torch's current stream)."""
@@ -182,6 +190,15 @@ class Decoder:
     def decode(self, syndromes, levels: bool = False, timestamps: bool = False, stats: bool = False) -> Batch:
         out = self.alloc(syndromes.shape[0], levels, timestamps, stats, device=syndromes.device)
         return self.decode_into(syndromes, out)
+
+    def last_overflow(self, stream=None) -> int:
+        """Shots of the last batch decoded by the overflow tier (synchronises)."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        n = ctypes.c_int32()
+        _check(lib().psb_decoder_last_overflow(self._h, ctypes.c_void_p(s.cuda_stream), ctypes.byref(n)),
+               "psb_decoder_last_overflow")
+        return n.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -19,6 +19,14 @@
 // All arithmetic is integer.  Times and radii are 128-bit integers in units
 // of the tie-broken even weights, so every event happens at an integer time.
 //
+// State.  Only detectors that a region has reached ("explored" nodes, the
+// detection events first, in ascending order) carry state; a hash maps a
+// detector id to its explored index.  Explored index i < nd is detection
+// event i, whose detector region is region i and whose arrival record is
+// record i.  The explored table, the hash, the event-cache block minima and
+// the region table form the StateLayout block, which lives in LDS for the
+// fast tier and in global memory for the overflow tier.
+//
 // Code style: every function is executed by all lanes of the wavefront with
 // identical (uniform) values except inside the lane-parallel loops
 // `for (i = lane(); i < n; i += PSB_WAVE)`.  Uniform stores of the same value
@@ -32,22 +40,20 @@ constexpr int K_LEAVE = 1000;
 constexpr int NB_BOUNDARY = -1;
 constexpr int NB_PAD = -2;
 constexpr int MATE_BOUNDARY = -2;
-constexpr int CHUNK = 64;
+constexpr int BLK = 64;           // event-cache block size
 constexpr int MAXH = 6;           // deepest path enumeration used by clustering
-constexpr int S_OK = 0, S_CAPACITY = 1, S_INFEASIBLE = 2, S_TRUNC = 3, S_INTERNAL = 4;
+constexpr int S_OK = 0, S_CAPACITY = 1, S_INFEASIBLE = 2, S_TRUNC = 3, S_INTERNAL = 4, S_OVERFLOW = 5;
 
 #define T_INF (((i128)1) << 124)
 
 // LDS scalars of one wavefront.
 struct Lds {
   int dblk_n;           // dirty event blocks pending refresh
-  int x_n;              // explored-node count (lane-parallel appends)
+  int x_n;              // explored-node count
   int fin_n;            // final compressed edges
   int stk_n;            // expansion stack
-  int lnk_n;
+  int rel_n;            // nodes released by a shatter
   int pad[3];
-  int dblk[512];        // dirty block ids
-  unsigned dmask[512];  // dirty block bitmap (up to 16384 blocks)
 };
 
 struct Ctx {
@@ -56,24 +62,22 @@ struct Ctx {
   // graph
   const int32_t* nbr; const int32_t* eid; const i128* wt; const int32_t* w; const uint64_t* obs;
   int deg, n_det;
-  // nodes
-  int32_t *n_top, *n_reg, *n_src, *n_eix, *n_rec, *n_pos, *n_did; i128* n_wr;
-  // explored
-  int32_t* x_node; i128* x_ev; i128* blk_min; int32_t* blk_arg;
-  // regions
-  i128* r_base; int32_t* r_f; int rcap;
-  // chunks
-  int32_t *ck_next, *ck_prev, *ck_nodes;
-  // pools
+  // per-shot state (StateLayout)
+  int32_t *x_node, *x_top, *x_reg, *x_src, *x_rec; i128 *x_wr, *x_ev;
+  int32_t *h_key, *h_val; uint32_t hmask; int hshift;
+  i128* blk_min; int32_t* blk_arg; unsigned* d_mask; int32_t* d_list;
+  i128* r_base; int32_t* r_f; int rcap, xcap;
+  // pools (global)
   int32_t *ce, *bc, *lg;
-  int32_t *defects, *uf, *cl_a, *cl_b, *cl_c, *cl_d, *bdl, *hit;
   int8_t* level;
+  int32_t *uf, *cl_a, *cl_b, *cl_c, *cl_d, *bdl, *hit;
   int32_t *shr, *chg, *stk, *fin; uint32_t* ebits;
   // uniform scalars
-  int nd, n_regions, n_ce, n_bc, n_log, n_ck, ck_free, n_shr, n_chg, stamp, status;
+  int nd, n_regions, n_ce, n_bc, n_log, n_shr, n_chg, stamp, status;
   i128 now;
   int64_t n_ev;
-  int n_visit;      // clustering search visits (statistics)
+  int n_visit;                       // clustering search visits (statistics)
+  uint64_t t0, t_cl, t_dyn, t_fuse;  // device clock marks (statistics)
 };
 
 #define RF(c, r, f) ((c).r_f[(int64_t)(f) * (c).rcap + (r)])
@@ -81,66 +85,87 @@ struct Ctx {
 
 PSB_DEV i128 yrad(const Ctx& c, int r, i128 t) { return c.r_base[r] + (i128)RF(c, r, RF_RATE) * t; }
 
+// A capacity of this tier is exhausted: the fast tier hands the shot to the
+// overflow tier, the overflow tier reports it.
+PSB_DEV void cap_fail(Ctx& c) { c.status = (c.P->tier == 0) ? S_OVERFLOW : S_CAPACITY; }
+
+// ---------------------------------------------------------------------------
+// detector id -> explored index (open addressing, linear probing)
+// ---------------------------------------------------------------------------
+PSB_DEV uint32_t hpos(const Ctx& c, int v) { return ((uint32_t)v * 2654435761u) >> c.hshift; }
+
+PSB_DEV int node_idx(const Ctx& c, int v) {
+  uint32_t s = hpos(c, v);
+  for (uint32_t k = 0; k <= c.hmask; ++k) {
+    const int key = c.h_key[s];
+    if (key == v) return c.h_val[s];
+    if (key < 0) return -1;
+    s = (s + 1) & c.hmask;
+  }
+  return -1;
+}
+
+// Uniform insert of a detector that is not present.
+PSB_DEV void hash_put(Ctx& c, int v, int idx) {
+  uint32_t s = hpos(c, v);
+  while (c.h_key[s] >= 0) s = (s + 1) & c.hmask;
+  c.h_key[s] = v;
+  c.h_val[s] = idx;
+}
+
+// Lane-parallel insert (distinct keys).
+PSB_DEV void hash_put_atomic(Ctx& c, int v, int idx) {
+  uint32_t s = hpos(c, v);
+  for (uint32_t k = 0; k <= c.hmask; ++k) {
+    if (atom_cas(&c.h_key[s], -1, v) == -1) { c.h_val[s] = idx; return; }
+    s = (s + 1) & c.hmask;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // event cache (explored nodes, 64-entry blocks with cached minima)
 // ---------------------------------------------------------------------------
 PSB_DEV void mark_block(Ctx& c, int b) {
-  unsigned bit = 1u << (b & 31);
-  unsigned old = (unsigned)atom_or((int*)&c.S->dmask[b >> 5], (int)bit);
+  const unsigned bit = 1u << (b & 31);
+  const unsigned old = (unsigned)atom_or((int*)&c.d_mask[b >> 5], (int)bit);
   if (!(old & bit)) {
-    int k = atom_add(&c.S->dblk_n, 1);
-    if (k < 512) c.S->dblk[k] = b;
+    const int k = atom_add(&c.S->dblk_n, 1);
+    c.d_list[k] = b;
   }
 }
 
 PSB_DEV void refresh_blocks(Ctx& c) {
   wave_sync();
-  int nb = c.S->dblk_n;
+  const int nb = c.S->dblk_n;
   const int xn = c.S->x_n;
-  if (nb > 512) {  // list overflowed: refresh every block
-    nb = (xn + CHUNK - 1) / CHUNK;
-    for (int b = 0; b < nb; ++b) {
-      i128 key = T_INF; int arg = 0x7fffffff;
-      for (int j = lane(); j < CHUNK; j += PSB_WAVE) {
-        int ix = b * CHUNK + j;
-        if (ix < xn) { i128 k = c.x_ev[ix]; if (k < key) { key = k; arg = ix; } }
-      }
-      wave_argmin(key, arg);
-      c.blk_min[b] = key; c.blk_arg[b] = arg;
+  for (int q = 0; q < nb; ++q) {
+    const int b = c.d_list[q];
+    i128 key = T_INF; int arg = 0x7fffffff;
+    for (int j = lane(); j < BLK; j += PSB_WAVE) {
+      const int ix = b * BLK + j;
+      if (ix < xn) { const i128 k = c.x_ev[ix]; if (k < key) { key = k; arg = ix; } }
     }
-    for (int i = lane(); i < 512; i += PSB_WAVE) c.S->dmask[i] = 0;
-  } else {
-    for (int i = 0; i < nb; ++i) {
-      int b = c.S->dblk[i];
-      i128 key = T_INF; int arg = 0x7fffffff;
-      for (int j = lane(); j < CHUNK; j += PSB_WAVE) {
-        int ix = b * CHUNK + j;
-        if (ix < xn) { i128 k = c.x_ev[ix]; if (k < key) { key = k; arg = ix; } }
-      }
-      wave_argmin(key, arg);
-      c.blk_min[b] = key; c.blk_arg[b] = arg;
-      c.S->dmask[b >> 5] = 0;   // whole word cleared: other bits of it are refreshed in this loop too
-    }
-    // clearing whole words may drop marks of blocks not in this list only if
-    // they share a word with a listed block; those are listed as well, since
-    // every set bit has a list entry.
+    wave_argmin(key, arg);
+    c.blk_min[b] = key; c.blk_arg[b] = arg;
   }
+  wave_sync();
+  for (int q = lane(); q < nb; q += PSB_WAVE) c.d_mask[c.d_list[q] >> 5] = 0;
   c.S->dblk_n = 0;
   wave_sync();
 }
 
 PSB_DEV void set_event(Ctx& c, int ix, i128 t) {
   c.x_ev[ix] = t;
-  mark_block(c, ix / CHUNK);
+  mark_block(c, ix / BLK);
 }
 
 // Next event among explored nodes: (time, explored index).
 PSB_DEV void node_min(Ctx& c, i128& t, int& ix) {
   refresh_blocks(c);
-  const int nb = (c.S->x_n + CHUNK - 1) / CHUNK;
+  const int nb = (c.S->x_n + BLK - 1) / BLK;
   i128 key = T_INF; int arg = 0x7fffffff;
   for (int b = lane(); b < nb; b += PSB_WAVE) {
-    i128 k = c.blk_min[b]; int a = c.blk_arg[b];
+    const i128 k = c.blk_min[b]; const int a = c.blk_arg[b];
     if (k < key || (k == key && a < arg)) { key = k; arg = a; }
   }
   wave_argmin(key, arg);
@@ -148,45 +173,46 @@ PSB_DEV void node_min(Ctx& c, i128& t, int& ix) {
 }
 
 // ---------------------------------------------------------------------------
-// node-level events (flooder): ARRIVE / COLLIDE / LEAVE times at node u
+// node-level events (flooder): ARRIVE / COLLIDE / LEAVE times at node i
 // ---------------------------------------------------------------------------
-PSB_DEV bool is_source_of(const Ctx& c, int u, int r) { return r < c.nd && c.defects[r] == u; }
-
-// Earliest event seen from node u: returns time (T_INF = none) and kind
-// (edge slot 0..deg-1 or K_LEAVE).  The local radius of an owned node is
-// l_u(t) = y_top(t) + wr_u; an edge (u, v) of weight W is reached by u's fill
-// when l_u = W (ARRIVE at an empty v, COLLIDE with the boundary) and two
+// Earliest event seen from explored node i: returns time (T_INF = none) and
+// kind (edge slot 0..deg-1 or K_LEAVE).  The local radius of an owned node
+// is l(t) = y_top(t) + wr; an edge of weight W is crossed by one fill when
+// l = W (ARRIVE at an empty neighbour, COLLIDE with the boundary) and two
 // fills meet when l_u + l_v = W, provided their rates add up to > 0.
-PSB_DEV void node_event(const Ctx& c, int u, i128& tbest, int& kbest) {
+PSB_DEV void node_event(const Ctx& c, int i, i128& tbest, int& kbest) {
   tbest = T_INF; kbest = K_NONE;
-  const int top = c.n_top[u];
+  const int top = c.x_top[i];
   if (top < 0) return;
   const int ra = RF(c, top, RF_RATE);
-  const i128 bu = c.r_base[top] + c.n_wr[u];      // l_u(t) = bu + ra * t
+  const i128 bu = c.r_base[top] + c.x_wr[i];       // l_u(t) = bu + ra * t
   if (ra < 0) {
-    if (c.n_reg[u] == top && !is_source_of(c, u, top)) { tbest = bu; kbest = K_LEAVE; }
+    // the detection event of a detector region is its own source: it never
+    // leaves (explored index i < nd is detection event i, region i)
+    if (c.x_reg[i] == top && !(i < c.nd && i == top)) { tbest = bu; kbest = K_LEAVE; }
     return;   // a shrinking fill cannot gain on any neighbour
   }
   const int deg = c.deg;
+  const int64_t row = (int64_t)c.x_node[i] * deg;
   for (int j = 0; j < deg; ++j) {
-    const int v = c.nbr[(int64_t)u * deg + j];
+    const int v = c.nbr[row + j];
     if (v == NB_PAD) break;
-    const i128 W = c.wt[c.eid[(int64_t)u * deg + j]];
+    const i128 W = c.wt[row + j];
     i128 t;
     if (v == NB_BOUNDARY) {
       if (ra <= 0) continue;
       t = W - bu;
     } else {
-      const int vt = c.n_top[v];
+      const int k = node_idx(c, v);
+      const int vt = (k >= 0) ? c.x_top[k] : -1;
       if (vt < 0) {
         if (ra <= 0) continue;
         t = W - bu;                                   // ARRIVE
       } else {
         if (vt == top) continue;
-        const int rb = RF(c, vt, RF_RATE);
-        const int rs = ra + rb;
+        const int rs = ra + RF(c, vt, RF_RATE);
         if (rs <= 0) continue;
-        const i128 num = W - bu - (c.r_base[vt] + c.n_wr[v]);
+        const i128 num = W - bu - (c.r_base[vt] + c.x_wr[k]);
         t = (rs == 1) ? num : (num >> 1);             // COLLIDE (num even when rs == 2)
       }
     }
@@ -194,113 +220,38 @@ PSB_DEV void node_event(const Ctx& c, int u, i128& tbest, int& kbest) {
   }
 }
 
-// Lane-parallel refresh of node v and all of its neighbours.
-PSB_DEV void refresh_star(Ctx& c, int v) {
+// Lane-parallel refresh of explored node i and all of its explored neighbours.
+PSB_DEV void refresh_star(Ctx& c, int i) {
   wave_sync();
   const int deg = c.deg;
+  const int64_t row = (int64_t)c.x_node[i] * deg;
   for (int j = lane(); j <= deg; j += PSB_WAVE) {
-    int x = v;
+    int x = i;
     if (j < deg) {
-      x = c.nbr[(int64_t)v * deg + j];
+      const int v = c.nbr[row + j];
+      if (v < 0) continue;
+      x = node_idx(c, v);
       if (x < 0) continue;
     }
-    const int ix = c.n_eix[x];
-    if (ix < 0) continue;
     i128 t; int k;
     node_event(c, x, t, k);
-    set_event(c, ix, t);
+    set_event(c, x, t);
   }
   wave_sync();
 }
 
-// ---------------------------------------------------------------------------
-// shells: the nodes that arrived while a region was top level, kept as a
-// chunked array with O(1) insert and swap-remove
-// ---------------------------------------------------------------------------
-PSB_DEV int chunk_alloc(Ctx& c) {
-  if (c.ck_free >= 0) { int k = c.ck_free; c.ck_free = c.ck_next[k]; return k; }
-  if (c.n_ck >= c.P->ckcap) { c.status = S_CAPACITY; return -1; }
-  return c.n_ck++;
-}
-
-PSB_DEV void shell_push(Ctx& c, int r, int v) {
-  const int cnt = RF(c, r, RF_CNT);
-  const int idx = cnt % CHUNK;
-  int tail = RF(c, r, RF_CKT);
-  if (idx == 0) {
-    const int k = chunk_alloc(c);
-    if (k < 0) return;
-    c.ck_next[k] = -1; c.ck_prev[k] = tail;
-    if (tail >= 0) c.ck_next[tail] = k; else RF(c, r, RF_CKH) = k;
-    RF(c, r, RF_CKT) = k;
-    tail = k;
-  }
-  c.ck_nodes[(int64_t)tail * CHUNK + idx] = v;
-  c.n_pos[v] = tail * CHUNK + idx;
-  RF(c, r, RF_CNT) = cnt + 1;
-}
-
-PSB_DEV void shell_remove(Ctx& c, int r, int v) {
-  int cnt = RF(c, r, RF_CNT);
-  const int tail = RF(c, r, RF_CKT);
-  const int lp = tail * CHUNK + (cnt - 1) % CHUNK;
-  const int p = c.n_pos[v];
-  const int last = c.ck_nodes[lp];
-  c.ck_nodes[p] = last;
-  c.n_pos[last] = p;
-  --cnt;
-  RF(c, r, RF_CNT) = cnt;
-  if (cnt % CHUNK == 0) {
-    const int prev = c.ck_prev[tail];
-    if (prev >= 0) c.ck_next[prev] = -1; else RF(c, r, RF_CKH) = -1;
-    RF(c, r, RF_CKT) = prev;
-    c.ck_next[tail] = c.ck_free;
-    c.ck_free = tail;
-  }
-}
-
-// Collect region r and all its blossom descendants into stk[base..); returns count.
-PSB_DEV int collect_descendants(Ctx& c, int r, int base) {
-  int n = 0, head = 0;
-  if (base + 1 > c.P->stkcap) { c.status = S_CAPACITY; return 0; }
-  c.stk[base + n++] = r;
-  while (head < n) {
-    const int x = c.stk[base + head++];
-    const int bn = RF(c, x, RF_BCN);
-    const int bo = RF(c, x, RF_BCO);
-    if (base + n + bn > c.P->stkcap) { c.status = S_CAPACITY; return n; }
-    for (int i = 0; i < bn; ++i) c.stk[base + n++] = c.bc[2 * (bo + i)];
-  }
-  return n;
-}
-
-// Operation applied lane-parallel to every node of a region's total area.
-enum AreaOp { OP_REFRESH = 0, OP_SET_TOP_ADD_WR = 2 };
-
-PSB_DEV void area_apply(Ctx& c, int r, int op, int new_top, i128 add_wr, int base) {
-  const int nreg = collect_descendants(c, r, base);
+// Append detector v to the explored table (uniform); returns its index.
+PSB_DEV int explore(Ctx& c, int v) {
+  const int ix = c.S->x_n;
+  if (ix >= c.xcap) { cap_fail(c); return -1; }
+  c.x_node[ix] = v; c.x_top[ix] = -1; c.x_reg[ix] = -1; c.x_src[ix] = -1; c.x_rec[ix] = -1;
+  c.x_wr[ix] = 0; c.x_ev[ix] = T_INF;
+  if (ix % BLK == 0) { c.blk_min[ix / BLK] = T_INF; c.blk_arg[ix / BLK] = ix; }
+  hash_put(c, v, ix);
   wave_sync();
-  for (int q = 0; q < nreg; ++q) {
-    const int x = c.stk[base + q];
-    int ck = RF(c, x, RF_CKH);
-    int remaining = RF(c, x, RF_CNT);
-    while (ck >= 0 && remaining > 0) {
-      const int m = remaining < CHUNK ? remaining : CHUNK;
-      for (int i = lane(); i < m; i += PSB_WAVE) {
-        const int v = c.ck_nodes[(int64_t)ck * CHUNK + i];
-        if (op == OP_REFRESH) {
-          const int ix = c.n_eix[v];
-          if (ix >= 0) { i128 t; int k; node_event(c, v, t, k); set_event(c, ix, t); }
-        } else {
-          c.n_top[v] = new_top;
-          if (op == OP_SET_TOP_ADD_WR) c.n_wr[v] = c.n_wr[v] + add_wr;
-        }
-      }
-      remaining -= m;
-      ck = c.ck_next[ck];
-    }
-  }
+  c.S->x_n = ix + 1;
   wave_sync();
+  return ix;
 }
 
 // ---------------------------------------------------------------------------
@@ -310,15 +261,15 @@ PSB_DEV void region_init(Ctx& c, int r, int rate, i128 base, int tid) {
   c.r_base[r] = base;
   RF(c, r, RF_RATE) = rate; RF(c, r, RF_BPAR) = -1; RF(c, r, RF_TPAR) = -1; RF(c, r, RF_TPE) = -1;
   RF(c, r, RF_TID) = tid; RF(c, r, RF_MATE) = -1; RF(c, r, RF_ME) = -1; RF(c, r, RF_BCO) = 0;
-  RF(c, r, RF_BCN) = 0; RF(c, r, RF_ALIVE) = 1; RF(c, r, RF_CKH) = -1; RF(c, r, RF_CKT) = -1;
-  RF(c, r, RF_CNT) = 0; RF(c, r, RF_MARK) = 0; RF(c, r, RF_INSHR) = 0; RF(c, r, RF_CHGM) = 0;
+  RF(c, r, RF_BCN) = 0; RF(c, r, RF_ALIVE) = 1; RF(c, r, RF_MARK) = 0; RF(c, r, RF_INSHR) = 0;
+  RF(c, r, RF_CHGM) = 0;
 }
 
+// Marks region r: the events of every node of its area must be recomputed.
 PSB_DEV void note_change(Ctx& c, int r) {
   if (RF(c, r, RF_CHGM) == c.stamp) return;
   RF(c, r, RF_CHGM) = c.stamp;
-  if (c.n_chg >= c.P->rcap) { c.status = S_CAPACITY; return; }
-  c.chg[c.n_chg++] = r;
+  ++c.n_chg;
 }
 
 PSB_DEV void set_rate(Ctx& c, int r, int rate) {
@@ -326,7 +277,7 @@ PSB_DEV void set_rate(Ctx& c, int r, int rate) {
   c.r_base[r] = y - (i128)rate * c.now;
   RF(c, r, RF_RATE) = rate;
   if (rate < 0 && !RF(c, r, RF_INSHR)) {
-    if (c.n_shr >= c.P->shrcap) { c.status = S_CAPACITY; return; }
+    if (c.n_shr >= c.P->shrcap) { cap_fail(c); return; }
     RF(c, r, RF_INSHR) = 1;
     c.shr[c.n_shr++] = r;
   }
@@ -334,7 +285,7 @@ PSB_DEV void set_rate(Ctx& c, int r, int rate) {
 }
 
 PSB_DEV int ce_leaf(Ctx& c, int e, int rec_a, int rec_b, int sa, int sb) {
-  if (c.n_ce >= c.P->cecap) { c.status = S_CAPACITY; return -1; }
+  if (c.n_ce >= c.P->cecap) { cap_fail(c); return -1; }
   const int i = c.n_ce++;
   CEF(c, i, CE_E) = e; CEF(c, i, CE_A) = rec_a; CEF(c, i, CE_B) = rec_b;
   CEF(c, i, CE_SA) = sa; CEF(c, i, CE_SB) = sb;
@@ -342,7 +293,7 @@ PSB_DEV int ce_leaf(Ctx& c, int e, int rec_a, int rec_b, int sa, int sb) {
 }
 
 PSB_DEV int ce_concat(Ctx& c, int a, int b, int sa, int sb) {
-  if (c.n_ce >= c.P->cecap) { c.status = S_CAPACITY; return -1; }
+  if (c.n_ce >= c.P->cecap) { cap_fail(c); return -1; }
   const int i = c.n_ce++;
   CEF(c, i, CE_E) = -1; CEF(c, i, CE_A) = a; CEF(c, i, CE_B) = b;
   CEF(c, i, CE_SA) = sa; CEF(c, i, CE_SB) = sb;
@@ -354,9 +305,8 @@ PSB_DEV int ce_other(const Ctx& c, int ce, int s) {
   return CEF(c, ce, CE_SA) == s ? CEF(c, ce, CE_SB) : CEF(c, ce, CE_SA);
 }
 
-// Child of blossom `b` (or b itself when b is top level) containing detection event s.
-PSB_DEV int child_containing(const Ctx& c, int s, int b) {
-  int x = s;
+// Child of blossom `b` containing region (or detection event) x.
+PSB_DEV int child_containing(const Ctx& c, int x, int b) {
   while (x >= 0 && RF(c, x, RF_BPAR) != b) x = RF(c, x, RF_BPAR);
   return x;
 }
@@ -432,19 +382,18 @@ PSB_DEV void form_blossom(Ctx& c, int a, int b, int ce) {
   ++c.stamp;   // fresh stamp for cycle membership
   const int cs = c.stamp;
   // cycle = [lca] + reverse(path a->lca) + path b->lca  (paths exclude lca)
-  // build in the stack scratch: path_a at [0..ma), path_b at [ma..ma+mb)
   int ma = 0, mb = 0;
   const int cap = c.P->stkcap;
   for (x = a; x != lca; x = RF(c, RF(c, x, RF_TPAR), RF_TPAR)) {
-    if (ma + 2 > cap) { c.status = S_CAPACITY; return; }
+    if (ma + 2 > cap) { cap_fail(c); return; }
     c.stk[ma++] = x; c.stk[ma++] = RF(c, x, RF_TPAR);
   }
   for (x = b; x != lca; x = RF(c, RF(c, x, RF_TPAR), RF_TPAR)) {
-    if (ma + mb + 2 > cap) { c.status = S_CAPACITY; return; }
+    if (ma + mb + 2 > cap) { cap_fail(c); return; }
     c.stk[ma + mb++] = x; c.stk[ma + mb++] = RF(c, x, RF_TPAR);
   }
   const int m = 1 + ma + mb;
-  if (c.n_bc + m > c.P->bccap || c.n_regions >= c.P->rcap) { c.status = S_CAPACITY; return; }
+  if (c.n_bc + m > c.P->bccap || c.n_regions >= c.rcap) { cap_fail(c); return; }
   const int bo = c.n_bc;
   c.n_bc += m;
   int* cyc = c.bc + 2 * bo;   // pairs (child, edge to next)
@@ -458,6 +407,7 @@ PSB_DEV void form_blossom(Ctx& c, int a, int b, int ce) {
     else e = RF(c, cyc[2 * i], RF_TPE);                    // child -> parent
     cyc[2 * i + 1] = e;
   }
+  wave_sync();
   // new blossom region
   const int X = c.n_regions++;
   const int tid = RF(c, lca, RF_TID);
@@ -469,24 +419,31 @@ PSB_DEV void form_blossom(Ctx& c, int a, int b, int ce) {
   RF(c, X, RF_BCO) = bo; RF(c, X, RF_BCN) = m;
   if (RF(c, lca, RF_TPAR) >= 0) RF(c, RF(c, lca, RF_TPAR), RF_MATE) = X;
   for (int i = 0; i < m; ++i) RF(c, cyc[2 * i], RF_MARK) = cs;
-  // tree children of cycle members that are not on the cycle hang from X
   wave_sync();
+  // tree children of cycle members that are not on the cycle hang from X
   for (int r = lane(); r < c.n_regions; r += PSB_WAVE) {
     if (r == X || !RF(c, r, RF_ALIVE) || RF(c, r, RF_BPAR) >= 0 || RF(c, r, RF_TID) != tid) continue;
     if (RF(c, r, RF_MARK) == cs) continue;
     const int p = RF(c, r, RF_TPAR);
     if (p >= 0 && RF(c, p, RF_MARK) == cs) RF(c, r, RF_TPAR) = X;
   }
+  // nodes of the members now belong to X: l = y_member(now) + wr = y_X(now) + wr'
+  // with y_X(now) = 0, so wr' = wr + y_member(now)
+  const int xn = c.S->x_n;
+  for (int i = lane(); i < xn; i += PSB_WAVE) {
+    const int t = c.x_top[i];
+    if (t < 0 || RF(c, t, RF_MARK) != cs) continue;
+    c.x_wr[i] = c.x_wr[i] + yrad(c, t, c.now);
+    c.x_top[i] = X;
+  }
   wave_sync();
-  // freeze the cycle members inside X; their nodes now belong to X's area
+  // freeze the cycle members inside X
   for (int i = 0; i < m; ++i) {
     const int ch = cyc[2 * i];
-    const i128 y_ch = yrad(c, ch, c.now);
-    c.r_base[ch] = y_ch;
+    c.r_base[ch] = yrad(c, ch, c.now);
     RF(c, ch, RF_RATE) = 0;
     RF(c, ch, RF_BPAR) = X;
     RF(c, ch, RF_TID) = -1; RF(c, ch, RF_TPAR) = -1; RF(c, ch, RF_MATE) = -1;
-    area_apply(c, ch, OP_SET_TOP_ADD_WR, X, y_ch, c.P->stkcap / 2);
   }
   note_change(c, X);
 }
@@ -511,22 +468,36 @@ PSB_DEV void shatter(Ctx& c, int B) {
   const int fwd = ((i_out - i_in) % m + m) % m;
   const int dir = (fwd % 2 == 0) ? 1 : -1;
   const int L = (dir == 1) ? fwd : m - fwd;
-  // children become top level again
-  for (int i = 0; i < m; ++i) {
-    const int ch = cyc[2 * i];
-    RF(c, ch, RF_BPAR) = -1;
-    // while inside B, l_v = y_B + wr_v with the child's frozen radius folded
-    // into wr_v; y_B = 0 now, so l_v = y_child + (wr_v - y_child)
-    area_apply(c, ch, OP_SET_TOP_ADD_WR, ch, -c.r_base[ch], c.P->stkcap / 2);
+  // children become top level; nodes of B's area move to the child holding
+  // their shell region: l = y_B(now) + wr = y_child + (wr - y_child).
+  // Nodes still in B's own shell sit exactly on its boundary and leave.
+  for (int i = 0; i < m; ++i) RF(c, cyc[2 * i], RF_BPAR) = -1;
+  wave_sync();
+  c.S->rel_n = 0;
+  wave_sync();
+  const int xn = c.S->x_n;
+  for (int i = lane(); i < xn; i += PSB_WAVE) {
+    if (c.x_top[i] != B) continue;
+    const int reg = c.x_reg[i];
+    if (reg == B) {
+      c.x_top[i] = -1; c.x_reg[i] = -1; c.x_src[i] = -1; c.x_rec[i] = -1;
+      const int k = atom_add(&c.S->rel_n, 1);
+      c.stk[k] = i;
+      continue;
+    }
+    int ch = reg;
+    while (RF(c, ch, RF_BPAR) >= 0 && RF(c, ch, RF_BPAR) != B) ch = RF(c, ch, RF_BPAR);
+    c.x_top[i] = ch;
+    c.x_wr[i] = c.x_wr[i] - c.r_base[ch];   // frozen child: y = base
   }
+  wave_sync();
   // the even path from c_in to c_out stays in the tree
   int prev = P_;
-  int prev_edge = ce_p;
   for (int j = 0; j <= L; ++j) {
     const int idx = ((i_in + dir * j) % m + m) % m;
     const int ch = cyc[2 * idx];
     int e;
-    if (j == 0) e = prev_edge;
+    if (j == 0) e = ce_p;
     else {
       const int pidx = ((i_in + dir * (j - 1)) % m + m) % m;
       e = (dir == 1) ? cyc[2 * pidx + 1] : cyc[2 * idx + 1];
@@ -556,17 +527,10 @@ PSB_DEV void shatter(Ctx& c, int B) {
     RF(c, cb, RF_MATE) = ca; RF(c, cb, RF_ME) = e; RF(c, cb, RF_TID) = -1; RF(c, cb, RF_TPAR) = -1;
     set_rate(c, ca, 0); set_rate(c, cb, 0);
   }
-  // nodes still in B's own shell sit exactly on its boundary: release them
-  while (RF(c, B, RF_CNT) > 0) {
-    const int ck = RF(c, B, RF_CKT);
-    const int v = c.ck_nodes[(int64_t)ck * CHUNK + (RF(c, B, RF_CNT) - 1) % CHUNK];
-    shell_remove(c, B, v);
-    c.n_top[v] = -1; c.n_reg[v] = -1; c.n_src[v] = -1; c.n_rec[v] = -1;
-    if (c.n_eix[v] >= 0) set_event(c, c.n_eix[v], T_INF);
-    refresh_star(c, v);
-  }
   RF(c, B, RF_ALIVE) = 0;
   RF(c, B, RF_TID) = -1;
+  const int nrel = c.S->rel_n;
+  for (int q = 0; q < nrel; ++q) refresh_star(c, c.stk[q]);
 }
 
 // (e) an inner detector region shrinks to radius zero: its tree parent and
@@ -622,69 +586,70 @@ PSB_DEV void collide(Ctx& c, int a, int b, int ce) {
 // ---------------------------------------------------------------------------
 // flooder events
 // ---------------------------------------------------------------------------
-PSB_DEV void add_explored(Ctx& c, int v) {
-  if (c.n_eix[v] >= 0) return;
-  const int ix = c.S->x_n;
-  c.x_node[ix] = v; c.x_ev[ix] = T_INF; c.n_eix[v] = ix;
-  wave_sync();
-  c.S->x_n = ix + 1;
-  wave_sync();
-}
-
-PSB_DEV void arrive(Ctx& c, int u, int v, int e) {
-  if (c.n_did[v] >= 0) { c.status = S_INTERNAL; return; }   // an unseeded detection event was reached
-  const int a = c.n_top[u];
-  if (c.n_log >= c.P->lcap) { c.status = S_CAPACITY; return; }
+PSB_DEV void arrive(Ctx& c, int iu, int v, int e) {
+  int k = node_idx(c, v);
+  if (k >= 0 && k < c.nd) { c.status = S_INTERNAL; return; }   // an unseeded detection event was reached
+  if (k < 0) { k = explore(c, v); if (k < 0) return; }
+  const int a = c.x_top[iu];
+  if (c.n_log >= c.P->lcap) { cap_fail(c); return; }
   const int rec = c.n_log++;
-  c.lg[3 * rec] = v; c.lg[3 * rec + 1] = c.n_rec[u]; c.lg[3 * rec + 2] = e;
-  c.n_top[v] = a; c.n_reg[v] = a; c.n_src[v] = c.n_src[u]; c.n_wr[v] = -yrad(c, a, c.now);
-  c.n_rec[v] = rec;
-  add_explored(c, v);
-  shell_push(c, a, v);
-  refresh_star(c, v);
+  c.lg[3 * rec] = v; c.lg[3 * rec + 1] = c.x_rec[iu]; c.lg[3 * rec + 2] = e;
+  c.x_top[k] = a; c.x_reg[k] = a; c.x_src[k] = c.x_src[iu]; c.x_wr[k] = -yrad(c, a, c.now);
+  c.x_rec[k] = rec;
+  refresh_star(c, k);
 }
 
-PSB_DEV void leave(Ctx& c, int u) {
-  const int a = c.n_top[u];
-  shell_remove(c, a, u);
-  c.n_top[u] = -1; c.n_reg[u] = -1; c.n_src[u] = -1; c.n_rec[u] = -1;
-  refresh_star(c, u);
+PSB_DEV void leave(Ctx& c, int i) {
+  c.x_top[i] = -1; c.x_reg[i] = -1; c.x_src[i] = -1; c.x_rec[i] = -1;
+  refresh_star(c, i);
 }
 
-// Refresh every node of every region recorded in the change list.
+// Recompute the events of every node whose top region was marked changed.
 PSB_DEV void flush_changes(Ctx& c) {
-  for (int i = 0; i < c.n_chg; ++i) {
-    const int r = c.chg[i];
-    if (!RF(c, r, RF_ALIVE)) continue;
-    area_apply(c, r, OP_REFRESH, 0, 0, c.P->stkcap / 2);
+  if (c.n_chg > 0) {
+    wave_sync();
+    const int xn = c.S->x_n;
+    const int st = c.stamp;
+    for (int i = lane(); i < xn; i += PSB_WAVE) {
+      const int t = c.x_top[i];
+      if (t < 0 || RF(c, t, RF_CHGM) != st) continue;
+      i128 tt; int k;
+      node_event(c, i, tt, k);
+      set_event(c, i, tt);
+    }
+    wave_sync();
   }
   c.n_chg = 0;
   ++c.stamp;
 }
 
-PSB_DEV void node_event_apply(Ctx& c, int u, int kind) {
-  if (kind == K_LEAVE) { leave(c, u); return; }
+PSB_DEV void node_event_apply(Ctx& c, int iu, int kind) {
+  if (kind == K_LEAVE) { leave(c, iu); return; }
   const int deg = c.deg;
-  const int v = c.nbr[(int64_t)u * deg + kind];
-  const int e = c.eid[(int64_t)u * deg + kind];
-  const int a = c.n_top[u];
+  const int64_t slot = (int64_t)c.x_node[iu] * deg + kind;
+  const int v = c.nbr[slot];
+  const int e = c.eid[slot];
+  const int a = c.x_top[iu];
   if (v == NB_BOUNDARY) {
-    const int ce = ce_leaf(c, e, c.n_rec[u], -1, c.n_src[u], -1);
+    const int ce = ce_leaf(c, e, c.x_rec[iu], -1, c.x_src[iu], -1);
     if (ce < 0) return;
     collide(c, a, -1, ce);
-  } else if (c.n_top[v] < 0) {
-    arrive(c, u, v, e);
   } else {
-    const int b = c.n_top[v];
-    int ce;
-    if (RF(c, a, RF_RATE) >= RF(c, b, RF_RATE)) {
-      ce = ce_leaf(c, e, c.n_rec[u], c.n_rec[v], c.n_src[u], c.n_src[v]);
-      if (ce < 0) return;
-      collide(c, a, b, ce);
+    const int kv = node_idx(c, v);
+    const int b = (kv >= 0) ? c.x_top[kv] : -1;
+    if (b < 0) {
+      arrive(c, iu, v, e);
     } else {
-      ce = ce_leaf(c, e, c.n_rec[v], c.n_rec[u], c.n_src[v], c.n_src[u]);
-      if (ce < 0) return;
-      collide(c, b, a, ce);
+      int ce;
+      if (RF(c, a, RF_RATE) >= RF(c, b, RF_RATE)) {
+        ce = ce_leaf(c, e, c.x_rec[iu], c.x_rec[kv], c.x_src[iu], c.x_src[kv]);
+        if (ce < 0) return;
+        collide(c, a, b, ce);
+      } else {
+        ce = ce_leaf(c, e, c.x_rec[kv], c.x_rec[iu], c.x_src[kv], c.x_src[iu]);
+        if (ce < 0) return;
+        collide(c, b, a, ce);
+      }
     }
   }
   flush_changes(c);
@@ -694,6 +659,7 @@ PSB_DEV void node_event_apply(Ctx& c, int u, int kind) {
 // radius y(t) = base - t reaches zero at t = base.
 PSB_DEV void region_min(Ctx& c, i128& t, int& r) {
   i128 key = T_INF; int arg = 0x7fffffff;
+  if (c.n_shr == 0) { t = key; r = arg; return; }
   wave_sync();
   for (int i = lane(); i < c.n_shr; i += PSB_WAVE) {
     const int x = c.shr[i];
@@ -724,41 +690,46 @@ PSB_DEV void run_dynamics(Ctx& c) {
       continue;
     }
     if (tn >= T_INF) return;
-    const int u = c.x_node[ix];
     i128 tf; int kf;
-    node_event(c, u, tf, kf);
-    if (tf != tn) { wave_sync(); c.x_ev[ix] = tf; mark_block(c, ix / CHUNK); continue; }
+    node_event(c, ix, tf, kf);
+    if (tf != tn) { wave_sync(); set_event(c, ix, tf); continue; }
     if (tf < c.now) { c.status = S_INTERNAL; return; }
     c.now = tf;
-    node_event_apply(c, u, kf);
+    node_event_apply(c, ix, kf);
   }
 }
 
 // ---------------------------------------------------------------------------
-// syndrome intake
+// syndrome intake: detection events become explored nodes 0..nd-1
 // ---------------------------------------------------------------------------
 PSB_DEV void load_defects(Ctx& c, const uint8_t* row) {
   const int nb = c.P->nbytes;
+  const int lim = c.xcap < c.P->cap.dcap ? c.xcap : c.P->cap.dcap;
   int total = 0;
   for (int b0 = 0; b0 < nb; b0 += PSB_WAVE) {
     int cnt = 0, byte = 0;
-    for (int i = b0 + lane(); i < b0 + PSB_WAVE && i < nb; i += PSB_WAVE) { byte = row[i]; cnt = __builtin_popcount(byte); }
-    const int off = wave_prefix(cnt);
-    int pos = total + off;
+    const int i = b0 + lane();
+    if (i < nb) { byte = row[i]; cnt = __builtin_popcount(byte); }
+    int pos = total + wave_prefix(cnt);
     for (int k = 0; k < 8; ++k) if (byte >> k & 1) {
-      const int d = 8 * (b0 + lane()) + k;
-      if (d < c.n_det && pos < c.P->dcap) c.defects[pos] = d;
+      const int d = 8 * i + k;
+      if (d < c.n_det && pos < lim) c.x_node[pos] = d;
       ++pos;
     }
     total += wave_sum(cnt);
   }
   wave_sync();
   c.nd = total;
-  if (total > c.P->dcap) { c.status = S_CAPACITY; return; }
+  if (total > lim) { cap_fail(c); return; }
   for (int i = lane(); i < total; i += PSB_WAVE) {
-    c.n_did[c.defects[i]] = i;
+    c.x_top[i] = -1; c.x_reg[i] = -1; c.x_src[i] = -1; c.x_rec[i] = -1; c.x_wr[i] = 0; c.x_ev[i] = T_INF;
     c.level[i] = 0;
+    hash_put_atomic(c, c.x_node[i], i);
   }
+  // block minima of the blocks these entries occupy start empty
+  for (int b = lane(); b < (total + BLK - 1) / BLK; b += PSB_WAVE) { c.blk_min[b] = T_INF; c.blk_arg[b] = b * BLK; }
+  wave_sync();
+  c.S->x_n = total;
   wave_sync();
 }
 
@@ -791,11 +762,10 @@ PSB_DEV void cluster(Ctx& c) {
   const int deg = c.deg;
   const int hitcap = c.P->hitcap, bdc = c.P->bdc;
   int32_t* close_cnt = c.cl_a;   // per event: close partners with larger index
-  int32_t* bcount = c.cl_b;      // per event: boundary edges within d_k (or loose flag bit 30)
+  int32_t* bcount = c.cl_b;      // per event: boundary edges within d_k (loose flag in bit 30)
   int32_t* csize = c.cl_c;       // per root: size
   int32_t* cclose = c.cl_d;      // per root: close pairs
   for (int k = 0; k < c.P->n_levels; ++k) {
-    // residual count
     int nres = 0;
     for (int i = lane(); i < nd; i += PSB_WAVE) nres += (c.level[i] == 0);
     nres = wave_sum(nres);
@@ -812,42 +782,62 @@ PSB_DEV void cluster(Ctx& c) {
     wave_sync();
     for (int i = lane(); i < nd; i += PSB_WAVE) {
       if (c.level[i] != 0) continue;
-      const int u = c.defects[i];
+      const int u = c.x_node[i];
       int32_t* hits = c.hit + (int64_t)(lane() % PSB_WAVE) * hitcap * 2;
       int nh = 0, nbd = 0, loose = 0, overflow = 0;
-      int st_node[MAXH + 1], st_slot[MAXH + 1];
-      i128 st_dist[MAXH + 1];
-      int dep = 0, nvis = 0;
-      st_node[0] = u; st_slot[0] = 0; st_dist[0] = 0;
-      while (dep >= 0) {
-        if (st_slot[dep] >= deg || dep >= H) { --dep; continue; }
-        const int x = st_node[dep];
-        const int j = st_slot[dep]++;
-        const int y = c.nbr[(int64_t)x * deg + j];
-        if (y == NB_PAD) { st_slot[dep] = deg; continue; }
-        const i128 nd_ = st_dist[dep] + c.wt[c.eid[(int64_t)x * deg + j]];
+      int nvis = 0;
+      // record one path of length nd_ from u ending at y (boundary: y < 0, edge e)
+      auto visit = [&](int y, int e, i128 nd_) {
         ++nvis;
-        if (nd_ > bk) continue;
+        if (nd_ > bk) return;
         if (y == NB_BOUNDARY) {
-          const int e = c.eid[(int64_t)x * deg + j];
           if (nd_ <= dk) {
             bool dup = false;
             for (int q = 0; q < nbd && q < bdc; ++q) dup |= (c.bdl[(int64_t)i * bdc + q] == e);
             if (!dup) { if (nbd < bdc) c.bdl[(int64_t)i * bdc + nbd] = e; ++nbd; }
           }
           if (2 * nd_ <= bk) loose = 1;
-          continue;
+          return;
         }
-        if (y != u) {
-          const int rj = c.n_did[y];
-          if (rj >= 0 && c.level[rj] == 0) {
-            const int cl = (nd_ <= dk) ? 1 : 0;
-            int q = 0;
-            for (; q < nh; ++q) if (hits[2 * q] == rj) { hits[2 * q + 1] |= cl; break; }
-            if (q == nh) { if (nh < hitcap) { hits[2 * nh] = rj; hits[2 * nh + 1] = cl; ++nh; } else overflow = 1; }
+        if (y == u) return;
+        const int rj = node_idx(c, y);
+        if (rj >= 0 && rj < nd && c.level[rj] == 0) {
+          const int cl = (nd_ <= dk) ? 1 : 0;
+          int q = 0;
+          for (; q < nh; ++q) if (hits[2 * q] == rj) { hits[2 * q + 1] |= cl; break; }
+          if (q == nh) { if (nh < hitcap) { hits[2 * nh] = rj; hits[2 * nh + 1] = cl; ++nh; } else overflow = 1; }
+        }
+      };
+      if (H <= 2) {
+        // two rounds of independent adjacency-row loads instead of a serial walk
+        for (int j = 0; j < deg && H >= 1; ++j) {
+          const int y = c.nbr[(int64_t)u * deg + j];
+          if (y == NB_PAD) break;
+          const i128 d1 = c.wt[(int64_t)u * deg + j];
+          visit(y, c.eid[(int64_t)u * deg + j], d1);
+          if (H < 2 || y < 0 || d1 >= bk) continue;
+          for (int k2 = 0; k2 < deg; ++k2) {
+            const int z = c.nbr[(int64_t)y * deg + k2];
+            if (z == NB_PAD) break;
+            visit(z, c.eid[(int64_t)y * deg + k2], d1 + c.wt[(int64_t)y * deg + k2]);
           }
         }
-        if (dep + 1 < H) { ++dep; st_node[dep] = y; st_slot[dep] = 0; st_dist[dep] = nd_; }
+      } else {
+        int st_node[MAXH + 1], st_slot[MAXH + 1];
+        i128 st_dist[MAXH + 1];
+        int dep = 0;
+        st_node[0] = u; st_slot[0] = 0; st_dist[0] = 0;
+        while (dep >= 0) {
+          if (st_slot[dep] >= deg || dep >= H) { --dep; continue; }
+          const int x = st_node[dep];
+          const int j = st_slot[dep]++;
+          const int y = c.nbr[(int64_t)x * deg + j];
+          if (y == NB_PAD) { st_slot[dep] = deg; continue; }
+          const i128 nd_ = st_dist[dep] + c.wt[(int64_t)x * deg + j];
+          visit(y, c.eid[(int64_t)x * deg + j], nd_);
+          if (y < 0 || nd_ > bk) continue;
+          if (dep + 1 < H) { ++dep; st_node[dep] = y; st_slot[dep] = 0; st_dist[dep] = nd_; }
+        }
       }
       visits += nvis;
       int cc = 0;
@@ -903,7 +893,7 @@ PSB_DEV void cluster(Ctx& c) {
     }
     wave_sync();
     for (int i = lane(); i < nd; i += PSB_WAVE)
-      if (c.level[i] == 0 && atom_load(&csize[atom_load(&c.uf[i])]) == -1) c.level[i] = (int8_t)(k + 1);
+      if (c.level[i] == 0 && atom_load(&csize[uf_find(c, i)]) == -1) c.level[i] = (int8_t)(k + 1);
     wave_sync();
   }
 }
@@ -951,7 +941,6 @@ PSB_DEV void collect_final(Ctx& c) {
   wave_sync();
   if (bad & 1) { c.status = S_INFEASIBLE; return; }
   if (bad & 2) { c.status = S_CAPACITY; return; }
-  if (c.S->fin_n > c.P->fincap) { c.status = S_CAPACITY; return; }
   while (c.S->stk_n > 0 && !c.status) {
     c.S->stk_n -= 2;
     const int X = c.stk[c.S->stk_n], s = c.stk[c.S->stk_n + 1];
@@ -978,6 +967,7 @@ PSB_DEV void collect_final(Ctx& c) {
 PSB_DEV void fuse_and_write(Ctx& c, int64_t shot) {
   collect_final(c);
   wave_sync();
+  if (c.status) return;
   const int nf = c.S->fin_n;
   // lane-parallel tracing; each lane flattens its compressed edges with a private stack
   int bad = 0;
@@ -991,20 +981,14 @@ PSB_DEV void fuse_and_write(Ctx& c, int64_t shot) {
       const int e = CEF(c, ce, CE_E);
       if (e >= 0) {
         atom_xor(&c.ebits[e >> 5], 1u << (e & 31));
-        const int ra = CEF(c, ce, CE_A), rb = CEF(c, ce, CE_B);
-        int rec = ra, guard = 0;
-        while (rec >= 0) {
-          const int ee = c.lg[3 * rec + 2];
-          if (ee >= 0) atom_xor(&c.ebits[ee >> 5], 1u << (ee & 31));
-          rec = c.lg[3 * rec + 1];
-          if (++guard > c.n_det + 1) { bad = 1; break; }
-        }
-        rec = rb; guard = 0;
-        while (rec >= 0) {
-          const int ee = c.lg[3 * rec + 2];
-          if (ee >= 0) atom_xor(&c.ebits[ee >> 5], 1u << (ee & 31));
-          rec = c.lg[3 * rec + 1];
-          if (++guard > c.n_det + 1) { bad = 1; break; }
+        for (int side = 0; side < 2; ++side) {
+          int rec = CEF(c, ce, side ? CE_B : CE_A), guard = 0;
+          while (rec >= 0) {
+            const int ee = c.lg[3 * rec + 2];
+            if (ee >= 0) atom_xor(&c.ebits[ee >> 5], 1u << (ee & 31));
+            rec = c.lg[3 * rec + 1];
+            if (++guard > c.n_det + 1) { bad = 1; break; }
+          }
         }
       } else {
         if (n + 2 > cap) { bad = 1; break; }
@@ -1015,7 +999,7 @@ PSB_DEV void fuse_and_write(Ctx& c, int64_t shot) {
   }
   if (wave_or(bad)) c.status = S_INTERNAL;
   wave_sync();
-  // scan the edge bitmap in ascending order
+  // scan the edge bitmap in ascending order (read-and-clear)
   const int64_t nwords = (c.P->n_edges + 31) / 32;
   int32_t* out = c.P->out_edges + shot * (int64_t)c.P->edge_stride;
   const int stride = c.P->edge_stride;
@@ -1023,7 +1007,7 @@ PSB_DEV void fuse_and_write(Ctx& c, int64_t shot) {
   int count = 0;
   for (int64_t w0 = 0; w0 < nwords; w0 += PSB_WAVE) {
     unsigned bits = 0;
-    int64_t wi = w0 + lane();
+    const int64_t wi = w0 + lane();
     if (wi < nwords) bits = atom_xchg(&c.ebits[wi], 0u);
     const int pc = __builtin_popcount(bits);
     int pos = count + wave_prefix(pc);
@@ -1034,7 +1018,6 @@ PSB_DEV void fuse_and_write(Ctx& c, int64_t shot) {
     }
     count += wave_sum(pc);
   }
-  // reduce weight / obs across lanes
   for (int m = PSB_WAVE / 2; m >= 1; m >>= 1) {
     const int lo = shfl_xor_i32((int)(uint32_t)(wsum & 0xffffffff), m);
     const int hi = shfl_xor_i32((int)(wsum >> 32), m);
@@ -1058,25 +1041,17 @@ PSB_DEV void seed_level(Ctx& c, int lvl) {
   // detector regions of this level start growing at t = 0 (one tree each)
   for (int i = lane(); i < c.nd; i += PSB_WAVE) {
     if (c.level[i] != lvl) continue;
-    const int u = c.defects[i];
+    const int u = c.x_node[i];
     c.lg[3 * i] = u; c.lg[3 * i + 1] = -1; c.lg[3 * i + 2] = -1;
-    c.n_top[u] = i; c.n_reg[u] = i; c.n_src[u] = i; c.n_wr[u] = 0; c.n_rec[u] = i;
-    c.n_did[u] = -1;    // seeded: arrivals are no longer an error
-    // shell: the reserved chunk i holds the detection event itself
-    c.ck_nodes[(int64_t)i * CHUNK] = u; c.ck_next[i] = -1; c.ck_prev[i] = -1;
-    c.n_pos[u] = i * CHUNK;
+    c.x_top[i] = i; c.x_reg[i] = i; c.x_src[i] = i; c.x_wr[i] = 0; c.x_rec[i] = i;
     RF(c, i, RF_RATE) = 1; c.r_base[i] = 0; RF(c, i, RF_TID) = i;
-    RF(c, i, RF_CKH) = i; RF(c, i, RF_CKT) = i; RF(c, i, RF_CNT) = 1;
-    const int ix = atom_add(&c.S->x_n, 1);
-    c.x_node[ix] = u; c.x_ev[ix] = T_INF; c.n_eix[u] = ix;
   }
   wave_sync();
   for (int i = lane(); i < c.nd; i += PSB_WAVE) {
     if (c.level[i] != lvl) continue;
-    const int u = c.defects[i];
     i128 t; int k;
-    node_event(c, u, t, k);
-    set_event(c, c.n_eix[u], t);
+    node_event(c, i, t, k);
+    set_event(c, i, t);
   }
   wave_sync();
 }
@@ -1090,38 +1065,63 @@ PSB_DEV void write_empty(Ctx& c, int64_t shot, int status) {
 
 PSB_DEV void cleanup(Ctx& c, int64_t shot) {
   wave_sync();
-  if (c.P->out_stats && lane() == 0) {
-    int32_t* st = c.P->out_stats + 4 * shot;
+  if (c.P->out_stats && lane() == 0 && c.status != S_OVERFLOW) {
+    int32_t* st = c.P->out_stats + 8 * shot;
+    const uint64_t t_end = dev_clock();
     st[0] = (int32_t)c.n_ev; st[1] = c.S->x_n; st[2] = c.n_visit; st[3] = c.n_log;
+    st[4] = (int32_t)(c.t_cl - c.t0); st[5] = (int32_t)(c.t_dyn - c.t_cl);
+    st[6] = (int32_t)(c.t_fuse - c.t_dyn); st[7] = (int32_t)(t_end - c.t0);
   }
+  // clear the hash slots of every explored node; a probe run that touched a
+  // slot of one of them is cleared to its end so no stale key survives
   const int xn = c.S->x_n;
-  for (int i = lane(); i < xn; i += PSB_WAVE) {
-    const int v = c.x_node[i];
-    c.n_top[v] = -1; c.n_reg[v] = -1; c.n_src[v] = -1; c.n_eix[v] = -1; c.n_rec[v] = -1;
-  }
-  const int nd = c.nd < c.P->dcap ? c.nd : c.P->dcap;
-  for (int i = lane(); i < nd; i += PSB_WAVE) {
-    const int u = c.defects[i];
-    c.n_did[u] = -1; c.n_top[u] = -1; c.n_reg[u] = -1; c.n_src[u] = -1; c.n_eix[u] = -1; c.n_rec[u] = -1;
+  if (4 * xn < (int)c.hmask) {
+    for (int i = lane(); i < xn; i += PSB_WAVE) {
+      uint32_t s = hpos(c, c.x_node[i]);
+      for (uint32_t k = 0; k <= c.hmask; ++k) {
+        if (c.h_key[s] == -1) break;
+        c.h_key[s] = -3;                 // cleared below; keeps other runs intact meanwhile
+        s = (s + 1) & c.hmask;
+      }
+    }
+    wave_sync();
+    for (int i = lane(); i < xn; i += PSB_WAVE) {
+      uint32_t s = hpos(c, c.x_node[i]);
+      for (uint32_t k = 0; k <= c.hmask; ++k) {
+        if (c.h_key[s] == -1) break;
+        c.h_key[s] = -1;
+        s = (s + 1) & c.hmask;
+      }
+    }
+  } else {
+    for (uint32_t i = lane(); i <= c.hmask; i += PSB_WAVE) c.h_key[i] = -1;
   }
   const int64_t nwords = (c.P->n_edges + 31) / 32;
   if (c.status) for (int64_t i = lane(); i < nwords; i += PSB_WAVE) c.ebits[i] = 0;
-  for (int i = lane(); i < 512; i += PSB_WAVE) c.S->dmask[i] = 0;
+  const int nblk = (xn + BLK - 1) / BLK;
+  for (int i = lane(); i <= nblk / 32; i += PSB_WAVE) c.d_mask[i] = 0;
   wave_sync();
-  c.S->x_n = 0; c.S->dblk_n = 0; c.S->fin_n = 0; c.S->stk_n = 0;
+  c.S->x_n = 0; c.S->dblk_n = 0; c.S->fin_n = 0; c.S->stk_n = 0; c.S->rel_n = 0;
   wave_sync();
 }
 
-PSB_DEV void decode_shot(Ctx& c, int64_t shot) {
+// Decodes one shot.  Returns the status; S_OVERFLOW means nothing was
+// written and the shot must be decoded by the overflow tier.
+PSB_DEV int decode_shot(Ctx& c, int64_t shot) {
   c.status = S_OK; c.n_ce = 0; c.n_bc = 0; c.n_shr = 0; c.n_chg = 0; c.stamp = 1; c.n_ev = 0;
-  c.ck_free = -1; c.now = 0; c.n_visit = 0; c.nd = 0; c.n_log = 0;
+  c.now = 0; c.n_visit = 0; c.nd = 0; c.n_log = 0; c.n_regions = 0;
+  c.t0 = dev_clock(); c.t_cl = c.t0; c.t_dyn = c.t0; c.t_fuse = c.t0;
   const uint8_t* row = c.P->synd + shot * (int64_t)c.P->nbytes;
   load_defects(c, row);
   const int nd = c.nd;
-  if (c.status) { write_empty(c, shot, c.status); cleanup(c, shot); return; }
-  if (nd == 0) { write_empty(c, shot, S_OK); cleanup(c, shot); return; }
-  if (nd > c.rcap) { write_empty(c, shot, S_CAPACITY); cleanup(c, shot); return; }
-  c.n_regions = nd; c.n_log = nd; c.n_ck = nd;
+  if (!c.status && nd > c.rcap) cap_fail(c);
+  if (c.status || nd == 0) {
+    const int st = c.status;
+    if (st != S_OVERFLOW) write_empty(c, shot, st);
+    cleanup(c, shot);
+    return st;
+  }
+  c.n_regions = nd; c.n_log = nd;
   for (int i = lane(); i < nd; i += PSB_WAVE) region_init(c, i, 0, 0, -1);
   wave_sync();
   int max_level = 1;
@@ -1135,6 +1135,7 @@ PSB_DEV void decode_shot(Ctx& c, int64_t shot) {
     max_level = wave_max(mx);
     if (wave_or(miss)) c.status = S_INTERNAL;
   }
+  c.t_cl = dev_clock();
   for (int lvl = 1; lvl <= max_level && !c.status; ++lvl) {
     int present = 0;
     for (int i = lane(); i < nd; i += PSB_WAVE) present |= (c.level[i] == lvl);
@@ -1143,47 +1144,66 @@ PSB_DEV void decode_shot(Ctx& c, int64_t shot) {
     seed_level(c, lvl);
     run_dynamics(c);
     if (!c.status) {
-      // every tree must have dissolved
       int open = 0;
       for (int r = lane(); r < c.n_regions; r += PSB_WAVE)
-        open |= (RF(c, r, RF_ALIVE) && RF(c, r, RF_BPAR) < 0 && RF(c, r, RF_TID) >= 0 &&
-                 (r >= nd || c.level[r] <= lvl));
+        open |= (RF(c, r, RF_ALIVE) && RF(c, r, RF_BPAR) < 0 && RF(c, r, RF_TID) >= 0);
       if (wave_or(open)) c.status = S_INFEASIBLE;
     }
   }
+  c.t_dyn = dev_clock(); c.t_fuse = c.t_dyn;
+  if (c.status == S_OVERFLOW) { cleanup(c, shot); return S_OVERFLOW; }
   if (c.P->out_levels && lane() == 0) {
-    int8_t* lv = c.P->out_levels + shot * (int64_t)c.P->dcap;
-    for (int i = 0; i < nd; ++i) lv[i] = (c.P->mode == 1) ? 0 : c.level[i];
+    int8_t* lv = c.P->out_levels + shot * (int64_t)c.P->level_stride;
+    for (int i = 0; i < nd && i < c.P->level_stride; ++i) lv[i] = (c.P->mode == 1) ? 0 : c.level[i];
   }
-  if (c.status) { write_empty(c, shot, c.status); cleanup(c, shot); return; }
-  fuse_and_write(c, shot);
-  if (lane() == 0) c.P->out_status[shot] = c.status;
+  if (!c.status) {
+    fuse_and_write(c, shot);
+    c.t_fuse = dev_clock();
+  }
+  if (c.status == S_OVERFLOW) { cleanup(c, shot); return S_OVERFLOW; }
+  if (c.status && c.status != S_TRUNC) write_empty(c, shot, c.status);
+  else if (lane() == 0) c.P->out_status[shot] = c.status;
+  const int st = c.status;
   cleanup(c, shot);
+  return st;
 }
 
-// Workspace pointers of slot `slot`.
-PSB_DEV void ctx_init(Ctx& c, const Params* P, Lds* S, int64_t slot) {
+// Per-shot state pointers (base = LDS block or the slot's global state block)
+// and global pool pointers of slot `slot`.
+PSB_DEV void ctx_init(Ctx& c, const Params* P, Lds* S, char* state, int64_t slot) {
   c.P = P; c.S = S;
   c.nbr = P->nbr; c.eid = P->eid; c.wt = P->wt; c.w = P->w; c.obs = P->obs;
-  c.deg = P->deg; c.n_det = P->n_det; c.rcap = P->rcap;
+  c.deg = P->deg; c.n_det = P->n_det;
+  c.rcap = P->cap.rcap; c.xcap = P->cap.xcap;
+  c.hmask = (uint32_t)P->cap.hcap - 1;
+  int lg = 0; while ((1 << lg) < P->cap.hcap) ++lg;
+  c.hshift = 32 - lg;
+  const StateLayout& SL = P->SL;
+  c.x_node = (int32_t*)(state + SL.x_node); c.x_top = (int32_t*)(state + SL.x_top);
+  c.x_reg = (int32_t*)(state + SL.x_reg); c.x_src = (int32_t*)(state + SL.x_src);
+  c.x_rec = (int32_t*)(state + SL.x_rec); c.x_wr = (i128*)(state + SL.x_wr); c.x_ev = (i128*)(state + SL.x_ev);
+  c.h_key = (int32_t*)(state + SL.h_key); c.h_val = (int32_t*)(state + SL.h_val);
+  c.blk_min = (i128*)(state + SL.blk_min); c.blk_arg = (int32_t*)(state + SL.blk_arg);
+  c.d_mask = (unsigned*)(state + SL.d_mask); c.d_list = (int32_t*)(state + SL.d_list);
+  c.r_base = (i128*)(state + SL.r_base); c.r_f = (int32_t*)(state + SL.r_f);
   char* base = P->ws + slot * P->L.total;
   const WsLayout& L = P->L;
-  c.n_top = (int32_t*)(base + L.n_top); c.n_reg = (int32_t*)(base + L.n_reg);
-  c.n_src = (int32_t*)(base + L.n_src); c.n_eix = (int32_t*)(base + L.n_eix);
-  c.n_rec = (int32_t*)(base + L.n_rec); c.n_pos = (int32_t*)(base + L.n_pos);
-  c.n_did = (int32_t*)(base + L.n_did); c.n_wr = (i128*)(base + L.n_wr);
-  c.x_node = (int32_t*)(base + L.x_node); c.x_ev = (i128*)(base + L.x_ev);
-  c.blk_min = (i128*)(base + L.blk_min); c.blk_arg = (int32_t*)(base + L.blk_arg);
-  c.r_base = (i128*)(base + L.r_base); c.r_f = (int32_t*)(base + L.r_f);
-  c.ck_next = (int32_t*)(base + L.ck_next); c.ck_prev = (int32_t*)(base + L.ck_prev);
-  c.ck_nodes = (int32_t*)(base + L.ck_nodes);
   c.ce = (int32_t*)(base + L.ce); c.bc = (int32_t*)(base + L.bc); c.lg = (int32_t*)(base + L.lg);
-  c.defects = (int32_t*)(base + L.defects); c.level = (int8_t*)(base + L.level);
+  c.level = (int8_t*)(base + L.level);
   c.uf = (int32_t*)(base + L.uf); c.cl_a = (int32_t*)(base + L.cl_a); c.cl_b = (int32_t*)(base + L.cl_b);
   c.cl_c = (int32_t*)(base + L.cl_c); c.cl_d = (int32_t*)(base + L.cl_d);
   c.bdl = (int32_t*)(base + L.bdl); c.hit = (int32_t*)(base + L.hit);
   c.shr = (int32_t*)(base + L.shr); c.chg = (int32_t*)(base + L.chg); c.stk = (int32_t*)(base + L.stk);
   c.fin = (int32_t*)(base + L.fin); c.ebits = (uint32_t*)(base + L.ebits);
+}
+
+// Fresh state block: empty hash, clean dirty-block bitmap.
+PSB_DEV void state_init(Ctx& c) {
+  for (uint32_t i = lane(); i <= c.hmask; i += PSB_WAVE) c.h_key[i] = -1;
+  const int nblk = (c.xcap + BLK - 1) / BLK;
+  for (int i = lane(); i <= nblk / 32; i += PSB_WAVE) c.d_mask[i] = 0;
+  if (lane() == 0) { c.S->x_n = 0; c.S->dblk_n = 0; c.S->fin_n = 0; c.S->stk_n = 0; c.S->rel_n = 0; }
+  wave_sync();
 }
 
 }  // namespace psb

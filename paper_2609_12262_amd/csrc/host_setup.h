@@ -185,35 +185,47 @@ static void tiebroken_weights(const int32_t* w, int64_t m, uint64_t seed, std::v
 
 
 
-// Capacities and workspace layout for one slot.
-static void plan_workspace(Params& P, int32_t n, int32_t deg, int64_t n_edges, int32_t dcap) {
+// Layout of the per-shot state block for the given capacities.
+static void plan_state(psb::StateLayout& SL, const psb::Caps& cap) {
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) { int64_t o = off; off += (bytes + 15) & ~(int64_t)15; return o; };
+  const int64_t x = cap.xcap, h = cap.hcap, r = cap.rcap;
+  const int64_t nblk = (x + psb::BLK - 1) / psb::BLK;
+  SL.x_wr = take(16 * x); SL.x_ev = take(16 * x); SL.r_base = take(16 * r); SL.blk_min = take(16 * nblk);
+  SL.x_node = take(4 * x); SL.x_top = take(4 * x); SL.x_reg = take(4 * x); SL.x_src = take(4 * x); SL.x_rec = take(4 * x);
+  SL.h_key = take(4 * h); SL.h_val = take(4 * h);
+  SL.blk_arg = take(4 * nblk); SL.d_mask = take(4 * (nblk / 32 + 1)); SL.d_list = take(4 * nblk);
+  SL.r_f = take(4LL * psb::RF_COUNT * r);
+  SL.total = off;
+}
+
+static int32_t next_pow2(int64_t x) { int32_t p = 1; while (p < x) p <<= 1; return p; }
+
+// Capacities and global workspace layout for one slot of a tier.  The state
+// block is part of the workspace only when it does not live in LDS.
+static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const psb::Caps& cap, bool state_in_ws) {
   P.n_det = n; P.deg = deg; P.nbytes = (n + 7) / 8; P.n_edges = n_edges;
-  P.dcap = dcap;
-  P.rcap = 4 * dcap + 64;
-  P.cecap = 8 * dcap + 256;
-  P.bccap = 8 * dcap + 256;
-  P.lcap = 2 * n + 4 * dcap + 64;
-  P.ckcap = 3 * dcap + n / psb::CHUNK + 64;
-  P.shrcap = P.rcap;
-  P.stkcap = 4 * P.rcap + 64;
-  P.fincap = 2 * dcap + 64;
+  P.cap = cap;
+  const int32_t d = cap.dcap;
+  P.cecap = 8 * d + 256;
+  P.bccap = 8 * d + 256;
+  P.lcap = std::min<int64_t>(2LL * n + 4 * d + 64, 2LL * cap.xcap + 4 * d + 64);
+  P.shrcap = cap.rcap;
+  P.stkcap = std::max(4 * cap.rcap + 64, cap.xcap + 64);
+  P.fincap = 2 * d + 64;
   P.hitcap = 32;
   P.bdc = 8;
-  P.max_events = (int64_t)64 * ((int64_t)n + 64 * (int64_t)dcap);
+  P.max_events = (int64_t)64 * ((int64_t)cap.xcap + 64 * (int64_t)d);
+  plan_state(P.SL, cap);
   WsLayout& L = P.L;
   int64_t off = 0;
   auto take = [&](int64_t bytes) { int64_t o = off; off = align256(off + bytes); return o; };
-  const int64_t nblk = (n + psb::CHUNK - 1) / psb::CHUNK;
-  L.n_top = take(4LL * n); L.n_reg = take(4LL * n); L.n_src = take(4LL * n); L.n_eix = take(4LL * n);
-  L.n_rec = take(4LL * n); L.n_pos = take(4LL * n); L.n_did = take(4LL * n); L.n_wr = take(16LL * n);
-  L.x_node = take(4LL * n); L.x_ev = take(16LL * n); L.blk_min = take(16 * nblk); L.blk_arg = take(4 * nblk);
-  L.r_base = take(16LL * P.rcap); L.r_f = take(4LL * psb::RF_COUNT * P.rcap);
-  L.ck_next = take(4LL * P.ckcap); L.ck_prev = take(4LL * P.ckcap); L.ck_nodes = take(4LL * psb::CHUNK * P.ckcap);
+  L.state = state_in_ws ? take(P.SL.total) : 0;
   L.ce = take(4LL * psb::CE_COUNT * P.cecap); L.bc = take(8LL * P.bccap); L.lg = take(12LL * P.lcap);
-  L.defects = take(4LL * dcap); L.level = take(dcap); L.uf = take(4LL * dcap);
-  L.cl_a = take(4LL * dcap); L.cl_b = take(4LL * dcap); L.cl_c = take(4LL * dcap); L.cl_d = take(4LL * dcap);
-  L.bdl = take(4LL * dcap * P.bdc); L.hit = take(4LL * 64 * P.hitcap * 2);
-  L.shr = take(4LL * P.shrcap); L.chg = take(4LL * P.rcap); L.stk = take(4LL * P.stkcap);
+  L.level = take(d); L.uf = take(4LL * d);
+  L.cl_a = take(4LL * d); L.cl_b = take(4LL * d); L.cl_c = take(4LL * d); L.cl_d = take(4LL * d);
+  L.bdl = take(4LL * d * P.bdc); L.hit = take(4LL * 64 * P.hitcap * 2);
+  L.shr = take(4LL * P.shrcap); L.chg = take(4LL * cap.rcap); L.stk = take(4LL * P.stkcap);
   L.fin = take(4LL * P.fincap); L.ebits = take(4 * ((n_edges + 31) / 32 + 1));
   L.total = off;
 }

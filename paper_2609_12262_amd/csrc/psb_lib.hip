@@ -40,38 +40,53 @@ extern "C" const char* psb_last_error(void) { return g_err.c_str(); }
 // kernels
 // ---------------------------------------------------------------------------
 __global__ void psb_zero_kernel(int32_t* p, int n, uint64_t* t_start) {
+  // resets the work counters (fill kernel rather than a memset node, so the
+  // launch sequence stays valid under stream capture)
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
   if (i == 0 && t_start) *t_start = wall_clock64();
 }
 
+// Persistent decode kernel, one wavefront per shot.  TIER 0 keeps the
+// per-shot state in LDS and hands shots that exceed its capacities to the
+// overflow list; TIER 1 keeps the state in global memory and decodes either
+// the overflow list (ovf_list != null) or every shot directly.
+template <int TIER>
 __global__ __launch_bounds__(64) void psb_decode_kernel(Params P) {
-  __shared__ psb::Lds S;
-  for (int i = threadIdx.x; i < 512; i += 64) { S.dmask[i] = 0; S.dblk[i] = 0; }
-  if (threadIdx.x == 0) { S.dblk_n = 0; S.x_n = 0; S.fin_n = 0; S.stk_n = 0; S.lnk_n = 0; }
-  __syncthreads();
-  psb::Ctx c;
-  psb::ctx_init(c, &P, &S, blockIdx.x);
-  for (;;) {
-    int shot = 0;
-    if (threadIdx.x == 0) shot = atomicAdd(P.counter, 1);
-    shot = __shfl(shot, 0, 64);
-    if (shot >= P.n_shots) break;
-    psb::decode_shot(c, shot);
-    if (P.out_tdone && threadIdx.x == 0) P.out_tdone[shot] = wall_clock64();
+  extern __shared__ __align__(16) char psb_dyn_lds[];
+  __shared__ psb::Lds s_static;
+  psb::Lds* S;
+  char* state;
+  if (TIER == 0) {
+    S = (psb::Lds*)psb_dyn_lds;
+    state = psb_dyn_lds + 64;
+  } else {
+    S = &s_static;
+    state = P.ws + (int64_t)blockIdx.x * P.L.total + P.L.state;
   }
-}
-
-// Marks the explored/defect state of fresh workspace slots as empty.
-__global__ void psb_ws_init_kernel(char* ws, int64_t stride, int64_t slots, WsLayout L, int32_t n_det) {
-  const int64_t slot = blockIdx.y;
-  if (slot >= slots) return;
-  char* base = ws + slot * stride;
-  int32_t* arr[7] = {(int32_t*)(base + L.n_top), (int32_t*)(base + L.n_reg), (int32_t*)(base + L.n_src),
-                     (int32_t*)(base + L.n_eix), (int32_t*)(base + L.n_rec), (int32_t*)(base + L.n_pos),
-                     (int32_t*)(base + L.n_did)};
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_det; i += (int64_t)gridDim.x * blockDim.x)
-    for (int a = 0; a < 7; ++a) arr[a][i] = -1;
+  psb::Ctx c;
+  psb::ctx_init(c, &P, S, state, blockIdx.x);
+  psb::state_init(c);
+  for (;;) {
+    int k = 0;
+    if (threadIdx.x == 0) k = atomicAdd(TIER == 0 ? &P.counter[0] : &P.counter[2], 1);
+    k = __shfl(k, 0, 64);
+    int64_t shot;
+    if (TIER == 0 || P.ovf_list == nullptr) {
+      if (k >= P.n_shots) break;
+      shot = k;
+    } else {
+      const int lim = __hip_atomic_load(&P.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (k >= lim) break;
+      shot = P.ovf_list[k];
+    }
+    const int st = psb::decode_shot(c, shot);
+    if (st == psb::S_OVERFLOW) {
+      if (threadIdx.x == 0) { const int q = atomicAdd(&P.counter[1], 1); P.ovf_list[q] = (int32_t)shot; }
+    } else if (P.out_tdone && threadIdx.x == 0) {
+      P.out_tdone[shot] = wall_clock64();
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -157,13 +172,18 @@ extern "C" int32_t psb_graph_syndrome_bytes(const psb_graph* g) { return g ? (g-
 struct psb_decoder {
   const psb_graph* g = nullptr;
   psb_decoder_opts opts{};
-  int32_t dcap = 0, edge_stride = 0, slots = 0;
+  int32_t edge_stride = 0, dcap = 0;
+  int32_t slots_fast = 0, slots_ovf = 0;
+  size_t lds_fast = 0;
+  bool fast_enabled = true;
   __int128* d_wt = nullptr;
   __int128* d_sd = nullptr; __int128* d_sb = nullptr; int32_t* d_shmax = nullptr;
   int32_t* d_counter = nullptr;
-  char* d_ws = nullptr;
-  WsLayout L{};
-  Params P{};
+  char* d_ws_fast = nullptr;
+  char* d_ws_ovf = nullptr;
+  int32_t* d_ovf_list = nullptr;
+  int64_t ovf_list_cap = 0;
+  Params P_fast{}, P_ovf{};
   LevelSchedule sched;
   std::vector<int32_t> hmax;
 };
@@ -180,13 +200,11 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   if (opts.boundary_reading != 0 && opts.boundary_reading != 1) return fail(PSB_E_INVALID, "boundary_reading must be 0 or 1");
   const int32_t n = g->n_det;
   int32_t dcap = opts.max_defects_per_shot > 0 ? opts.max_defects_per_shot : std::min(n, n > 20000 ? 1024 : 512);
-  if (dcap > n) dcap = n;
-  if (dcap < 1) dcap = 1;
+  dcap = std::max(1, std::min(dcap, n));
   const int32_t stride = opts.edges_per_shot > 0 ? opts.edges_per_shot : std::max(64, dcap * 8);
-  const int32_t slots = opts.num_slots > 0 ? opts.num_slots : 2048;
 
   psb_decoder* D = new psb_decoder();
-  D->g = g; D->opts = opts; D->dcap = dcap; D->edge_stride = stride; D->slots = slots;
+  D->g = g; D->opts = opts; D->dcap = dcap; D->edge_stride = stride;
   std::vector<__int128> wt;
   __int128 wmax, wmin;
   tiebroken_weights(g->w.data(), g->n_edges, opts.tiebreak_seed, wt, wmax, wmin);
@@ -200,16 +218,47 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
     return fail(PSB_E_UNSUPPORTED, "level " + std::to_string(bad_level) + " needs paths of more than " +
                                        std::to_string(psb::MAXH) + " edges; the clustering kernel enumerates at most that");
   }
-  Params& P = D->P;
-  plan_workspace(P, n, g->deg, g->n_edges, dcap);
-  P.n_levels = (int32_t)D->sched.d.size(); P.reading = opts.boundary_reading; P.mode = opts.mode;
-  P.edge_stride = stride;
-  const WsLayout& L = P.L;
-  D->L = L;
+  // tier capacities
+  psb::Caps cf, co;
+  co.xcap = n; co.hcap = next_pow2(2LL * n); co.dcap = dcap; co.rcap = 4 * dcap + 64;
+  D->fast_enabled = opts.fast_max_nodes >= 0;
+  cf.xcap = std::min(n, opts.fast_max_nodes > 0 ? opts.fast_max_nodes : 256);
+  cf.rcap = opts.fast_max_regions > 0 ? opts.fast_max_regions : 192;
+  cf.dcap = std::min(std::min(cf.xcap, cf.rcap), dcap);
+  cf.hcap = next_pow2(2LL * cf.xcap);
+  Params& PF = D->P_fast;
+  Params& PO = D->P_ovf;
+  plan_tier(PF, n, g->deg, g->n_edges, cf, false);
+  plan_tier(PO, n, g->deg, g->n_edges, co, true);
+  for (Params* P : {&PF, &PO}) {
+    P->n_levels = (int32_t)D->sched.d.size(); P->reading = opts.boundary_reading; P->mode = opts.mode;
+    P->edge_stride = stride;
+  }
+  PF.tier = 0; PO.tier = 1;
+  D->lds_fast = 64 + (size_t)PF.SL.total;
+  // occupancy-derived slot counts
+  int dev = 0, cus = 256;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int per_cu = 0;
+  if (D->lds_fast > 160 * 1024) D->fast_enabled = false;
+  if (D->fast_enabled) {
+    HIP_TRY(hipFuncSetAttribute((const void*)psb_decode_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)D->lds_fast));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, psb_decode_kernel<0>, 64, D->lds_fast));
+    if (per_cu < 1) D->fast_enabled = false;
+  }
+  D->slots_fast = opts.num_slots > 0 ? opts.num_slots : std::max(1, per_cu) * cus;
+  D->slots_ovf = opts.overflow_slots > 0 ? opts.overflow_slots : (D->fast_enabled ? 2 * cus : 8 * cus);
   // device buffers
   auto fail_dev = [&](const char* what) { psb_decoder_destroy(D); return fail(PSB_E_NOMEM, std::string("device allocation failed: ") + what); };
-  if (hipMalloc((void**)&D->d_wt, 16 * std::max<int64_t>(1, g->n_edges)) != hipSuccess) return fail_dev("weights");
-  if (g->n_edges) HIP_TRY(hipMemcpy(D->d_wt, wt.data(), 16 * g->n_edges, hipMemcpyHostToDevice));
+  {
+    // weights laid out like the adjacency rows, so a row is read in one pass
+    std::vector<__int128> ell_w((size_t)n * g->deg, 0);
+    for (size_t k = 0; k < ell_w.size(); ++k) if (g->eid[k] >= 0) ell_w[k] = wt[g->eid[k]];
+    if (hipMalloc((void**)&D->d_wt, 16 * ell_w.size()) != hipSuccess) return fail_dev("weights");
+    HIP_TRY(hipMemcpy(D->d_wt, ell_w.data(), 16 * ell_w.size(), hipMemcpyHostToDevice));
+  }
   const size_t nl = D->sched.d.size();
   std::vector<__int128> sd(nl), sb(nl);
   for (size_t k = 0; k < nl; ++k) { sd[k] = (__int128)D->sched.d[k]; sb[k] = (__int128)D->sched.b[k]; }
@@ -219,17 +268,19 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   HIP_TRY(hipMemcpy(D->d_sd, sd.data(), 16 * nl, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(D->d_sb, sb.data(), 16 * nl, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(D->d_shmax, D->hmax.data(), 4 * nl, hipMemcpyHostToDevice));
-  if (hipMalloc((void**)&D->d_ws, (size_t)L.total * slots) != hipSuccess) return fail_dev("workspace");
-  HIP_TRY(hipMemset(D->d_ws, 0, (size_t)L.total * slots));
-  {
-    dim3 grid(64, slots);
-    psb_ws_init_kernel<<<grid, 256>>>(D->d_ws, L.total, slots, L, n);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipDeviceSynchronize());
+  if (D->fast_enabled) {
+    if (hipMalloc((void**)&D->d_ws_fast, (size_t)PF.L.total * D->slots_fast) != hipSuccess) return fail_dev("workspace");
+    HIP_TRY(hipMemset(D->d_ws_fast, 0, (size_t)PF.L.total * D->slots_fast));
   }
-  P.nbr = g->d_nbr; P.eid = g->d_eid; P.wt = D->d_wt; P.w = g->d_w; P.obs = g->d_obs;
-  P.sd = D->d_sd; P.sb = D->d_sb; P.shmax = D->d_shmax;
-  P.counter = D->d_counter; P.ws = D->d_ws;
+  if (hipMalloc((void**)&D->d_ws_ovf, (size_t)PO.L.total * D->slots_ovf) != hipSuccess) return fail_dev("overflow workspace");
+  HIP_TRY(hipMemset(D->d_ws_ovf, 0, (size_t)PO.L.total * D->slots_ovf));
+  HIP_TRY(hipDeviceSynchronize());
+  for (Params* P : {&PF, &PO}) {
+    P->nbr = g->d_nbr; P->eid = g->d_eid; P->wt = D->d_wt; P->w = g->d_w; P->obs = g->d_obs;
+    P->sd = D->d_sd; P->sb = D->d_sb; P->shmax = D->d_shmax;
+    P->counter = D->d_counter;
+  }
+  PF.ws = D->d_ws_fast; PO.ws = D->d_ws_ovf;
   *out = D;
   return PSB_OK;
 }
@@ -241,7 +292,9 @@ extern "C" int32_t psb_decoder_destroy(psb_decoder* D) {
   if (D->d_sb) (void)hipFree(D->d_sb);
   if (D->d_shmax) (void)hipFree(D->d_shmax);
   if (D->d_counter) (void)hipFree(D->d_counter);
-  if (D->d_ws) (void)hipFree(D->d_ws);
+  if (D->d_ws_fast) (void)hipFree(D->d_ws_fast);
+  if (D->d_ws_ovf) (void)hipFree(D->d_ws_ovf);
+  if (D->d_ovf_list) (void)hipFree(D->d_ovf_list);
   delete D;
   return PSB_OK;
 }
@@ -263,6 +316,15 @@ extern "C" int32_t psb_decoder_levels(const psb_decoder* D, int32_t max_levels, 
 extern "C" int32_t psb_decoder_edges_per_shot(const psb_decoder* D) { return D ? D->edge_stride : -1; }
 extern "C" int32_t psb_decoder_max_defects(const psb_decoder* D) { return D ? D->dcap : -1; }
 
+extern "C" int32_t psb_decoder_slots(const psb_decoder* D, int32_t* fast_slots, int32_t* overflow_slots,
+                                     int32_t* fast_lds_bytes) {
+  if (!D) return fail(PSB_E_INVALID, "null decoder");
+  if (fast_slots) *fast_slots = D->fast_enabled ? D->slots_fast : 0;
+  if (overflow_slots) *overflow_slots = D->slots_ovf;
+  if (fast_lds_bytes) *fast_lds_bytes = D->fast_enabled ? (int32_t)D->lds_fast : 0;
+  return PSB_OK;
+}
+
 extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, int64_t n, int32_t* edges,
                                     int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
                                     int8_t* levels, uint64_t* t_done, int32_t* stats, void* stream) {
@@ -272,13 +334,30 @@ extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, in
   if (n > (int64_t)INT32_MAX) return fail(PSB_E_INVALID, "batch too large");
   if (!syndromes || !edges || !n_edges || !weight || !obs || !status) return fail(PSB_E_INVALID, "null output");
   hipStream_t s = (hipStream_t)stream;
-  Params P = D->P;
-  P.n_shots = n; P.synd = syndromes; P.out_edges = edges; P.out_nedges = n_edges; P.out_weight = weight;
-  P.out_obs = obs; P.out_status = status; P.out_levels = levels; P.out_tdone = t_done; P.out_stats = stats;
-  psb_zero_kernel<<<1, 64, 0, s>>>(D->d_counter, 1, t_done ? t_done + n : nullptr);
+  if (D->fast_enabled && D->ovf_list_cap < n) {
+    // grows only between launches; the caller's stream is synchronised first
+    HIP_TRY(hipStreamSynchronize(s));
+    if (D->d_ovf_list) (void)hipFree(D->d_ovf_list);
+    D->d_ovf_list = nullptr;
+    if (hipMalloc((void**)&D->d_ovf_list, 4 * (size_t)n) != hipSuccess) return fail(PSB_E_NOMEM, "overflow list");
+    D->ovf_list_cap = n;
+  }
+  Params* tiers[2] = {&D->P_fast, &D->P_ovf};
+  for (Params* P : tiers) {
+    P->n_shots = n; P->synd = syndromes; P->out_edges = edges; P->out_nedges = n_edges; P->out_weight = weight;
+    P->out_obs = obs; P->out_status = status; P->out_levels = levels; P->out_tdone = t_done; P->out_stats = stats;
+    P->level_stride = D->dcap;
+    P->ovf_list = D->fast_enabled ? D->d_ovf_list : nullptr;
+  }
+  psb_zero_kernel<<<1, 64, 0, s>>>(D->d_counter, 3, t_done ? t_done + n : nullptr);
   HIP_TRY(hipGetLastError());
-  const int64_t grid = std::min<int64_t>(n, D->slots);
-  psb_decode_kernel<<<(unsigned)grid, 64, 0, s>>>(P);
+  if (D->fast_enabled) {
+    const int64_t grid = std::min<int64_t>(n, D->slots_fast);
+    psb_decode_kernel<0><<<(unsigned)grid, 64, D->lds_fast, s>>>(D->P_fast);
+    HIP_TRY(hipGetLastError());
+  }
+  const int64_t grid_o = D->fast_enabled ? D->slots_ovf : std::min<int64_t>(n, D->slots_ovf);
+  psb_decode_kernel<1><<<(unsigned)grid_o, 64, 0, s>>>(D->P_ovf);
   HIP_TRY(hipGetLastError());
   return PSB_OK;
 }
@@ -301,4 +380,13 @@ extern "C" int32_t psb_schedule_levels(uint64_t wmax_hi, uint64_t wmax_lo, uint6
     final_level[k] = S.final_level[k];
   }
   return nl;
+}
+
+extern "C" int32_t psb_decoder_last_overflow(psb_decoder* D, void* stream, int32_t* n_overflow) {
+  if (!D || !n_overflow) return fail(PSB_E_INVALID, "null argument");
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  int32_t v[3] = {0, 0, 0};
+  HIP_TRY(hipMemcpy(v, D->d_counter, sizeof(v), hipMemcpyDeviceToHost));
+  *n_overflow = D->fast_enabled ? v[1] : 0;
+  return PSB_OK;
 }

@@ -4,23 +4,28 @@
 
 namespace psb {
 
-// Byte offsets of the per-slot workspace arrays (one slot = one shot in flight).
+// Byte offsets of the per-shot state that the event loop touches on every
+// event.  The same layout is placed in LDS (fast tier, small capacities) or
+// in the slot's global workspace (overflow tier, capacities sized for the
+// worst case).
+struct StateLayout {
+  int64_t x_node, x_top, x_reg, x_src, x_rec;   // explored nodes [xcap], int32
+  int64_t x_wr, x_ev;                            // [xcap], int128
+  int64_t h_key, h_val;                          // detector -> explored index hash [hcap], int32
+  int64_t blk_min, blk_arg;                      // event-cache block minima [nblk]
+  int64_t d_mask, d_list;                        // dirty-block bitmap [nblk/32+1] and list [nblk]
+  int64_t r_base, r_f;                           // regions: base [rcap] int128, fields [RF_COUNT][rcap] int32
+  int64_t total;
+};
+
+// Byte offsets of the per-slot global workspace (pools touched per matcher
+// event or once per shot).
 struct WsLayout {
-  // per detector [n_det]
-  int64_t n_top, n_reg, n_src, n_eix, n_rec, n_pos, n_did, n_wr;
-  // explored-node event cache [n_det] and its block minima [n_blk]
-  int64_t x_node, x_ev, blk_min, blk_arg;
-  // regions [rcap]: radius base (i128) and int fields [RF_COUNT][rcap]
-  int64_t r_base, r_f;
-  // shell chunks [ckcap] (+ 64 node ids each)
-  int64_t ck_next, ck_prev, ck_nodes;
-  // compressed edges [cecap][CE_COUNT], blossom cycles [bccap][2], arrival log [lcap][3]
-  int64_t ce, bc, lg;
-  // defects and clustering [dcap]
-  int64_t defects, level, uf, cl_a, cl_b, cl_c, cl_d, bdl, hit;
-  // scratch lists
-  int64_t shr, chg, stk, fin, ebits;
-  int64_t total;  // bytes per slot (multiple of 256)
+  int64_t state;                                 // StateLayout block (overflow tier only)
+  int64_t ce, bc, lg;                            // compressed edges, blossom cycles, arrival log
+  int64_t level, uf, cl_a, cl_b, cl_c, cl_d, bdl, hit;   // clustering
+  int64_t shr, chg, stk, fin, ebits;             // scratch lists, edge bitmap
+  int64_t total;                                 // bytes per slot (multiple of 256)
 };
 
 // Region int-field indices (structure of arrays: field * rcap + region).
@@ -29,15 +34,12 @@ enum RegionField {
   RF_BPAR,       // blossom parent, -1 if top level
   RF_TPAR,       // alternating-tree parent (top-level region), -1 for roots / no tree
   RF_TPE,        // compressed edge to the tree parent
-  RF_TID,        // tree id (root detector region), -1 if not in a tree
+  RF_TID,        // tree id (root detection event), -1 if not in a tree
   RF_MATE,       // matched region, -2 boundary, -1 none
   RF_ME,         // compressed edge of the match
   RF_BCO,        // blossom cycle offset into the cycle pool
   RF_BCN,        // blossom cycle length (0 = detector region)
   RF_ALIVE,
-  RF_CKH,        // shell: first chunk
-  RF_CKT,        // shell: last chunk
-  RF_CNT,        // shell: number of nodes
   RF_MARK,       // scratch stamp
   RF_INSHR,      // present in the shrinking-region list
   RF_CHGM,       // change-list stamp
@@ -51,22 +53,27 @@ enum RegionField {
 // the two ends, -1 for the boundary.
 enum CeField { CE_E = 0, CE_A, CE_B, CE_SA, CE_SB, CE_COUNT };
 
+struct Caps {
+  int32_t xcap, hcap, rcap, dcap;                // explored nodes, hash slots (power of 2), regions, events
+};
+
 struct Params {
   // graph (device pointers)
   int32_t n_det, deg, nbytes, pad0;
   int64_t n_edges;
   const int32_t* nbr;     // [n_det*deg]: neighbour detector, -1 boundary, -2 padding
   const int32_t* eid;     // [n_det*deg]: edge id
-  const __int128* wt;     // [n_edges]: tie-broken even weights
+  const __int128* wt;     // [n_det*deg]: tie-broken even weight of each adjacency slot
   const int32_t* w;       // [n_edges]: caller weights
   const uint64_t* obs;    // [n_edges]
   // schedule
-  int32_t n_levels, reading, mode, pad1;
+  int32_t n_levels, reading, mode, tier;         // tier: 0 fast (LDS state), 1 overflow (global state)
   const __int128* sd;     // [n_levels] d_k
   const __int128* sb;     // [n_levels] b_k
   const int32_t* shmax;   // [n_levels] path-enumeration depth, -1 = final level
-  // capacities
-  int32_t dcap, rcap, cecap, bccap, lcap, ckcap, shrcap, stkcap, fincap, hitcap, bdc, pad2;
+  // capacities (this tier)
+  Caps cap;
+  int32_t cecap, bccap, lcap, shrcap, stkcap, fincap, hitcap, bdc;
   int64_t max_events;
   // batch
   int64_t n_shots;
@@ -78,12 +85,15 @@ struct Params {
   uint64_t* out_obs;
   int32_t* out_status;
   int8_t* out_levels;
+  int32_t level_stride, pad4;
   uint64_t* out_tdone;
-  int32_t* out_stats;     // [n][4] or null
-  int32_t* counter;       // work queue head
+  int32_t* out_stats;     // [n][8] or null
+  int32_t* counter;       // [0] fast-tier work head, [1] overflow count, [2] overflow head
+  int32_t* ovf_list;      // [n_shots] shots handed to the overflow tier
   // workspace
   char* ws;
   WsLayout L;
+  StateLayout SL;
 };
 
 }  // namespace psb

@@ -96,3 +96,4 @@ PSB_DEV int atom_load(int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __
 
 PSB_DEV uint64_t ballot(int pred) { return __ballot(pred); }
 PSB_DEV uint64_t lanemask_lt() { return (lane() == 0) ? 0ull : (~0ull >> (64 - lane())); }
+PSB_DEV uint64_t dev_clock() { return wall_clock64(); }

@@ -16,12 +16,14 @@ def say(msg):
 
 
 def gpu_decode(g, syndromes, mode=0, reading=0, max_defects=0, edges_per_shot=0, num_slots=0,
-               levels=False, seed=SEED, timestamps=False):
+               levels=False, seed=SEED, timestamps=False, fast_max_nodes=0, fast_max_regions=0,
+               overflow_slots=0, want_overflow=False):
     import torch
     import paper_2609_12262_amd as psb
     G = psb.Graph.from_synth(g)
     dec = psb.Decoder(G, tiebreak_seed=seed, mode=mode, boundary_reading=reading, max_defects=max_defects,
-                      edges_per_shot=edges_per_shot, num_slots=num_slots)
+                      edges_per_shot=edges_per_shot, num_slots=num_slots, fast_max_nodes=fast_max_nodes,
+                      fast_max_regions=fast_max_regions, overflow_slots=overflow_slots)
     synd = torch.from_numpy(np.ascontiguousarray(syndromes)).to("cuda")
     out = dec.decode(synd, levels=levels, timestamps=timestamps)
     torch.cuda.synchronize()
@@ -30,6 +32,8 @@ def gpu_decode(g, syndromes, mode=0, reading=0, max_defects=0, edges_per_shot=0,
                status=out.status.cpu().numpy(),
                levels=out.levels.cpu().numpy() if levels else None,
                t_done=out.t_done.cpu().numpy() if timestamps else None)
+    if want_overflow:
+        res["n_overflow"] = dec.last_overflow()
     dec.close(); G.close()
     return res
 

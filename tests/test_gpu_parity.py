@@ -175,3 +175,28 @@ def test_determinism_and_order_independence():
     for k in ("n_edges", "weight", "obs", "status"):
         assert np.array_equal(a[k], b[k])
         assert np.array_equal(a[k][perm], c[k])
+
+
+@pytest.mark.parametrize("fast_max_nodes,mode", [(24, 0), (24, 1), (-1, 0)])
+def test_overflow_tier_parity(fast_max_nodes, mode):
+    """Shots that exceed the fast tier's LDS capacities -- at intake or in the
+    middle of the dynamics -- are finished by the global-state tier with the
+    same result; fast_max_nodes = -1 runs every shot on that tier."""
+    g = synth.rotated_phenom_graph(11, 0.01)
+    s = synth.sample(g, 3000, seed=41)
+    res = gpu_decode(g, s.syndromes, mode=mode, fast_max_nodes=fast_max_nodes, want_overflow=True)
+    if fast_max_nodes > 0:
+        assert 0 < res["n_overflow"] < 3000
+    bad = compare(g, s.syndromes, res, range(3000))
+    assert not bad, bad[:5]
+
+
+def test_default_tiers_d21_overflow_share():
+    """At the benchmark shape almost every shot stays in the fast tier."""
+    g = synth.rotated_phenom_graph(21, 0.005)
+    s = synth.sample(g, 20000, seed=42)
+    res = gpu_decode(g, s.syndromes, want_overflow=True)
+    assert (res["status"] == 0).all()
+    assert res["n_overflow"] < 200
+    rng = np.random.default_rng(3)
+    assert not compare(g, s.syndromes, res, sorted(rng.integers(0, 20000, 60).tolist()))
