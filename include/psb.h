@@ -85,9 +85,11 @@ typedef struct {
   /* Fast tier: per-shot state held in LDS, for shots that reach at most
    * fast_max_nodes detectors and create at most fast_max_regions regions
    * (0 = 256 / 192; fast_max_nodes < 0 disables the tier).  Shots beyond
-   * these bounds are decoded by the overflow tier (state in global memory,
-   * overflow_slots shots in flight, 0 = chosen from the device) within the
-   * same psb_decode_batch call; results do not depend on the tier. */
+   * these bounds are decoded by the overflow tier (up to 1024 detectors and
+   * 768 regions per shot in LDS, overflow_slots shots in flight, 0 = chosen
+   * from the device) within the same psb_decode_batch call; results do not
+   * depend on the tier.  Shots beyond the overflow tier report
+   * PSB_S_CAPACITY. */
   int32_t fast_max_nodes, fast_max_regions, overflow_slots;
 } psb_decoder_opts;
 

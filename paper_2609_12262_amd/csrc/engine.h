@@ -24,8 +24,8 @@
 // detector id to its explored index.  Explored index i < nd is detection
 // event i, whose detector region is region i and whose arrival record is
 // record i.  The explored table, the hash, the event-cache block minima and
-// the region table form the StateLayout block, which lives in LDS for the
-// fast tier and in global memory for the overflow tier.
+// the region table form the StateLayout block, which lives in LDS (a small
+// block for the fast tier, a large one for the overflow tier).
 //
 // Code style: every function is executed by all lanes of the wavefront with
 // identical (uniform) values except inside the lane-parallel loops
@@ -105,12 +105,16 @@ PSB_DEV int node_idx(const Ctx& c, int v) {
   return -1;
 }
 
-// Uniform insert of a detector that is not present.
-PSB_DEV void hash_put(Ctx& c, int v, int idx) {
+// Uniform insert of a detector that is not present (the table is sized at
+// twice the explored capacity, so a free slot exists; the probe is bounded
+// regardless).
+PSB_DEV bool hash_put(Ctx& c, int v, int idx) {
   uint32_t s = hpos(c, v);
-  while (c.h_key[s] >= 0) s = (s + 1) & c.hmask;
-  c.h_key[s] = v;
-  c.h_val[s] = idx;
+  for (uint32_t k = 0; k <= c.hmask; ++k) {
+    if (c.h_key[s] < 0) { c.h_key[s] = v; c.h_val[s] = idx; return true; }
+    s = (s + 1) & c.hmask;
+  }
+  return false;
 }
 
 // Lane-parallel insert (distinct keys).
@@ -247,7 +251,7 @@ PSB_DEV int explore(Ctx& c, int v) {
   c.x_node[ix] = v; c.x_top[ix] = -1; c.x_reg[ix] = -1; c.x_src[ix] = -1; c.x_rec[ix] = -1;
   c.x_wr[ix] = 0; c.x_ev[ix] = T_INF;
   if (ix % BLK == 0) { c.blk_min[ix / BLK] = T_INF; c.blk_arg[ix / BLK] = ix; }
-  hash_put(c, v, ix);
+  if (!hash_put(c, v, ix)) { cap_fail(c); return -1; }
   wave_sync();
   c.S->x_n = ix + 1;
   wave_sync();

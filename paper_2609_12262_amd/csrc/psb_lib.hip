@@ -47,23 +47,15 @@ __global__ void psb_zero_kernel(int32_t* p, int n, uint64_t* t_start) {
   if (i == 0 && t_start) *t_start = wall_clock64();
 }
 
-// Persistent decode kernel, one wavefront per shot.  TIER 0 keeps the
-// per-shot state in LDS and hands shots that exceed its capacities to the
-// overflow list; TIER 1 keeps the state in global memory and decodes either
-// the overflow list (ovf_list != null) or every shot directly.
+// Persistent decode kernel, one wavefront per shot, per-shot state in LDS.
+// TIER 0 (small capacities, many waves per CU) hands shots that exceed its
+// capacities to the overflow list; TIER 1 (large capacities, one wave per
+// CU) decodes either that list (ovf_list != null) or every shot directly.
 template <int TIER>
 __global__ __launch_bounds__(64) void psb_decode_kernel(Params P) {
   extern __shared__ __align__(16) char psb_dyn_lds[];
-  __shared__ psb::Lds s_static;
-  psb::Lds* S;
-  char* state;
-  if (TIER == 0) {
-    S = (psb::Lds*)psb_dyn_lds;
-    state = psb_dyn_lds + 64;
-  } else {
-    S = &s_static;
-    state = P.ws + (int64_t)blockIdx.x * P.L.total + P.L.state;
-  }
+  psb::Lds* S = (psb::Lds*)psb_dyn_lds;
+  char* state = psb_dyn_lds + 64;
   psb::Ctx c;
   psb::ctx_init(c, &P, S, state, blockIdx.x);
   psb::state_init(c);
@@ -174,7 +166,7 @@ struct psb_decoder {
   psb_decoder_opts opts{};
   int32_t edge_stride = 0, dcap = 0;
   int32_t slots_fast = 0, slots_ovf = 0;
-  size_t lds_fast = 0;
+  size_t lds_fast = 0, lds_ovf = 0;
   bool fast_enabled = true;
   __int128* d_wt = nullptr;
   __int128* d_sd = nullptr; __int128* d_sb = nullptr; int32_t* d_shmax = nullptr;
@@ -218,9 +210,10 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
     return fail(PSB_E_UNSUPPORTED, "level " + std::to_string(bad_level) + " needs paths of more than " +
                                        std::to_string(psb::MAXH) + " edges; the clustering kernel enumerates at most that");
   }
-  // tier capacities
+  // tier capacities (both tiers keep their per-shot state in LDS)
   psb::Caps cf, co;
-  co.xcap = n; co.hcap = next_pow2(2LL * n); co.dcap = dcap; co.rcap = 4 * dcap + 64;
+  co.xcap = std::min(n, 1024); co.rcap = std::min(4 * dcap + 64, 768);
+  co.dcap = std::min(std::min(co.xcap, co.rcap), dcap); co.hcap = next_pow2(2LL * co.xcap);
   D->fast_enabled = opts.fast_max_nodes >= 0;
   cf.xcap = std::min(n, opts.fast_max_nodes > 0 ? opts.fast_max_nodes : 256);
   cf.rcap = opts.fast_max_regions > 0 ? opts.fast_max_regions : 192;
@@ -229,18 +222,23 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   Params& PF = D->P_fast;
   Params& PO = D->P_ovf;
   plan_tier(PF, n, g->deg, g->n_edges, cf, false);
-  plan_tier(PO, n, g->deg, g->n_edges, co, true);
+  plan_tier(PO, n, g->deg, g->n_edges, co, false);
   for (Params* P : {&PF, &PO}) {
     P->n_levels = (int32_t)D->sched.d.size(); P->reading = opts.boundary_reading; P->mode = opts.mode;
     P->edge_stride = stride;
   }
   PF.tier = 0; PO.tier = 1;
   D->lds_fast = 64 + (size_t)PF.SL.total;
+  D->lds_ovf = 64 + (size_t)PO.SL.total;
+  if (D->lds_ovf > 160 * 1024) {
+    delete D;
+    return fail(PSB_E_UNSUPPORTED, "per-shot state of the overflow tier exceeds 160 KB of LDS");
+  }
   // occupancy-derived slot counts
   int dev = 0, cus = 256;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  int per_cu = 0;
+  int per_cu = 0, per_cu_o = 0;
   if (D->lds_fast > 160 * 1024) D->fast_enabled = false;
   if (D->fast_enabled) {
     HIP_TRY(hipFuncSetAttribute((const void*)psb_decode_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -248,8 +246,12 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, psb_decode_kernel<0>, 64, D->lds_fast));
     if (per_cu < 1) D->fast_enabled = false;
   }
+  HIP_TRY(hipFuncSetAttribute((const void*)psb_decode_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)D->lds_ovf));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_o, psb_decode_kernel<1>, 64, D->lds_ovf));
+  if (per_cu_o < 1) { delete D; return fail(PSB_E_UNSUPPORTED, "overflow tier does not fit on a compute unit"); }
   D->slots_fast = opts.num_slots > 0 ? opts.num_slots : std::max(1, per_cu) * cus;
-  D->slots_ovf = opts.overflow_slots > 0 ? opts.overflow_slots : (D->fast_enabled ? 2 * cus : 8 * cus);
+  D->slots_ovf = opts.overflow_slots > 0 ? opts.overflow_slots : per_cu_o * cus;
   // device buffers
   auto fail_dev = [&](const char* what) { psb_decoder_destroy(D); return fail(PSB_E_NOMEM, std::string("device allocation failed: ") + what); };
   {
@@ -357,7 +359,7 @@ extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, in
     HIP_TRY(hipGetLastError());
   }
   const int64_t grid_o = D->fast_enabled ? D->slots_ovf : std::min<int64_t>(n, D->slots_ovf);
-  psb_decode_kernel<1><<<(unsigned)grid_o, 64, 0, s>>>(D->P_ovf);
+  psb_decode_kernel<1><<<(unsigned)grid_o, 64, D->lds_ovf, s>>>(D->P_ovf);
   HIP_TRY(hipGetLastError());
   return PSB_OK;
 }

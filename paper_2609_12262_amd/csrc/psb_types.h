@@ -5,9 +5,8 @@
 namespace psb {
 
 // Byte offsets of the per-shot state that the event loop touches on every
-// event.  The same layout is placed in LDS (fast tier, small capacities) or
-// in the slot's global workspace (overflow tier, capacities sized for the
-// worst case).
+// event.  The block lives in LDS: small capacities for the fast tier, large
+// ones for the overflow tier.
 struct StateLayout {
   int64_t x_node, x_top, x_reg, x_src, x_rec;   // explored nodes [xcap], int32
   int64_t x_wr, x_ev;                            // [xcap], int128
@@ -21,7 +20,7 @@ struct StateLayout {
 // Byte offsets of the per-slot global workspace (pools touched per matcher
 // event or once per shot).
 struct WsLayout {
-  int64_t state;                                 // StateLayout block (overflow tier only)
+  int64_t state;                                 // unused (state lives in LDS), kept 0
   int64_t ce, bc, lg;                            // compressed edges, blossom cycles, arrival log
   int64_t level, uf, cl_a, cl_b, cl_c, cl_d, bdl, hit;   // clustering
   int64_t shr, chg, stk, fin, ebits;             // scratch lists, edge bitmap
@@ -67,7 +66,7 @@ struct Params {
   const int32_t* w;       // [n_edges]: caller weights
   const uint64_t* obs;    // [n_edges]
   // schedule
-  int32_t n_levels, reading, mode, tier;         // tier: 0 fast (LDS state), 1 overflow (global state)
+  int32_t n_levels, reading, mode, tier;         // tier: 0 fast, 1 overflow (both keep state in LDS)
   const __int128* sd;     // [n_levels] d_k
   const __int128* sb;     // [n_levels] b_k
   const int32_t* shmax;   // [n_levels] path-enumeration depth, -1 = final level
