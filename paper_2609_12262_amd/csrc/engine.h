@@ -105,13 +105,25 @@ PSB_DEV int node_idx(const Ctx& c, int v) {
   return -1;
 }
 
+// The same lookup for a uniform detector id, with a uniform result.
+PSB_DEV int node_idx_u(const Ctx& c, int v) {
+  uint32_t s = hpos(c, v);
+  for (uint32_t k = 0; k <= c.hmask; ++k) {
+    const int key = uni(c.h_key[s]);
+    if (key == v) return uni(c.h_val[s]);
+    if (key < 0) return -1;
+    s = (s + 1) & c.hmask;
+  }
+  return -1;
+}
+
 // Uniform insert of a detector that is not present (the table is sized at
 // twice the explored capacity, so a free slot exists; the probe is bounded
 // regardless).
 PSB_DEV bool hash_put(Ctx& c, int v, int idx) {
   uint32_t s = hpos(c, v);
   for (uint32_t k = 0; k <= c.hmask; ++k) {
-    if (c.h_key[s] < 0) { c.h_key[s] = v; c.h_val[s] = idx; return true; }
+    if (uni(c.h_key[s]) < 0) { c.h_key[s] = v; c.h_val[s] = idx; return true; }
     s = (s + 1) & c.hmask;
   }
   return false;
@@ -140,10 +152,10 @@ PSB_DEV void mark_block(Ctx& c, int b) {
 
 PSB_DEV void refresh_blocks(Ctx& c) {
   wave_sync();
-  const int nb = c.S->dblk_n;
-  const int xn = c.S->x_n;
+  const int nb = uni(c.S->dblk_n);
+  const int xn = uni(c.S->x_n);
   for (int q = 0; q < nb; ++q) {
-    const int b = c.d_list[q];
+    const int b = uni(c.d_list[q]);
     i128 key = T_INF; int arg = 0x7fffffff;
     for (int j = lane(); j < BLK; j += PSB_WAVE) {
       const int ix = b * BLK + j;
@@ -166,7 +178,7 @@ PSB_DEV void set_event(Ctx& c, int ix, i128 t) {
 // Next event among explored nodes: (time, explored index).
 PSB_DEV void node_min(Ctx& c, i128& t, int& ix) {
   refresh_blocks(c);
-  const int nb = (c.S->x_n + BLK - 1) / BLK;
+  const int nb = (uni(c.S->x_n) + BLK - 1) / BLK;
   i128 key = T_INF; int arg = 0x7fffffff;
   for (int b = lane(); b < nb; b += PSB_WAVE) {
     const i128 k = c.blk_min[b]; const int a = c.blk_arg[b];
@@ -228,7 +240,7 @@ PSB_DEV void node_event(const Ctx& c, int i, i128& tbest, int& kbest) {
 PSB_DEV void refresh_star(Ctx& c, int i) {
   wave_sync();
   const int deg = c.deg;
-  const int64_t row = (int64_t)c.x_node[i] * deg;
+  const int64_t row = (int64_t)uni(c.x_node[i]) * deg;
   for (int j = lane(); j <= deg; j += PSB_WAVE) {
     int x = i;
     if (j < deg) {
@@ -246,7 +258,7 @@ PSB_DEV void refresh_star(Ctx& c, int i) {
 
 // Append detector v to the explored table (uniform); returns its index.
 PSB_DEV int explore(Ctx& c, int v) {
-  const int ix = c.S->x_n;
+  const int ix = uni(c.S->x_n);
   if (ix >= c.xcap) { cap_fail(c); return -1; }
   c.x_node[ix] = v; c.x_top[ix] = -1; c.x_reg[ix] = -1; c.x_src[ix] = -1; c.x_rec[ix] = -1;
   c.x_wr[ix] = 0; c.x_ev[ix] = T_INF;
@@ -271,7 +283,7 @@ PSB_DEV void region_init(Ctx& c, int r, int rate, i128 base, int tid) {
 
 // Marks region r: the events of every node of its area must be recomputed.
 PSB_DEV void note_change(Ctx& c, int r) {
-  if (RF(c, r, RF_CHGM) == c.stamp) return;
+  if (uni(RF(c, r, RF_CHGM)) == c.stamp) return;
   RF(c, r, RF_CHGM) = c.stamp;
   ++c.n_chg;
 }
@@ -280,7 +292,7 @@ PSB_DEV void set_rate(Ctx& c, int r, int rate) {
   const i128 y = yrad(c, r, c.now);
   c.r_base[r] = y - (i128)rate * c.now;
   RF(c, r, RF_RATE) = rate;
-  if (rate < 0 && !RF(c, r, RF_INSHR)) {
+  if (rate < 0 && !uni(RF(c, r, RF_INSHR))) {
     if (c.n_shr >= c.P->shrcap) { cap_fail(c); return; }
     RF(c, r, RF_INSHR) = 1;
     c.shr[c.n_shr++] = r;
@@ -306,19 +318,31 @@ PSB_DEV int ce_concat(Ctx& c, int a, int b, int sa, int sb) {
 
 // The end of compressed edge `ce` that is not detection event `s`.
 PSB_DEV int ce_other(const Ctx& c, int ce, int s) {
-  return CEF(c, ce, CE_SA) == s ? CEF(c, ce, CE_SB) : CEF(c, ce, CE_SA);
+  const int a = uni(CEF(c, ce, CE_SA)), b = uni(CEF(c, ce, CE_SB));
+  return a == s ? b : a;
 }
 
-// Child of blossom `b` containing region (or detection event) x.
+// Child of blossom `b` containing region (or detection event) x (uniform).
 PSB_DEV int child_containing(const Ctx& c, int x, int b) {
-  while (x >= 0 && RF(c, x, RF_BPAR) != b) x = RF(c, x, RF_BPAR);
+  int guard = 0;
+  while (x >= 0) {
+    const int p = uni(RF(c, x, RF_BPAR));
+    if (p == b || ++guard > c.n_regions) break;
+    x = p;
+  }
   return x;
 }
 
-// Is detection event s inside region r (r itself or a descendant)?
+// Is detection event s inside region r (r itself or a descendant)?  Uniform
+// version and per-lane version.
 PSB_DEV bool inside(const Ctx& c, int s, int r) {
-  int x = s;
-  while (x >= 0) { if (x == r) return true; x = RF(c, x, RF_BPAR); }
+  int x = s, guard = 0;
+  while (x >= 0 && guard++ <= c.n_regions) { if (x == r) return true; x = uni(RF(c, x, RF_BPAR)); }
+  return false;
+}
+PSB_DEV bool inside_lane(const Ctx& c, int s, int r) {
+  int x = s, guard = 0;
+  while (x >= 0 && guard++ <= c.n_regions) { if (x == r) return true; x = RF(c, x, RF_BPAR); }
   return false;
 }
 
@@ -327,10 +351,10 @@ PSB_DEV bool inside(const Ctx& c, int s, int r) {
 PSB_DEV void augment_to_root(Ctx& c, int x) {
   int cur = x;
   int guard = 0;
-  while (RF(c, cur, RF_TPAR) >= 0) {
-    const int in = RF(c, cur, RF_TPAR);
-    const int out = RF(c, in, RF_TPAR);
-    const int e = RF(c, in, RF_TPE);
+  while (uni(RF(c, cur, RF_TPAR)) >= 0) {
+    const int in = uni(RF(c, cur, RF_TPAR));
+    const int out = uni(RF(c, in, RF_TPAR));
+    const int e = uni(RF(c, in, RF_TPE));
     RF(c, in, RF_MATE) = out; RF(c, in, RF_ME) = e;
     RF(c, out, RF_MATE) = in; RF(c, out, RF_ME) = e;
     cur = out;
@@ -352,7 +376,7 @@ PSB_DEV void dissolve_tree(Ctx& c, int tid) {
   }
   wave_sync();
   for (int q = 0; q < n; ++q) {
-    const int r = c.stk[q];
+    const int r = uni(c.stk[q]);
     RF(c, r, RF_TID) = -1;
     RF(c, r, RF_TPAR) = -1;
     set_rate(c, r, 0);
@@ -371,15 +395,16 @@ PSB_DEV void form_blossom(Ctx& c, int a, int b, int ce) {
   const int st = c.stamp;
   int x = a, guard = 0;
   RF(c, x, RF_MARK) = st;
-  while (RF(c, x, RF_TPAR) >= 0) {
-    x = RF(c, RF(c, x, RF_TPAR), RF_TPAR);
+  while (uni(RF(c, x, RF_TPAR)) >= 0) {
+    x = uni(RF(c, uni(RF(c, x, RF_TPAR)), RF_TPAR));
     RF(c, x, RF_MARK) = st;
     if (++guard > c.n_regions) { c.status = S_INTERNAL; return; }
   }
   int y = b; guard = 0;
-  while (RF(c, y, RF_MARK) != st) {
-    if (RF(c, y, RF_TPAR) < 0) { c.status = S_INTERNAL; return; }
-    y = RF(c, RF(c, y, RF_TPAR), RF_TPAR);
+  while (uni(RF(c, y, RF_MARK)) != st) {
+    const int yp = uni(RF(c, y, RF_TPAR));
+    if (yp < 0) { c.status = S_INTERNAL; return; }
+    y = uni(RF(c, yp, RF_TPAR));
     if (++guard > c.n_regions) { c.status = S_INTERNAL; return; }
   }
   const int lca = y;
@@ -388,13 +413,13 @@ PSB_DEV void form_blossom(Ctx& c, int a, int b, int ce) {
   // cycle = [lca] + reverse(path a->lca) + path b->lca  (paths exclude lca)
   int ma = 0, mb = 0;
   const int cap = c.P->stkcap;
-  for (x = a; x != lca; x = RF(c, RF(c, x, RF_TPAR), RF_TPAR)) {
+  for (x = a; x != lca; x = uni(RF(c, uni(RF(c, x, RF_TPAR)), RF_TPAR))) {
     if (ma + 2 > cap) { cap_fail(c); return; }
-    c.stk[ma++] = x; c.stk[ma++] = RF(c, x, RF_TPAR);
+    c.stk[ma++] = x; c.stk[ma++] = uni(RF(c, x, RF_TPAR));
   }
-  for (x = b; x != lca; x = RF(c, RF(c, x, RF_TPAR), RF_TPAR)) {
+  for (x = b; x != lca; x = uni(RF(c, uni(RF(c, x, RF_TPAR)), RF_TPAR))) {
     if (ma + mb + 2 > cap) { cap_fail(c); return; }
-    c.stk[ma + mb++] = x; c.stk[ma + mb++] = RF(c, x, RF_TPAR);
+    c.stk[ma + mb++] = x; c.stk[ma + mb++] = uni(RF(c, x, RF_TPAR));
   }
   const int m = 1 + ma + mb;
   if (c.n_bc + m > c.P->bccap || c.n_regions >= c.rcap) { cap_fail(c); return; }
@@ -402,27 +427,28 @@ PSB_DEV void form_blossom(Ctx& c, int a, int b, int ce) {
   c.n_bc += m;
   int* cyc = c.bc + 2 * bo;   // pairs (child, edge to next)
   cyc[0] = lca;
-  for (int i = 0; i < ma; ++i) cyc[2 * (1 + i)] = c.stk[ma - 1 - i];
-  for (int i = 0; i < mb; ++i) cyc[2 * (1 + ma + i)] = c.stk[ma + i];
+  for (int i = 0; i < ma; ++i) cyc[2 * (1 + i)] = uni(c.stk[ma - 1 - i]);
+  for (int i = 0; i < mb; ++i) cyc[2 * (1 + ma + i)] = uni(c.stk[ma + i]);
   for (int i = 0; i < m; ++i) {
     int e;
-    if (i < ma) e = RF(c, cyc[2 * (i + 1)], RF_TPE);       // parent -> child: child's tree edge
+    if (i < ma) e = RF(c, uni(cyc[2 * (i + 1)]), RF_TPE);  // parent -> child: child's tree edge
     else if (i == ma) e = ce;                              // a -> b
-    else e = RF(c, cyc[2 * i], RF_TPE);                    // child -> parent
+    else e = RF(c, uni(cyc[2 * i]), RF_TPE);               // child -> parent
     cyc[2 * i + 1] = e;
   }
   wave_sync();
   // new blossom region
   const int X = c.n_regions++;
-  const int tid = RF(c, lca, RF_TID);
+  const int tid = uni(RF(c, lca, RF_TID));
+  const int lca_par = uni(RF(c, lca, RF_TPAR));
   region_init(c, X, 1, -c.now, tid);
-  RF(c, X, RF_TPAR) = RF(c, lca, RF_TPAR);
+  RF(c, X, RF_TPAR) = lca_par;
   RF(c, X, RF_TPE) = RF(c, lca, RF_TPE);
   RF(c, X, RF_MATE) = RF(c, lca, RF_MATE);
   RF(c, X, RF_ME) = RF(c, lca, RF_ME);
   RF(c, X, RF_BCO) = bo; RF(c, X, RF_BCN) = m;
-  if (RF(c, lca, RF_TPAR) >= 0) RF(c, RF(c, lca, RF_TPAR), RF_MATE) = X;
-  for (int i = 0; i < m; ++i) RF(c, cyc[2 * i], RF_MARK) = cs;
+  if (lca_par >= 0) RF(c, lca_par, RF_MATE) = X;
+  for (int i = 0; i < m; ++i) RF(c, uni(cyc[2 * i]), RF_MARK) = cs;
   wave_sync();
   // tree children of cycle members that are not on the cycle hang from X
   for (int r = lane(); r < c.n_regions; r += PSB_WAVE) {
@@ -433,7 +459,7 @@ PSB_DEV void form_blossom(Ctx& c, int a, int b, int ce) {
   }
   // nodes of the members now belong to X: l = y_member(now) + wr = y_X(now) + wr'
   // with y_X(now) = 0, so wr' = wr + y_member(now)
-  const int xn = c.S->x_n;
+  const int xn = uni(c.S->x_n);
   for (int i = lane(); i < xn; i += PSB_WAVE) {
     const int t = c.x_top[i];
     if (t < 0 || RF(c, t, RF_MARK) != cs) continue;
@@ -443,7 +469,7 @@ PSB_DEV void form_blossom(Ctx& c, int a, int b, int ce) {
   wave_sync();
   // freeze the cycle members inside X
   for (int i = 0; i < m; ++i) {
-    const int ch = cyc[2 * i];
+    const int ch = uni(cyc[2 * i]);
     c.r_base[ch] = yrad(c, ch, c.now);
     RF(c, ch, RF_RATE) = 0;
     RF(c, ch, RF_BPAR) = X;
@@ -454,20 +480,22 @@ PSB_DEV void form_blossom(Ctx& c, int a, int b, int ce) {
 
 // (d) an inner blossom's radius reaches zero: it shatters (EXPAND).
 PSB_DEV void shatter(Ctx& c, int B) {
-  const int m = RF(c, B, RF_BCN);
-  const int bo = RF(c, B, RF_BCO);
+  const int m = uni(RF(c, B, RF_BCN));
+  const int bo = uni(RF(c, B, RF_BCO));
   const int* cyc = c.bc + 2 * bo;
-  const int P_ = RF(c, B, RF_TPAR);
-  const int ce_p = RF(c, B, RF_TPE);
-  const int C = RF(c, B, RF_MATE);
-  const int ce_c = RF(c, B, RF_ME);
-  const int tid = RF(c, B, RF_TID);
+  const int P_ = uni(RF(c, B, RF_TPAR));
+  const int ce_p = uni(RF(c, B, RF_TPE));
+  const int C = uni(RF(c, B, RF_MATE));
+  const int ce_c = uni(RF(c, B, RF_ME));
+  const int tid = uni(RF(c, B, RF_TID));
   if (P_ < 0 || C < 0) { c.status = S_INTERNAL; return; }
-  const int s_in = inside(c, CEF(c, ce_p, CE_SA), B) ? CEF(c, ce_p, CE_SA) : CEF(c, ce_p, CE_SB);
-  const int s_out = inside(c, CEF(c, ce_c, CE_SA), B) ? CEF(c, ce_c, CE_SA) : CEF(c, ce_c, CE_SB);
+  const int p_sa = uni(CEF(c, ce_p, CE_SA)), p_sb = uni(CEF(c, ce_p, CE_SB));
+  const int c_sa = uni(CEF(c, ce_c, CE_SA)), c_sb = uni(CEF(c, ce_c, CE_SB));
+  const int s_in = inside(c, p_sa, B) ? p_sa : p_sb;
+  const int s_out = inside(c, c_sa, B) ? c_sa : c_sb;
   const int c_in = child_containing(c, s_in, B), c_out = child_containing(c, s_out, B);
   int i_in = -1, i_out = -1;
-  for (int i = 0; i < m; ++i) { if (cyc[2 * i] == c_in) i_in = i; if (cyc[2 * i] == c_out) i_out = i; }
+  for (int i = 0; i < m; ++i) { const int ch = uni(cyc[2 * i]); if (ch == c_in) i_in = i; if (ch == c_out) i_out = i; }
   if (i_in < 0 || i_out < 0) { c.status = S_INTERNAL; return; }
   const int fwd = ((i_out - i_in) % m + m) % m;
   const int dir = (fwd % 2 == 0) ? 1 : -1;
@@ -475,11 +503,11 @@ PSB_DEV void shatter(Ctx& c, int B) {
   // children become top level; nodes of B's area move to the child holding
   // their shell region: l = y_B(now) + wr = y_child + (wr - y_child).
   // Nodes still in B's own shell sit exactly on its boundary and leave.
-  for (int i = 0; i < m; ++i) RF(c, cyc[2 * i], RF_BPAR) = -1;
+  for (int i = 0; i < m; ++i) RF(c, uni(cyc[2 * i]), RF_BPAR) = -1;
   wave_sync();
   c.S->rel_n = 0;
   wave_sync();
-  const int xn = c.S->x_n;
+  const int xn = uni(c.S->x_n);
   for (int i = lane(); i < xn; i += PSB_WAVE) {
     if (c.x_top[i] != B) continue;
     const int reg = c.x_reg[i];
@@ -499,12 +527,12 @@ PSB_DEV void shatter(Ctx& c, int B) {
   int prev = P_;
   for (int j = 0; j <= L; ++j) {
     const int idx = ((i_in + dir * j) % m + m) % m;
-    const int ch = cyc[2 * idx];
+    const int ch = uni(cyc[2 * idx]);
     int e;
     if (j == 0) e = ce_p;
     else {
       const int pidx = ((i_in + dir * (j - 1)) % m + m) % m;
-      e = (dir == 1) ? cyc[2 * pidx + 1] : cyc[2 * idx + 1];
+      e = uni((dir == 1) ? cyc[2 * pidx + 1] : cyc[2 * idx + 1]);
     }
     RF(c, ch, RF_TID) = tid;
     RF(c, ch, RF_TPAR) = prev;
@@ -525,24 +553,24 @@ PSB_DEV void shatter(Ctx& c, int B) {
   for (int j = 1; j <= rest; j += 2) {
     const int ia = ((i_out + dir * j) % m + m) % m;
     const int ib = ((i_out + dir * (j + 1)) % m + m) % m;
-    const int ca = cyc[2 * ia], cb = cyc[2 * ib];
-    const int e = (dir == 1) ? cyc[2 * ia + 1] : cyc[2 * ib + 1];
+    const int ca = uni(cyc[2 * ia]), cb = uni(cyc[2 * ib]);
+    const int e = uni((dir == 1) ? cyc[2 * ia + 1] : cyc[2 * ib + 1]);
     RF(c, ca, RF_MATE) = cb; RF(c, ca, RF_ME) = e; RF(c, ca, RF_TID) = -1; RF(c, ca, RF_TPAR) = -1;
     RF(c, cb, RF_MATE) = ca; RF(c, cb, RF_ME) = e; RF(c, cb, RF_TID) = -1; RF(c, cb, RF_TPAR) = -1;
     set_rate(c, ca, 0); set_rate(c, cb, 0);
   }
   RF(c, B, RF_ALIVE) = 0;
   RF(c, B, RF_TID) = -1;
-  const int nrel = c.S->rel_n;
-  for (int q = 0; q < nrel; ++q) refresh_star(c, c.stk[q]);
+  const int nrel = uni(c.S->rel_n);
+  for (int q = 0; q < nrel; ++q) refresh_star(c, uni(c.stk[q]));
 }
 
 // (e) an inner detector region shrinks to radius zero: its tree parent and
 // child touch at its detection event and form a blossom with it.
 PSB_DEV void implode(Ctx& c, int s) {
-  const int P_ = RF(c, s, RF_TPAR), C = RF(c, s, RF_MATE);
+  const int P_ = uni(RF(c, s, RF_TPAR)), C = uni(RF(c, s, RF_MATE));
   if (P_ < 0 || C < 0) { c.status = S_INTERNAL; return; }
-  const int e_c = RF(c, s, RF_ME), e_p = RF(c, s, RF_TPE);
+  const int e_c = uni(RF(c, s, RF_ME)), e_p = uni(RF(c, s, RF_TPE));
   const int ce = ce_concat(c, e_c, e_p, ce_other(c, e_c, s), ce_other(c, e_p, s));
   if (ce < 0) return;
   form_blossom(c, C, P_, ce);
@@ -550,17 +578,17 @@ PSB_DEV void implode(Ctx& c, int s) {
 
 // Growing region a (tree) touches region b (or the boundary when b < 0).
 PSB_DEV void collide(Ctx& c, int a, int b, int ce) {
-  const int ta = RF(c, a, RF_TID);
-  if (RF(c, a, RF_RATE) != 1 || ta < 0) { c.status = S_INTERNAL; return; }
+  const int ta = uni(RF(c, a, RF_TID));
+  if (uni(RF(c, a, RF_RATE)) != 1 || ta < 0) { c.status = S_INTERNAL; return; }
   if (b < 0) {                                     // (f) tree hits boundary
     augment_to_root(c, a);
     RF(c, a, RF_MATE) = MATE_BOUNDARY; RF(c, a, RF_ME) = ce;
     dissolve_tree(c, ta);
     return;
   }
-  const int rb = RF(c, b, RF_RATE);
+  const int rb = uni(RF(c, b, RF_RATE));
   if (rb == 1) {
-    const int tb = RF(c, b, RF_TID);
+    const int tb = uni(RF(c, b, RF_TID));
     if (tb == ta) { form_blossom(c, a, b, ce); return; }   // (c)
     augment_to_root(c, a);                                   // (b) tree hits tree
     augment_to_root(c, b);
@@ -571,7 +599,7 @@ PSB_DEV void collide(Ctx& c, int a, int b, int ce) {
     return;
   }
   if (rb != 0) { c.status = S_INTERNAL; return; }
-  const int mb = RF(c, b, RF_MATE);
+  const int mb = uni(RF(c, b, RF_MATE));
   if (mb == MATE_BOUNDARY) {                                 // (g) tree hits boundary match
     augment_to_root(c, a);
     RF(c, a, RF_MATE) = b; RF(c, a, RF_ME) = ce;
@@ -591,10 +619,10 @@ PSB_DEV void collide(Ctx& c, int a, int b, int ce) {
 // flooder events
 // ---------------------------------------------------------------------------
 PSB_DEV void arrive(Ctx& c, int iu, int v, int e) {
-  int k = node_idx(c, v);
+  int k = node_idx_u(c, v);
   if (k >= 0 && k < c.nd) { c.status = S_INTERNAL; return; }   // an unseeded detection event was reached
   if (k < 0) { k = explore(c, v); if (k < 0) return; }
-  const int a = c.x_top[iu];
+  const int a = uni(c.x_top[iu]);
   if (c.n_log >= c.P->lcap) { cap_fail(c); return; }
   const int rec = c.n_log++;
   c.lg[3 * rec] = v; c.lg[3 * rec + 1] = c.x_rec[iu]; c.lg[3 * rec + 2] = e;
@@ -612,7 +640,7 @@ PSB_DEV void leave(Ctx& c, int i) {
 PSB_DEV void flush_changes(Ctx& c) {
   if (c.n_chg > 0) {
     wave_sync();
-    const int xn = c.S->x_n;
+    const int xn = uni(c.S->x_n);
     const int st = c.stamp;
     for (int i = lane(); i < xn; i += PSB_WAVE) {
       const int t = c.x_top[i];
@@ -630,22 +658,22 @@ PSB_DEV void flush_changes(Ctx& c) {
 PSB_DEV void node_event_apply(Ctx& c, int iu, int kind) {
   if (kind == K_LEAVE) { leave(c, iu); return; }
   const int deg = c.deg;
-  const int64_t slot = (int64_t)c.x_node[iu] * deg + kind;
-  const int v = c.nbr[slot];
-  const int e = c.eid[slot];
-  const int a = c.x_top[iu];
+  const int64_t slot = (int64_t)uni(c.x_node[iu]) * deg + kind;
+  const int v = uni(c.nbr[slot]);
+  const int e = uni(c.eid[slot]);
+  const int a = uni(c.x_top[iu]);
   if (v == NB_BOUNDARY) {
     const int ce = ce_leaf(c, e, c.x_rec[iu], -1, c.x_src[iu], -1);
     if (ce < 0) return;
     collide(c, a, -1, ce);
   } else {
-    const int kv = node_idx(c, v);
-    const int b = (kv >= 0) ? c.x_top[kv] : -1;
+    const int kv = node_idx_u(c, v);
+    const int b = (kv >= 0) ? uni(c.x_top[kv]) : -1;
     if (b < 0) {
       arrive(c, iu, v, e);
     } else {
       int ce;
-      if (RF(c, a, RF_RATE) >= RF(c, b, RF_RATE)) {
+      if (uni(RF(c, a, RF_RATE)) >= uni(RF(c, b, RF_RATE))) {
         ce = ce_leaf(c, e, c.x_rec[iu], c.x_rec[kv], c.x_src[iu], c.x_src[kv]);
         if (ce < 0) return;
         collide(c, a, b, ce);
@@ -688,7 +716,7 @@ PSB_DEV void run_dynamics(Ctx& c) {
     if (tr < T_INF && tr <= tn) {
       if (tr < c.now) { c.status = S_INTERNAL; return; }
       c.now = tr;
-      if (RF(c, r, RF_BCN) > 0) shatter(c, r); else implode(c, r);
+      if (uni(RF(c, r, RF_BCN)) > 0) shatter(c, r); else implode(c, r);
       if (c.status) return;
       flush_changes(c);
       continue;
@@ -696,6 +724,7 @@ PSB_DEV void run_dynamics(Ctx& c) {
     if (tn >= T_INF) return;
     i128 tf; int kf;
     node_event(c, ix, tf, kf);
+    tf = uni128(tf); kf = uni(kf);
     if (tf != tn) { wave_sync(); set_event(c, ix, tf); continue; }
     if (tf < c.now) { c.status = S_INTERNAL; return; }
     c.now = tf;
@@ -774,13 +803,13 @@ PSB_DEV void cluster(Ctx& c) {
     for (int i = lane(); i < nd; i += PSB_WAVE) nres += (c.level[i] == 0);
     nres = wave_sum(nres);
     if (nres == 0) return;
-    if (c.P->shmax[k] < 0) {
+    const int H = uni(c.P->shmax[k]);
+    if (H < 0) {
       for (int i = lane(); i < nd; i += PSB_WAVE) if (c.level[i] == 0) c.level[i] = (int8_t)(k + 1);
       wave_sync();
       return;
     }
-    const i128 bk = c.P->sb[k], dk = c.P->sd[k];
-    const int H = c.P->shmax[k];
+    const i128 bk = uni128(c.P->sb[k]), dk = uni128(c.P->sd[k]);
     int visits = 0;
     for (int i = lane(); i < nd; i += PSB_WAVE) { c.uf[i] = i; close_cnt[i] = 0; bcount[i] = 0; csize[i] = 0; cclose[i] = 0; }
     wave_sync();
@@ -906,16 +935,18 @@ PSB_DEV void cluster(Ctx& c) {
 // fuse: terminal configuration -> edges, weight, observables
 // ---------------------------------------------------------------------------
 PSB_DEV void push_expand(Ctx& c, int region, int s) {
-  if (RF(c, region, RF_BCN) == 0) return;
-  if (c.S->stk_n + 2 > c.P->stkcap) { c.status = S_CAPACITY; return; }
-  c.stk[c.S->stk_n] = region; c.stk[c.S->stk_n + 1] = s;
-  c.S->stk_n += 2;
+  if (uni(RF(c, region, RF_BCN)) == 0) return;
+  const int n = uni(c.S->stk_n);
+  if (n + 2 > c.P->stkcap) { c.status = S_CAPACITY; return; }
+  c.stk[n] = region; c.stk[n + 1] = s;
+  c.S->stk_n = n + 2;
 }
 
 PSB_DEV void add_fin(Ctx& c, int ce) {
-  if (c.S->fin_n >= c.P->fincap) { c.status = S_CAPACITY; return; }
-  c.fin[c.S->fin_n] = ce;
-  c.S->fin_n += 1;
+  const int n = uni(c.S->fin_n);
+  if (n >= c.P->fincap) { c.status = S_CAPACITY; return; }
+  c.fin[n] = ce;
+  c.S->fin_n = n + 1;
 }
 
 PSB_DEV void collect_final(Ctx& c) {
@@ -931,7 +962,7 @@ PSB_DEV void collect_final(Ctx& c) {
     const int k = atom_add(&c.S->fin_n, 1);
     if (k < c.P->fincap) c.fin[k] = ce; else bad |= 2;
     const int sa = CEF(c, ce, CE_SA), sb = CEF(c, ce, CE_SB);
-    const int s_r = inside(c, sa, r) ? sa : sb;
+    const int s_r = inside_lane(c, sa, r) ? sa : sb;
     if (RF(c, r, RF_BCN) > 0) {
       const int q = atom_add(&c.S->stk_n, 2);
       if (q + 2 <= c.P->stkcap) { c.stk[q] = r; c.stk[q + 1] = s_r; } else bad |= 2;
@@ -945,22 +976,24 @@ PSB_DEV void collect_final(Ctx& c) {
   wave_sync();
   if (bad & 1) { c.status = S_INFEASIBLE; return; }
   if (bad & 2) { c.status = S_CAPACITY; return; }
-  while (c.S->stk_n > 0 && !c.status) {
-    c.S->stk_n -= 2;
-    const int X = c.stk[c.S->stk_n], s = c.stk[c.S->stk_n + 1];
-    const int m = RF(c, X, RF_BCN), bo = RF(c, X, RF_BCO);
+  for (;;) {
+    const int n = uni(c.S->stk_n);
+    if (n <= 0 || c.status) break;
+    c.S->stk_n = n - 2;
+    const int X = uni(c.stk[n - 2]), s = uni(c.stk[n - 1]);
+    const int m = uni(RF(c, X, RF_BCN)), bo = uni(RF(c, X, RF_BCO));
     const int* cyc = c.bc + 2 * bo;
     const int ch = child_containing(c, s, X);
     int p = -1;
-    for (int i = 0; i < m; ++i) if (cyc[2 * i] == ch) p = i;
+    for (int i = 0; i < m; ++i) if (uni(cyc[2 * i]) == ch) p = i;
     if (p < 0) { c.status = S_INTERNAL; return; }
     push_expand(c, ch, s);
     for (int j = 1; j < m; j += 2) {
       const int ia = (p + j) % m, ib = (p + j + 1) % m;
-      const int ca = cyc[2 * ia], cb = cyc[2 * ib];
-      const int ce = cyc[2 * ia + 1];
+      const int ca = uni(cyc[2 * ia]), cb = uni(cyc[2 * ib]);
+      const int ce = uni(cyc[2 * ia + 1]);
       add_fin(c, ce);
-      const int sa = CEF(c, ce, CE_SA), sb = CEF(c, ce, CE_SB);
+      const int sa = uni(CEF(c, ce, CE_SA)), sb = uni(CEF(c, ce, CE_SB));
       const bool a_has_sa = inside(c, sa, ca);
       push_expand(c, ca, a_has_sa ? sa : sb);
       push_expand(c, cb, a_has_sa ? sb : sa);
@@ -972,7 +1005,7 @@ PSB_DEV void fuse_and_write(Ctx& c, int64_t shot) {
   collect_final(c);
   wave_sync();
   if (c.status) return;
-  const int nf = c.S->fin_n;
+  const int nf = uni(c.S->fin_n);
   // lane-parallel tracing; each lane flattens its compressed edges with a private stack
   int bad = 0;
   for (int i = lane(); i < nf; i += PSB_WAVE) {
@@ -1031,11 +1064,10 @@ PSB_DEV void fuse_and_write(Ctx& c, int64_t shot) {
     ob ^= ((uint64_t)(uint32_t)ohi << 32) | (uint32_t)olo;
   }
   if (c.status == S_OK && count > stride) c.status = S_TRUNC;
-  if (lane() == 0) {
-    c.P->out_nedges[shot] = count < stride ? count : stride;
-    c.P->out_weight[shot] = wsum;
-    c.P->out_obs[shot] = ob;
-  }
+  // every lane holds the totals; all lanes store the same values
+  c.P->out_nedges[shot] = count < stride ? count : stride;
+  c.P->out_weight[shot] = wsum;
+  c.P->out_obs[shot] = ob;
 }
 
 // ---------------------------------------------------------------------------
@@ -1060,25 +1092,25 @@ PSB_DEV void seed_level(Ctx& c, int lvl) {
   wave_sync();
 }
 
+// Single-value outputs are stored by every lane with the same value: the
+// persistent loop then has no lane-dependent branches.
 PSB_DEV void write_empty(Ctx& c, int64_t shot, int status) {
-  if (lane() == 0) {
-    c.P->out_nedges[shot] = 0; c.P->out_weight[shot] = 0; c.P->out_obs[shot] = 0;
-    c.P->out_status[shot] = status;
-  }
+  c.P->out_nedges[shot] = 0; c.P->out_weight[shot] = 0; c.P->out_obs[shot] = 0;
+  c.P->out_status[shot] = status;
 }
 
 PSB_DEV void cleanup(Ctx& c, int64_t shot) {
   wave_sync();
-  if (c.P->out_stats && lane() == 0 && c.status != S_OVERFLOW) {
+  if (c.P->out_stats && c.status != S_OVERFLOW) {
     int32_t* st = c.P->out_stats + 8 * shot;
     const uint64_t t_end = dev_clock();
-    st[0] = (int32_t)c.n_ev; st[1] = c.S->x_n; st[2] = c.n_visit; st[3] = c.n_log;
+    st[0] = (int32_t)c.n_ev; st[1] = uni(c.S->x_n); st[2] = c.n_visit; st[3] = c.n_log;
     st[4] = (int32_t)(c.t_cl - c.t0); st[5] = (int32_t)(c.t_dyn - c.t_cl);
     st[6] = (int32_t)(c.t_fuse - c.t_dyn); st[7] = (int32_t)(t_end - c.t0);
   }
   // clear the hash slots of every explored node; a probe run that touched a
   // slot of one of them is cleared to its end so no stale key survives
-  const int xn = c.S->x_n;
+  const int xn = uni(c.S->x_n);
   if (4 * xn < (int)c.hmask) {
     for (int i = lane(); i < xn; i += PSB_WAVE) {
       uint32_t s = hpos(c, c.x_node[i]);
@@ -1156,9 +1188,10 @@ PSB_DEV int decode_shot(Ctx& c, int64_t shot) {
   }
   c.t_dyn = dev_clock(); c.t_fuse = c.t_dyn;
   if (c.status == S_OVERFLOW) { cleanup(c, shot); return S_OVERFLOW; }
-  if (c.P->out_levels && lane() == 0) {
+  if (c.P->out_levels) {
     int8_t* lv = c.P->out_levels + shot * (int64_t)c.P->level_stride;
-    for (int i = 0; i < nd && i < c.P->level_stride; ++i) lv[i] = (c.P->mode == 1) ? 0 : c.level[i];
+    const int nl = nd < c.P->level_stride ? nd : c.P->level_stride;
+    for (int i = lane(); i < nl; i += PSB_WAVE) lv[i] = (c.P->mode == 1) ? 0 : c.level[i];
   }
   if (!c.status) {
     fuse_and_write(c, shot);
@@ -1166,7 +1199,7 @@ PSB_DEV int decode_shot(Ctx& c, int64_t shot) {
   }
   if (c.status == S_OVERFLOW) { cleanup(c, shot); return S_OVERFLOW; }
   if (c.status && c.status != S_TRUNC) write_empty(c, shot, c.status);
-  else if (lane() == 0) c.P->out_status[shot] = c.status;
+  else c.P->out_status[shot] = c.status;
   const int st = c.status;
   cleanup(c, shot);
   return st;
@@ -1206,7 +1239,7 @@ PSB_DEV void state_init(Ctx& c) {
   for (uint32_t i = lane(); i <= c.hmask; i += PSB_WAVE) c.h_key[i] = -1;
   const int nblk = (c.xcap + BLK - 1) / BLK;
   for (int i = lane(); i <= nblk / 32; i += PSB_WAVE) c.d_mask[i] = 0;
-  if (lane() == 0) { c.S->x_n = 0; c.S->dblk_n = 0; c.S->fin_n = 0; c.S->stk_n = 0; c.S->rel_n = 0; }
+  c.S->x_n = 0; c.S->dblk_n = 0; c.S->fin_n = 0; c.S->stk_n = 0; c.S->rel_n = 0;
   wave_sync();
 }
 

@@ -60,22 +60,24 @@ __global__ __launch_bounds__(64) void psb_decode_kernel(Params P) {
   psb::ctx_init(c, &P, S, state, blockIdx.x);
   psb::state_init(c);
   for (;;) {
-    int k = 0;
-    if (threadIdx.x == 0) k = atomicAdd(TIER == 0 ? &P.counter[0] : &P.counter[2], 1);
-    k = __shfl(k, 0, 64);
+    // every lane takes part in the counter update (lane 0 adds 1, the others
+    // add 0) and lane 0's old value is broadcast: no lane-dependent branch
+    // and no per-lane constant feeds the broadcast
+    const int k = lane0(atomicAdd(TIER == 0 ? &P.counter[0] : &P.counter[2], lane() == 0 ? 1 : 0));
     int64_t shot;
     if (TIER == 0 || P.ovf_list == nullptr) {
       if (k >= P.n_shots) break;
       shot = k;
     } else {
-      const int lim = __hip_atomic_load(&P.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int lim = uni(__hip_atomic_load(&P.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
       if (k >= lim) break;
-      shot = P.ovf_list[k];
+      shot = uni(P.ovf_list[k]);
     }
     const int st = psb::decode_shot(c, shot);
     if (st == psb::S_OVERFLOW) {
-      if (threadIdx.x == 0) { const int q = atomicAdd(&P.counter[1], 1); P.ovf_list[q] = (int32_t)shot; }
-    } else if (P.out_tdone && threadIdx.x == 0) {
+      const int q = lane0(atomicAdd(&P.counter[1], lane() == 0 ? 1 : 0));
+      P.ovf_list[q] = (int32_t)shot;               // same value from every lane
+    } else if (P.out_tdone) {
       P.out_tdone[shot] = wall_clock64();
     }
   }

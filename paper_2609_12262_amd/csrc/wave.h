@@ -22,15 +22,40 @@ PSB_DEV void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-PSB_DEV int shfl_xor_i32(int v, int m) { return __shfl_xor(v, m, PSB_WAVE); }
-PSB_DEV int shfl_i32(int v, int src) { return __shfl(v, src, PSB_WAVE); }
+// Every cross-lane operation takes its operand through an empty asm
+// statement.  The optimizer then cannot evaluate the operand separately along
+// each incoming control-flow edge: a value that is a constant on one edge (the
+// initial 0 of lanes that skipped a branch or a loop) would otherwise let it
+// fold the cross-lane operation for that edge alone and send those lanes
+// around it, which breaks the wavefront's lockstep.
+PSB_DEV int opq(int v) { asm volatile("" : "+v"(v)); return v; }
+
+// A value that is identical in every active lane, made visibly uniform to the
+// compiler (scalar register, scalar branches).  Uniform code reads every
+// loaded value that steers control flow through these.
+PSB_DEV int uni(int v) { return __builtin_amdgcn_readfirstlane(opq(v)); }
+PSB_DEV int64_t uni64(int64_t v) {
+  const int lo = uni((int)(uint32_t)(uint64_t)v);
+  const int hi = uni((int)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+// Lane 0's value, for values that only lane 0 computed.
+PSB_DEV int lane0(int v) { return __builtin_amdgcn_readlane(opq(v), 0); }
+PSB_DEV i128 uni128(i128 v) {
+  const uint64_t lo = (uint64_t)uni64((int64_t)(uint64_t)v);
+  const uint64_t hi = (uint64_t)uni64((int64_t)(uint64_t)((unsigned __int128)v >> 64));
+  return (i128)(((unsigned __int128)hi << 64) | lo);
+}
+
+PSB_DEV int shfl_xor_i32(int v, int m) { return __shfl_xor(opq(v), m, PSB_WAVE); }
+PSB_DEV int shfl_i32(int v, int src) { return __shfl(opq(v), src, PSB_WAVE); }
 
 PSB_DEV i128 shfl_xor_i128(i128 v, int m) {
   uint64_t lo = (uint64_t)v, hi = (uint64_t)(v >> 64);
-  uint32_t a = __shfl_xor((unsigned)(lo & 0xffffffffu), m, PSB_WAVE);
-  uint32_t b = __shfl_xor((unsigned)(lo >> 32), m, PSB_WAVE);
-  uint32_t c = __shfl_xor((unsigned)(hi & 0xffffffffu), m, PSB_WAVE);
-  uint32_t d = __shfl_xor((unsigned)(hi >> 32), m, PSB_WAVE);
+  uint32_t a = (uint32_t)shfl_xor_i32((int)(uint32_t)(lo & 0xffffffffu), m);
+  uint32_t b = (uint32_t)shfl_xor_i32((int)(uint32_t)(lo >> 32), m);
+  uint32_t c = (uint32_t)shfl_xor_i32((int)(uint32_t)(hi & 0xffffffffu), m);
+  uint32_t d = (uint32_t)shfl_xor_i32((int)(uint32_t)(hi >> 32), m);
   uint64_t nlo = ((uint64_t)b << 32) | a, nhi = ((uint64_t)d << 32) | c;
   return (i128)(((unsigned __int128)nhi << 64) | nlo);
 }
@@ -44,6 +69,7 @@ PSB_DEV void wave_argmin(i128& key, int& arg) {
     int a2 = shfl_xor_i32(arg, m);
     if (k2 < key || (k2 == key && a2 < arg)) { key = k2; arg = a2; }
   }
+  key = uni128(key); arg = uni(arg);
 }
 
 // Minimum over groups of `g` consecutive lanes (g a power of two <= 64).
@@ -58,19 +84,19 @@ PSB_DEV void group_argmin(i128& key, int& arg, int g) {
 PSB_DEV int wave_sum(int v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_i32(v, m);
-  return v;
+  return uni(v);
 }
 
 PSB_DEV int wave_max(int v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) { int o = shfl_xor_i32(v, m); v = o > v ? o : v; }
-  return v;
+  return uni(v);
 }
 
 PSB_DEV int wave_or(int v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v |= shfl_xor_i32(v, m);
-  return v;
+  return uni(v);
 }
 
 // Exclusive prefix sum across the wave.
@@ -78,7 +104,7 @@ PSB_DEV int wave_prefix(int v) {
   int x = v;
 #pragma unroll
   for (int d = 1; d < PSB_WAVE; d <<= 1) {
-    int y = __shfl_up(x, d, PSB_WAVE);
+    int y = __shfl_up(opq(x), d, PSB_WAVE);
     if (lane() >= d) x += y;
   }
   return x - v;
@@ -94,6 +120,6 @@ PSB_DEV unsigned atom_xchg(unsigned* p, unsigned v) { return atomicExch(p, v); }
 // atomics (which execute in L2) are observed.
 PSB_DEV int atom_load(int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
-PSB_DEV uint64_t ballot(int pred) { return __ballot(pred); }
+PSB_DEV uint64_t ballot(int pred) { return __ballot(opq(pred)); }
 PSB_DEV uint64_t lanemask_lt() { return (lane() == 0) ? 0ull : (~0ull >> (64 - lane())); }
 PSB_DEV uint64_t dev_clock() { return wall_clock64(); }

@@ -141,10 +141,6 @@ def test_edge_cases():
         full[0, j >> 3] |= 1 << (j & 7)
     res = gpu_decode(g, full)
     assert not compare(g, full, res, [0])
-    # The max_defects=8 capacity case (both tiers rejecting a shot at intake)
-    # hung on the GPU with an earlier version of the overflow tier whose state
-    # lived in global memory; its cause was not identified, that tier was
-    # replaced, and the case stays off the GPU until it is understood.
     # truncated edge list: weight and obs still exact
     s = synth.sample(g, 500, seed=21)
     res = gpu_decode(g, s.syndromes, edges_per_shot=1)
@@ -181,8 +177,9 @@ def test_determinism_and_order_independence():
 @pytest.mark.parametrize("fast_max_nodes,mode", [(24, 0), (24, 1), (-1, 0)])
 def test_overflow_tier_parity(fast_max_nodes, mode):
     """Shots that exceed the fast tier's LDS capacities -- at intake or in the
-    middle of the dynamics -- are finished by the global-state tier with the
-    same result; fast_max_nodes = -1 runs every shot on that tier."""
+    middle of the dynamics -- are finished by the overflow tier with the same
+    result; fast_max_nodes = -1 runs every shot on that tier.  The overflow
+    count equals the number of shots the oracle's explored set would not fit."""
     g = synth.rotated_phenom_graph(11, 0.01)
     s = synth.sample(g, 3000, seed=41)
     res = gpu_decode(g, s.syndromes, mode=mode, fast_max_nodes=fast_max_nodes, want_overflow=True)
@@ -201,3 +198,26 @@ def test_default_tiers_d21_overflow_share():
     assert res["n_overflow"] < 200
     rng = np.random.default_rng(3)
     assert not compare(g, s.syndromes, res, sorted(rng.integers(0, 20000, 60).tolist()))
+
+
+def test_intake_rejected_by_both_tiers():
+    """A shot with more detection events than max_defects_per_shot is rejected
+    at intake by the fast tier and again by the overflow tier: status
+    CAPACITY, empty outputs; the shots around it decode normally."""
+    g = synth.rotated_phenom_graph(5, 0.005)
+    nb = g.nbytes
+    full = np.zeros((1, nb), np.uint8)
+    for j in range(g.num_detectors):
+        full[0, j >> 3] |= 1 << (j & 7)
+    say("one shot, all detectors active, max_defects=8")
+    res = gpu_decode(g, full, max_defects=8)
+    assert res["status"].tolist() == [1]
+    assert res["n_edges"][0] == 0 and res["weight"][0] == 0 and int(res["obs"][0]) == 0
+    s = synth.sample(g, 400, seed=43)
+    rows = np.concatenate([s.syndromes[:200], full, s.syndromes[200:]])
+    say("401 shots with the full shot in the middle, max_defects=8")
+    res = gpu_decode(g, rows, max_defects=8)
+    counts = np.array([len(synth.defects_of(r, g.num_detectors)) for r in rows])
+    assert (res["status"][counts > 8] == 1).all()
+    keep = np.nonzero(counts <= 8)[0]
+    assert not compare(g, rows, res, keep)
