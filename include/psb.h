@@ -81,16 +81,20 @@ typedef struct {
   int32_t boundary_reading;
   int32_t max_defects_per_shot;   /* 0 = choose from the graph */
   int32_t edges_per_shot;         /* output stride of psb_decode_batch; 0 = max_defects_per_shot*8 */
-  int32_t num_slots;              /* fast-tier shots in flight; 0 = as many as fit the device */
-  /* Fast tier: per-shot state held in LDS, for shots that reach at most
-   * fast_max_nodes detectors and create at most fast_max_regions regions
-   * (0 = 256 / 192; fast_max_nodes < 0 disables the tier).  Shots beyond
-   * these bounds are decoded by the overflow tier (up to 1024 detectors and
-   * 768 regions per shot in LDS, overflow_slots shots in flight, 0 = chosen
-   * from the device) within the same psb_decode_batch call; results do not
-   * depend on the tier.  Shots beyond the overflow tier report
-   * PSB_S_CAPACITY. */
+  int32_t num_slots;              /* first-tier shots in flight; 0 = as many as fit the device
+                                     (lane tier: at most 65536 lanes) */
+  /* First tier, for shots that reach at most fast_max_nodes detectors and
+   * create at most fast_max_regions regions (fast_max_nodes < 0 disables the
+   * tier).  first_tier = 0 (default): one shot per wavefront, per-shot state
+   * in LDS (0 = 256 / 192); first_tier = 1: one shot per lane, per-shot state
+   * in a global workspace slot of the lane (0 = 320 / 256).  Shots beyond these
+   * bounds are decoded by the overflow tier (one shot per wavefront, up to
+   * 1024 detectors and 768 regions per shot in LDS, overflow_slots shots in
+   * flight, 0 = chosen from the device) within the same psb_decode_batch
+   * call; results do not depend on the tier.  Shots beyond the overflow tier
+   * report PSB_S_CAPACITY. */
   int32_t fast_max_nodes, fast_max_regions, overflow_slots;
+  int32_t first_tier;
 } psb_decoder_opts;
 
 /* Builds the decoder: tie-broken weights, level parameters d_k, b_k (exact

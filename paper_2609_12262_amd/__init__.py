@@ -39,7 +39,7 @@ class _DecoderOpts(ctypes.Structure):
                 ("boundary_reading", ctypes.c_int32), ("max_defects_per_shot", ctypes.c_int32),
                 ("edges_per_shot", ctypes.c_int32), ("num_slots", ctypes.c_int32),
                 ("fast_max_nodes", ctypes.c_int32), ("fast_max_regions", ctypes.c_int32),
-                ("overflow_slots", ctypes.c_int32)]
+                ("overflow_slots", ctypes.c_int32), ("first_tier", ctypes.c_int32)]
 
 
 def lib():
@@ -133,11 +133,11 @@ class Decoder:
     def __init__(self, graph: Graph, tiebreak_seed: int = 0x5EED, mode: int = MODE_PARTITION,
                  boundary_reading: int = 0, max_defects: int = 0, edges_per_shot: int = 0,
                  num_slots: int = 0, q=(1, 10), phi_min=(1, 100), fast_max_nodes: int = 0,
-                 fast_max_regions: int = 0, overflow_slots: int = 0):
+                 fast_max_regions: int = 0, overflow_slots: int = 0, first_tier: int = 0):
         self.graph = graph
         opts = _DecoderOpts(q[0], q[1], phi_min[0], phi_min[1], tiebreak_seed & ((1 << 64) - 1), mode,
                             boundary_reading, max_defects, edges_per_shot, num_slots, fast_max_nodes,
-                            fast_max_regions, overflow_slots)
+                            fast_max_regions, overflow_slots, first_tier)
         h = ctypes.c_void_p()
         _check(lib().psb_decoder_create(graph._h, ctypes.byref(opts), ctypes.byref(h)), "psb_decoder_create")
         self._h = h

@@ -4,7 +4,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libpsb.so")
-SRC = os.path.join(HERE, "csrc", "psb_lib.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("psb_lib.hip", "psb_lane.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -15,7 +15,7 @@ HIPCC_FLAGS = [
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp, SRC]
+    cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp, *SRCS]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + r.stderr[-4000:])

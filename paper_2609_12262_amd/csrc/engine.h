@@ -31,18 +31,24 @@
 // identical (uniform) values except inside the lane-parallel loops
 // `for (i = lane(); i < n; i += PSB_WAVE)`.  Uniform stores of the same value
 // by all lanes are intentional.
+//
+// The file is compiled twice: with the wavefront primitives of wave.h (one
+// shot per wavefront, namespace psb::engine_wave, 64-entry event blocks) and
+// with the single-lane primitives of lane_wave.h (one shot per lane, namespace
+// psb::engine_lane, smaller event blocks).
 #pragma once
 
-namespace psb {
+#ifndef PSB_ENGINE_NS
+#define PSB_ENGINE_NS engine_wave
+#endif
+#ifndef PSB_BLK
+#define PSB_BLK 64
+#endif
 
-constexpr int K_NONE = -1;
-constexpr int K_LEAVE = 1000;
-constexpr int NB_BOUNDARY = -1;
-constexpr int NB_PAD = -2;
-constexpr int MATE_BOUNDARY = -2;
-constexpr int BLK = 64;           // event-cache block size
-constexpr int MAXH = 6;           // deepest path enumeration used by clustering
-constexpr int S_OK = 0, S_CAPACITY = 1, S_INFEASIBLE = 2, S_TRUNC = 3, S_INTERNAL = 4, S_OVERFLOW = 5;
+namespace psb {
+namespace PSB_ENGINE_NS {
+
+constexpr int BLK = PSB_BLK;      // event-cache block size
 
 #define T_INF (((i128)1) << 124)
 
@@ -1243,4 +1249,5 @@ PSB_DEV void state_init(Ctx& c) {
   wave_sync();
 }
 
+}  // namespace PSB_ENGINE_NS
 }  // namespace psb

@@ -186,11 +186,11 @@ static void tiebroken_weights(const int32_t* w, int64_t m, uint64_t seed, std::v
 
 
 // Layout of the per-shot state block for the given capacities.
-static void plan_state(psb::StateLayout& SL, const psb::Caps& cap) {
+static void plan_state(psb::StateLayout& SL, const psb::Caps& cap, int blk) {
   int64_t off = 0;
   auto take = [&](int64_t bytes) { int64_t o = off; off += (bytes + 15) & ~(int64_t)15; return o; };
   const int64_t x = cap.xcap, h = cap.hcap, r = cap.rcap;
-  const int64_t nblk = (x + psb::BLK - 1) / psb::BLK;
+  const int64_t nblk = (x + blk - 1) / blk;
   SL.x_wr = take(16 * x); SL.x_ev = take(16 * x); SL.r_base = take(16 * r); SL.blk_min = take(16 * nblk);
   SL.x_node = take(4 * x); SL.x_top = take(4 * x); SL.x_reg = take(4 * x); SL.x_src = take(4 * x); SL.x_rec = take(4 * x);
   SL.h_key = take(4 * h); SL.h_val = take(4 * h);
@@ -201,14 +201,18 @@ static void plan_state(psb::StateLayout& SL, const psb::Caps& cap) {
 
 static int32_t next_pow2(int64_t x) { int32_t p = 1; while (p < x) p <<= 1; return p; }
 
-// Capacities and global workspace layout for one slot of a tier.  The state
-// block is part of the workspace only when it does not live in LDS.
-static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const psb::Caps& cap, bool state_in_ws) {
+// Capacities and global workspace layout for one slot of a tier.  A slot is
+// one wavefront (wavefront tiers: per-shot state in LDS, 64 lanes share the
+// clustering hit buffers) or one lane (lane tier: the Lds header and the state
+// block sit at the start of the slot, pools are sized more tightly and a shot
+// that exceeds them is handed on).
+static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const psb::Caps& cap, bool lane_slot,
+                      int blk) {
   P.n_det = n; P.deg = deg; P.nbytes = (n + 7) / 8; P.n_edges = n_edges;
   P.cap = cap;
   const int32_t d = cap.dcap;
-  P.cecap = 8 * d + 256;
-  P.bccap = 8 * d + 256;
+  P.cecap = lane_slot ? 4 * d + 128 : 8 * d + 256;
+  P.bccap = lane_slot ? 4 * d + 128 : 8 * d + 256;
   P.lcap = std::min<int64_t>(2LL * n + 4 * d + 64, 2LL * cap.xcap + 4 * d + 64);
   P.shrcap = cap.rcap;
   P.stkcap = std::max(4 * cap.rcap + 64, cap.xcap + 64);
@@ -216,15 +220,15 @@ static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const 
   P.hitcap = 32;
   P.bdc = 8;
   P.max_events = (int64_t)64 * ((int64_t)cap.xcap + 64 * (int64_t)d);
-  plan_state(P.SL, cap);
+  plan_state(P.SL, cap, blk);
   WsLayout& L = P.L;
   int64_t off = 0;
   auto take = [&](int64_t bytes) { int64_t o = off; off = align256(off + bytes); return o; };
-  L.state = state_in_ws ? take(P.SL.total) : 0;
+  L.state = lane_slot ? take(64 + P.SL.total) : 0;
   L.ce = take(4LL * psb::CE_COUNT * P.cecap); L.bc = take(8LL * P.bccap); L.lg = take(12LL * P.lcap);
   L.level = take(d); L.uf = take(4LL * d);
   L.cl_a = take(4LL * d); L.cl_b = take(4LL * d); L.cl_c = take(4LL * d); L.cl_d = take(4LL * d);
-  L.bdl = take(4LL * d * P.bdc); L.hit = take(4LL * 64 * P.hitcap * 2);
+  L.bdl = take(4LL * d * P.bdc); L.hit = take(4LL * (lane_slot ? 1 : 64) * P.hitcap * 2);
   L.shr = take(4LL * P.shrcap); L.chg = take(4LL * cap.rcap); L.stk = take(4LL * P.stkcap);
   L.fin = take(4LL * P.fincap); L.ebits = take(4 * ((n_edges + 31) / 32 + 1));
   L.total = off;

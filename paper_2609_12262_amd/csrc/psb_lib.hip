@@ -15,10 +15,12 @@
 #include "wave.h"
 #include "engine.h"
 #include "host_setup.h"
+#include "lane_launch.h"
 
 using namespace psb_host;
 
 using psb::Params;
+namespace ew = psb::engine_wave;
 using psb::WsLayout;
 typedef unsigned __int128 u128;
 
@@ -54,11 +56,11 @@ __global__ void psb_zero_kernel(int32_t* p, int n, uint64_t* t_start) {
 template <int TIER>
 __global__ __launch_bounds__(64) void psb_decode_kernel(Params P) {
   extern __shared__ __align__(16) char psb_dyn_lds[];
-  psb::Lds* S = (psb::Lds*)psb_dyn_lds;
+  ew::Lds* S = (ew::Lds*)psb_dyn_lds;
   char* state = psb_dyn_lds + 64;
-  psb::Ctx c;
-  psb::ctx_init(c, &P, S, state, blockIdx.x);
-  psb::state_init(c);
+  ew::Ctx c;
+  ew::ctx_init(c, &P, S, state, blockIdx.x);
+  ew::state_init(c);
   for (;;) {
     // every lane takes part in the counter update (lane 0 adds 1, the others
     // add 0) and lane 0's old value is broadcast: no lane-dependent branch
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(64) void psb_decode_kernel(Params P) {
       if (k >= lim) break;
       shot = uni(P.ovf_list[k]);
     }
-    const int st = psb::decode_shot(c, shot);
+    const int st = ew::decode_shot(c, shot);
     if (st == psb::S_OVERFLOW) {
       const int q = lane0(atomicAdd(&P.counter[1], lane() == 0 ? 1 : 0));
       P.ovf_list[q] = (int32_t)shot;               // same value from every lane
@@ -170,6 +172,7 @@ struct psb_decoder {
   int32_t slots_fast = 0, slots_ovf = 0;
   size_t lds_fast = 0, lds_ovf = 0;
   bool fast_enabled = true;
+  bool first_lane = true;          // first tier: one shot per lane (else one per wavefront)
   __int128* d_wt = nullptr;
   __int128* d_sd = nullptr; __int128* d_sb = nullptr; int32_t* d_shmax = nullptr;
   int32_t* d_counter = nullptr;
@@ -212,25 +215,29 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
     return fail(PSB_E_UNSUPPORTED, "level " + std::to_string(bad_level) + " needs paths of more than " +
                                        std::to_string(psb::MAXH) + " edges; the clustering kernel enumerates at most that");
   }
-  // tier capacities (both tiers keep their per-shot state in LDS)
+  // tier capacities: the first tier (one shot per lane, state in its global
+  // workspace slot; or one shot per wavefront, state in LDS) and the
+  // overflow tier (one shot per wavefront, large LDS state)
+  if (opts.first_tier != 0 && opts.first_tier != 1) { delete D; return fail(PSB_E_INVALID, "first_tier must be 0 or 1"); }
+  D->first_lane = opts.first_tier == 1;
   psb::Caps cf, co;
   co.xcap = std::min(n, 1024); co.rcap = std::min(4 * dcap + 64, 768);
   co.dcap = std::min(std::min(co.xcap, co.rcap), dcap); co.hcap = next_pow2(2LL * co.xcap);
   D->fast_enabled = opts.fast_max_nodes >= 0;
-  cf.xcap = std::min(n, opts.fast_max_nodes > 0 ? opts.fast_max_nodes : 256);
-  cf.rcap = opts.fast_max_regions > 0 ? opts.fast_max_regions : 192;
+  cf.xcap = std::min(n, opts.fast_max_nodes > 0 ? opts.fast_max_nodes : (D->first_lane ? 320 : 256));
+  cf.rcap = opts.fast_max_regions > 0 ? opts.fast_max_regions : (D->first_lane ? 256 : 192);
   cf.dcap = std::min(std::min(cf.xcap, cf.rcap), dcap);
   cf.hcap = next_pow2(2LL * cf.xcap);
   Params& PF = D->P_fast;
   Params& PO = D->P_ovf;
-  plan_tier(PF, n, g->deg, g->n_edges, cf, false);
-  plan_tier(PO, n, g->deg, g->n_edges, co, false);
+  plan_tier(PF, n, g->deg, g->n_edges, cf, D->first_lane, D->first_lane ? psb_lane_block() : ew::BLK);
+  plan_tier(PO, n, g->deg, g->n_edges, co, false, ew::BLK);
   for (Params* P : {&PF, &PO}) {
     P->n_levels = (int32_t)D->sched.d.size(); P->reading = opts.boundary_reading; P->mode = opts.mode;
     P->edge_stride = stride;
   }
   PF.tier = 0; PO.tier = 1;
-  D->lds_fast = 64 + (size_t)PF.SL.total;
+  D->lds_fast = D->first_lane ? 0 : 64 + (size_t)PF.SL.total;
   D->lds_ovf = 64 + (size_t)PO.SL.total;
   if (D->lds_ovf > 160 * 1024) {
     delete D;
@@ -242,7 +249,10 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   int per_cu = 0, per_cu_o = 0;
   if (D->lds_fast > 160 * 1024) D->fast_enabled = false;
-  if (D->fast_enabled) {
+  if (D->fast_enabled && D->first_lane) {
+    HIP_TRY(psb_lane_occupancy(&per_cu));
+    if (per_cu < 1) D->fast_enabled = false;
+  } else if (D->fast_enabled) {
     HIP_TRY(hipFuncSetAttribute((const void*)psb_decode_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)D->lds_fast));
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, psb_decode_kernel<0>, 64, D->lds_fast));
@@ -252,7 +262,13 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
                               (int)D->lds_ovf));
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_o, psb_decode_kernel<1>, 64, D->lds_ovf));
   if (per_cu_o < 1) { delete D; return fail(PSB_E_UNSUPPORTED, "overflow tier does not fit on a compute unit"); }
-  D->slots_fast = opts.num_slots > 0 ? opts.num_slots : std::max(1, per_cu) * cus;
+  if (D->first_lane) {
+    // lanes in flight: every wave the chip holds, at most 65536 lanes
+    const int64_t lanes = opts.num_slots > 0 ? opts.num_slots : std::min<int64_t>(65536, 64LL * std::max(1, per_cu) * cus);
+    D->slots_fast = (int32_t)((lanes + 63) / 64 * 64);
+  } else {
+    D->slots_fast = opts.num_slots > 0 ? opts.num_slots : std::max(1, per_cu) * cus;
+  }
   D->slots_ovf = opts.overflow_slots > 0 ? opts.overflow_slots : per_cu_o * cus;
   // device buffers
   auto fail_dev = [&](const char* what) { psb_decoder_destroy(D); return fail(PSB_E_NOMEM, std::string("device allocation failed: ") + what); };
@@ -355,7 +371,10 @@ extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, in
   }
   psb_zero_kernel<<<1, 64, 0, s>>>(D->d_counter, 3, t_done ? t_done + n : nullptr);
   HIP_TRY(hipGetLastError());
-  if (D->fast_enabled) {
+  if (D->fast_enabled && D->first_lane) {
+    const int64_t waves = std::min<int64_t>((n + 63) / 64, D->slots_fast / 64);
+    HIP_TRY(psb_lane_launch(D->P_fast, (unsigned)waves, s));
+  } else if (D->fast_enabled) {
     const int64_t grid = std::min<int64_t>(n, D->slots_fast);
     psb_decode_kernel<0><<<(unsigned)grid, 64, D->lds_fast, s>>>(D->P_fast);
     HIP_TRY(hipGetLastError());

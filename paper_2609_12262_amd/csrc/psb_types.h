@@ -4,9 +4,17 @@
 
 namespace psb {
 
+constexpr int K_NONE = -1;
+constexpr int K_LEAVE = 1000;
+constexpr int NB_BOUNDARY = -1;
+constexpr int NB_PAD = -2;
+constexpr int MATE_BOUNDARY = -2;
+constexpr int MAXH = 6;           // deepest path enumeration used by clustering
+constexpr int S_OK = 0, S_CAPACITY = 1, S_INFEASIBLE = 2, S_TRUNC = 3, S_INTERNAL = 4, S_OVERFLOW = 5;
+
 // Byte offsets of the per-shot state that the event loop touches on every
-// event.  The block lives in LDS: small capacities for the fast tier, large
-// ones for the overflow tier.
+// event.  For the wavefront tiers the block lives in LDS; for the lane tier
+// (one shot per lane) it lives in the lane's global workspace slot.
 struct StateLayout {
   int64_t x_node, x_top, x_reg, x_src, x_rec;   // explored nodes [xcap], int32
   int64_t x_wr, x_ev;                            // [xcap], int128
@@ -20,7 +28,7 @@ struct StateLayout {
 // Byte offsets of the per-slot global workspace (pools touched per matcher
 // event or once per shot).
 struct WsLayout {
-  int64_t state;                                 // unused (state lives in LDS), kept 0
+  int64_t state;                                 // lane tier: Lds header + StateLayout block; else unused
   int64_t ce, bc, lg;                            // compressed edges, blossom cycles, arrival log
   int64_t level, uf, cl_a, cl_b, cl_c, cl_d, bdl, hit;   // clustering
   int64_t shr, chg, stk, fin, ebits;             // scratch lists, edge bitmap
@@ -66,7 +74,7 @@ struct Params {
   const int32_t* w;       // [n_edges]: caller weights
   const uint64_t* obs;    // [n_edges]
   // schedule
-  int32_t n_levels, reading, mode, tier;         // tier: 0 fast, 1 overflow (both keep state in LDS)
+  int32_t n_levels, reading, mode, tier;         // tier: 0 first tier (wave or lane), 1 overflow tier
   const __int128* sd;     // [n_levels] d_k
   const __int128* sb;     // [n_levels] b_k
   const int32_t* shmax;   // [n_levels] path-enumeration depth, -1 = final level
@@ -87,7 +95,7 @@ struct Params {
   int32_t level_stride, pad4;
   uint64_t* out_tdone;
   int32_t* out_stats;     // [n][8] or null
-  int32_t* counter;       // [0] fast-tier work head, [1] overflow count, [2] overflow head
+  int32_t* counter;       // [0] first-tier work head, [1] overflow count, [2] overflow head
   int32_t* ovf_list;      // [n_shots] shots handed to the overflow tier
   // workspace
   char* ws;

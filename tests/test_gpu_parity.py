@@ -221,3 +221,31 @@ def test_intake_rejected_by_both_tiers():
     assert (res["status"][counts > 8] == 1).all()
     keep = np.nonzero(counts <= 8)[0]
     assert not compare(g, rows, res, keep)
+
+
+@pytest.mark.parametrize("fast_max_nodes,mode", [(0, 0), (0, 1), (24, 0)])
+def test_lane_tier_parity(fast_max_nodes, mode):
+    """The same engine with one shot per lane (first_tier = 1): every shot of
+    a d=11 batch equals the oracle, including shots handed to the overflow
+    tier."""
+    g = synth.rotated_phenom_graph(11, 0.01)
+    s = synth.sample(g, 3000, seed=44)
+    say(f"lane tier d11 fast_max_nodes={fast_max_nodes} mode={mode}")
+    res = gpu_decode(g, s.syndromes, mode=mode, fast_max_nodes=fast_max_nodes, first_tier=1, want_overflow=True)
+    if fast_max_nodes > 0:
+        assert 0 < res["n_overflow"] < 3000
+    bad = compare(g, s.syndromes, res, range(3000))
+    assert not bad, bad[:5]
+
+
+def test_lane_tier_equals_wave_tier_d21():
+    """At the benchmark shape the lane tier returns exactly the wavefront
+    tier's outputs on every shot."""
+    g = synth.rotated_phenom_graph(21, 0.005)
+    s = synth.sample(g, 20000, seed=45)
+    a = gpu_decode(g, s.syndromes, first_tier=0)
+    b = gpu_decode(g, s.syndromes, first_tier=1)
+    for k in ("n_edges", "weight", "obs", "status"):
+        assert np.array_equal(a[k], b[k]), k
+    m = np.arange(a["edges"].shape[1])[None, :] < a["n_edges"][:, None]
+    assert np.array_equal(np.where(m, a["edges"], 0), np.where(m, b["edges"], 0))
