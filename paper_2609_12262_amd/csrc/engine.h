@@ -202,6 +202,25 @@ PSB_DEV void node_min(Ctx& c, i128& t, int& ix) {
 // is l(t) = y_top(t) + wr; an edge of weight W is crossed by one fill when
 // l = W (ARRIVE at an empty neighbour, COLLIDE with the boundary) and two
 // fills meet when l_u + l_v = W, provided their rates add up to > 0.
+// Time of the event through adjacency slot j of explored node i (owned by
+// top region `top` with rate ra > 0 or 0 and l_u(t) = bu + ra * t); T_INF if
+// the slot gives none.
+PSB_DEV i128 slot_event(const Ctx& c, int top, int ra, i128 bu, int64_t row, int j) {
+  const int v = c.nbr[row + j];
+  if (v == NB_PAD) return T_INF;
+  const i128 W = c.wt[row + j];
+  if (v == NB_BOUNDARY) return (ra > 0) ? W - bu : T_INF;
+  const int k = node_idx(c, v);
+  const int vt = (k >= 0) ? c.x_top[k] : -1;
+  if (vt < 0) return (ra > 0) ? W - bu : T_INF;      // ARRIVE
+  if (vt == top) return T_INF;
+  const int rs = ra + RF(c, vt, RF_RATE);
+  if (rs <= 0) return T_INF;
+  const i128 num = W - bu - (c.r_base[vt] + c.x_wr[k]);
+  return (rs == 1) ? num : (num >> 1);               // COLLIDE (num even when rs == 2)
+}
+
+// Earliest event seen from explored node i, evaluated by one lane.
 PSB_DEV void node_event(const Ctx& c, int i, i128& tbest, int& kbest) {
   tbest = T_INF; kbest = K_NONE;
   const int top = c.x_top[i];
@@ -217,37 +236,74 @@ PSB_DEV void node_event(const Ctx& c, int i, i128& tbest, int& kbest) {
   const int deg = c.deg;
   const int64_t row = (int64_t)c.x_node[i] * deg;
   for (int j = 0; j < deg; ++j) {
-    const int v = c.nbr[row + j];
-    if (v == NB_PAD) break;
-    const i128 W = c.wt[row + j];
-    i128 t;
-    if (v == NB_BOUNDARY) {
-      if (ra <= 0) continue;
-      t = W - bu;
-    } else {
-      const int k = node_idx(c, v);
-      const int vt = (k >= 0) ? c.x_top[k] : -1;
-      if (vt < 0) {
-        if (ra <= 0) continue;
-        t = W - bu;                                   // ARRIVE
-      } else {
-        if (vt == top) continue;
-        const int rs = ra + RF(c, vt, RF_RATE);
-        if (rs <= 0) continue;
-        const i128 num = W - bu - (c.r_base[vt] + c.x_wr[k]);
-        t = (rs == 1) ? num : (num >> 1);             // COLLIDE (num even when rs == 2)
-      }
-    }
+    const i128 t = slot_event(c, top, ra, bu, row, j);
     if (t < tbest) { tbest = t; kbest = j; }
   }
 }
 
-// Lane-parallel refresh of explored node i and all of its explored neighbours.
+#if PSB_WAVE > 1
+// The same event with the adjacency slots of node i spread over a group of G
+// lanes (G a power of two >= deg, groups aligned to G): lane q of the group
+// evaluates slot q, a butterfly over the group keeps the earliest (ties to
+// the smaller slot, as the serial scan does).  i < 0 marks an idle group.
+// Every lane of the wavefront must call this; each receives its group's result.
+PSB_DEV void node_event_group(const Ctx& c, int i, int G, i128& tbest, int& kbest) {
+  const int q = lane() & (G - 1);
+  i128 t = T_INF; int k = 0x7fffffff;
+  if (i >= 0) {
+    const int top = c.x_top[i];
+    if (top >= 0) {
+      const int ra = RF(c, top, RF_RATE);
+      const i128 bu = c.r_base[top] + c.x_wr[i];
+      if (ra < 0) {
+        if (q == 0 && c.x_reg[i] == top && !(i < c.nd && i == top)) { t = bu; k = K_LEAVE; }
+      } else if (q < c.deg) {
+        t = slot_event(c, top, ra, bu, (int64_t)c.x_node[i] * c.deg, q);
+        k = q;
+      }
+    }
+  }
+  group_argmin(t, k, G);
+  tbest = t; kbest = (t < T_INF) ? k : K_NONE;
+}
+
+PSB_DEV int slot_group(const Ctx& c) { int G = 1; while (G < c.deg) G <<= 1; return G; }
+#endif
+
+// Earliest event of explored node i for uniform code (uniform result).
+PSB_DEV void node_event_u(const Ctx& c, int i, i128& t, int& k) {
+#if PSB_WAVE > 1
+  node_event_group(c, i, slot_group(c), t, k);
+  t = uni128(t); k = uni(k);
+#else
+  node_event(c, i, t, k);
+#endif
+}
+
+// Refresh of explored node i and all of its explored neighbours: the deg+1
+// nodes are spread over groups of lanes, each group evaluating one node's
+// adjacency slots.
 PSB_DEV void refresh_star(Ctx& c, int i) {
   wave_sync();
   const int deg = c.deg;
   const int64_t row = (int64_t)uni(c.x_node[i]) * deg;
-  for (int j = lane(); j <= deg; j += PSB_WAVE) {
+#if PSB_WAVE > 1
+  const int G = slot_group(c), per = PSB_WAVE / G;
+  for (int j0 = 0; j0 <= deg; j0 += per) {
+    const int j = j0 + lane() / G;
+    int x = -1;
+    if (j < deg) {
+      const int v = c.nbr[row + j];
+      if (v >= 0) x = node_idx(c, v);
+    } else if (j == deg) {
+      x = i;
+    }
+    i128 t; int k;
+    node_event_group(c, x, G, t, k);
+    if (x >= 0 && (lane() & (G - 1)) == 0) set_event(c, x, t);
+  }
+#else
+  for (int j = 0; j <= deg; ++j) {
     int x = i;
     if (j < deg) {
       const int v = c.nbr[row + j];
@@ -259,6 +315,7 @@ PSB_DEV void refresh_star(Ctx& c, int i) {
     node_event(c, x, t, k);
     set_event(c, x, t);
   }
+#endif
   wave_sync();
 }
 
@@ -648,13 +705,36 @@ PSB_DEV void flush_changes(Ctx& c) {
     wave_sync();
     const int xn = uni(c.S->x_n);
     const int st = c.stamp;
-    for (int i = lane(); i < xn; i += PSB_WAVE) {
+#if PSB_WAVE > 1
+    // compact the changed nodes into the change list, then evaluate them a
+    // group of lanes per node
+    int n = 0;
+    for (int i0 = 0; i0 < xn; i0 += PSB_WAVE) {
+      const int i = i0 + lane();
+      int take = 0;
+      if (i < xn) { const int t = c.x_top[i]; take = (t >= 0 && RF(c, t, RF_CHGM) == st) ? 1 : 0; }
+      const uint64_t mask = ballot(take);
+      if (take) c.chg[n + __builtin_popcountll(mask & lanemask_lt())] = i;
+      n += __builtin_popcountll(mask);
+    }
+    wave_sync();
+    const int G = slot_group(c), per = PSB_WAVE / G;
+    for (int j0 = 0; j0 < n; j0 += per) {
+      const int j = j0 + lane() / G;
+      const int x = (j < n) ? c.chg[j] : -1;
+      i128 tt; int k;
+      node_event_group(c, x, G, tt, k);
+      if (x >= 0 && (lane() & (G - 1)) == 0) set_event(c, x, tt);
+    }
+#else
+    for (int i = 0; i < xn; ++i) {
       const int t = c.x_top[i];
       if (t < 0 || RF(c, t, RF_CHGM) != st) continue;
       i128 tt; int k;
       node_event(c, i, tt, k);
       set_event(c, i, tt);
     }
+#endif
     wave_sync();
   }
   c.n_chg = 0;
@@ -729,8 +809,7 @@ PSB_DEV void run_dynamics(Ctx& c) {
     }
     if (tn >= T_INF) return;
     i128 tf; int kf;
-    node_event(c, ix, tf, kf);
-    tf = uni128(tf); kf = uni(kf);
+    node_event_u(c, ix, tf, kf);
     if (tf != tn) { wave_sync(); set_event(c, ix, tf); continue; }
     if (tf < c.now) { c.status = S_INTERNAL; return; }
     c.now = tf;
