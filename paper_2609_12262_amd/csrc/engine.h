@@ -69,10 +69,11 @@ struct Ctx {
   const int32_t* nbr; const int32_t* eid; const i128* wt; const int32_t* w; const uint64_t* obs;
   int deg, n_det;
   // per-shot state (StateLayout)
-  int32_t *x_node, *x_top, *x_reg, *x_src, *x_rec; i128 *x_wr, *x_ev;
+  int32_t* x_node; int16_t *x_top, *x_reg, *x_src, *x_rec; i128 *x_wr, *x_ev;
   int32_t *h_key, *h_val; uint32_t hmask; int hshift;
+  int16_t* dmap;                     // direct detector -> explored index map (global), or null
   i128* blk_min; int32_t* blk_arg; unsigned* d_mask; int32_t* d_list;
-  i128* r_base; int32_t* r_f; int rcap, xcap;
+  i128* r_base; int16_t* r_f16; int32_t* r_f32; int rcap, xcap;
   // pools (global)
   int32_t *ce, *bc, *lg;
   int8_t* level;
@@ -86,7 +87,16 @@ struct Ctx {
   uint64_t t0, t_cl, t_dyn, t_fuse;  // device clock marks (statistics)
 };
 
-#define RF(c, r, f) ((c).r_f[(int64_t)(f) * (c).rcap + (r)])
+// Region field f of region r: int16 storage for ids, rates and flags, int32
+// for the two stamps.
+template <int F> struct RFType { typedef int16_t T; };
+template <> struct RFType<RF_MARK> { typedef int32_t T; };
+template <> struct RFType<RF_CHGM> { typedef int32_t T; };
+template <int F> PSB_DEV typename RFType<F>::T& rf_ref(const Ctx& c, int r) {
+  if constexpr (F >= RF_N16) return c.r_f32[(int64_t)(F - RF_N16) * c.rcap + r];
+  else return c.r_f16[(int64_t)F * c.rcap + r];
+}
+#define RF(c, r, f) (rf_ref<(f)>((c), (r)))
 #define CEF(c, i, f) ((c).ce[(int64_t)(i) * CE_COUNT + (f)])
 
 PSB_DEV i128 yrad(const Ctx& c, int r, i128 t) { return c.r_base[r] + (i128)RF(c, r, RF_RATE) * t; }
@@ -101,6 +111,7 @@ PSB_DEV void cap_fail(Ctx& c) { c.status = (c.P->tier == 0) ? S_OVERFLOW : S_CAP
 PSB_DEV uint32_t hpos(const Ctx& c, int v) { return ((uint32_t)v * 2654435761u) >> c.hshift; }
 
 PSB_DEV int node_idx(const Ctx& c, int v) {
+  if (c.dmap) return c.dmap[v];
   uint32_t s = hpos(c, v);
   for (uint32_t k = 0; k <= c.hmask; ++k) {
     const int key = c.h_key[s];
@@ -113,6 +124,7 @@ PSB_DEV int node_idx(const Ctx& c, int v) {
 
 // The same lookup for a uniform detector id, with a uniform result.
 PSB_DEV int node_idx_u(const Ctx& c, int v) {
+  if (c.dmap) return uni(c.dmap[v]);
   uint32_t s = hpos(c, v);
   for (uint32_t k = 0; k <= c.hmask; ++k) {
     const int key = uni(c.h_key[s]);
@@ -127,6 +139,7 @@ PSB_DEV int node_idx_u(const Ctx& c, int v) {
 // twice the explored capacity, so a free slot exists; the probe is bounded
 // regardless).
 PSB_DEV bool hash_put(Ctx& c, int v, int idx) {
+  if (c.dmap) { c.dmap[v] = (int16_t)idx; return true; }
   uint32_t s = hpos(c, v);
   for (uint32_t k = 0; k <= c.hmask; ++k) {
     if (uni(c.h_key[s]) < 0) { c.h_key[s] = v; c.h_val[s] = idx; return true; }
@@ -137,6 +150,7 @@ PSB_DEV bool hash_put(Ctx& c, int v, int idx) {
 
 // Lane-parallel insert (distinct keys).
 PSB_DEV void hash_put_atomic(Ctx& c, int v, int idx) {
+  if (c.dmap) { c.dmap[v] = (int16_t)idx; return; }
   uint32_t s = hpos(c, v);
   for (uint32_t k = 0; k <= c.hmask; ++k) {
     if (atom_cas(&c.h_key[s], -1, v) == -1) { c.h_val[s] = idx; return; }
@@ -1196,7 +1210,9 @@ PSB_DEV void cleanup(Ctx& c, int64_t shot) {
   // clear the hash slots of every explored node; a probe run that touched a
   // slot of one of them is cleared to its end so no stale key survives
   const int xn = uni(c.S->x_n);
-  if (4 * xn < (int)c.hmask) {
+  if (c.dmap) {
+    for (int i = lane(); i < xn; i += PSB_WAVE) c.dmap[c.x_node[i]] = -1;
+  } else if (4 * xn < (int)c.hmask) {
     for (int i = lane(); i < xn; i += PSB_WAVE) {
       uint32_t s = hpos(c, c.x_node[i]);
       for (uint32_t k = 0; k <= c.hmask; ++k) {
@@ -1297,17 +1313,18 @@ PSB_DEV void ctx_init(Ctx& c, const Params* P, Lds* S, char* state, int64_t slot
   c.nbr = P->nbr; c.eid = P->eid; c.wt = P->wt; c.w = P->w; c.obs = P->obs;
   c.deg = P->deg; c.n_det = P->n_det;
   c.rcap = P->cap.rcap; c.xcap = P->cap.xcap;
-  c.hmask = (uint32_t)P->cap.hcap - 1;
+  c.hmask = P->cap.hcap > 0 ? (uint32_t)P->cap.hcap - 1 : 0;
   int lg = 0; while ((1 << lg) < P->cap.hcap) ++lg;
   c.hshift = 32 - lg;
   const StateLayout& SL = P->SL;
-  c.x_node = (int32_t*)(state + SL.x_node); c.x_top = (int32_t*)(state + SL.x_top);
-  c.x_reg = (int32_t*)(state + SL.x_reg); c.x_src = (int32_t*)(state + SL.x_src);
-  c.x_rec = (int32_t*)(state + SL.x_rec); c.x_wr = (i128*)(state + SL.x_wr); c.x_ev = (i128*)(state + SL.x_ev);
+  c.x_node = (int32_t*)(state + SL.x_node); c.x_top = (int16_t*)(state + SL.x_top);
+  c.x_reg = (int16_t*)(state + SL.x_reg); c.x_src = (int16_t*)(state + SL.x_src);
+  c.x_rec = (int16_t*)(state + SL.x_rec); c.x_wr = (i128*)(state + SL.x_wr); c.x_ev = (i128*)(state + SL.x_ev);
   c.h_key = (int32_t*)(state + SL.h_key); c.h_val = (int32_t*)(state + SL.h_val);
   c.blk_min = (i128*)(state + SL.blk_min); c.blk_arg = (int32_t*)(state + SL.blk_arg);
   c.d_mask = (unsigned*)(state + SL.d_mask); c.d_list = (int32_t*)(state + SL.d_list);
-  c.r_base = (i128*)(state + SL.r_base); c.r_f = (int32_t*)(state + SL.r_f);
+  c.r_base = (i128*)(state + SL.r_base);
+  c.r_f16 = (int16_t*)(state + SL.r_f16); c.r_f32 = (int32_t*)(state + SL.r_f32);
   char* base = P->ws + slot * P->L.total;
   const WsLayout& L = P->L;
   c.ce = (int32_t*)(base + L.ce); c.bc = (int32_t*)(base + L.bc); c.lg = (int32_t*)(base + L.lg);
@@ -1317,11 +1334,16 @@ PSB_DEV void ctx_init(Ctx& c, const Params* P, Lds* S, char* state, int64_t slot
   c.bdl = (int32_t*)(base + L.bdl); c.hit = (int32_t*)(base + L.hit);
   c.shr = (int32_t*)(base + L.shr); c.chg = (int32_t*)(base + L.chg); c.stk = (int32_t*)(base + L.stk);
   c.fin = (int32_t*)(base + L.fin); c.ebits = (uint32_t*)(base + L.ebits);
+  c.dmap = P->cap.hcap == 0 ? (int16_t*)(base + L.dmap) : nullptr;
 }
 
 // Fresh state block: empty hash, clean dirty-block bitmap.
 PSB_DEV void state_init(Ctx& c) {
-  for (uint32_t i = lane(); i <= c.hmask; i += PSB_WAVE) c.h_key[i] = -1;
+  if (c.dmap) {
+    for (int i = lane(); i < c.n_det; i += PSB_WAVE) c.dmap[i] = -1;
+  } else {
+    for (uint32_t i = lane(); i <= c.hmask; i += PSB_WAVE) c.h_key[i] = -1;
+  }
   const int nblk = (c.xcap + BLK - 1) / BLK;
   for (int i = lane(); i <= nblk / 32; i += PSB_WAVE) c.d_mask[i] = 0;
   c.S->x_n = 0; c.S->dblk_n = 0; c.S->fin_n = 0; c.S->stk_n = 0; c.S->rel_n = 0;

@@ -192,10 +192,11 @@ static void plan_state(psb::StateLayout& SL, const psb::Caps& cap, int blk) {
   const int64_t x = cap.xcap, h = cap.hcap, r = cap.rcap;
   const int64_t nblk = (x + blk - 1) / blk;
   SL.x_wr = take(16 * x); SL.x_ev = take(16 * x); SL.r_base = take(16 * r); SL.blk_min = take(16 * nblk);
-  SL.x_node = take(4 * x); SL.x_top = take(4 * x); SL.x_reg = take(4 * x); SL.x_src = take(4 * x); SL.x_rec = take(4 * x);
+  SL.x_node = take(4 * x); SL.x_top = take(2 * x); SL.x_reg = take(2 * x); SL.x_src = take(2 * x); SL.x_rec = take(2 * x);
   SL.h_key = take(4 * h); SL.h_val = take(4 * h);
   SL.blk_arg = take(4 * nblk); SL.d_mask = take(4 * (nblk / 32 + 1)); SL.d_list = take(4 * nblk);
-  SL.r_f = take(4LL * psb::RF_COUNT * r);
+  SL.r_f32 = take(4LL * (psb::RF_COUNT - psb::RF_N16) * r);
+  SL.r_f16 = take(2LL * psb::RF_N16 * r);
   SL.total = off;
 }
 
@@ -231,6 +232,7 @@ static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const 
   L.bdl = take(4LL * d * P.bdc); L.hit = take(4LL * (lane_slot ? 1 : 64) * P.hitcap * 2);
   L.shr = take(4LL * P.shrcap); L.chg = take(4LL * cap.xcap); L.stk = take(4LL * P.stkcap);
   L.fin = take(4LL * P.fincap); L.ebits = take(4 * ((n_edges + 31) / 32 + 1));
+  L.dmap = cap.hcap == 0 ? take(2LL * n) : 0;
   L.total = off;
 }
 

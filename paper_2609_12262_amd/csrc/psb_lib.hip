@@ -222,12 +222,16 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   D->first_lane = opts.first_tier == 1;
   psb::Caps cf, co;
   co.xcap = std::min(n, 1024); co.rcap = std::min(4 * dcap + 64, 768);
-  co.dcap = std::min(std::min(co.xcap, co.rcap), dcap); co.hcap = next_pow2(2LL * co.xcap);
+  // detector -> explored index: a direct int16 map in the slot's workspace
+  // when the graph is small enough (2 bytes per detector), else a hash in the
+  // state block
+  const bool direct = n <= 32768;
+  co.dcap = std::min(std::min(co.xcap, co.rcap), dcap); co.hcap = direct ? 0 : next_pow2(2LL * co.xcap);
   D->fast_enabled = opts.fast_max_nodes >= 0;
   cf.xcap = std::min(n, opts.fast_max_nodes > 0 ? opts.fast_max_nodes : (D->first_lane ? 320 : 256));
   cf.rcap = opts.fast_max_regions > 0 ? opts.fast_max_regions : (D->first_lane ? 256 : 192);
   cf.dcap = std::min(std::min(cf.xcap, cf.rcap), dcap);
-  cf.hcap = next_pow2(2LL * cf.xcap);
+  cf.hcap = direct ? 0 : next_pow2(2LL * cf.xcap);
   Params& PF = D->P_fast;
   Params& PO = D->P_ovf;
   plan_tier(PF, n, g->deg, g->n_edges, cf, D->first_lane, D->first_lane ? psb_lane_block() : ew::BLK);
@@ -237,6 +241,15 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
     P->edge_stride = stride;
   }
   PF.tier = 0; PO.tier = 1;
+  for (const Params* P : {&PF, &PO}) {
+    // region ids, log records and pool offsets are stored as int16
+    const int64_t widest = std::max<int64_t>({P->cap.rcap, P->cap.xcap, P->cecap, P->bccap, P->lcap});
+    if (widest >= 32767) {
+      delete D;
+      return fail(PSB_E_UNSUPPORTED, "tier capacities exceed the 16-bit state indices (lower fast_max_nodes / "
+                                     "fast_max_regions / max_defects_per_shot)");
+    }
+  }
   D->lds_fast = D->first_lane ? 0 : 64 + (size_t)PF.SL.total;
   D->lds_ovf = 64 + (size_t)PO.SL.total;
   if (D->lds_ovf > 160 * 1024) {

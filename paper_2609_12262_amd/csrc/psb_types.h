@@ -16,12 +16,15 @@ constexpr int S_OK = 0, S_CAPACITY = 1, S_INFEASIBLE = 2, S_TRUNC = 3, S_INTERNA
 // event.  For the wavefront tiers the block lives in LDS; for the lane tier
 // (one shot per lane) it lives in the lane's global workspace slot.
 struct StateLayout {
-  int64_t x_node, x_top, x_reg, x_src, x_rec;   // explored nodes [xcap], int32
+  int64_t x_node;                                // explored nodes [xcap]: detector id, int32
+  int64_t x_top, x_reg, x_src, x_rec;            // [xcap], int16 (region, region, event, log record)
   int64_t x_wr, x_ev;                            // [xcap], int128
-  int64_t h_key, h_val;                          // detector -> explored index hash [hcap], int32
+  int64_t h_key, h_val;                          // detector -> explored index hash [hcap], int32 (hcap 0:
+                                                 // the direct map of the workspace is used instead)
   int64_t blk_min, blk_arg;                      // event-cache block minima [nblk]
   int64_t d_mask, d_list;                        // dirty-block bitmap [nblk/32+1] and list [nblk]
-  int64_t r_base, r_f;                           // regions: base [rcap] int128, fields [RF_COUNT][rcap] int32
+  int64_t r_base, r_f16, r_f32;                  // regions: base [rcap] int128, fields [RF_N16][rcap] int16
+                                                 // and [RF_COUNT - RF_N16][rcap] int32
   int64_t total;
 };
 
@@ -32,6 +35,8 @@ struct WsLayout {
   int64_t ce, bc, lg;                            // compressed edges, blossom cycles, arrival log
   int64_t level, uf, cl_a, cl_b, cl_c, cl_d, bdl, hit;   // clustering
   int64_t shr, chg, stk, fin, ebits;             // scratch lists, edge bitmap
+  int64_t dmap;                                  // detector -> explored index [n_det] int16, -1 absent
+                                                 // (only when the state block has no hash)
   int64_t total;                                 // bytes per slot (multiple of 256)
 };
 
@@ -47,8 +52,9 @@ enum RegionField {
   RF_BCO,        // blossom cycle offset into the cycle pool
   RF_BCN,        // blossom cycle length (0 = detector region)
   RF_ALIVE,
-  RF_MARK,       // scratch stamp
   RF_INSHR,      // present in the shrinking-region list
+  RF_N16,        // fields above are int16, fields below int32
+  RF_MARK = RF_N16,   // scratch stamp
   RF_CHGM,       // change-list stamp
   RF_COUNT
 };
