@@ -41,20 +41,15 @@
 #ifndef PSB_ENGINE_NS
 #define PSB_ENGINE_NS engine_wave
 #endif
-#ifndef PSB_BLK
-#define PSB_BLK 64
-#endif
 
 namespace psb {
 namespace PSB_ENGINE_NS {
 
-constexpr int BLK = PSB_BLK;      // event-cache block size
 
 #define T_INF (((i128)1) << 124)
 
 // LDS scalars of one wavefront.
 struct Lds {
-  int dblk_n;           // dirty event blocks pending refresh
   int x_n;              // explored-node count
   int fin_n;            // final compressed edges
   int stk_n;            // expansion stack
@@ -72,7 +67,6 @@ struct Ctx {
   int32_t* x_node; int16_t *x_top, *x_reg, *x_src, *x_rec; i128 *x_wr, *x_ev;
   int32_t *h_key, *h_val; uint32_t hmask; int hshift;
   int16_t* dmap;                     // direct detector -> explored index map (global), or null
-  i128* blk_min; int32_t* blk_arg; unsigned* d_mask; int32_t* d_list;
   i128* r_base; int16_t* r_f16; int32_t* r_f32; int rcap, xcap;
   // pools (global)
   int32_t *ce, *bc, *lg;
@@ -159,53 +153,35 @@ PSB_DEV void hash_put_atomic(Ctx& c, int v, int idx) {
 }
 
 // ---------------------------------------------------------------------------
-// event cache (explored nodes, 64-entry blocks with cached minima)
+// event cache: the earliest event of every explored node, x_ev[i]
 // ---------------------------------------------------------------------------
-PSB_DEV void mark_block(Ctx& c, int b) {
-  const unsigned bit = 1u << (b & 31);
-  const unsigned old = (unsigned)atom_or((int*)&c.d_mask[b >> 5], (int)bit);
-  if (!(old & bit)) {
-    const int k = atom_add(&c.S->dblk_n, 1);
-    c.d_list[k] = b;
-  }
-}
+PSB_DEV void set_event(Ctx& c, int ix, i128 t) { c.x_ev[ix] = t; }
 
-PSB_DEV void refresh_blocks(Ctx& c) {
+// Region codes rank before node codes at equal time (a region event is
+// handled first); within a kind the smaller index wins.
+constexpr int EV_NODE = 1 << 24;
+
+// Next event of the dynamics: the earliest cached node event and the earliest
+// shrinking top-level region reaching radius zero (y(t) = base - t is zero at
+// t = base), in one scan and one reduction.  code < EV_NODE: region code;
+// otherwise explored index code - EV_NODE.
+PSB_DEV void next_event(Ctx& c, i128& t, int& code) {
   wave_sync();
-  const int nb = uni(c.S->dblk_n);
   const int xn = uni(c.S->x_n);
-  for (int q = 0; q < nb; ++q) {
-    const int b = uni(c.d_list[q]);
-    i128 key = T_INF; int arg = 0x7fffffff;
-    for (int j = lane(); j < BLK; j += PSB_WAVE) {
-      const int ix = b * BLK + j;
-      if (ix < xn) { const i128 k = c.x_ev[ix]; if (k < key) { key = k; arg = ix; } }
-    }
-    wave_argmin(key, arg);
-    c.blk_min[b] = key; c.blk_arg[b] = arg;
-  }
-  wave_sync();
-  for (int q = lane(); q < nb; q += PSB_WAVE) c.d_mask[c.d_list[q] >> 5] = 0;
-  c.S->dblk_n = 0;
-  wave_sync();
-}
-
-PSB_DEV void set_event(Ctx& c, int ix, i128 t) {
-  c.x_ev[ix] = t;
-  mark_block(c, ix / BLK);
-}
-
-// Next event among explored nodes: (time, explored index).
-PSB_DEV void node_min(Ctx& c, i128& t, int& ix) {
-  refresh_blocks(c);
-  const int nb = (uni(c.S->x_n) + BLK - 1) / BLK;
   i128 key = T_INF; int arg = 0x7fffffff;
-  for (int b = lane(); b < nb; b += PSB_WAVE) {
-    const i128 k = c.blk_min[b]; const int a = c.blk_arg[b];
-    if (k < key || (k == key && a < arg)) { key = k; arg = a; }
+  for (int i = lane(); i < xn; i += PSB_WAVE) {
+    const i128 k = c.x_ev[i];
+    if (k < key) { key = k; arg = EV_NODE + i; }
+  }
+  for (int q = lane(); q < c.n_shr; q += PSB_WAVE) {
+    const int x = c.shr[q];
+    if (RF(c, x, RF_ALIVE) && RF(c, x, RF_BPAR) < 0 && RF(c, x, RF_RATE) < 0) {
+      const i128 k = c.r_base[x];
+      if (k < key || (k == key && x < arg)) { key = k; arg = x; }
+    }
   }
   wave_argmin(key, arg);
-  t = key; ix = arg;
+  t = key; code = arg;
 }
 
 // ---------------------------------------------------------------------------
@@ -339,7 +315,6 @@ PSB_DEV int explore(Ctx& c, int v) {
   if (ix >= c.xcap) { cap_fail(c); return -1; }
   c.x_node[ix] = v; c.x_top[ix] = -1; c.x_reg[ix] = -1; c.x_src[ix] = -1; c.x_rec[ix] = -1;
   c.x_wr[ix] = 0; c.x_ev[ix] = T_INF;
-  if (ix % BLK == 0) { c.blk_min[ix / BLK] = T_INF; c.blk_arg[ix / BLK] = ix; }
   if (!hash_put(c, v, ix)) { cap_fail(c); return -1; }
   wave_sync();
   c.S->x_n = ix + 1;
@@ -787,41 +762,25 @@ PSB_DEV void node_event_apply(Ctx& c, int iu, int kind) {
   flush_changes(c);
 }
 
-// Earliest region-level event: an inner (shrinking) top-level region whose
-// radius y(t) = base - t reaches zero at t = base.
-PSB_DEV void region_min(Ctx& c, i128& t, int& r) {
-  i128 key = T_INF; int arg = 0x7fffffff;
-  if (c.n_shr == 0) { t = key; r = arg; return; }
-  wave_sync();
-  for (int i = lane(); i < c.n_shr; i += PSB_WAVE) {
-    const int x = c.shr[i];
-    if (RF(c, x, RF_ALIVE) && RF(c, x, RF_BPAR) < 0 && RF(c, x, RF_RATE) < 0) {
-      const i128 k = c.r_base[x];
-      if (k < key || (k == key && x < arg)) { key = k; arg = x; }
-    }
-  }
-  wave_argmin(key, arg);
-  t = key; r = arg;
-}
-
 // Run the dynamics until no alternating tree is left.
 PSB_DEV void run_dynamics(Ctx& c) {
   const int64_t max_ev = c.P->max_events;
   for (;;) {
     if (c.status) return;
     if (++c.n_ev > max_ev) { c.status = S_INTERNAL; return; }
-    i128 tn, tr; int ix, r;
-    node_min(c, tn, ix);
-    region_min(c, tr, r);
-    if (tr < T_INF && tr <= tn) {
-      if (tr < c.now) { c.status = S_INTERNAL; return; }
-      c.now = tr;
+    i128 tn; int code;
+    next_event(c, tn, code);
+    if (tn >= T_INF) return;
+    if (code < EV_NODE) {
+      const int r = code;
+      if (tn < c.now) { c.status = S_INTERNAL; return; }
+      c.now = tn;
       if (uni(RF(c, r, RF_BCN)) > 0) shatter(c, r); else implode(c, r);
       if (c.status) return;
       flush_changes(c);
       continue;
     }
-    if (tn >= T_INF) return;
+    const int ix = code - EV_NODE;
     i128 tf; int kf;
     node_event_u(c, ix, tf, kf);
     if (tf != tn) { wave_sync(); set_event(c, ix, tf); continue; }
@@ -859,7 +818,6 @@ PSB_DEV void load_defects(Ctx& c, const uint8_t* row) {
     hash_put_atomic(c, c.x_node[i], i);
   }
   // block minima of the blocks these entries occupy start empty
-  for (int b = lane(); b < (total + BLK - 1) / BLK; b += PSB_WAVE) { c.blk_min[b] = T_INF; c.blk_arg[b] = b * BLK; }
   wave_sync();
   c.S->x_n = total;
   wave_sync();
@@ -1235,10 +1193,8 @@ PSB_DEV void cleanup(Ctx& c, int64_t shot) {
   }
   const int64_t nwords = (c.P->n_edges + 31) / 32;
   if (c.status) for (int64_t i = lane(); i < nwords; i += PSB_WAVE) c.ebits[i] = 0;
-  const int nblk = (xn + BLK - 1) / BLK;
-  for (int i = lane(); i <= nblk / 32; i += PSB_WAVE) c.d_mask[i] = 0;
   wave_sync();
-  c.S->x_n = 0; c.S->dblk_n = 0; c.S->fin_n = 0; c.S->stk_n = 0; c.S->rel_n = 0;
+  c.S->x_n = 0; c.S->fin_n = 0; c.S->stk_n = 0; c.S->rel_n = 0;
   wave_sync();
 }
 
@@ -1321,8 +1277,6 @@ PSB_DEV void ctx_init(Ctx& c, const Params* P, Lds* S, char* state, int64_t slot
   c.x_reg = (int16_t*)(state + SL.x_reg); c.x_src = (int16_t*)(state + SL.x_src);
   c.x_rec = (int16_t*)(state + SL.x_rec); c.x_wr = (i128*)(state + SL.x_wr); c.x_ev = (i128*)(state + SL.x_ev);
   c.h_key = (int32_t*)(state + SL.h_key); c.h_val = (int32_t*)(state + SL.h_val);
-  c.blk_min = (i128*)(state + SL.blk_min); c.blk_arg = (int32_t*)(state + SL.blk_arg);
-  c.d_mask = (unsigned*)(state + SL.d_mask); c.d_list = (int32_t*)(state + SL.d_list);
   c.r_base = (i128*)(state + SL.r_base);
   c.r_f16 = (int16_t*)(state + SL.r_f16); c.r_f32 = (int32_t*)(state + SL.r_f32);
   char* base = P->ws + slot * P->L.total;
@@ -1344,9 +1298,7 @@ PSB_DEV void state_init(Ctx& c) {
   } else {
     for (uint32_t i = lane(); i <= c.hmask; i += PSB_WAVE) c.h_key[i] = -1;
   }
-  const int nblk = (c.xcap + BLK - 1) / BLK;
-  for (int i = lane(); i <= nblk / 32; i += PSB_WAVE) c.d_mask[i] = 0;
-  c.S->x_n = 0; c.S->dblk_n = 0; c.S->fin_n = 0; c.S->stk_n = 0; c.S->rel_n = 0;
+  c.S->x_n = 0; c.S->fin_n = 0; c.S->stk_n = 0; c.S->rel_n = 0;
   wave_sync();
 }
 

@@ -186,15 +186,13 @@ static void tiebroken_weights(const int32_t* w, int64_t m, uint64_t seed, std::v
 
 
 // Layout of the per-shot state block for the given capacities.
-static void plan_state(psb::StateLayout& SL, const psb::Caps& cap, int blk) {
+static void plan_state(psb::StateLayout& SL, const psb::Caps& cap) {
   int64_t off = 0;
   auto take = [&](int64_t bytes) { int64_t o = off; off += (bytes + 15) & ~(int64_t)15; return o; };
   const int64_t x = cap.xcap, h = cap.hcap, r = cap.rcap;
-  const int64_t nblk = (x + blk - 1) / blk;
-  SL.x_wr = take(16 * x); SL.x_ev = take(16 * x); SL.r_base = take(16 * r); SL.blk_min = take(16 * nblk);
+  SL.x_wr = take(16 * x); SL.x_ev = take(16 * x); SL.r_base = take(16 * r);
   SL.x_node = take(4 * x); SL.x_top = take(2 * x); SL.x_reg = take(2 * x); SL.x_src = take(2 * x); SL.x_rec = take(2 * x);
   SL.h_key = take(4 * h); SL.h_val = take(4 * h);
-  SL.blk_arg = take(4 * nblk); SL.d_mask = take(4 * (nblk / 32 + 1)); SL.d_list = take(4 * nblk);
   SL.r_f32 = take(4LL * (psb::RF_COUNT - psb::RF_N16) * r);
   SL.r_f16 = take(2LL * psb::RF_N16 * r);
   SL.total = off;
@@ -207,8 +205,7 @@ static int32_t next_pow2(int64_t x) { int32_t p = 1; while (p < x) p <<= 1; retu
 // clustering hit buffers) or one lane (lane tier: the Lds header and the state
 // block sit at the start of the slot, pools are sized more tightly and a shot
 // that exceeds them is handed on).
-static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const psb::Caps& cap, bool lane_slot,
-                      int blk) {
+static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const psb::Caps& cap, bool lane_slot) {
   P.n_det = n; P.deg = deg; P.nbytes = (n + 7) / 8; P.n_edges = n_edges;
   P.cap = cap;
   const int32_t d = cap.dcap;
@@ -221,7 +218,7 @@ static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const 
   P.hitcap = 32;
   P.bdc = 8;
   P.max_events = (int64_t)64 * ((int64_t)cap.xcap + 64 * (int64_t)d);
-  plan_state(P.SL, cap, blk);
+  plan_state(P.SL, cap);
   WsLayout& L = P.L;
   int64_t off = 0;
   auto take = [&](int64_t bytes) { int64_t o = off; off = align256(off + bytes); return o; };

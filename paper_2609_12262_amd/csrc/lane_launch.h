@@ -5,4 +5,3 @@
 
 hipError_t psb_lane_launch(const psb::Params& P, unsigned waves, hipStream_t s);
 hipError_t psb_lane_occupancy(int* waves_per_cu);
-int psb_lane_block();

@@ -9,7 +9,6 @@
 #include "psb_types.h"
 #include "lane_wave.h"
 #define PSB_ENGINE_NS engine_lane
-#define PSB_BLK 16
 #include "engine.h"
 #include "lane_launch.h"
 
@@ -43,5 +42,3 @@ hipError_t psb_lane_launch(const psb::Params& P, unsigned waves, hipStream_t s) 
 hipError_t psb_lane_occupancy(int* waves_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, psb_lane_kernel, 64, 0);
 }
-
-int psb_lane_block() { return el::BLK; }

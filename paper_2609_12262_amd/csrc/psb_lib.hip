@@ -234,8 +234,8 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   cf.hcap = direct ? 0 : next_pow2(2LL * cf.xcap);
   Params& PF = D->P_fast;
   Params& PO = D->P_ovf;
-  plan_tier(PF, n, g->deg, g->n_edges, cf, D->first_lane, D->first_lane ? psb_lane_block() : ew::BLK);
-  plan_tier(PO, n, g->deg, g->n_edges, co, false, ew::BLK);
+  plan_tier(PF, n, g->deg, g->n_edges, cf, D->first_lane);
+  plan_tier(PO, n, g->deg, g->n_edges, co, false);
   for (Params* P : {&PF, &PO}) {
     P->n_levels = (int32_t)D->sched.d.size(); P->reading = opts.boundary_reading; P->mode = opts.mode;
     P->edge_stride = stride;

@@ -21,8 +21,6 @@ struct StateLayout {
   int64_t x_wr, x_ev;                            // [xcap], int128
   int64_t h_key, h_val;                          // detector -> explored index hash [hcap], int32 (hcap 0:
                                                  // the direct map of the workspace is used instead)
-  int64_t blk_min, blk_arg;                      // event-cache block minima [nblk]
-  int64_t d_mask, d_list;                        // dirty-block bitmap [nblk/32+1] and list [nblk]
   int64_t r_base, r_f16, r_f32;                  // regions: base [rcap] int128, fields [RF_N16][rcap] int16
                                                  // and [RF_COUNT - RF_N16][rcap] int32
   int64_t total;

@@ -13,6 +13,7 @@
 #define PSB_WAVE 64
 
 typedef __int128 i128;
+#define T_INF_W (((i128)1) << 124)
 
 PSB_DEV int lane() { return (int)__lane_id(); }
 
@@ -60,25 +61,60 @@ PSB_DEV i128 shfl_xor_i128(i128 v, int m) {
   return (i128)(((unsigned __int128)nhi << 64) | nlo);
 }
 
-// Wave-wide (key, arg) minimum; ties broken by the smaller arg.  All lanes
-// receive the result.
-PSB_DEV void wave_argmin(i128& key, int& arg) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    i128 k2 = shfl_xor_i128(key, m);
-    int a2 = shfl_xor_i32(arg, m);
-    if (k2 < key || (k2 == key && a2 < arg)) { key = k2; arg = a2; }
-  }
-  key = uni128(key); arg = uni(arg);
+// (key, arg) minimum steps over lane permutations inside a row of 16 lanes,
+// done with DPP moves (a VALU operand modifier) rather than LDS-routed
+// permutes.  Every pattern used here reads an active lane of the same row, so
+// no lane reads an out-of-range source.
+constexpr int DPP_QUAD_XOR1 = 0xB1;     // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7-i within each 8 lanes
+constexpr int DPP_MIRROR = 0x140;       // lane i <-> 15-i within each 16 lanes
+
+template <int CTRL> PSB_DEV int dpp_mov(int v) {
+  return __builtin_amdgcn_update_dpp(0, opq(v), CTRL, 0xF, 0xF, false);
 }
 
-// Minimum over groups of `g` consecutive lanes (g a power of two <= 64).
+PSB_DEV i128 make_i128(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  const uint64_t lo = ((uint64_t)b << 32) | a, hi = ((uint64_t)d << 32) | c;
+  return (i128)(((unsigned __int128)hi << 64) | lo);
+}
+
+template <int CTRL> PSB_DEV void argmin_step(i128& key, int& arg) {
+  const unsigned __int128 u = (unsigned __int128)key;
+  const uint64_t lo = (uint64_t)u, hi = (uint64_t)(u >> 64);
+  const i128 k2 = make_i128((uint32_t)dpp_mov<CTRL>((int)(uint32_t)lo), (uint32_t)dpp_mov<CTRL>((int)(uint32_t)(lo >> 32)),
+                            (uint32_t)dpp_mov<CTRL>((int)(uint32_t)hi), (uint32_t)dpp_mov<CTRL>((int)(uint32_t)(hi >> 32)));
+  const int a2 = dpp_mov<CTRL>(arg);
+  if (k2 < key || (k2 == key && a2 < arg)) { key = k2; arg = a2; }
+}
+
+// Minimum over aligned groups of g lanes (g a power of two <= 16); ties to the
+// smaller arg.  Every lane of the group receives its group's result.  All
+// lanes of the wavefront must call this.
 PSB_DEV void group_argmin(i128& key, int& arg, int g) {
-  for (int m = g >> 1; m >= 1; m >>= 1) {
-    i128 k2 = shfl_xor_i128(key, m);
-    int a2 = shfl_xor_i32(arg, m);
-    if (k2 < key || (k2 == key && a2 < arg)) { key = k2; arg = a2; }
+  if (g >= 2) argmin_step<DPP_QUAD_XOR1>(key, arg);
+  if (g >= 4) argmin_step<DPP_QUAD_XOR2>(key, arg);
+  if (g >= 8) argmin_step<DPP_HALF_MIRROR>(key, arg);
+  if (g >= 16) argmin_step<DPP_MIRROR>(key, arg);
+}
+
+// Wave-wide (key, arg) minimum; ties broken by the smaller arg.  The four
+// row minima are combined as scalars: the result is uniform.
+PSB_DEV void wave_argmin(i128& key, int& arg) {
+  group_argmin(key, arg, 16);
+  const unsigned __int128 u = (unsigned __int128)key;
+  const int w0 = opq((int)(uint32_t)(uint64_t)u), w1 = opq((int)(uint32_t)((uint64_t)u >> 32));
+  const int w2 = opq((int)(uint32_t)(uint64_t)(u >> 64)), w3 = opq((int)(uint32_t)((uint64_t)(u >> 64) >> 32));
+  const int av = opq(arg);
+  i128 bk = T_INF_W; int ba = 0x7fffffff;
+#pragma unroll
+  for (int row = 0; row < 4; ++row) {
+    const i128 k2 = make_i128((uint32_t)__builtin_amdgcn_readlane(w0, 16 * row), (uint32_t)__builtin_amdgcn_readlane(w1, 16 * row),
+                              (uint32_t)__builtin_amdgcn_readlane(w2, 16 * row), (uint32_t)__builtin_amdgcn_readlane(w3, 16 * row));
+    const int a2 = __builtin_amdgcn_readlane(av, 16 * row);
+    if (row == 0 || k2 < bk || (k2 == bk && a2 < ba)) { bk = k2; ba = a2; }
   }
+  key = bk; arg = ba;
 }
 
 PSB_DEV int wave_sum(int v) {
