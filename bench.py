@@ -152,7 +152,8 @@ def main():
                                f"p=q={args.p}, {args.shots} shots per step, one persistent launch",
                    "d": args.d, "rounds": args.d, "p": args.p, "shots_per_step": args.shots,
                    "mode": "partition-and-fuse" if args.mode == 0 else "global sparse blossom",
-                   "slots": dec.__dict__.get("slots", args.slots or 2048)},
+                   "first_tier_slots": dec.fast_slots, "overflow_tier_slots": dec.overflow_slots,
+                   "overflow_shots": dec.last_overflow()},
         "latency_us_per_round": {"p50": round(float(np.percentile(per_round, 50)), 3),
                                  "p99": round(float(np.percentile(per_round, 99)), 3),
                                  "basis": "batch submission to shot completion (device clock), last step"},

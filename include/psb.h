@@ -85,9 +85,10 @@ typedef struct {
                                      (lane tier: at most 65536 lanes) */
   /* First tier, for shots that reach at most fast_max_nodes detectors and
    * create at most fast_max_regions regions (fast_max_nodes < 0 disables the
-   * tier).  first_tier = 0 (default): one shot per wavefront, per-shot state
-   * in LDS (0 = 256 / 192); first_tier = 1: one shot per lane, per-shot state
-   * in a global workspace slot of the lane (0 = 320 / 256).  Shots beyond these
+   * tier).  first_tier = 0 (default): one shot per wavefront, the per-shot
+   * state touched on every event in LDS, the rest in the wavefront's global
+   * workspace slot (0 = 320 / 208); first_tier = 1: one shot per lane, the
+   * per-shot state in the lane's global workspace slot (0 = 320 / 256).  Shots beyond these
    * bounds are decoded by the overflow tier (one shot per wavefront, up to
    * 1024 detectors and 768 regions per shot in LDS, overflow_slots shots in
    * flight, 0 = chosen from the device) within the same psb_decode_batch

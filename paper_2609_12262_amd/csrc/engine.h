@@ -173,9 +173,9 @@ PSB_DEV void next_event(Ctx& c, i128& t, int& code) {
     const i128 k = c.x_ev[i];
     if (k < key) { key = k; arg = EV_NODE + i; }
   }
-  for (int q = lane(); q < c.n_shr; q += PSB_WAVE) {
-    const int x = c.shr[q];
-    if (RF(c, x, RF_ALIVE) && RF(c, x, RF_BPAR) < 0 && RF(c, x, RF_RATE) < 0) {
+  // regions: only once some region has been inner in this shot
+  for (int x = lane(); c.n_shr > 0 && x < c.n_regions; x += PSB_WAVE) {
+    if (RF(c, x, RF_RATE) < 0 && RF(c, x, RF_BPAR) < 0 && RF(c, x, RF_ALIVE)) {
       const i128 k = c.r_base[x];
       if (k < key || (k == key && x < arg)) { key = k; arg = x; }
     }
@@ -344,11 +344,7 @@ PSB_DEV void set_rate(Ctx& c, int r, int rate) {
   const i128 y = yrad(c, r, c.now);
   c.r_base[r] = y - (i128)rate * c.now;
   RF(c, r, RF_RATE) = rate;
-  if (rate < 0 && !uni(RF(c, r, RF_INSHR))) {
-    if (c.n_shr >= c.P->shrcap) { cap_fail(c); return; }
-    RF(c, r, RF_INSHR) = 1;
-    c.shr[c.n_shr++] = r;
-  }
+  if (rate < 0) c.n_shr = 1;                 // region events are possible from now on
   note_change(c, r);
 }
 
@@ -1275,12 +1271,14 @@ PSB_DEV void ctx_init(Ctx& c, const Params* P, Lds* S, char* state, int64_t slot
   const StateLayout& SL = P->SL;
   c.x_node = (int32_t*)(state + SL.x_node); c.x_top = (int16_t*)(state + SL.x_top);
   c.x_reg = (int16_t*)(state + SL.x_reg); c.x_src = (int16_t*)(state + SL.x_src);
-  c.x_rec = (int16_t*)(state + SL.x_rec); c.x_wr = (i128*)(state + SL.x_wr); c.x_ev = (i128*)(state + SL.x_ev);
+  c.x_rec = (int16_t*)(state + SL.x_rec);
   c.h_key = (int32_t*)(state + SL.h_key); c.h_val = (int32_t*)(state + SL.h_val);
-  c.r_base = (i128*)(state + SL.r_base);
-  c.r_f16 = (int16_t*)(state + SL.r_f16); c.r_f32 = (int32_t*)(state + SL.r_f32);
   char* base = P->ws + slot * P->L.total;
   const WsLayout& L = P->L;
+  c.x_ev = SL.x_ev >= 0 ? (i128*)(state + SL.x_ev) : (i128*)(base + L.x_ev);
+  c.x_wr = SL.x_wr >= 0 ? (i128*)(state + SL.x_wr) : (i128*)(base + L.x_wr);
+  c.r_base = SL.r_base >= 0 ? (i128*)(state + SL.r_base) : (i128*)(base + L.r_base);
+  c.r_f16 = (int16_t*)(state + SL.r_f16); c.r_f32 = (int32_t*)(state + SL.r_f32);
   c.ce = (int32_t*)(base + L.ce); c.bc = (int32_t*)(base + L.bc); c.lg = (int32_t*)(base + L.lg);
   c.level = (int8_t*)(base + L.level);
   c.uf = (int32_t*)(base + L.uf); c.cl_a = (int32_t*)(base + L.cl_a); c.cl_b = (int32_t*)(base + L.cl_b);
@@ -1291,7 +1289,7 @@ PSB_DEV void ctx_init(Ctx& c, const Params* P, Lds* S, char* state, int64_t slot
   c.dmap = P->cap.hcap == 0 ? (int16_t*)(base + L.dmap) : nullptr;
 }
 
-// Fresh state block: empty hash, clean dirty-block bitmap.
+// Fresh state block: empty detector map or hash, zero scalars.
 PSB_DEV void state_init(Ctx& c) {
   if (c.dmap) {
     for (int i = lane(); i < c.n_det; i += PSB_WAVE) c.dmap[i] = -1;

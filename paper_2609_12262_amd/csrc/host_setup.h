@@ -186,11 +186,16 @@ static void tiebroken_weights(const int32_t* w, int64_t m, uint64_t seed, std::v
 
 
 // Layout of the per-shot state block for the given capacities.
-static void plan_state(psb::StateLayout& SL, const psb::Caps& cap) {
+// lean >= 1: the event cache and the region bases go to the workspace;
+// lean >= 2: the explored nodes' radius offsets too.  Each shrinks the LDS
+// block by 16 bytes per node or region.
+static void plan_state(psb::StateLayout& SL, const psb::Caps& cap, int lean) {
   int64_t off = 0;
   auto take = [&](int64_t bytes) { int64_t o = off; off += (bytes + 15) & ~(int64_t)15; return o; };
   const int64_t x = cap.xcap, h = cap.hcap, r = cap.rcap;
-  SL.x_wr = take(16 * x); SL.x_ev = take(16 * x); SL.r_base = take(16 * r);
+  SL.x_wr = lean >= 2 ? -1 : take(16 * x);
+  SL.x_ev = lean >= 1 ? -1 : take(16 * x);
+  SL.r_base = lean >= 1 ? -1 : take(16 * r);
   SL.x_node = take(4 * x); SL.x_top = take(2 * x); SL.x_reg = take(2 * x); SL.x_src = take(2 * x); SL.x_rec = take(2 * x);
   SL.h_key = take(4 * h); SL.h_val = take(4 * h);
   SL.r_f32 = take(4LL * (psb::RF_COUNT - psb::RF_N16) * r);
@@ -205,7 +210,8 @@ static int32_t next_pow2(int64_t x) { int32_t p = 1; while (p < x) p <<= 1; retu
 // clustering hit buffers) or one lane (lane tier: the Lds header and the state
 // block sit at the start of the slot, pools are sized more tightly and a shot
 // that exceeds them is handed on).
-static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const psb::Caps& cap, bool lane_slot) {
+static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const psb::Caps& cap, bool lane_slot,
+                      int lean = 0) {
   P.n_det = n; P.deg = deg; P.nbytes = (n + 7) / 8; P.n_edges = n_edges;
   P.cap = cap;
   const int32_t d = cap.dcap;
@@ -218,7 +224,7 @@ static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const 
   P.hitcap = 32;
   P.bdc = 8;
   P.max_events = (int64_t)64 * ((int64_t)cap.xcap + 64 * (int64_t)d);
-  plan_state(P.SL, cap);
+  plan_state(P.SL, cap, lean);
   WsLayout& L = P.L;
   int64_t off = 0;
   auto take = [&](int64_t bytes) { int64_t o = off; off = align256(off + bytes); return o; };
@@ -230,6 +236,9 @@ static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const 
   L.shr = take(4LL * P.shrcap); L.chg = take(4LL * cap.xcap); L.stk = take(4LL * P.stkcap);
   L.fin = take(4LL * P.fincap); L.ebits = take(4 * ((n_edges + 31) / 32 + 1));
   L.dmap = cap.hcap == 0 ? take(2LL * n) : 0;
+  L.x_ev = lean >= 1 ? take(16LL * cap.xcap) : 0;
+  L.r_base = lean >= 1 ? take(16LL * cap.rcap) : 0;
+  L.x_wr = lean >= 2 ? take(16LL * cap.xcap) : 0;
   L.total = off;
 }
 

@@ -51,10 +51,12 @@ __global__ void psb_zero_kernel(int32_t* p, int n, uint64_t* t_start) {
 
 // Persistent decode kernel, one wavefront per shot, per-shot state in LDS.
 // TIER 0 (small capacities, many waves per CU) hands shots that exceed its
-// capacities to the overflow list; TIER 1 (large capacities, one wave per
-// CU) decodes either that list (ovf_list != null) or every shot directly.
+// capacities to the overflow list; TIER 1 (large capacities, a few waves
+// per CU) decodes either that list (ovf_list != null) or every shot directly.
+// At most 128 VGPRs, so that four wavefronts share a SIMD (the per-shot
+// event loop is latency-bound: throughput grows with resident wavefronts).
 template <int TIER>
-__global__ __launch_bounds__(64) void psb_decode_kernel(Params P) {
+__global__ __launch_bounds__(64, 4) void psb_decode_kernel(Params P) {
   extern __shared__ __align__(16) char psb_dyn_lds[];
   ew::Lds* S = (ew::Lds*)psb_dyn_lds;
   char* state = psb_dyn_lds + 64;
@@ -228,13 +230,16 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   const bool direct = n <= 32768;
   co.dcap = std::min(std::min(co.xcap, co.rcap), dcap); co.hcap = direct ? 0 : next_pow2(2LL * co.xcap);
   D->fast_enabled = opts.fast_max_nodes >= 0;
-  cf.xcap = std::min(n, opts.fast_max_nodes > 0 ? opts.fast_max_nodes : (D->first_lane ? 320 : 256));
-  cf.rcap = opts.fast_max_regions > 0 ? opts.fast_max_regions : (D->first_lane ? 256 : 192);
+  cf.xcap = std::min(n, opts.fast_max_nodes > 0 ? opts.fast_max_nodes : 320);
+  cf.rcap = opts.fast_max_regions > 0 ? opts.fast_max_regions : (D->first_lane ? 256 : 208);
   cf.dcap = std::min(std::min(cf.xcap, cf.rcap), dcap);
   cf.hcap = direct ? 0 : next_pow2(2LL * cf.xcap);
   Params& PF = D->P_fast;
   Params& PO = D->P_ovf;
-  plan_tier(PF, n, g->deg, g->n_edges, cf, D->first_lane);
+  // the wavefront first tier keeps its event cache, region bases and radius
+  // offsets in the workspace: its LDS block (about 10 KB at the default
+  // capacities) lets 16 wavefronts share a CU
+  plan_tier(PF, n, g->deg, g->n_edges, cf, D->first_lane, D->first_lane ? 0 : 2);
   plan_tier(PO, n, g->deg, g->n_edges, co, false);
   for (Params* P : {&PF, &PO}) {
     P->n_levels = (int32_t)D->sched.d.size(); P->reading = opts.boundary_reading; P->mode = opts.mode;

@@ -18,10 +18,11 @@ constexpr int S_OK = 0, S_CAPACITY = 1, S_INFEASIBLE = 2, S_TRUNC = 3, S_INTERNA
 struct StateLayout {
   int64_t x_node;                                // explored nodes [xcap]: detector id, int32
   int64_t x_top, x_reg, x_src, x_rec;            // [xcap], int16 (region, region, event, log record)
-  int64_t x_wr, x_ev;                            // [xcap], int128
+  int64_t x_wr, x_ev;                            // [xcap], int128 (x_ev -1: in the workspace)
   int64_t h_key, h_val;                          // detector -> explored index hash [hcap], int32 (hcap 0:
                                                  // the direct map of the workspace is used instead)
-  int64_t r_base, r_f16, r_f32;                  // regions: base [rcap] int128, fields [RF_N16][rcap] int16
+  int64_t r_base, r_f16, r_f32;                  // regions: base [rcap] int128 (-1: in the workspace),
+                                                 // fields [RF_N16][rcap] int16
                                                  // and [RF_COUNT - RF_N16][rcap] int32
   int64_t total;
 };
@@ -35,6 +36,8 @@ struct WsLayout {
   int64_t shr, chg, stk, fin, ebits;             // scratch lists, edge bitmap
   int64_t dmap;                                  // detector -> explored index [n_det] int16, -1 absent
                                                  // (only when the state block has no hash)
+  int64_t x_ev, r_base, x_wr;                    // event cache, region bases, radius offsets, when the state block
+                                                 // leaves them out (else unused)
   int64_t total;                                 // bytes per slot (multiple of 256)
 };
 
