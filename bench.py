@@ -41,6 +41,36 @@ def algorithmic_bytes(stats, nbytes, deg, n_edges_out):
     return int(b)
 
 
+def kernel_source_hash():
+    import glob
+    import hashlib
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2609_12262_amd", "csrc", "*.h"))
+                   + glob.glob(os.path.join(ROOT, "paper_2609_12262_amd", "csrc", "*.hip")))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(d, p, shots):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload,
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"psb_decode_kernel_d{d}_p{str(p).split('.')[1][:3]}_traffic.md")
+    if (d, p, shots) != (21, 0.005, 50000) or not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+                k, v = line.split(":", 1)
+                vals[k] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def cpu_oracle_baseline(g, syndromes, seed, budget_s=15.0):
     """The oracle (Dijkstra + Edmonds, plain C) on host cores, bounded sample."""
     import multiprocessing as mp
@@ -91,7 +121,21 @@ def main():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (3 times): the reference "
+                         "kernel that scales rocprof FETCH_SIZE / WRITE_SIZE readings to bytes")
     args = ap.parse_args()
+    if args.copy_calibration_mib > 0:
+        import torch
+        n = args.copy_calibration_mib << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the decoder's multi-GPU "
               "sharding is a design note, not part of this build.", file=sys.stderr)
@@ -158,7 +202,8 @@ def main():
                                  "p99": round(float(np.percentile(per_round, 99)), 3),
                                  "basis": "batch submission to shot completion (device clock), last step"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": measured_traffic(args.d, args.p, args.shots),
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(avg_launch_s * 1e3, 3),
                      "kernel": "psb_decode_kernel"},
         "work_per_shot": {"events": float(stats[:, 0].mean()), "reached": float(stats[:, 1].mean()),
