@@ -293,7 +293,8 @@ def brute_mwem_edges(g, defects, seed: int):
     minimum-weight subset whose odd-degree detectors are exactly `defects`."""
     E = g.num_edges
     assert E <= 22
-    key = (id(g), int(seed))
+    # keyed on the graph's content: an id() can be reused by a later graph
+    key = (g.u.tobytes(), g.v.tobytes(), np.asarray(g.w).tobytes(), int(seed))
     if key not in _brute_cache:
         masks = np.arange(1 << E, dtype=np.int64)
         bits = ((masks[:, None] >> np.arange(E)[None, :]) & 1).astype(np.int64)   # [2^E, E]
