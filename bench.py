@@ -109,6 +109,54 @@ def _oracle_chunk(rows):
     return len(rows)
 
 
+def latency_scaling(args):
+    """One shot per launch (the whole GPU holds one shot): per-round latency from launch to completion, per d."""
+    import torch
+    import synth
+    import paper_2609_12262_amd as psb
+    p = args.p if args.p != 0.005 else 0.001
+    rows = []
+    for d in [int(x) for x in args.latency.split(",")]:
+        g = synth.rotated_phenom_graph(d, p)
+        shots = synth.sample(g, args.latency_shots, seed=10 + d)
+        G = psb.Graph.from_synth(g)
+        dec = psb.Decoder(G, tiebreak_seed=0x5EED, mode=args.mode)
+        synd = torch.from_numpy(shots.syndromes).cuda()
+        out = dec.alloc(1, timestamps=True)
+        stream = torch.cuda.current_stream()
+        for i in range(min(3, args.latency_shots)):          # warm-up launches
+            dec.decode_into(synd[i:i + 1], out)
+        torch.cuda.synchronize()
+        ev_ms, dev_us, ovf = [], [], 0
+        for i in range(args.latency_shots):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            dec.decode_into(synd[i:i + 1], out)
+            b.record(stream)
+            b.synchronize()
+            ev_ms.append(a.elapsed_time(b))
+            td = out.t_done.cpu().numpy().astype(np.int64)
+            dev_us.append((td[0] - td[1]) / DEVICE_CLOCK_HZ * 1e6)
+            ovf += dec.last_overflow()
+            if out.status.cpu().numpy()[0] != 0:
+                log(f"WARNING: d={d} shot {i} status {out.status.cpu().numpy()[0]}")
+        ev_us = np.array(ev_ms) * 1e3
+        dev_us = np.array(dev_us)
+        rows.append({"d": d, "rounds": d, "detectors": g.num_detectors, "shots": args.latency_shots,
+                     "defects_mean": float(np.unpackbits(shots.syndromes, axis=1, bitorder="little")
+                                           [:, :g.num_detectors].sum(1).mean()),
+                     "overflow_tier_shots": ovf,
+                     "us_per_round_launch_p50": round(float(np.percentile(ev_us, 50)) / d, 3),
+                     "us_per_round_launch_p99": round(float(np.percentile(ev_us, 99)) / d, 3),
+                     "us_per_round_device_p50": round(float(np.percentile(dev_us, 50)) / d, 3),
+                     "us_per_round_device_p99": round(float(np.percentile(dev_us, 99)) / d, 3)})
+        log(f"d={d}: {rows[-1]}")
+        dec.close(); G.close()
+    print(json.dumps({"metric": "one-shot-per-launch latency, us per round", "p": p, "mode": args.mode,
+                      "basis": "launch = HIP events around the launch on its stream; device = kernel start stamp "
+                               "to shot completion (device clock)", "per_d": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,7 +172,17 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (3 times): the reference "
                          "kernel that scales rocprof FETCH_SIZE / WRITE_SIZE readings to bytes")
+    ap.add_argument("--latency", type=str, default="",
+                    help="latency-scaling mode: comma-separated distances (e.g. 11,21,31,41,51); every shot is "
+                         "decoded alone, one launch per shot, at p=q=--p (default 0.001 in this mode)")
+    ap.add_argument("--latency-shots", type=int, default=200)
     args = ap.parse_args()
+    if args.latency:
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        latency_scaling(args)
+        return
     if args.copy_calibration_mib > 0:
         import torch
         n = args.copy_calibration_mib << 20

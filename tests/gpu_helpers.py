@@ -78,3 +78,30 @@ def valid_embedded(g, syndromes, res, chunk=2000):
         diff = np.nonzero((par != want).any(1))[0]
         bad.extend((s0 + diff).tolist())
     return bad
+
+
+_PAR = None
+
+
+def _par_init(g, seed, syndromes, res):
+    global _PAR
+    _PAR = (g, seed, syndromes, res)
+
+
+def _par_chunk(idx):
+    g, seed, syndromes, res = _PAR
+    return compare(g, syndromes, res, idx, seed)
+
+
+def compare_parallel(g, syndromes, res, idx, seed=SEED, workers=16, chunk=64):
+    """compare() spread over host processes (forked; the children only run the CPU oracle)."""
+    import multiprocessing as mp
+    idx = list(idx)
+    parts = [idx[i:i + chunk] for i in range(0, len(idx), chunk)]
+    ctx = mp.get_context("fork")
+    keep = {k: res[k] for k in ("edges", "n_edges", "weight", "obs", "status")}
+    with ctx.Pool(min(workers, len(parts)), initializer=_par_init, initargs=(g, seed, syndromes, keep)) as pool:
+        bad = []
+        for b in pool.imap(_par_chunk, parts):
+            bad.extend(b)
+    return bad

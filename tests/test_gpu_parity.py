@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import SEED, compare, gpu_decode, say, valid_embedded
+from gpu_helpers import SEED, compare, compare_parallel, gpu_decode, say, valid_embedded
 
 pytestmark = pytest.mark.gpu
 
@@ -249,3 +249,28 @@ def test_lane_tier_equals_wave_tier_d21():
         assert np.array_equal(a[k], b[k]), k
     m = np.arange(a["edges"].shape[1])[None, :] < a["n_edges"][:, None]
     assert np.array_equal(np.where(m, a["edges"], 0), np.where(m, b["edges"], 0))
+
+
+def test_d11_config_100k_every_shot():
+    """d=11, p=q=0.003: 100,000 shots in one persistent launch, every shot
+    against the oracle."""
+    g = synth.rotated_phenom_graph(11, 0.003)
+    s = synth.sample(g, 100000, seed=2)
+    say("d11: decoding 100000 shots")
+    res = gpu_decode(g, s.syndromes)
+    say("d11: comparing 100000 shots with the oracle")
+    bad = compare_parallel(g, s.syndromes, res, range(100000))
+    assert not bad, bad[:5]
+
+
+def test_hash_map_large_graph_d41():
+    """A graph above 32,768 detectors (d=41: 35,280) uses the per-shot hash
+    instead of the direct detector map; shots of about 200 detection events
+    go through both tiers."""
+    g = synth.rotated_phenom_graph(41, 0.001)
+    s = synth.sample(g, 32, seed=51)
+    say("d41: decoding 32 shots")
+    res = gpu_decode(g, s.syndromes, want_overflow=True)
+    say(f"d41: {res['n_overflow']} shots on the overflow tier; comparing with the oracle")
+    bad = compare_parallel(g, s.syndromes, res, range(32), chunk=2)
+    assert not bad, bad[:5]
