@@ -144,6 +144,9 @@ int32_t psb_schedule_levels(uint64_t wmax_hi, uint64_t wmax_lo, uint64_t diam_hi
                             int32_t max_levels, uint64_t* d_hi, uint64_t* d_lo, uint64_t* b_hi,
                             uint64_t* b_lo, int32_t* final_level);
 
+/* Device memory the decoder holds (workspaces, weights, schedule), in bytes. */
+int32_t psb_decoder_device_bytes(const psb_decoder* d, int64_t* bytes);
+
 /* Shots in flight per tier and the fast tier's LDS bytes per shot. */
 int32_t psb_decoder_slots(const psb_decoder* d, int32_t* fast_slots, int32_t* overflow_slots,
                           int32_t* fast_lds_bytes);
@@ -156,6 +159,46 @@ int32_t psb_decoder_last_overflow(psb_decoder* d, void* stream, int32_t* n_overf
 int32_t psb_decoder_edges_per_shot(const psb_decoder* d);
 int32_t psb_decoder_max_defects(const psb_decoder* d);
 int32_t psb_graph_syndrome_bytes(const psb_graph* g);
+
+/* ---------------------------------------------------------------------
+ * Serving (windows arriving one at a time while others decode).
+ *
+ * A server owns one decoder per graph (built with `opts`; edges_per_shot 0
+ * selects 1024 here) plus, on first use, one per graph for requests that
+ * carry a uniform per-request weight.  A worker thread groups pending
+ * requests of the same (graph, weight set) into one psb_decode_batch launch
+ * on that group's stream (a stream of its own, or `stream` for every group
+ * when it is not NULL), copies results to pinned host memory and completes
+ * the tickets.  Each result is identical to psb_decode_batch on that window
+ * alone: the decoding of a shot does not depend on the other shots of its
+ * batch (Results, "Decoding task": every window is an independent MWEM).
+ * device_mem_budget > 0 bounds the bytes of decoders and batch buffers
+ * (batches shrink to fit; PSB_E_NOMEM if a 64-shot batch does not).
+ * All calls are thread-safe; one server per device.
+ * Errors: PSB_E_INVALID, PSB_E_NOMEM, PSB_E_DEVICE, PSB_E_UNSUPPORTED. */
+typedef struct psb_server psb_server;
+int32_t psb_server_create(const psb_graph* const* graphs, int32_t n_graphs, const psb_decoder_opts* opts,
+                          int64_t device_mem_budget, void* stream, psb_server** out);
+/* Queues one window: syndrome_host [ceil(num_detectors/8)] bytes (host
+ * memory, copied before the call returns).  w_override: NULL (the graph's
+ * weights) or [num_edges] int32 holding one positive weight for every edge
+ * (the MWEM under a uniform weight does not depend on its value, so the
+ * window decodes on the unit-weight decoder and its weight is scaled);
+ * non-uniform overrides return PSB_E_UNSUPPORTED.  *ticket identifies the
+ * request. */
+int32_t psb_server_submit(psb_server* s, int32_t graph_idx, const uint8_t* syndrome_host,
+                          const int32_t* w_override, uint64_t* ticket);
+/* Non-blocking: *done = 0 while the window is pending; once done, copies the
+ * results to the host pointers (any may be NULL; edges gets at most
+ * edges_cap ids, status PSB_S_EDGES_TRUNCATED if more exist), writes the
+ * submit-to-completion time in nanoseconds to *latency_ns and releases the
+ * ticket. */
+int32_t psb_server_poll(psb_server* s, uint64_t ticket, int32_t* done, int64_t* weight, uint64_t* obs,
+                        int32_t* edges, int64_t edges_cap, int64_t* n_edges, int32_t* status,
+                        int64_t* latency_ns);
+/* Stops the worker after its running batches and frees everything;
+ * uncollected tickets are dropped. */
+int32_t psb_server_destroy(psb_server* s);
 
 const char* psb_last_error(void);
 

@@ -53,7 +53,8 @@ def lib():
         for name in ("psb_graph_create", "psb_graph_destroy", "psb_decoder_create", "psb_decoder_destroy",
                      "psb_decode_batch", "psb_decoder_levels", "psb_decoder_edges_per_shot",
                      "psb_decoder_max_defects", "psb_graph_syndrome_bytes", "psb_schedule_levels",
-                     "psb_decoder_slots", "psb_decoder_last_overflow"):
+                     "psb_decoder_slots", "psb_decoder_last_overflow", "psb_decoder_device_bytes",
+                     "psb_server_create", "psb_server_submit", "psb_server_poll", "psb_server_destroy"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -203,6 +204,60 @@ class Decoder:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().psb_decoder_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """psb_server: windows submitted one at a time while earlier ones decode."""
+
+    def __init__(self, graphs, opts: dict = None, device_mem_budget: int = 0, stream=None):
+        o = opts or {}
+        self.graphs = list(graphs)
+        c = _DecoderOpts(o.get("q", (1, 10))[0], o.get("q", (1, 10))[1], o.get("phi_min", (1, 100))[0],
+                         o.get("phi_min", (1, 100))[1], o.get("tiebreak_seed", 0x5EED) & ((1 << 64) - 1),
+                         o.get("mode", MODE_PARTITION), o.get("boundary_reading", 0), o.get("max_defects", 0),
+                         o.get("edges_per_shot", 0), o.get("num_slots", 0), o.get("fast_max_nodes", 0),
+                         o.get("fast_max_regions", 0), o.get("overflow_slots", 0), o.get("first_tier", 0))
+        arr = (ctypes.c_void_p * len(self.graphs))(*[g._h.value for g in self.graphs])
+        h = ctypes.c_void_p()
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else ctypes.c_void_p(0)
+        _check(lib().psb_server_create(arr, ctypes.c_int32(len(self.graphs)), ctypes.byref(c),
+                                       ctypes.c_int64(device_mem_budget), s, ctypes.byref(h)), "psb_server_create")
+        self._h = h
+
+    def submit(self, graph_idx: int, syndrome, w_override=None) -> int:
+        syn = np.ascontiguousarray(syndrome, np.uint8)
+        t = ctypes.c_uint64()
+        wp = ctypes.c_void_p(0)
+        if w_override is not None:
+            w_override = np.ascontiguousarray(w_override, np.int32)
+            wp = ctypes.c_void_p(w_override.ctypes.data)
+        _check(lib().psb_server_submit(self._h, ctypes.c_int32(graph_idx), ctypes.c_void_p(syn.ctypes.data), wp,
+                                       ctypes.byref(t)), "psb_server_submit")
+        return t.value
+
+    def poll(self, ticket: int, edges_cap: int = 1024):
+        """None while pending, else dict(weight, obs, edges, status, latency_ns)."""
+        done = ctypes.c_int32(); w = ctypes.c_int64(); ob = ctypes.c_uint64(); ne = ctypes.c_int64()
+        st = ctypes.c_int32(); lat = ctypes.c_int64()
+        edges = np.zeros(max(edges_cap, 1), np.int32)
+        _check(lib().psb_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(w),
+                                     ctypes.byref(ob), ctypes.c_void_p(edges.ctypes.data), ctypes.c_int64(edges_cap),
+                                     ctypes.byref(ne), ctypes.byref(st), ctypes.byref(lat)), "psb_server_poll")
+        if not done.value:
+            return None
+        return dict(weight=w.value, obs=ob.value, edges=edges[: min(ne.value, edges_cap)].copy(), n_edges=ne.value,
+                    status=st.value, latency_ns=lat.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().psb_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -164,6 +164,18 @@ extern "C" int32_t psb_graph_destroy(psb_graph* g) {
 
 extern "C" int32_t psb_graph_syndrome_bytes(const psb_graph* g) { return g ? (g->n_det + 7) / 8 : -1; }
 
+// For the serving runtime: the same graph with every weight 1 (requests with
+// one uniform weight decode on it; their reported weight is scaled), and the
+// edge count.
+int32_t psb_graph_unit_copy(const psb_graph* g, psb_graph** out) {
+  std::vector<int32_t> w1(g->n_edges, 1);
+  psb_graph_desc d{};
+  d.num_detectors = g->n_det; d.num_edges = g->n_edges;
+  d.u = g->u.data(); d.v = g->v.data(); d.w = w1.data(); d.obs_mask = g->obs.data();
+  return psb_graph_create(&d, out);
+}
+int64_t psb_graph_edges(const psb_graph* g) { return g->n_edges; }
+
 // ---------------------------------------------------------------------------
 // decoder
 // ---------------------------------------------------------------------------
@@ -352,6 +364,15 @@ extern "C" int32_t psb_decoder_levels(const psb_decoder* D, int32_t max_levels, 
 }
 
 extern "C" int32_t psb_decoder_edges_per_shot(const psb_decoder* D) { return D ? D->edge_stride : -1; }
+
+extern "C" int32_t psb_decoder_device_bytes(const psb_decoder* D, int64_t* bytes) {
+  if (!D || !bytes) return fail(PSB_E_INVALID, "null argument");
+  int64_t b = (int64_t)D->P_ovf.L.total * D->slots_ovf + 16LL * D->g->n_det * D->g->deg + 256;
+  if (D->fast_enabled) b += (int64_t)D->P_fast.L.total * D->slots_fast;
+  b += 4 * D->ovf_list_cap;
+  *bytes = b;
+  return PSB_OK;
+}
 extern "C" int32_t psb_decoder_max_defects(const psb_decoder* D) { return D ? D->dcap : -1; }
 
 extern "C" int32_t psb_decoder_slots(const psb_decoder* D, int32_t* fast_slots, int32_t* overflow_slots,

@@ -274,3 +274,49 @@ def test_hash_map_large_graph_d41():
     say(f"d41: {res['n_overflow']} shots on the overflow tier; comparing with the oracle")
     bad = compare_parallel(g, s.syndromes, res, range(32), chunk=2)
     assert not bad, bad[:5]
+
+
+def test_server_windows_equal_oracle():
+    """Serving: windows of three graphs, some with a uniform per-request
+    weight, submitted one at a time and polled; every result equals the
+    oracle on that window alone (with the request's weights)."""
+    import time
+    import paper_2609_12262_amd as psb
+    gs = [synth.rotated_phenom_graph(d, 0.005) for d in (5, 9, 13)]
+    Gs = [psb.Graph.from_synth(g) for g in gs]
+    srv = psb.Server(Gs)
+    rng = np.random.default_rng(61)
+    reqs = []
+    for j in range(600):
+        k = int(rng.integers(0, 3))
+        g = gs[k]
+        row = synth.sample(g, 1, seed=1000 + j).syndromes[0]
+        w = None
+        if j % 3 == 0:
+            p = float(rng.uniform(0.001, 0.007))
+            w = np.full(g.num_edges, synth.weight_from_p(p), np.int32)
+        reqs.append((k, row, w, srv.submit(k, row, w)))
+    say("server: 600 windows submitted")
+    results = {}
+    t0 = time.time()
+    while len(results) < len(reqs) and time.time() - t0 < 60:
+        for (k, row, w, t) in reqs:
+            if t not in results:
+                r = srv.poll(t)
+                if r is not None:
+                    results[t] = r
+    srv.close()
+    assert len(results) == len(reqs)
+    oracles = {}
+    for (k, row, w, t) in reqs:
+        g = gs[k]
+        if w is not None:
+            g = synth.DetectorGraph(g.num_detectors, g.u, g.v, w, g.obs_mask, g.p)
+        key = (k, None if w is None else int(w[0]))
+        if key not in oracles:
+            oracles[key] = oracle.Graph(g, SEED)
+        ref = oracles[key].mwem(synth.defects_of(row, g.num_detectors))
+        r = results[t]
+        assert r["status"] == 0, (k, r)
+        assert r["edges"].tolist() == ref.edges.tolist() and r["weight"] == ref.weight and r["obs"] == ref.obs
+        assert r["latency_ns"] > 0
