@@ -44,8 +44,10 @@ def algorithmic_bytes(stats, nbytes, deg, n_edges_out):
 def kernel_source_hash():
     import glob
     import hashlib
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2609_12262_amd", "csrc", "*.h"))
-                   + glob.glob(os.path.join(ROOT, "paper_2609_12262_amd", "csrc", "*.hip")))
+    csrc = os.path.join(ROOT, "paper_2609_12262_amd", "csrc")
+    # the decode kernels, their headers and the host code that lays out their state (not the serving runtime)
+    files = sorted(glob.glob(os.path.join(csrc, "*.h"))
+                   + [os.path.join(csrc, f) for f in ("psb_lib.hip", "psb_lane.hip")])
     h = hashlib.sha256()
     for f in files:
         h.update(os.path.basename(f).encode())
@@ -157,6 +159,85 @@ def latency_scaling(args):
                                "to shot completion (device clock)", "per_d": rows}), flush=True)
 
 
+def serving(args):
+    """Windows arrive one at a time (Poisson) at a mixed set of distances and noise rates; the server batches
+    them per graph.  Latency per window = submit to completion (server clock), reported per round."""
+    import torch
+    import synth
+    import paper_2609_12262_amd as psb
+    rng = np.random.default_rng(6)
+    ds = [9, 13, 17, 21, 25]
+    gs = [synth.rotated_phenom_graph(d, 0.004) for d in ds]
+    n = args.serve
+    kind = rng.integers(0, len(ds), n)
+    ps = rng.uniform(0.001, 0.007, n)
+    log(f"sampling {n} windows")
+    rows, ws = [], []
+    for i in range(n):
+        g = gs[kind[i]]
+        gp = synth.DetectorGraph(g.num_detectors, g.u, g.v, g.w, g.obs_mask, np.full(g.num_edges, ps[i]))
+        rows.append(synth.sample(gp, 1, seed=5000 + i).syndromes[0])
+        ws.append(np.full(g.num_edges, synth.weight_from_p(float(ps[i])), np.int32))
+    Gs = [psb.Graph.from_synth(g) for g in gs]
+    srv = psb.Server(Gs)
+    import ctypes
+    psb.lib()
+    rep = ctypes.CDLL(os.path.join(ROOT, "paper_2609_12262_amd", "libpsb_replay.so"))
+    rep.psb_replay.restype = ctypes.c_int32
+    rows = [np.ascontiguousarray(r) for r in rows]
+    syn_ptrs = (ctypes.c_void_p * n)(*[r.ctypes.data for r in rows])
+    w_ptrs = (ctypes.c_void_p * n)(*[w.ctypes.data for w in ws])
+    gidx = np.ascontiguousarray(kind, np.int32)
+
+    def run(arrivals):
+        lat = np.zeros(n, np.int64)
+        st = np.zeros(n, np.int32)
+        span, wall = ctypes.c_double(), ctypes.c_double()
+        arr = None if arrivals is None else np.ascontiguousarray(arrivals, np.float64)
+        rc = rep.psb_replay(srv._h, ctypes.c_int64(n), ctypes.c_void_p(gidx.ctypes.data), syn_ptrs, w_ptrs,
+                            ctypes.c_void_p(arr.ctypes.data) if arr is not None else ctypes.c_void_p(0),
+                            ctypes.c_void_p(lat.ctypes.data), ctypes.c_void_p(st.ctypes.data),
+                            ctypes.byref(span), ctypes.byref(wall))
+        if rc != 0:
+            raise RuntimeError(f"psb_replay failed ({rc})")
+        if not (st == 0).all():
+            log(f"WARNING: statuses {np.bincount(st)}")
+        return lat, span.value, wall.value
+
+    run(None)                                             # warm-up: builds the unit-weight decoders
+    s0 = srv.stats()
+    lat, _, wall = run(None)
+    s1 = srv.stats()
+    capacity = n / wall
+    rate = args.serve_load * capacity
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
+    log(f"capacity {capacity:.0f} windows/s; offering {rate:.0f} windows/s")
+    lat, t_sub, wall = run(arrivals)
+    s2 = srv.stats()
+    offered = n / t_sub
+
+    def delta(a, b):
+        nb, nw = b["batches"] - a["batches"], b["windows"] - a["windows"]
+        return {"batches": nb, "mean_batch": round(nw / max(nb, 1), 1),
+                "mean_queue_us": round((b["mean_queue_us"] * b["windows"] - a["mean_queue_us"] * a["windows"]) / max(nw, 1), 1),
+                "mean_batch_run_us": round((b["mean_batch_run_us"] * b["batches"] - a["mean_batch_run_us"] * a["batches"]) / max(nb, 1), 1),
+                "mean_launch_us": round((b["mean_launch_us"] * b["batches"] - a["mean_launch_us"] * a["batches"]) / max(nb, 1), 1)}
+    per_round = lat / 1e3 / np.asarray(ds)[kind]
+    srv.close()
+    out = {"metric": "serving: window latency, us per round (submit to completion)", "windows": n,
+           "distances": ds, "p_range": [0.001, 0.007], "capacity_windows_per_s": round(capacity, 1),
+           "target_load": args.serve_load, "offered_windows_per_s": round(offered, 1),
+           "p50_us_per_round": round(float(np.percentile(per_round, 50)), 3),
+           "p99_us_per_round": round(float(np.percentile(per_round, 99)), 3),
+           "per_d": {str(d): {"p50_us_per_round": round(float(np.percentile(per_round[kind == j], 50)), 3),
+                              "p99_us_per_round": round(float(np.percentile(per_round[kind == j], 99)), 3)}
+                     for j, d in enumerate(ds)},
+           "server_capacity_run": delta(s0, s1), "server_load_run": delta(s1, s2),
+           "driver": "native replay thread (libpsb_replay.so): submits at the arrival times, a second thread "
+                     "collects completions"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,7 +257,15 @@ def main():
                     help="latency-scaling mode: comma-separated distances (e.g. 11,21,31,41,51); every shot is "
                          "decoded alone, one launch per shot, at p=q=--p (default 0.001 in this mode)")
     ap.add_argument("--latency-shots", type=int, default=200)
+    ap.add_argument("--serve", type=int, default=0,
+                    help="serving mode: this many windows with d in {9,13,17,21,25} (d rounds) and p ~ U[0.001, "
+                         "0.007] (uniform per-window weight), Poisson arrivals at --serve-load x the measured "
+                         "capacity for the mix")
+    ap.add_argument("--serve-load", type=float, default=0.7)
     args = ap.parse_args()
+    if args.serve:
+        serving(args)
+        return
     if args.latency:
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)

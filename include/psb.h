@@ -147,6 +147,15 @@ int32_t psb_schedule_levels(uint64_t wmax_hi, uint64_t wmax_lo, uint64_t diam_hi
 /* Device memory the decoder holds (workspaces, weights, schedule), in bytes. */
 int32_t psb_decoder_device_bytes(const psb_decoder* d, int64_t* bytes);
 
+/* Sizes the decoder's internal per-batch storage (the list of shots the fast
+ * tier hands to the overflow tier) for batches of up to `max_batch` shots.
+ * psb_decode_batch grows that list by itself when a larger batch comes, which
+ * synchronises the stream and frees device memory (a device-wide wait); a
+ * caller that keeps several batches in flight reserves once up front.
+ * Returns PSB_E_INVALID for max_batch < 0, PSB_E_NOMEM if allocation fails.
+ * Not safe to call while a batch of this decoder is in flight. */
+int32_t psb_decoder_reserve(psb_decoder* d, int64_t max_batch);
+
 /* Shots in flight per tier and the fast tier's LDS bytes per shot. */
 int32_t psb_decoder_slots(const psb_decoder* d, int32_t* fast_slots, int32_t* overflow_slots,
                           int32_t* fast_lds_bytes);
@@ -196,6 +205,17 @@ int32_t psb_server_submit(psb_server* s, int32_t graph_idx, const uint8_t* syndr
 int32_t psb_server_poll(psb_server* s, uint64_t ticket, int32_t* done, int64_t* weight, uint64_t* obs,
                         int32_t* edges, int64_t edges_cap, int64_t* n_edges, int32_t* status,
                         int64_t* latency_ns);
+/* Collects up to `max` finished windows in completion order without their
+ * edge lists: tickets, weights, observable masks, statuses and
+ * submit-to-completion nanoseconds (any output but tickets may be NULL);
+ * releases them and returns how many were written (0 if none is finished). */
+int32_t psb_server_collect(psb_server* s, int32_t max, uint64_t* tickets, int64_t* weight, uint64_t* obs,
+                           int32_t* status, int64_t* latency_ns);
+/* Running totals since creation, out5[5]: batches launched, windows in them,
+ * summed submit-to-launch nanoseconds over windows, summed launch-to-
+ * completion nanoseconds over batches, summed host nanoseconds spent
+ * launching batches. */
+int32_t psb_server_stats(psb_server* s, int64_t* out5);
 /* Stops the worker after its running batches and frees everything;
  * uncollected tickets are dropped. */
 int32_t psb_server_destroy(psb_server* s);

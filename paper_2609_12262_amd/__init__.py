@@ -53,8 +53,9 @@ def lib():
         for name in ("psb_graph_create", "psb_graph_destroy", "psb_decoder_create", "psb_decoder_destroy",
                      "psb_decode_batch", "psb_decoder_levels", "psb_decoder_edges_per_shot",
                      "psb_decoder_max_defects", "psb_graph_syndrome_bytes", "psb_schedule_levels",
-                     "psb_decoder_slots", "psb_decoder_last_overflow", "psb_decoder_device_bytes",
-                     "psb_server_create", "psb_server_submit", "psb_server_poll", "psb_server_destroy"):
+                     "psb_decoder_slots", "psb_decoder_last_overflow", "psb_decoder_device_bytes", "psb_decoder_reserve",
+                     "psb_server_create", "psb_server_submit", "psb_server_poll", "psb_server_collect",
+                     "psb_server_stats", "psb_server_destroy"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -192,6 +193,10 @@ class Decoder:
         out = self.alloc(syndromes.shape[0], levels, timestamps, stats, device=syndromes.device)
         return self.decode_into(syndromes, out)
 
+    def reserve(self, max_batch: int):
+        """Pre-size per-batch storage so that batches up to max_batch never reallocate."""
+        _check(lib().psb_decoder_reserve(self._h, ctypes.c_int64(int(max_batch))), "psb_decoder_reserve")
+
     def last_overflow(self, stream=None) -> int:
         """Shots of the last batch decoded by the overflow tier (synchronises)."""
         import torch
@@ -254,6 +259,14 @@ class Server:
             return None
         return dict(weight=w.value, obs=ob.value, edges=edges[: min(ne.value, edges_cap)].copy(), n_edges=ne.value,
                     status=st.value, latency_ns=lat.value)
+
+    def stats(self) -> dict:
+        """Running totals: batches, windows, mean submit-to-launch and launch-to-completion times."""
+        v = (ctypes.c_int64 * 5)()
+        _check(lib().psb_server_stats(self._h, v), "psb_server_stats")
+        b, w = max(v[0], 1), max(v[1], 1)
+        return {"batches": v[0], "windows": v[1], "mean_batch": v[1] / b, "mean_queue_us": v[2] / w / 1e3,
+                "mean_batch_run_us": v[3] / b / 1e3, "mean_launch_us": v[4] / b / 1e3}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

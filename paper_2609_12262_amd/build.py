@@ -4,6 +4,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libpsb.so")
+REPLAY = os.path.join(HERE, "libpsb_replay.so")
 SRCS = [os.path.join(HERE, "csrc", f) for f in ("psb_lib.hip", "psb_lane.hip", "psb_server.hip")]
 
 HIPCC_FLAGS = [
@@ -22,6 +23,14 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print(r.stderr)
     os.replace(tmp, LIB)
+    # load replay tool for the serving benchmark (links against libpsb.so)
+    rtmp = REPLAY + f".tmp{os.getpid()}"
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", rtmp,
+           os.path.join(HERE, "csrc", "serve_replay.cpp"), "-L" + HERE, "-lpsb", "-Wl,-rpath,$ORIGIN", "-pthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("g++ failed:\n" + r.stderr[-4000:])
+    os.replace(rtmp, REPLAY)
     return LIB
 
 

@@ -375,6 +375,20 @@ extern "C" int32_t psb_decoder_device_bytes(const psb_decoder* D, int64_t* bytes
 }
 extern "C" int32_t psb_decoder_max_defects(const psb_decoder* D) { return D ? D->dcap : -1; }
 
+extern "C" int32_t psb_decoder_reserve(psb_decoder* D, int64_t max_batch) {
+  if (!D) return fail(PSB_E_INVALID, "null decoder");
+  if (max_batch < 0 || max_batch > (int64_t)INT32_MAX) return fail(PSB_E_INVALID, "max_batch out of range");
+  if (!D->fast_enabled || D->ovf_list_cap >= max_batch) return PSB_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  if (D->d_ovf_list) (void)hipFree(D->d_ovf_list);
+  D->d_ovf_list = nullptr;
+  D->ovf_list_cap = 0;
+  if (hipMalloc((void**)&D->d_ovf_list, 4 * (size_t)std::max<int64_t>(max_batch, 1)) != hipSuccess)
+    return fail(PSB_E_NOMEM, "overflow list");
+  D->ovf_list_cap = max_batch;
+  return PSB_OK;
+}
+
 extern "C" int32_t psb_decoder_slots(const psb_decoder* D, int32_t* fast_slots, int32_t* overflow_slots,
                                      int32_t* fast_lds_bytes) {
   if (!D) return fail(PSB_E_INVALID, "null decoder");

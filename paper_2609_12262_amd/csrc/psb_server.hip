@@ -42,24 +42,37 @@ struct Request {
   Clock::time_point t_submit, t_done;
 };
 
-// One decoder (graph x weight set) with its stream and batch buffers.
-struct Group {
-  psb_graph* own_graph = nullptr;    // unit-weight copy owned by the server, else null
+// One in-flight batch: a decoder of the group's graph, its stream and batch
+// buffers (two batches of one decoder would share its per-slot workspaces,
+// so concurrent batches use separate decoders).
+struct Pipe {
   psb_decoder* dec = nullptr;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int64_t max_batch = 0;
-  int32_t nbytes = 0, stride = 0;
   uint8_t *h_synd = nullptr, *d_synd = nullptr;
   int32_t *d_edges = nullptr, *d_ne = nullptr, *d_st = nullptr;
   int64_t* d_w = nullptr; uint64_t* d_obs = nullptr;
   int32_t *h_edges = nullptr, *h_ne = nullptr, *h_st = nullptr;
   int64_t* h_w = nullptr; uint64_t* h_obs = nullptr;
   hipEvent_t done_ev = nullptr;
-  std::deque<uint64_t> pending;
   std::vector<uint64_t> inflight;
   bool busy = false;
+  Clock::time_point t_launch;
 };
+
+// Requests of one (graph, weight set): a FIFO and kPipes batches in flight.
+struct Group {
+  const psb_graph* graph = nullptr;
+  psb_graph* own_graph = nullptr;    // unit-weight copy owned by the server, else null
+  int32_t nbytes = 0, stride = 0;
+  std::deque<uint64_t> pending;
+  std::vector<std::unique_ptr<Pipe>> pipes;
+};
+
+// Pipes per group, all made with the group: making one later would wait for
+// the whole device (decoder set-up synchronises), stalling every batch in flight.
+constexpr int kPipes = 4;
 
 }  // namespace
 
@@ -71,140 +84,187 @@ struct psb_server {
   hipStream_t user_stream = nullptr;
   std::vector<std::unique_ptr<Group>> groups;    // [2 * graph + (unit weights ? 1 : 0)]
   std::unordered_map<uint64_t, Request> reqs;
+  std::deque<uint64_t> finished;                 // completion order, for psb_server_collect
   std::mutex mu;
   std::condition_variable cv;
   std::thread worker;
   bool stop = false;
   uint64_t next_ticket = 1;
   std::string worker_error;
+  // running totals reported by psb_server_stats
+  int64_t n_batches = 0, n_windows = 0, queue_ns = 0, run_ns = 0, launch_ns = 0;
 };
+
+static int64_t ns_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(b - a).count();
+}
 
 // graph accessors implemented in psb_lib.hip
 extern "C" int32_t psb_graph_syndrome_bytes(const psb_graph* g);
 int32_t psb_graph_unit_copy(const psb_graph* g, psb_graph** out);
 int64_t psb_graph_edges(const psb_graph* g);
 
-static void free_group(Group* G) {
-  if (!G) return;
-  if (G->done_ev) (void)hipEventDestroy(G->done_ev);
-  for (void* p : {(void*)G->d_synd, (void*)G->d_edges, (void*)G->d_ne, (void*)G->d_st, (void*)G->d_w, (void*)G->d_obs})
+static void free_pipe(Pipe* P) {
+  if (!P) return;
+  if (P->stream) (void)hipStreamSynchronize(P->stream);
+  if (P->done_ev) (void)hipEventDestroy(P->done_ev);
+  for (void* p : {(void*)P->d_synd, (void*)P->d_edges, (void*)P->d_ne, (void*)P->d_st, (void*)P->d_w, (void*)P->d_obs})
     if (p) (void)hipFree(p);
-  for (void* p : {(void*)G->h_synd, (void*)G->h_edges, (void*)G->h_ne, (void*)G->h_st, (void*)G->h_w, (void*)G->h_obs})
+  for (void* p : {(void*)P->h_synd, (void*)P->h_edges, (void*)P->h_ne, (void*)P->h_st, (void*)P->h_w, (void*)P->h_obs})
     if (p) (void)hipHostFree(p);
-  if (G->dec) psb_decoder_destroy(G->dec);
-  if (G->own_graph) psb_graph_destroy(G->own_graph);
-  if (G->own_stream && G->stream) (void)hipStreamDestroy(G->stream);
+  if (P->dec) psb_decoder_destroy(P->dec);
+  if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
 }
 
-// Builds the decoder and buffers of group `gi`; called with the lock held or
-// before the worker starts.
+static void free_group(Group* G) {
+  if (!G) return;
+  for (auto& P : G->pipes) free_pipe(P.get());
+  G->pipes.clear();
+  if (G->own_graph) psb_graph_destroy(G->own_graph);
+  G->own_graph = nullptr;
+}
+
+static int32_t add_pipe(psb_server* S, Group* G);
+
 static int32_t make_group(psb_server* S, int gi) {
-  const int graph = gi / 2;
-  const bool unit = gi % 2 == 1;
   auto G = std::make_unique<Group>();
-  const psb_graph* g = S->graphs[graph];
-  if (unit) {
-    const int32_t rc = psb_graph_unit_copy(g, &G->own_graph);
+  G->graph = S->graphs[gi / 2];
+  if (gi % 2 == 1) {
+    const int32_t rc = psb_graph_unit_copy(G->graph, &G->own_graph);
     if (rc != PSB_OK) return rc;
-    g = G->own_graph;
+    G->graph = G->own_graph;
   }
-  int32_t rc = psb_decoder_create(g, &S->opts, &G->dec);
-  if (rc != PSB_OK) { free_group(G.get()); return rc; }
-  G->nbytes = psb_graph_syndrome_bytes(g);
-  G->stride = psb_decoder_edges_per_shot(G->dec);
-  int32_t fs = 0, os = 0, lds = 0;
-  psb_decoder_slots(G->dec, &fs, &os, &lds);
-  int64_t ws = 0;
-  psb_decoder_device_bytes(G->dec, &ws);
-  G->max_batch = std::max<int64_t>(64, (int64_t)fs * 4);
-  const int64_t per_shot = G->nbytes + 4LL * G->stride + 4 + 8 + 8 + 4;
-  if (S->budget > 0) {
-    const int64_t left = S->budget - S->used - ws;
-    if (left < 64 * per_shot) {
-      free_group(G.get());
-      return fail(PSB_E_NOMEM, "device_mem_budget too small for another decoder and a 64-shot batch");
-    }
-    G->max_batch = std::min<int64_t>(G->max_batch, left / per_shot);
+  G->nbytes = psb_graph_syndrome_bytes(G->graph);
+  for (int i = 0; i < kPipes; ++i) {
+    const int32_t rc = add_pipe(S, G.get());
+    if (rc != PSB_OK) { free_group(G.get()); return rc; }
   }
-  const int64_t B = G->max_batch;
-  bool ok = hipMalloc((void**)&G->d_synd, (size_t)B * G->nbytes) == hipSuccess &&
-            hipMalloc((void**)&G->d_edges, (size_t)B * G->stride * 4) == hipSuccess &&
-            hipMalloc((void**)&G->d_ne, (size_t)B * 4) == hipSuccess &&
-            hipMalloc((void**)&G->d_st, (size_t)B * 4) == hipSuccess &&
-            hipMalloc((void**)&G->d_w, (size_t)B * 8) == hipSuccess &&
-            hipMalloc((void**)&G->d_obs, (size_t)B * 8) == hipSuccess &&
-            hipHostMalloc((void**)&G->h_synd, (size_t)B * G->nbytes, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&G->h_edges, (size_t)B * G->stride * 4, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&G->h_ne, (size_t)B * 4, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&G->h_st, (size_t)B * 4, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&G->h_w, (size_t)B * 8, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&G->h_obs, (size_t)B * 8, hipHostMallocDefault) == hipSuccess &&
-            hipEventCreateWithFlags(&G->done_ev, hipEventDisableTiming) == hipSuccess;
-  if (ok && S->user_stream) {
-    G->stream = S->user_stream;
-  } else if (ok) {
-    ok = hipStreamCreateWithFlags(&G->stream, hipStreamNonBlocking) == hipSuccess;
-    G->own_stream = ok;
-  }
-  if (!ok) { free_group(G.get()); return fail(PSB_E_NOMEM, "server batch buffers"); }
-  S->used += ws + B * per_shot;
   S->groups[gi] = std::move(G);
   return PSB_OK;
 }
 
-// Launches the next batch of group G (lock held).
-static void launch(psb_server* S, Group* G) {
-  const int64_t k = std::min<int64_t>((int64_t)G->pending.size(), G->max_batch);
-  G->inflight.clear();
+// Adds a pipe (decoder, stream, buffers) to group G; lock held or before
+// the worker starts.  The pipe's decoder and buffers count against the budget.
+static int32_t add_pipe(psb_server* S, Group* G) {
+  auto P = std::make_unique<Pipe>();
+  int32_t rc = psb_decoder_create(G->graph, &S->opts, &P->dec);
+  if (rc != PSB_OK) return rc;
+  G->stride = psb_decoder_edges_per_shot(P->dec);
+  int32_t fs = 0, os = 0, lds = 0;
+  psb_decoder_slots(P->dec, &fs, &os, &lds);
+  int64_t ws = 0;
+  psb_decoder_device_bytes(P->dec, &ws);
+  // one shot per fast-tier slot: a batch finishes after one shot's decode time
+  P->max_batch = std::max<int64_t>(64, (int64_t)fs);
+  const int64_t per_shot = G->nbytes + 4LL * G->stride + 4 + 8 + 8 + 4;
+  if (S->budget > 0) {
+    const int64_t left = S->budget - S->used - ws;
+    if (left < 64 * per_shot) {
+      free_pipe(P.get());
+      return fail(PSB_E_NOMEM, "device_mem_budget too small for another decoder and a 64-shot batch");
+    }
+    P->max_batch = std::min<int64_t>(P->max_batch, left / per_shot);
+  }
+  const int64_t B = P->max_batch;
+  bool ok = hipMalloc((void**)&P->d_synd, (size_t)B * G->nbytes) == hipSuccess &&
+            hipMalloc((void**)&P->d_edges, (size_t)B * G->stride * 4) == hipSuccess &&
+            hipMalloc((void**)&P->d_ne, (size_t)B * 4) == hipSuccess &&
+            hipMalloc((void**)&P->d_st, (size_t)B * 4) == hipSuccess &&
+            hipMalloc((void**)&P->d_w, (size_t)B * 8) == hipSuccess &&
+            hipMalloc((void**)&P->d_obs, (size_t)B * 8) == hipSuccess &&
+            hipHostMalloc((void**)&P->h_synd, (size_t)B * G->nbytes, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&P->h_edges, (size_t)B * G->stride * 4, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&P->h_ne, (size_t)B * 4, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&P->h_st, (size_t)B * 4, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&P->h_w, (size_t)B * 8, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&P->h_obs, (size_t)B * 8, hipHostMallocDefault) == hipSuccess &&
+            hipEventCreateWithFlags(&P->done_ev, hipEventDisableTiming) == hipSuccess;
+  if (ok && S->user_stream) {
+    P->stream = S->user_stream;
+  } else if (ok) {
+    ok = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) == hipSuccess;
+    P->own_stream = ok;
+  }
+  if (ok) ok = psb_decoder_reserve(P->dec, B) == PSB_OK;
+  if (!ok) { free_pipe(P.get()); return fail(PSB_E_NOMEM, "server batch buffers"); }
+  S->used += ws + B * per_shot;
+  G->pipes.push_back(std::move(P));
+  return PSB_OK;
+}
+
+// Launches the next batch of group G on pipe P (lock held).
+static void launch(psb_server* S, Group* G, Pipe* P) {
+  const int64_t k = std::min<int64_t>((int64_t)G->pending.size(), P->max_batch);
+  const auto t0 = Clock::now();
+  P->inflight.clear();
   for (int64_t i = 0; i < k; ++i) {
     const uint64_t t = G->pending.front();
     G->pending.pop_front();
-    G->inflight.push_back(t);
-    memcpy(G->h_synd + i * G->nbytes, S->reqs[t].synd.data(), G->nbytes);
+    P->inflight.push_back(t);
+    const Request& R = S->reqs[t];
+    memcpy(P->h_synd + i * G->nbytes, R.synd.data(), G->nbytes);
+    S->queue_ns += ns_between(R.t_submit, t0);
   }
-  hipError_t e = hipMemcpyAsync(G->d_synd, G->h_synd, (size_t)k * G->nbytes, hipMemcpyHostToDevice, G->stream);
-  int32_t rc = e == hipSuccess ? psb_decode_batch(G->dec, G->d_synd, k, G->d_edges, G->d_ne, G->d_w, G->d_obs,
-                                                  G->d_st, nullptr, nullptr, nullptr, G->stream)
+  hipError_t e = hipMemcpyAsync(P->d_synd, P->h_synd, (size_t)k * G->nbytes, hipMemcpyHostToDevice, P->stream);
+  int32_t rc = e == hipSuccess ? psb_decode_batch(P->dec, P->d_synd, k, P->d_edges, P->d_ne, P->d_w, P->d_obs,
+                                                  P->d_st, nullptr, nullptr, nullptr, P->stream)
                                : PSB_E_DEVICE;
   if (rc == PSB_OK) {
-    e = hipMemcpyAsync(G->h_ne, G->d_ne, (size_t)k * 4, hipMemcpyDeviceToHost, G->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(G->h_st, G->d_st, (size_t)k * 4, hipMemcpyDeviceToHost, G->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(G->h_w, G->d_w, (size_t)k * 8, hipMemcpyDeviceToHost, G->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(G->h_obs, G->d_obs, (size_t)k * 8, hipMemcpyDeviceToHost, G->stream);
+    e = hipMemcpyAsync(P->h_ne, P->d_ne, (size_t)k * 4, hipMemcpyDeviceToHost, P->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->h_st, P->d_st, (size_t)k * 4, hipMemcpyDeviceToHost, P->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->h_w, P->d_w, (size_t)k * 8, hipMemcpyDeviceToHost, P->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->h_obs, P->d_obs, (size_t)k * 8, hipMemcpyDeviceToHost, P->stream);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(G->h_edges, G->d_edges, (size_t)k * G->stride * 4, hipMemcpyDeviceToHost, G->stream);
-    if (e == hipSuccess) e = hipEventRecord(G->done_ev, G->stream);
+      e = hipMemcpyAsync(P->h_edges, P->d_edges, (size_t)k * G->stride * 4, hipMemcpyDeviceToHost, P->stream);
+    if (e == hipSuccess) e = hipEventRecord(P->done_ev, P->stream);
     if (e != hipSuccess) rc = PSB_E_DEVICE;
   }
   if (rc != PSB_OK) {
     // the batch cannot run: its requests complete with an internal status
     const auto now = Clock::now();
-    for (uint64_t t : G->inflight) { Request& R = S->reqs[t]; R.done = true; R.status = PSB_S_INTERNAL; R.t_done = now; }
-    G->inflight.clear();
+    for (uint64_t t : P->inflight) {
+      Request& R = S->reqs[t]; R.done = true; R.status = PSB_S_INTERNAL; R.t_done = now;
+      S->finished.push_back(t);
+    }
+    P->inflight.clear();
     S->worker_error = "batch launch failed";
     S->cv.notify_all();
     return;
   }
-  G->busy = true;
+  P->busy = true;
+  P->t_launch = Clock::now();
+  S->n_batches += 1;
+  S->n_windows += k;
+  S->launch_ns += ns_between(t0, P->t_launch);
 }
 
-// Scatters a finished batch into its requests (lock held).
-static void complete(psb_server* S, Group* G) {
+// Scatters a finished batch into its requests (lock held); a batch whose
+// device work failed completes with an internal status.
+static void complete(psb_server* S, Group* G, Pipe* P, bool ok) {
   const auto now = Clock::now();
-  for (size_t i = 0; i < G->inflight.size(); ++i) {
-    Request& R = S->reqs[G->inflight[i]];
-    R.status = G->h_st[i];
-    R.weight = G->h_w[i] * R.scale;
-    R.obs = G->h_obs[i];
-    R.n_edges = G->h_ne[i];
+  S->run_ns += ns_between(P->t_launch, now);
+  for (size_t i = 0; i < P->inflight.size(); ++i) {
+    Request& R = S->reqs[P->inflight[i]];
+    R.status = ok ? P->h_st[i] : PSB_S_INTERNAL;
+    R.weight = P->h_w[i] * R.scale;
+    R.obs = P->h_obs[i];
+    R.n_edges = P->h_ne[i];
     const int64_t m = std::min<int64_t>(R.n_edges, G->stride);
-    R.edges.assign(G->h_edges + i * (int64_t)G->stride, G->h_edges + i * (int64_t)G->stride + m);
+    R.edges.assign(P->h_edges + i * (int64_t)G->stride, P->h_edges + i * (int64_t)G->stride + m);
     R.synd.clear(); R.synd.shrink_to_fit();
     R.done = true;
     R.t_done = now;
+    S->finished.push_back(P->inflight[i]);
   }
-  G->inflight.clear();
-  G->busy = false;
+  P->inflight.clear();
+  P->busy = false;
+  // tickets already taken by psb_server_poll stay in the completion list
+  // until psb_server_collect passes them; drop them once they dominate it
+  if (S->finished.size() > 2 * S->reqs.size() + 4096) {
+    std::deque<uint64_t> keep;
+    for (uint64_t t : S->finished) if (S->reqs.count(t)) keep.push_back(t);
+    S->finished.swap(keep);
+  }
   S->cv.notify_all();
 }
 
@@ -213,16 +273,19 @@ static void worker_main(psb_server* S) {
   std::unique_lock<std::mutex> lk(S->mu);
   while (!S->stop) {
     bool busy = false, work = false;
-    for (auto& up : S->groups) {
-      Group* G = up.get();
+    for (auto& ug : S->groups) {
+      Group* G = ug.get();
       if (!G) continue;
-      if (G->busy) {
-        const hipError_t q = hipEventQuery(G->done_ev);
-        if (q == hipSuccess) complete(S, G);
-        else if (q != hipErrorNotReady) { S->worker_error = "device error while a batch ran"; complete(S, G); }
+      for (auto& up : G->pipes) {
+        Pipe* P = up.get();
+        if (!P->busy) continue;
+        const hipError_t q = hipEventQuery(P->done_ev);
+        if (q == hipSuccess) complete(S, G, P, true);
+        else if (q != hipErrorNotReady) { S->worker_error = "device error while a batch ran"; complete(S, G, P, false); }
       }
-      if (!G->busy && !G->pending.empty()) launch(S, G);
-      busy |= G->busy;
+      for (auto& up : G->pipes)
+        if (!up->busy && !G->pending.empty()) launch(S, G, up.get());
+      for (auto& up : G->pipes) busy |= up->busy;
       work |= !G->pending.empty();
     }
     if (busy || work) {
@@ -249,6 +312,8 @@ extern "C" int32_t psb_server_create(const psb_graph* const* graphs, int32_t n_g
   S->budget = device_mem_budget;
   S->user_stream = (hipStream_t)stream;
   S->groups.resize(2 * (size_t)n_graphs);
+  if (S->opts.num_slots == 0) S->opts.num_slots = 1024;          // kPipes decoders of 1024 slots per group
+  if (S->opts.overflow_slots == 0) S->opts.overflow_slots = 256;
   for (int32_t i = 0; i < n_graphs; ++i) {
     const int32_t rc = make_group(S.get(), 2 * i);
     if (rc != PSB_OK) { for (auto& G : S->groups) free_group(G.get()); return rc; }
@@ -274,6 +339,7 @@ extern "C" int32_t psb_server_submit(psb_server* S, int32_t graph_idx, const uin
     scale = w0;
     gi += 1;
   }
+  const auto t_submit = Clock::now();
   std::lock_guard<std::mutex> lk(S->mu);
   if (!S->groups[gi]) {
     const int32_t rc = make_group(S, gi);
@@ -285,7 +351,7 @@ extern "C" int32_t psb_server_submit(psb_server* S, int32_t graph_idx, const uin
   R.group = gi;
   R.scale = scale;
   R.synd.assign(syndrome_host, syndrome_host + G->nbytes);
-  R.t_submit = Clock::now();
+  R.t_submit = t_submit;
   G->pending.push_back(t);
   *ticket = t;
   S->cv.notify_all();
@@ -316,6 +382,36 @@ extern "C" int32_t psb_server_poll(psb_server* S, uint64_t ticket, int32_t* done
   return PSB_OK;
 }
 
+extern "C" int32_t psb_server_collect(psb_server* S, int32_t max, uint64_t* tickets, int64_t* weight, uint64_t* obs,
+                                      int32_t* status, int64_t* latency_ns) {
+  if (!S || max < 0 || (max > 0 && !tickets)) return fail(PSB_E_INVALID, "null argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  int32_t k = 0;
+  while (k < max && !S->finished.empty()) {
+    const uint64_t t = S->finished.front();
+    S->finished.pop_front();
+    auto it = S->reqs.find(t);
+    if (it == S->reqs.end()) continue;            // already collected by psb_server_poll
+    const Request& R = it->second;
+    tickets[k] = t;
+    if (weight) weight[k] = R.weight;
+    if (obs) obs[k] = R.obs;
+    if (status) status[k] = R.status;
+    if (latency_ns) latency_ns[k] = std::chrono::duration_cast<std::chrono::nanoseconds>(R.t_done - R.t_submit).count();
+    S->reqs.erase(it);
+    ++k;
+  }
+  return k;
+}
+
+extern "C" int32_t psb_server_stats(psb_server* S, int64_t* out5) {
+  if (!S || !out5) return fail(PSB_E_INVALID, "null argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  out5[0] = S->n_batches; out5[1] = S->n_windows; out5[2] = S->queue_ns; out5[3] = S->run_ns;
+  out5[4] = S->launch_ns;
+  return PSB_OK;
+}
+
 extern "C" int32_t psb_server_destroy(psb_server* S) {
   if (!S) return PSB_OK;
   {
@@ -324,10 +420,7 @@ extern "C" int32_t psb_server_destroy(psb_server* S) {
     S->cv.notify_all();
   }
   if (S->worker.joinable()) S->worker.join();
-  for (auto& G : S->groups) {
-    if (G && G->stream) (void)hipStreamSynchronize(G->stream);
-    free_group(G.get());
-  }
+  for (auto& G : S->groups) free_group(G.get());
   delete S;
   return PSB_OK;
 }

@@ -278,8 +278,9 @@ def test_hash_map_large_graph_d41():
 
 def test_server_windows_equal_oracle():
     """Serving: windows of three graphs, some with a uniform per-request
-    weight, submitted one at a time and polled; every result equals the
-    oracle on that window alone (with the request's weights)."""
+    weight, submitted one at a time in bursts (so several batches of one
+    graph are in flight) and polled; every result equals the oracle on that
+    window alone (with the request's weights)."""
     import time
     import paper_2609_12262_amd as psb
     gs = [synth.rotated_phenom_graph(d, 0.005) for d in (5, 9, 13)]
@@ -296,6 +297,8 @@ def test_server_windows_equal_oracle():
             p = float(rng.uniform(0.001, 0.007))
             w = np.full(g.num_edges, synth.weight_from_p(p), np.int32)
         reqs.append((k, row, w, srv.submit(k, row, w)))
+        if j % 40 == 39:
+            time.sleep(0.0003)   # batches overlap: later windows land on further in-flight batches
     say("server: 600 windows submitted")
     results = {}
     t0 = time.time()
