@@ -56,19 +56,25 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(d, p, shots):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload,
-    or None when the kernel sources changed since the counters were taken."""
+def decoder_config_key(kw):
+    return (f"first_tier={kw.get('first_tier', 0)} state={kw.get('fast_max_nodes', 0)}/"
+            f"{kw.get('fast_max_regions', 0)} q={kw.get('q', (1, 10))[0]}/{kw.get('q', (1, 10))[1]}")
+
+
+def measured_traffic(d, p, shots, kw):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload and
+    decoder configuration, or None when the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"psb_decode_kernel_d{d}_p{str(p).split('.')[1][:3]}_traffic.md")
     if (d, p, shots) != (21, 0.005, 50000) or not os.path.exists(path):
         return None
     vals = {}
     with open(path) as fh:
         for line in fh:
-            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256",
+                                                      "decoder_config"):
                 k, v = line.split(":", 1)
                 vals[k] = v.strip()
-    if vals.get("kernel_source_sha256") != kernel_source_hash():
+    if vals.get("kernel_source_sha256") != kernel_source_hash() or vals.get("decoder_config") != decoder_config_key(kw):
         return None
     return int(vals["traffic_bytes_per_launch"])
 
@@ -248,6 +254,10 @@ def main():
     ap.add_argument("--shots", type=int, default=50000)
     ap.add_argument("--mode", type=int, default=0, help="0 partition-and-fuse, 1 global sparse blossom")
     ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true", help="default decoder configuration instead of the "
+                                                                 "autotuner's pick")
+    ap.add_argument("--no-graph", action="store_true", help="eager psb_decode_batch launches instead of a "
+                                                              "captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -297,14 +307,26 @@ def main():
     log(f"sampling {args.shots} shots d={args.d} p={args.p}")
     shots = synth.sample(g, args.shots, seed=seed_sample)
     G = psb.Graph.from_synth(g)
-    dec = psb.Decoder(G, tiebreak_seed=0x5EED, mode=args.mode, num_slots=args.slots)
     synd = torch.from_numpy(shots.syndromes).cuda()
+    base = dict(tiebreak_seed=0x5EED, mode=args.mode, num_slots=args.slots)
+    tune_table = None
+    if args.no_autotune:
+        kw = base
+    else:
+        log("autotune")
+        kw, tune_table = psb.autotune(G, synd, reps=1, **base)
+    dec = psb.Decoder(G, **kw)
     out = dec.alloc(args.shots, timestamps=True, stats=True)
     stream = torch.cuda.current_stream()
+    if args.no_graph:
+        step = lambda: dec.decode_into(synd, out, stream)
+    else:
+        bg = dec.capture(synd, out)
+        step = lambda: bg.launch(stream)
     torch.cuda.synchronize()
     log("warmup")
     for _ in range(args.warmup):
-        dec.decode_into(synd, out)
+        step()
     torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -312,7 +334,7 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         ev[k][0].record(stream)
-        dec.decode_into(synd, out)
+        step()
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -343,16 +365,22 @@ def main():
                                f"p=q={args.p}, {args.shots} shots per step, one persistent launch",
                    "d": args.d, "rounds": args.d, "p": args.p, "shots_per_step": args.shots,
                    "mode": "partition-and-fuse" if args.mode == 0 else "global sparse blossom",
+                   "first_tier": "one shot per lane" if kw.get("first_tier", 0) else "one shot per wavefront",
+                   "first_tier_state": [kw.get("fast_max_nodes", 0), kw.get("fast_max_regions", 0)],
+                   "schedule_q": list(kw.get("q", (1, 10))),
                    "first_tier_slots": dec.fast_slots, "overflow_tier_slots": dec.overflow_slots,
-                   "overflow_shots": dec.last_overflow()},
+                   "overflow_shots": dec.last_overflow(), "hip_graph": not args.no_graph,
+                   "autotune": None if tune_table is None else
+                   [{"first_tier": t["first_tier"], "state": [t["fast_max_nodes"], t["fast_max_regions"]],
+                     "q": list(t["q"]), "ms": t["ms"], "status": t["status"]} for t in tune_table]},
         "latency_us_per_round": {"p50": round(float(np.percentile(per_round, 50)), 3),
                                  "p99": round(float(np.percentile(per_round, 99)), 3),
                                  "basis": "batch submission to shot completion (device clock), last step"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": measured_traffic(args.d, args.p, args.shots),
+                     "traffic": measured_traffic(args.d, args.p, args.shots, kw),
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(avg_launch_s * 1e3, 3),
-                     "kernel": "psb_decode_kernel"},
+                     "kernel": "psb_lane_kernel" if kw.get("first_tier", 0) else "psb_decode_kernel<0>"},
         "work_per_shot": {"events": float(stats[:, 0].mean()), "reached": float(stats[:, 1].mean()),
                           "cluster_visits": float(stats[:, 2].mean()), "log_records": float(stats[:, 3].mean()),
                           "us_intake_cluster": float(stats[:, 4].mean()) * 1e6 / DEVICE_CLOCK_HZ,

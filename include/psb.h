@@ -30,6 +30,7 @@ extern "C" {
 #define PSB_E_NOMEM (-2)        /* host or device allocation failed */
 #define PSB_E_DEVICE (-3)       /* HIP runtime error (launch, copy) */
 #define PSB_E_UNSUPPORTED (-4)  /* graph/schedule combination outside the kernel's limits */
+#define PSB_E_INTERNAL (-5)     /* an internal consistency check failed (autotune candidates disagree) */
 
 /* Per-shot status codes written by psb_decode_batch. */
 #define PSB_S_OK 0
@@ -147,6 +148,23 @@ int32_t psb_schedule_levels(uint64_t wmax_hi, uint64_t wmax_lo, uint64_t diam_hi
 /* Device memory the decoder holds (workspaces, weights, schedule), in bytes. */
 int32_t psb_decoder_device_bytes(const psb_decoder* d, int64_t* bytes);
 
+/* A psb_decode_batch call captured once into a HIP graph and replayed with
+ * one launch: the counter reset and both tiers' persistent kernels (a fill
+ * kernel clears the counters, no memset node).  The arguments are those of
+ * psb_decode_batch and are fixed at capture (the caller refills
+ * `syndromes` in place between launches); all pointers are DEVICE memory
+ * owned by the caller and must outlive the graph.  Creation reserves the
+ * decoder's per-batch storage for n shots and captures on a stream of its
+ * own; a replay may run on any stream.  A replay and any other batch of the
+ * same decoder must not overlap (they share its workspaces and counters).
+ * Errors: PSB_E_INVALID, PSB_E_NOMEM, PSB_E_DEVICE. */
+typedef struct psb_batch_graph psb_batch_graph;
+int32_t psb_batch_graph_create(psb_decoder* d, const uint8_t* syndromes, int64_t n, int32_t* edges,
+                               int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
+                               int8_t* levels, uint64_t* t_done, int32_t* stats, psb_batch_graph** out);
+int32_t psb_batch_graph_launch(psb_batch_graph* g, void* stream);
+int32_t psb_batch_graph_destroy(psb_batch_graph* g);
+
 /* Sizes the decoder's internal per-batch storage (the list of shots the fast
  * tier hands to the overflow tier) for batches of up to `max_batch` shots.
  * psb_decode_batch grows that list by itself when a larger batch comes, which
@@ -155,6 +173,32 @@ int32_t psb_decoder_device_bytes(const psb_decoder* d, int64_t* bytes);
  * Returns PSB_E_INVALID for max_batch < 0, PSB_E_NOMEM if allocation fails.
  * Not safe to call while a batch of this decoder is in flight. */
 int32_t psb_decoder_reserve(psb_decoder* d, int64_t max_batch);
+
+/* Autotuner.  Decodes a sample batch `syndromes` (DEVICE, [n][ceil(num_detectors/8)])
+ * with each of psb_autotune_candidates() configurations built from `base`
+ * (NULL = defaults) by overriding first_tier, fast_max_nodes,
+ * fast_max_regions and the schedule ratio q; times `reps` launches of each
+ * (after one warm-up) with HIP events on `stream` and writes one record per
+ * candidate to entries[0 .. psb_autotune_candidates()-1]: its options, the
+ * fastest launch in milliseconds (-1 if skipped) and its status (PSB_OK, or
+ * the error that skipped it, e.g. PSB_E_UNSUPPORTED when its state does not
+ * fit).  *best_index = the fastest candidate.  These options change speed
+ * only: the partition-and-fuse result is the serial MWEM for every
+ * admissible schedule (Methods, "Parallel sparse blossom"), and every
+ * candidate's weights and observables are checked against the first one's
+ * (PSB_E_INTERNAL if any differ).  Synchronises the device (decoders are
+ * created and destroyed).  Returns the number of candidates, or an error:
+ * PSB_E_INVALID, PSB_E_NOMEM, PSB_E_DEVICE, PSB_E_INTERNAL, PSB_E_UNSUPPORTED
+ * (no candidate fits). */
+typedef struct {
+  psb_decoder_opts opts;
+  float ms;
+  int32_t status;
+} psb_tune_entry;
+int32_t psb_autotune_candidates(void);
+int32_t psb_autotune(const psb_graph* g, const psb_decoder_opts* base, const uint8_t* syndromes, int64_t n,
+                     int32_t reps, void* stream, psb_tune_entry* entries, int32_t max_entries,
+                     int32_t* best_index);
 
 /* Shots in flight per tier and the fast tier's LDS bytes per shot. */
 int32_t psb_decoder_slots(const psb_decoder* d, int32_t* fast_slots, int32_t* overflow_slots,
@@ -172,14 +216,19 @@ int32_t psb_graph_syndrome_bytes(const psb_graph* g);
 /* ---------------------------------------------------------------------
  * Serving (windows arriving one at a time while others decode).
  *
- * A server owns one decoder per graph (built with `opts`; edges_per_shot 0
- * selects 1024 here) plus, on first use, one per graph for requests that
- * carry a uniform per-request weight.  A worker thread groups pending
- * requests of the same (graph, weight set) into one psb_decode_batch launch
- * on that group's stream (a stream of its own, or `stream` for every group
- * when it is not NULL), copies results to pinned host memory and completes
- * the tickets.  Each result is identical to psb_decode_batch on that window
- * alone: the decoding of a shot does not depend on the other shots of its
+ * Requests are grouped per (graph, weight set): the graph's own weights, or,
+ * for requests that carry a uniform per-request weight, the graph with unit
+ * weights (made on first use).  Each group holds 4 decoders built with that
+ * graph's options (`opts`: NULL, or an array of n_graphs records, one per
+ * graph; zeros here select edges_per_shot 1024, num_slots 1024 and
+ * overflow_slots 256), each with its own stream (or `stream` for all when it
+ * is not NULL) and pinned batch buffers, so up to 4 batches of one group are
+ * on the device at once.  A worker thread launches the pending requests of
+ * a group on any of its idle decoders as one psb_decode_batch launch (up to
+ * num_slots shots, one per slot), copies results to pinned host memory and
+ * completes the tickets; requests that arrive meanwhile wait for the next
+ * idle decoder.  Each result is identical to psb_decode_batch on that
+ * window alone: a shot's decoding does not depend on the other shots of its
  * batch (Results, "Decoding task": every window is an independent MWEM).
  * device_mem_budget > 0 bounds the bytes of decoders and batch buffers
  * (batches shrink to fit; PSB_E_NOMEM if a 64-shot batch does not).

@@ -42,6 +42,27 @@ class _DecoderOpts(ctypes.Structure):
                 ("overflow_slots", ctypes.c_int32), ("first_tier", ctypes.c_int32)]
 
 
+class _TuneEntry(ctypes.Structure):
+    _fields_ = [("opts", _DecoderOpts), ("ms", ctypes.c_float), ("status", ctypes.c_int32)]
+
+
+def _make_opts(tiebreak_seed: int = 0x5EED, mode: int = 0, boundary_reading: int = 0, max_defects: int = 0,
+               edges_per_shot: int = 0, num_slots: int = 0, q=(1, 10), phi_min=(1, 100), fast_max_nodes: int = 0,
+               fast_max_regions: int = 0, overflow_slots: int = 0, first_tier: int = 0) -> _DecoderOpts:
+    return _DecoderOpts(q[0], q[1], phi_min[0], phi_min[1], tiebreak_seed & ((1 << 64) - 1), mode,
+                        boundary_reading, max_defects, edges_per_shot, num_slots, fast_max_nodes,
+                        fast_max_regions, overflow_slots, first_tier)
+
+
+def _opts_kwargs(o: _DecoderOpts) -> dict:
+    """Decoder keyword arguments equal to an options record."""
+    return {"tiebreak_seed": o.tiebreak_seed, "mode": o.mode, "boundary_reading": o.boundary_reading,
+            "max_defects": o.max_defects_per_shot, "edges_per_shot": o.edges_per_shot, "num_slots": o.num_slots,
+            "q": (o.q_num, o.q_den), "phi_min": (o.phi_min_num, o.phi_min_den),
+            "fast_max_nodes": o.fast_max_nodes, "fast_max_regions": o.fast_max_regions,
+            "overflow_slots": o.overflow_slots, "first_tier": o.first_tier}
+
+
 def lib():
     """The loaded libpsb.so; raises if it has not been built (no fallback)."""
     global _lib
@@ -55,7 +76,8 @@ def lib():
                      "psb_decoder_max_defects", "psb_graph_syndrome_bytes", "psb_schedule_levels",
                      "psb_decoder_slots", "psb_decoder_last_overflow", "psb_decoder_device_bytes", "psb_decoder_reserve",
                      "psb_server_create", "psb_server_submit", "psb_server_poll", "psb_server_collect",
-                     "psb_server_stats", "psb_server_destroy"):
+                     "psb_server_stats", "psb_server_destroy", "psb_autotune", "psb_autotune_candidates",
+                     "psb_batch_graph_create", "psb_batch_graph_launch", "psb_batch_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -137,9 +159,8 @@ class Decoder:
                  num_slots: int = 0, q=(1, 10), phi_min=(1, 100), fast_max_nodes: int = 0,
                  fast_max_regions: int = 0, overflow_slots: int = 0, first_tier: int = 0):
         self.graph = graph
-        opts = _DecoderOpts(q[0], q[1], phi_min[0], phi_min[1], tiebreak_seed & ((1 << 64) - 1), mode,
-                            boundary_reading, max_defects, edges_per_shot, num_slots, fast_max_nodes,
-                            fast_max_regions, overflow_slots, first_tier)
+        opts = _make_opts(tiebreak_seed, mode, boundary_reading, max_defects, edges_per_shot, num_slots, q, phi_min,
+                          fast_max_nodes, fast_max_regions, overflow_slots, first_tier)
         h = ctypes.c_void_p()
         _check(lib().psb_decoder_create(graph._h, ctypes.byref(opts), ctypes.byref(h)), "psb_decoder_create")
         self._h = h
@@ -193,6 +214,22 @@ class Decoder:
         out = self.alloc(syndromes.shape[0], levels, timestamps, stats, device=syndromes.device)
         return self.decode_into(syndromes, out)
 
+    def capture(self, syndromes, out: Batch) -> "BatchGraph":
+        """Capture psb_decode_batch(syndromes -> out) into a HIP graph; refill `syndromes` in place and
+        replay with BatchGraph.launch()."""
+        import torch
+        if not syndromes.is_cuda or syndromes.dtype != torch.uint8 or not syndromes.is_contiguous():
+            raise PsbError("syndromes must be a contiguous uint8 CUDA tensor")
+        n = syndromes.shape[0]
+        if out.edges.shape[0] < n:
+            raise PsbError("output batch too small")
+        P = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+        h = ctypes.c_void_p()
+        _check(lib().psb_batch_graph_create(self._h, P(syndromes), ctypes.c_int64(n), P(out.edges), P(out.n_edges),
+                                            P(out.weight), P(out.obs), P(out.status), P(out.levels),
+                                            P(out.t_done), P(out.stats), ctypes.byref(h)), "psb_batch_graph_create")
+        return BatchGraph(h, (self, syndromes, out))
+
     def reserve(self, max_batch: int):
         """Pre-size per-batch storage so that batches up to max_batch never reallocate."""
         _check(lib().psb_decoder_reserve(self._h, ctypes.c_int64(int(max_batch))), "psb_decoder_reserve")
@@ -218,21 +255,61 @@ class Decoder:
             pass
 
 
+class BatchGraph:
+    """psb_batch_graph: one captured psb_decode_batch call, replayed with a single graph launch."""
+
+    def __init__(self, h, keep):
+        self._h = h
+        self._keep = keep            # decoder and buffers the graph's arguments point into
+
+    def launch(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().psb_batch_graph_launch(self._h, ctypes.c_void_p(s.cuda_stream)), "psb_batch_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().psb_batch_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(graph: "Graph", syndromes, reps: int = 2, stream=None, **base):
+    """Times every candidate configuration on the sample batch `syndromes` (uint8 device tensor) and
+    returns (keyword arguments of the fastest Decoder, list of per-candidate records)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    nc = lib().psb_autotune_candidates()
+    entries = (_TuneEntry * nc)()
+    best = ctypes.c_int32(-1)
+    b = _make_opts(**base)
+    _check(lib().psb_autotune(graph._h, ctypes.byref(b), ctypes.c_void_p(syndromes.data_ptr()),
+                              ctypes.c_int64(syndromes.shape[0]), ctypes.c_int32(reps),
+                              ctypes.c_void_p(s.cuda_stream), entries, ctypes.c_int32(nc), ctypes.byref(best)),
+           "psb_autotune")
+    table = [dict(_opts_kwargs(e.opts), ms=round(float(e.ms), 4), status=int(e.status)) for e in entries]
+    return _opts_kwargs(entries[best.value].opts), table
+
+
 class Server:
     """psb_server: windows submitted one at a time while earlier ones decode."""
 
-    def __init__(self, graphs, opts: dict = None, device_mem_budget: int = 0, stream=None):
-        o = opts or {}
+    def __init__(self, graphs, opts=None, device_mem_budget: int = 0, stream=None):
+        """opts: None, one dict of Decoder keyword arguments for every graph, or a list of them (one per graph)."""
         self.graphs = list(graphs)
-        c = _DecoderOpts(o.get("q", (1, 10))[0], o.get("q", (1, 10))[1], o.get("phi_min", (1, 100))[0],
-                         o.get("phi_min", (1, 100))[1], o.get("tiebreak_seed", 0x5EED) & ((1 << 64) - 1),
-                         o.get("mode", MODE_PARTITION), o.get("boundary_reading", 0), o.get("max_defects", 0),
-                         o.get("edges_per_shot", 0), o.get("num_slots", 0), o.get("fast_max_nodes", 0),
-                         o.get("fast_max_regions", 0), o.get("overflow_slots", 0), o.get("first_tier", 0))
+        per = opts if isinstance(opts, (list, tuple)) else [opts] * len(self.graphs)
+        if len(per) != len(self.graphs):
+            raise PsbError("one options record per graph")
+        c = (_DecoderOpts * len(self.graphs))(*[_make_opts(**(o or {})) for o in per])
         arr = (ctypes.c_void_p * len(self.graphs))(*[g._h.value for g in self.graphs])
         h = ctypes.c_void_p()
         s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else ctypes.c_void_p(0)
-        _check(lib().psb_server_create(arr, ctypes.c_int32(len(self.graphs)), ctypes.byref(c),
+        _check(lib().psb_server_create(arr, ctypes.c_int32(len(self.graphs)), c,
                                        ctypes.c_int64(device_mem_budget), s, ctypes.byref(h)), "psb_server_create")
         self._h = h
 

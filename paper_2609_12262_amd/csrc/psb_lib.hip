@@ -438,6 +438,57 @@ extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, in
   return PSB_OK;
 }
 
+struct psb_batch_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int32_t psb_batch_graph_destroy(psb_batch_graph* B) {
+  if (!B) return PSB_OK;
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  delete B;
+  return PSB_OK;
+}
+
+extern "C" int32_t psb_batch_graph_create(psb_decoder* D, const uint8_t* syndromes, int64_t n, int32_t* edges,
+                                          int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
+                                          int8_t* levels, uint64_t* t_done, int32_t* stats,
+                                          psb_batch_graph** out) {
+  if (!D || !out) return fail(PSB_E_INVALID, "null argument");
+  *out = nullptr;
+  if (n <= 0) return fail(PSB_E_INVALID, "a captured batch needs at least one shot");
+  // per-batch storage sized before capture: nothing is allocated or synchronised inside it
+  int32_t rc = psb_decoder_reserve(D, n);
+  if (rc != PSB_OK) return rc;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(PSB_E_DEVICE, "capture stream");
+  auto* B = new psb_batch_graph();
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipStreamDestroy(cs); delete B;
+    return fail(PSB_E_DEVICE, "hipStreamBeginCapture");
+  }
+  rc = psb_decode_batch(D, syndromes, n, edges, n_edges, weight, obs, status, levels, t_done, stats, cs);
+  const hipError_t e = hipStreamEndCapture(cs, &B->graph);
+  (void)hipStreamDestroy(cs);
+  if (rc != PSB_OK || e != hipSuccess) {
+    psb_batch_graph_destroy(B);
+    return rc != PSB_OK ? rc : fail(PSB_E_DEVICE, "hipStreamEndCapture");
+  }
+  if (hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) != hipSuccess) {
+    psb_batch_graph_destroy(B);
+    return fail(PSB_E_DEVICE, "hipGraphInstantiate");
+  }
+  *out = B;
+  return PSB_OK;
+}
+
+extern "C" int32_t psb_batch_graph_launch(psb_batch_graph* B, void* stream) {
+  if (!B || !B->exec) return fail(PSB_E_INVALID, "null batch graph");
+  HIP_TRY(hipGraphLaunch(B->exec, (hipStream_t)stream));
+  return PSB_OK;
+}
+
 extern "C" int32_t psb_schedule_levels(uint64_t wmax_hi, uint64_t wmax_lo, uint64_t diam_hi, uint64_t diam_lo,
                                        int64_t q_num, int64_t q_den, int64_t phi_min_num, int64_t phi_min_den,
                                        int32_t max_levels, uint64_t* d_hi, uint64_t* d_lo, uint64_t* b_hi,

@@ -63,6 +63,7 @@ struct Pipe {
 
 // Requests of one (graph, weight set): a FIFO and kPipes batches in flight.
 struct Group {
+  int32_t graph_idx = 0;
   const psb_graph* graph = nullptr;
   psb_graph* own_graph = nullptr;    // unit-weight copy owned by the server, else null
   int32_t nbytes = 0, stride = 0;
@@ -79,7 +80,7 @@ constexpr int kPipes = 4;
 struct psb_server {
   int device = 0;
   std::vector<const psb_graph*> graphs;
-  psb_decoder_opts opts{};
+  std::vector<psb_decoder_opts> opts;            // per graph
   int64_t budget = 0, used = 0;
   hipStream_t user_stream = nullptr;
   std::vector<std::unique_ptr<Group>> groups;    // [2 * graph + (unit weights ? 1 : 0)]
@@ -128,6 +129,7 @@ static int32_t add_pipe(psb_server* S, Group* G);
 
 static int32_t make_group(psb_server* S, int gi) {
   auto G = std::make_unique<Group>();
+  G->graph_idx = gi / 2;
   G->graph = S->graphs[gi / 2];
   if (gi % 2 == 1) {
     const int32_t rc = psb_graph_unit_copy(G->graph, &G->own_graph);
@@ -147,7 +149,7 @@ static int32_t make_group(psb_server* S, int gi) {
 // the worker starts.  The pipe's decoder and buffers count against the budget.
 static int32_t add_pipe(psb_server* S, Group* G) {
   auto P = std::make_unique<Pipe>();
-  int32_t rc = psb_decoder_create(G->graph, &S->opts, &P->dec);
+  int32_t rc = psb_decoder_create(G->graph, &S->opts[G->graph_idx], &P->dec);
   if (rc != PSB_OK) return rc;
   G->stride = psb_decoder_edges_per_shot(P->dec);
   int32_t fs = 0, os = 0, lds = 0;
@@ -307,13 +309,17 @@ extern "C" int32_t psb_server_create(const psb_graph* const* graphs, int32_t n_g
   auto S = std::make_unique<psb_server>();
   if (hipGetDevice(&S->device) != hipSuccess) return fail(PSB_E_DEVICE, "hipGetDevice");
   S->graphs.assign(graphs, graphs + n_graphs);
-  if (opts) S->opts = *opts;
-  if (S->opts.edges_per_shot == 0) S->opts.edges_per_shot = 1024;   // results are copied per request
+  S->opts.assign(n_graphs, psb_decoder_opts{});
+  for (int32_t i = 0; i < n_graphs; ++i) {
+    psb_decoder_opts& o = S->opts[i];
+    if (opts) o = opts[i];
+    if (o.edges_per_shot == 0) o.edges_per_shot = 1024;       // results are copied per request
+    if (o.num_slots == 0) o.num_slots = 1024;                 // kPipes decoders of 1024 slots per group
+    if (o.overflow_slots == 0) o.overflow_slots = 256;
+  }
   S->budget = device_mem_budget;
   S->user_stream = (hipStream_t)stream;
   S->groups.resize(2 * (size_t)n_graphs);
-  if (S->opts.num_slots == 0) S->opts.num_slots = 1024;          // kPipes decoders of 1024 slots per group
-  if (S->opts.overflow_slots == 0) S->opts.overflow_slots = 256;
   for (int32_t i = 0; i < n_graphs; ++i) {
     const int32_t rc = make_group(S.get(), 2 * i);
     if (rc != PSB_OK) { for (auto& G : S->groups) free_group(G.get()); return rc; }

@@ -285,7 +285,8 @@ def test_server_windows_equal_oracle():
     import paper_2609_12262_amd as psb
     gs = [synth.rotated_phenom_graph(d, 0.005) for d in (5, 9, 13)]
     Gs = [psb.Graph.from_synth(g) for g in gs]
-    srv = psb.Server(Gs)
+    # per-graph options: default, wider first tier, one shot per lane
+    srv = psb.Server(Gs, opts=[{}, {"fast_max_nodes": 640, "fast_max_regions": 416}, {"first_tier": 1}])
     rng = np.random.default_rng(61)
     reqs = []
     for j in range(600):
