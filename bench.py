@@ -167,32 +167,50 @@ def latency_scaling(args):
 
 def serving(args):
     """Windows arrive one at a time (Poisson) at a mixed set of distances and noise rates; the server batches
-    them per graph.  Latency per window = submit to completion (server clock), reported per round."""
+    them per graph.  Latency per window = submit to completion (server clock), reported per round.  The same
+    stream is then decoded in the one-shot-per-launch form (one window per launch, in arrival order)."""
+    import ctypes
     import torch
     import synth
     import paper_2609_12262_amd as psb
     rng = np.random.default_rng(6)
-    ds = [9, 13, 17, 21, 25]
+    ds = [int(x) for x in args.serve_dists.split(",")]
+    p_lo, p_hi = (float(x) for x in args.serve_p.split(","))
     gs = [synth.rotated_phenom_graph(d, 0.004) for d in ds]
     n = args.serve
     kind = rng.integers(0, len(ds), n)
-    ps = rng.uniform(0.001, 0.007, n)
+    ps = rng.uniform(p_lo, p_hi, n)
     log(f"sampling {n} windows")
     rows, ws = [], []
     for i in range(n):
         g = gs[kind[i]]
         gp = synth.DetectorGraph(g.num_detectors, g.u, g.v, g.w, g.obs_mask, np.full(g.num_edges, ps[i]))
         rows.append(synth.sample(gp, 1, seed=5000 + i).syndromes[0])
-        ws.append(np.full(g.num_edges, synth.weight_from_p(float(ps[i])), np.int32))
+        ws.append(synth.weight_from_p(float(ps[i])))
     Gs = [psb.Graph.from_synth(g) for g in gs]
-    srv = psb.Server(Gs)
-    import ctypes
+    # windows carry a uniform weight, so they decode on unit-weight graphs: tune and compare there
+    units = [psb.Graph.from_synth(synth.DetectorGraph(g.num_detectors, g.u, g.v, np.ones(g.num_edges, np.int32),
+                                                       g.obs_mask, g.p)) for g in gs]
+    base = dict(tiebreak_seed=0x5EED, num_slots=1024, overflow_slots=256, edges_per_shot=1024)
+    opts, tuned = [], {}
+    for j, d in enumerate(ds):
+        if args.no_autotune:
+            opts.append(base)
+            continue
+        sel = [r for r, k in zip(rows, kind) if k == j][:2048]
+        best, _ = psb.autotune(units[j], torch.from_numpy(np.stack(sel)).cuda(), reps=1, **base)
+        opts.append(best)
+        tuned[str(d)] = {"first_tier": best["first_tier"], "state": [best["fast_max_nodes"], best["fast_max_regions"]],
+                         "q": list(best["q"])}
+    log(f"autotuned {tuned}")
+    srv = psb.Server(Gs, opts=opts)
     psb.lib()
     rep = ctypes.CDLL(os.path.join(ROOT, "paper_2609_12262_amd", "libpsb_replay.so"))
     rep.psb_replay.restype = ctypes.c_int32
+    rep.psb_replay_oneshot.restype = ctypes.c_int32
     rows = [np.ascontiguousarray(r) for r in rows]
     syn_ptrs = (ctypes.c_void_p * n)(*[r.ctypes.data for r in rows])
-    w_ptrs = (ctypes.c_void_p * n)(*[w.ctypes.data for w in ws])
+    wts = np.ascontiguousarray(ws, np.int32)
     gidx = np.ascontiguousarray(kind, np.int32)
 
     def run(arrivals):
@@ -200,7 +218,8 @@ def serving(args):
         st = np.zeros(n, np.int32)
         span, wall = ctypes.c_double(), ctypes.c_double()
         arr = None if arrivals is None else np.ascontiguousarray(arrivals, np.float64)
-        rc = rep.psb_replay(srv._h, ctypes.c_int64(n), ctypes.c_void_p(gidx.ctypes.data), syn_ptrs, w_ptrs,
+        rc = rep.psb_replay(srv._h, ctypes.c_int64(n), ctypes.c_void_p(gidx.ctypes.data), syn_ptrs,
+                            ctypes.c_void_p(wts.ctypes.data),
                             ctypes.c_void_p(arr.ctypes.data) if arr is not None else ctypes.c_void_p(0),
                             ctypes.c_void_p(lat.ctypes.data), ctypes.c_void_p(st.ctypes.data),
                             ctypes.byref(span), ctypes.byref(wall))
@@ -221,6 +240,7 @@ def serving(args):
     lat, t_sub, wall = run(arrivals)
     s2 = srv.stats()
     offered = n / t_sub
+    srv.close()
 
     def delta(a, b):
         nb, nw = b["batches"] - a["batches"], b["windows"] - a["windows"]
@@ -228,17 +248,58 @@ def serving(args):
                 "mean_queue_us": round((b["mean_queue_us"] * b["windows"] - a["mean_queue_us"] * a["windows"]) / max(nw, 1), 1),
                 "mean_batch_run_us": round((b["mean_batch_run_us"] * b["batches"] - a["mean_batch_run_us"] * a["batches"]) / max(nb, 1), 1),
                 "mean_launch_us": round((b["mean_launch_us"] * b["batches"] - a["mean_launch_us"] * a["batches"]) / max(nb, 1), 1)}
-    per_round = lat / 1e3 / np.asarray(ds)[kind]
-    srv.close()
+
+    dv = np.asarray(ds)[kind]
+    per_round = lat / 1e3 / dv
+
+    def pct(x, q):
+        return round(float(np.percentile(x, q)), 3)
+
+    # one-shot-per-launch form: the first m windows of the same stream
+    m = min(n, args.oneshot_windows)
+    decs = [psb.Decoder(u, tiebreak_seed=0x5EED) for u in units]
+    dec_arr = (ctypes.c_void_p * len(decs))(*[dd._h.value for dd in decs])
+    nbytes = np.ascontiguousarray([u.syndrome_bytes for u in units], np.int32)
+
+    def run1(arr):
+        lat1 = np.zeros(m, np.int64)
+        st1 = np.zeros(m, np.int32)
+        wall1 = ctypes.c_double()
+        a1 = None if arr is None else np.ascontiguousarray(arr[:m], np.float64)
+        rc = rep.psb_replay_oneshot(dec_arr, ctypes.c_int32(len(decs)), ctypes.c_int64(m),
+                                    ctypes.c_void_p(gidx.ctypes.data), syn_ptrs, ctypes.c_void_p(nbytes.ctypes.data),
+                                    ctypes.c_void_p(a1.ctypes.data) if a1 is not None else ctypes.c_void_p(0),
+                                    ctypes.c_void_p(lat1.ctypes.data), ctypes.c_void_p(st1.ctypes.data),
+                                    ctypes.byref(wall1))
+        if rc != 0:
+            raise RuntimeError(f"psb_replay_oneshot failed ({rc})")
+        return lat1, wall1.value
+
+    log(f"one-shot-per-launch form on {m} windows")
+    run1(None)
+    lat1, wall1 = run1(None)
+    cap1 = m / wall1
+    lat1q, _ = run1(arrivals)
+    pr1 = lat1q / 1e3 / dv[:m]
+    pr1_alone = lat1 / 1e3 / dv[:m]
+    for dd in decs:
+        dd.close()
     out = {"metric": "serving: window latency, us per round (submit to completion)", "windows": n,
-           "distances": ds, "p_range": [0.001, 0.007], "capacity_windows_per_s": round(capacity, 1),
+           "distances": ds, "p_range": [p_lo, p_hi], "capacity_windows_per_s": round(capacity, 1),
            "target_load": args.serve_load, "offered_windows_per_s": round(offered, 1),
-           "p50_us_per_round": round(float(np.percentile(per_round, 50)), 3),
-           "p99_us_per_round": round(float(np.percentile(per_round, 99)), 3),
-           "per_d": {str(d): {"p50_us_per_round": round(float(np.percentile(per_round[kind == j], 50)), 3),
-                              "p99_us_per_round": round(float(np.percentile(per_round[kind == j], 99)), 3)}
+           "p50_us_per_round": pct(per_round, 50), "p99_us_per_round": pct(per_round, 99),
+           "per_d": {str(d): {"p50_us_per_round": pct(per_round[kind == j], 50),
+                              "p99_us_per_round": pct(per_round[kind == j], 99)}
                      for j, d in enumerate(ds)},
+           "autotuned": tuned,
            "server_capacity_run": delta(s0, s1), "server_load_run": delta(s1, s2),
+           "one_shot_per_launch": {
+               "windows": m, "capacity_windows_per_s": round(cap1, 1),
+               "alone_p50_us_per_round": pct(pr1_alone, 50), "alone_p99_us_per_round": pct(pr1_alone, 99),
+               "same_stream_p50_us_per_round": pct(pr1, 50), "same_stream_p99_us_per_round": pct(pr1, 99),
+               "basis": "one window per psb_decode_batch launch in arrival order (copy in, decode, copy out, "
+                        "wait); 'alone' = back to back without queueing, 'same_stream' = the first windows of "
+                        "the served Poisson stream, queueing included"},
            "driver": "native replay thread (libpsb_replay.so): submits at the arrival times, a second thread "
                      "collects completions"}
     print(json.dumps(out), flush=True)
@@ -272,6 +333,9 @@ def main():
                          "0.007] (uniform per-window weight), Poisson arrivals at --serve-load x the measured "
                          "capacity for the mix")
     ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-dists", default="9,13,17,21,25")
+    ap.add_argument("--serve-p", default="0.001,0.007", help="window noise rates drawn uniformly from this range")
+    ap.add_argument("--oneshot-windows", type=int, default=3000)
     args = ap.parse_args()
     if args.serve:
         serving(args)

@@ -246,6 +246,17 @@ int32_t psb_server_create(const psb_graph* const* graphs, int32_t n_graphs, cons
  * request. */
 int32_t psb_server_submit(psb_server* s, int32_t graph_idx, const uint8_t* syndrome_host,
                           const int32_t* w_override, uint64_t* ticket);
+/* Queues n windows under one lock: window i decodes on graph graph_idx[i]
+ * with syndrome syndromes[i] (host memory, copied before the call returns);
+ * uniform_weight NULL or uniform_weight[i] == 0 = the graph's weights,
+ * uniform_weight[i] > 0 = that weight on every edge (as a uniform
+ * w_override in psb_server_submit).  tickets[n] receives the tickets.  On an
+ * error in window i, windows before i stay queued (their tickets written).
+ * Errors: PSB_E_INVALID (checked for every window before any is queued),
+ * PSB_E_NOMEM, PSB_E_DEVICE, PSB_E_UNSUPPORTED. */
+int32_t psb_server_submit_many(psb_server* s, int32_t n, const int32_t* graph_idx,
+                               const uint8_t* const* syndromes, const int32_t* uniform_weight,
+                               uint64_t* tickets);
 /* Non-blocking: *done = 0 while the window is pending; once done, copies the
  * results to the host pointers (any may be NULL; edges gets at most
  * edges_cap ids, status PSB_S_EDGES_TRUNCATED if more exist), writes the

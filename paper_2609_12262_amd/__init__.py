@@ -75,7 +75,7 @@ def lib():
                      "psb_decode_batch", "psb_decoder_levels", "psb_decoder_edges_per_shot",
                      "psb_decoder_max_defects", "psb_graph_syndrome_bytes", "psb_schedule_levels",
                      "psb_decoder_slots", "psb_decoder_last_overflow", "psb_decoder_device_bytes", "psb_decoder_reserve",
-                     "psb_server_create", "psb_server_submit", "psb_server_poll", "psb_server_collect",
+                     "psb_server_create", "psb_server_submit", "psb_server_submit_many", "psb_server_poll", "psb_server_collect",
                      "psb_server_stats", "psb_server_destroy", "psb_autotune", "psb_autotune_candidates",
                      "psb_batch_graph_create", "psb_batch_graph_launch", "psb_batch_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int32
@@ -323,6 +323,19 @@ class Server:
         _check(lib().psb_server_submit(self._h, ctypes.c_int32(graph_idx), ctypes.c_void_p(syn.ctypes.data), wp,
                                        ctypes.byref(t)), "psb_server_submit")
         return t.value
+
+    def submit_many(self, graph_idx, syndromes, uniform_weight=None) -> list:
+        """Queue several windows in one call; uniform_weight[i] = 0 keeps the graph's weights."""
+        n = len(syndromes)
+        rows = [np.ascontiguousarray(r, np.uint8) for r in syndromes]
+        ptrs = (ctypes.c_void_p * n)(*[r.ctypes.data for r in rows])
+        gi = np.ascontiguousarray(graph_idx, np.int32)
+        uw = None if uniform_weight is None else np.ascontiguousarray(uniform_weight, np.int32)
+        t = np.zeros(n, np.uint64)
+        _check(lib().psb_server_submit_many(self._h, ctypes.c_int32(n), ctypes.c_void_p(gi.ctypes.data), ptrs,
+                                            ctypes.c_void_p(uw.ctypes.data) if uw is not None else ctypes.c_void_p(0),
+                                            ctypes.c_void_p(t.ctypes.data)), "psb_server_submit_many")
+        return [int(x) for x in t]
 
     def poll(self, ticket: int, edges_cap: int = 1024):
         """None while pending, else dict(weight, obs, edges, status, latency_ns)."""

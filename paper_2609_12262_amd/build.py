@@ -25,11 +25,11 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     # load replay tool for the serving benchmark (links against libpsb.so)
     rtmp = REPLAY + f".tmp{os.getpid()}"
-    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", rtmp,
+    cmd = ["hipcc", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", rtmp,
            os.path.join(HERE, "csrc", "serve_replay.cpp"), "-L" + HERE, "-lpsb", "-Wl,-rpath,$ORIGIN", "-pthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError("g++ failed:\n" + r.stderr[-4000:])
+        raise RuntimeError("hipcc (replay tool) failed:\n" + r.stderr[-4000:])
     os.replace(rtmp, REPLAY)
     return LIB
 

@@ -330,6 +330,25 @@ extern "C" int32_t psb_server_create(const psb_graph* const* graphs, int32_t n_g
   return PSB_OK;
 }
 
+// Queues one window (lock held): gi = group index, scale = weight multiplier.
+static int32_t enqueue(psb_server* S, int gi, int64_t scale, const uint8_t* syndrome_host, Clock::time_point t_submit,
+                       uint64_t* ticket) {
+  if (!S->groups[gi]) {
+    const int32_t rc = make_group(S, gi);
+    if (rc != PSB_OK) return rc;
+  }
+  Group* G = S->groups[gi].get();
+  const uint64_t t = S->next_ticket++;
+  Request& R = S->reqs[t];
+  R.group = gi;
+  R.scale = scale;
+  R.synd.assign(syndrome_host, syndrome_host + G->nbytes);
+  R.t_submit = t_submit;
+  G->pending.push_back(t);
+  *ticket = t;
+  return PSB_OK;
+}
+
 extern "C" int32_t psb_server_submit(psb_server* S, int32_t graph_idx, const uint8_t* syndrome_host,
                                      const int32_t* w_override, uint64_t* ticket) {
   if (!S || !syndrome_host || !ticket) return fail(PSB_E_INVALID, "null argument");
@@ -347,19 +366,27 @@ extern "C" int32_t psb_server_submit(psb_server* S, int32_t graph_idx, const uin
   }
   const auto t_submit = Clock::now();
   std::lock_guard<std::mutex> lk(S->mu);
-  if (!S->groups[gi]) {
-    const int32_t rc = make_group(S, gi);
-    if (rc != PSB_OK) return rc;
+  const int32_t rc = enqueue(S, gi, scale, syndrome_host, t_submit, ticket);
+  if (rc == PSB_OK) S->cv.notify_all();
+  return rc;
+}
+
+extern "C" int32_t psb_server_submit_many(psb_server* S, int32_t n, const int32_t* graph_idx,
+                                          const uint8_t* const* syndromes, const int32_t* uniform_weight,
+                                          uint64_t* tickets) {
+  if (!S || n < 0 || (n > 0 && (!graph_idx || !syndromes || !tickets))) return fail(PSB_E_INVALID, "null argument");
+  for (int32_t i = 0; i < n; ++i) {
+    if (graph_idx[i] < 0 || graph_idx[i] >= (int32_t)S->graphs.size()) return fail(PSB_E_INVALID, "graph_idx out of range");
+    if (!syndromes[i]) return fail(PSB_E_INVALID, "null syndrome");
+    if (uniform_weight && uniform_weight[i] < 0) return fail(PSB_E_INVALID, "weights must be positive");
   }
-  Group* G = S->groups[gi].get();
-  const uint64_t t = S->next_ticket++;
-  Request& R = S->reqs[t];
-  R.group = gi;
-  R.scale = scale;
-  R.synd.assign(syndrome_host, syndrome_host + G->nbytes);
-  R.t_submit = t_submit;
-  G->pending.push_back(t);
-  *ticket = t;
+  const auto t_submit = Clock::now();
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t w = uniform_weight ? uniform_weight[i] : 0;
+    const int32_t rc = enqueue(S, 2 * graph_idx[i] + (w > 0 ? 1 : 0), w > 0 ? w : 1, syndromes[i], t_submit, &tickets[i]);
+    if (rc != PSB_OK) { S->cv.notify_all(); return rc; }      // windows 0..i-1 stay queued
+  }
   S->cv.notify_all();
   return PSB_OK;
 }

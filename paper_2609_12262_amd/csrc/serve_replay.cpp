@@ -1,9 +1,13 @@
 // Load replay for the serving runtime (measurement tool, not on the decoding
 // path): submits windows at given arrival times from a native thread while a
 // second thread collects completions, so that the offered load is not
-// limited by an interpreter.  Built as libpsb_replay.so next to libpsb.so.
+// limited by an interpreter; and the same stream decoded one window per
+// launch, for comparison.  Built as libpsb_replay.so next to libpsb.so.
+#include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <thread>
@@ -13,12 +17,11 @@
 #include "../../include/psb.h"
 
 extern "C" int32_t psb_replay(psb_server* s, int64_t n, const int32_t* graph_idx, const uint8_t* const* syndromes,
-                              const int32_t* const* w_override, const double* arrival_s, int64_t* latency_ns,
+                              const int32_t* uniform_weight, const double* arrival_s, int64_t* latency_ns,
                               int32_t* status, double* submit_span_s, double* wall_s) {
   if (!s || n <= 0 || !graph_idx || !syndromes || !latency_ns || !status) return -1;
   std::vector<uint64_t> tickets(n, 0);
-  std::unordered_map<uint64_t, int64_t> index;
-  index.reserve((size_t)n * 2);
+  std::vector<int64_t> lag(n, 0);       // arrival to submission, added to the server's latency
   std::atomic<int64_t> submitted{0};
   std::atomic<int32_t> error{0};
   using Clock = std::chrono::steady_clock;
@@ -28,6 +31,7 @@ extern "C" int32_t psb_replay(psb_server* s, int64_t n, const int32_t* graph_idx
     std::vector<int64_t> lat(4096);
     std::vector<int32_t> st(4096);
     std::unordered_map<uint64_t, int64_t> local;
+    local.reserve((size_t)n * 2);
     int64_t got = 0, seen = 0;
     while (got < n && !error.load()) {
       const int32_t k = psb_server_collect(s, 4096, t.data(), nullptr, nullptr, st.data(), lat.data());
@@ -43,27 +47,106 @@ extern "C" int32_t psb_replay(psb_server* s, int64_t n, const int32_t* graph_idx
           it = local.find(t[j]);
           if (it == local.end()) { error = 2; break; }
         }
-        latency_ns[it->second] = lat[j];
+        latency_ns[it->second] = lat[j] + lag[it->second];
         status[it->second] = st[j];
         ++got;
       }
       if (k == 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
   });
-  for (int64_t i = 0; i < n && !error.load(); ++i) {
+  // windows whose arrival time has passed are submitted together (at most 1024 per call)
+  constexpr int64_t kBurst = 1024;
+  int64_t i = 0;
+  while (i < n && !error.load()) {
     if (arrival_s) {
       while (std::chrono::duration<double>(Clock::now() - t0).count() < arrival_s[i]) {}
     }
-    uint64_t t = 0;
-    if (psb_server_submit(s, graph_idx[i], syndromes[i], w_override ? w_override[i] : nullptr, &t) != 0) {
+    int64_t j = i + 1;
+    if (arrival_s) {
+      const double now = std::chrono::duration<double>(Clock::now() - t0).count();
+      while (j < n && j - i < kBurst && arrival_s[j] <= now) ++j;
+    } else {
+      j = std::min<int64_t>(n, i + kBurst);
+    }
+    if (arrival_s) {
+      const double now = std::chrono::duration<double>(Clock::now() - t0).count();
+      for (int64_t k = i; k < j; ++k) lag[k] = (int64_t)((now - arrival_s[k]) * 1e9);
+    }
+    if (psb_server_submit_many(s, (int32_t)(j - i), graph_idx + i, syndromes + i,
+                               uniform_weight ? uniform_weight + i : nullptr, tickets.data() + i) != 0) {
       error = 3;
       break;
     }
-    tickets[i] = t;
-    submitted.store(i + 1, std::memory_order_release);
+    submitted.store(j, std::memory_order_release);
+    i = j;
   }
   if (submit_span_s) *submit_span_s = std::chrono::duration<double>(Clock::now() - t0).count();
   collector.join();
   if (wall_s) *wall_s = std::chrono::duration<double>(Clock::now() - t0).count();
   return error.load() ? -error.load() : 0;
+}
+
+// The one-shot-per-launch form on the same stream of windows: one thread
+// takes the windows in arrival order and decodes each alone (copy in, one
+// psb_decode_batch of one shot, copy results out, wait), so a window that
+// arrives while another decodes waits for it.  decs[dec_idx[i]] decodes
+// window i; latency = completion minus arrival (minus the start of its own
+// decode when arrival_s is NULL, i.e. back to back).
+extern "C" int32_t psb_replay_oneshot(psb_decoder* const* decs, int32_t n_dec, int64_t n, const int32_t* dec_idx,
+                                      const uint8_t* const* syndromes, const int32_t* syndrome_bytes,
+                                      const double* arrival_s, int64_t* latency_ns, int32_t* status,
+                                      double* wall_s) {
+  if (!decs || n_dec <= 0 || n <= 0 || !dec_idx || !syndromes || !syndrome_bytes || !latency_ns || !status)
+    return -1;
+  int32_t max_bytes = 1, max_stride = 1;
+  for (int32_t j = 0; j < n_dec; ++j) {
+    max_bytes = std::max(max_bytes, syndrome_bytes[j]);
+    max_stride = std::max(max_stride, psb_decoder_edges_per_shot(decs[j]));
+  }
+  hipStream_t s = nullptr;
+  uint8_t *d_synd = nullptr, *h_synd = nullptr;
+  int32_t *d_edges = nullptr, *d_small = nullptr, *h_edges = nullptr, *h_small = nullptr;
+  int64_t* d_w = nullptr; uint64_t* d_obs = nullptr;
+  int32_t rc = 0;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+      hipMalloc((void**)&d_synd, max_bytes) != hipSuccess ||
+      hipMalloc((void**)&d_edges, 4 * (size_t)max_stride) != hipSuccess ||
+      hipMalloc((void**)&d_small, 32) != hipSuccess || hipMalloc((void**)&d_w, 8) != hipSuccess ||
+      hipMalloc((void**)&d_obs, 8) != hipSuccess ||
+      hipHostMalloc((void**)&h_synd, max_bytes, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&h_edges, 4 * (size_t)max_stride + 64, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&h_small, 64, hipHostMallocDefault) != hipSuccess)
+    rc = -2;
+  using Clock = std::chrono::steady_clock;
+  const auto t0 = Clock::now();
+  for (int64_t i = 0; i < n && rc == 0; ++i) {
+    const int32_t j = dec_idx[i];
+    if (j < 0 || j >= n_dec) { rc = -1; break; }
+    Clock::time_point t_arr;
+    if (arrival_s) {
+      t_arr = t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[i]));
+      while (Clock::now() < t_arr) {}
+    } else {
+      t_arr = Clock::now();
+    }
+    memcpy(h_synd, syndromes[i], syndrome_bytes[j]);
+    const int32_t stride = psb_decoder_edges_per_shot(decs[j]);
+    bool ok = hipMemcpyAsync(d_synd, h_synd, syndrome_bytes[j], hipMemcpyHostToDevice, s) == hipSuccess &&
+              psb_decode_batch(decs[j], d_synd, 1, d_edges, d_small, d_w, d_obs, d_small + 1, nullptr, nullptr,
+                               nullptr, s) == PSB_OK &&
+              hipMemcpyAsync(h_small, d_small, 8, hipMemcpyDeviceToHost, s) == hipSuccess &&
+              hipMemcpyAsync(h_small + 2, d_w, 8, hipMemcpyDeviceToHost, s) == hipSuccess &&
+              hipMemcpyAsync(h_small + 4, d_obs, 8, hipMemcpyDeviceToHost, s) == hipSuccess &&
+              hipMemcpyAsync(h_edges, d_edges, 4 * (size_t)stride, hipMemcpyDeviceToHost, s) == hipSuccess &&
+              hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) { rc = -3; break; }
+    latency_ns[i] = std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t_arr).count();
+    status[i] = h_small[1];
+  }
+  if (wall_s) *wall_s = std::chrono::duration<double>(Clock::now() - t0).count();
+  if (s) (void)hipStreamSynchronize(s);
+  for (void* p : {(void*)d_synd, (void*)d_edges, (void*)d_small, (void*)d_w, (void*)d_obs}) if (p) (void)hipFree(p);
+  for (void* p : {(void*)h_synd, (void*)h_edges, (void*)h_small}) if (p) (void)hipHostFree(p);
+  if (s) (void)hipStreamDestroy(s);
+  return rc;
 }
