@@ -58,7 +58,8 @@ def kernel_source_hash():
 
 def decoder_config_key(kw):
     return (f"first_tier={kw.get('first_tier', 0)} state={kw.get('fast_max_nodes', 0)}/"
-            f"{kw.get('fast_max_regions', 0)} q={kw.get('q', (1, 10))[0]}/{kw.get('q', (1, 10))[1]}")
+            f"{kw.get('fast_max_regions', 0)} lds_state={kw.get('fast_lds_state', 0)} "
+            f"q={kw.get('q', (1, 10))[0]}/{kw.get('q', (1, 10))[1]}")
 
 
 def measured_traffic(d, p, shots, kw):
@@ -128,8 +129,13 @@ def latency_scaling(args):
         g = synth.rotated_phenom_graph(d, p)
         shots = synth.sample(g, args.latency_shots, seed=10 + d)
         G = psb.Graph.from_synth(g)
-        dec = psb.Decoder(G, tiebreak_seed=0x5EED, mode=args.mode)
         synd = torch.from_numpy(shots.syndromes).cuda()
+        kw = dict(tiebreak_seed=0x5EED, mode=args.mode)
+        if not args.no_autotune:
+            # a batch of 64 shots, one per wavefront on an otherwise idle device, lasts about as long as its
+            # slowest shot alone: the tuner's proxy for one-shot latency
+            kw, _ = psb.autotune(G, synd[:64].contiguous(), reps=2, **kw)
+        dec = psb.Decoder(G, **kw)
         out = dec.alloc(1, timestamps=True)
         stream = torch.cuda.current_stream()
         for i in range(min(3, args.latency_shots)):          # warm-up launches
@@ -151,6 +157,8 @@ def latency_scaling(args):
         ev_us = np.array(ev_ms) * 1e3
         dev_us = np.array(dev_us)
         rows.append({"d": d, "rounds": d, "detectors": g.num_detectors, "shots": args.latency_shots,
+                     "decoder": {"first_tier_state": [kw.get("fast_max_nodes", 0), kw.get("fast_max_regions", 0)],
+                                 "lds_state": kw.get("fast_lds_state", 0), "q": list(kw.get("q", (1, 10)))},
                      "defects_mean": float(np.unpackbits(shots.syndromes, axis=1, bitorder="little")
                                            [:, :g.num_detectors].sum(1).mean()),
                      "overflow_tier_shots": ovf,
@@ -201,7 +209,7 @@ def serving(args):
         best, _ = psb.autotune(units[j], torch.from_numpy(np.stack(sel)).cuda(), reps=1, **base)
         opts.append(best)
         tuned[str(d)] = {"first_tier": best["first_tier"], "state": [best["fast_max_nodes"], best["fast_max_regions"]],
-                         "q": list(best["q"])}
+                         "lds_state": best["fast_lds_state"], "q": list(best["q"])}
     log(f"autotuned {tuned}")
     srv = psb.Server(Gs, opts=opts)
     psb.lib()
@@ -431,12 +439,14 @@ def main():
                    "mode": "partition-and-fuse" if args.mode == 0 else "global sparse blossom",
                    "first_tier": "one shot per lane" if kw.get("first_tier", 0) else "one shot per wavefront",
                    "first_tier_state": [kw.get("fast_max_nodes", 0), kw.get("fast_max_regions", 0)],
+                   "first_tier_lds_state": kw.get("fast_lds_state", 0),
                    "schedule_q": list(kw.get("q", (1, 10))),
                    "first_tier_slots": dec.fast_slots, "overflow_tier_slots": dec.overflow_slots,
                    "overflow_shots": dec.last_overflow(), "hip_graph": not args.no_graph,
                    "autotune": None if tune_table is None else
                    [{"first_tier": t["first_tier"], "state": [t["fast_max_nodes"], t["fast_max_regions"]],
-                     "q": list(t["q"]), "ms": t["ms"], "status": t["status"]} for t in tune_table]},
+                     "lds_state": t["fast_lds_state"], "q": list(t["q"]), "ms": t["ms"], "status": t["status"]}
+                    for t in tune_table]},
         "latency_us_per_round": {"p50": round(float(np.percentile(per_round, 50)), 3),
                                  "p99": round(float(np.percentile(per_round, 99)), 3),
                                  "basis": "batch submission to shot completion (device clock), last step"},

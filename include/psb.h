@@ -97,6 +97,13 @@ typedef struct {
    * report PSB_S_CAPACITY. */
   int32_t fast_max_nodes, fast_max_regions, overflow_slots;
   int32_t first_tier;
+  /* Placement of the wavefront first tier's per-shot state (first_tier = 0):
+   * 0 or 1 = event cache, region bases and radius offsets in the wavefront's
+   * global workspace slot, the rest in LDS (default; most wavefronts per CU);
+   * 2 = radius offsets in the workspace, event cache and region bases in LDS;
+   * 3 = all per-shot state in LDS (fewest dependent global loads per event,
+   * fewer wavefronts per CU).  Results do not depend on it. */
+  int32_t fast_lds_state;
 } psb_decoder_opts;
 
 /* Builds the decoder: tie-broken weights, level parameters d_k, b_k (exact
@@ -177,7 +184,7 @@ int32_t psb_decoder_reserve(psb_decoder* d, int64_t max_batch);
 /* Autotuner.  Decodes a sample batch `syndromes` (DEVICE, [n][ceil(num_detectors/8)])
  * with each of psb_autotune_candidates() configurations built from `base`
  * (NULL = defaults) by overriding first_tier, fast_max_nodes,
- * fast_max_regions and the schedule ratio q; times `reps` launches of each
+ * fast_max_regions, fast_lds_state and the schedule ratio q; times `reps` launches of each
  * (after one warm-up) with HIP events on `stream` and writes one record per
  * candidate to entries[0 .. psb_autotune_candidates()-1]: its options, the
  * fastest launch in milliseconds (-1 if skipped) and its status (PSB_OK, or

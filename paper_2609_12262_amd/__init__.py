@@ -39,7 +39,8 @@ class _DecoderOpts(ctypes.Structure):
                 ("boundary_reading", ctypes.c_int32), ("max_defects_per_shot", ctypes.c_int32),
                 ("edges_per_shot", ctypes.c_int32), ("num_slots", ctypes.c_int32),
                 ("fast_max_nodes", ctypes.c_int32), ("fast_max_regions", ctypes.c_int32),
-                ("overflow_slots", ctypes.c_int32), ("first_tier", ctypes.c_int32)]
+                ("overflow_slots", ctypes.c_int32), ("first_tier", ctypes.c_int32),
+                ("fast_lds_state", ctypes.c_int32)]
 
 
 class _TuneEntry(ctypes.Structure):
@@ -48,10 +49,11 @@ class _TuneEntry(ctypes.Structure):
 
 def _make_opts(tiebreak_seed: int = 0x5EED, mode: int = 0, boundary_reading: int = 0, max_defects: int = 0,
                edges_per_shot: int = 0, num_slots: int = 0, q=(1, 10), phi_min=(1, 100), fast_max_nodes: int = 0,
-               fast_max_regions: int = 0, overflow_slots: int = 0, first_tier: int = 0) -> _DecoderOpts:
+               fast_max_regions: int = 0, overflow_slots: int = 0, first_tier: int = 0,
+               fast_lds_state: int = 0) -> _DecoderOpts:
     return _DecoderOpts(q[0], q[1], phi_min[0], phi_min[1], tiebreak_seed & ((1 << 64) - 1), mode,
                         boundary_reading, max_defects, edges_per_shot, num_slots, fast_max_nodes,
-                        fast_max_regions, overflow_slots, first_tier)
+                        fast_max_regions, overflow_slots, first_tier, fast_lds_state)
 
 
 def _opts_kwargs(o: _DecoderOpts) -> dict:
@@ -60,7 +62,7 @@ def _opts_kwargs(o: _DecoderOpts) -> dict:
             "max_defects": o.max_defects_per_shot, "edges_per_shot": o.edges_per_shot, "num_slots": o.num_slots,
             "q": (o.q_num, o.q_den), "phi_min": (o.phi_min_num, o.phi_min_den),
             "fast_max_nodes": o.fast_max_nodes, "fast_max_regions": o.fast_max_regions,
-            "overflow_slots": o.overflow_slots, "first_tier": o.first_tier}
+            "overflow_slots": o.overflow_slots, "first_tier": o.first_tier, "fast_lds_state": o.fast_lds_state}
 
 
 def lib():
@@ -157,10 +159,10 @@ class Decoder:
     def __init__(self, graph: Graph, tiebreak_seed: int = 0x5EED, mode: int = MODE_PARTITION,
                  boundary_reading: int = 0, max_defects: int = 0, edges_per_shot: int = 0,
                  num_slots: int = 0, q=(1, 10), phi_min=(1, 100), fast_max_nodes: int = 0,
-                 fast_max_regions: int = 0, overflow_slots: int = 0, first_tier: int = 0):
+                 fast_max_regions: int = 0, overflow_slots: int = 0, first_tier: int = 0, fast_lds_state: int = 0):
         self.graph = graph
         opts = _make_opts(tiebreak_seed, mode, boundary_reading, max_defects, edges_per_shot, num_slots, q, phi_min,
-                          fast_max_nodes, fast_max_regions, overflow_slots, first_tier)
+                          fast_max_nodes, fast_max_regions, overflow_slots, first_tier, fast_lds_state)
         h = ctypes.c_void_p()
         _check(lib().psb_decoder_create(graph._h, ctypes.byref(opts), ctypes.byref(h)), "psb_decoder_create")
         self._h = h

@@ -233,6 +233,7 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   // workspace slot; or one shot per wavefront, state in LDS) and the
   // overflow tier (one shot per wavefront, large LDS state)
   if (opts.first_tier != 0 && opts.first_tier != 1) { delete D; return fail(PSB_E_INVALID, "first_tier must be 0 or 1"); }
+  if (opts.fast_lds_state < 0 || opts.fast_lds_state > 3) { delete D; return fail(PSB_E_INVALID, "fast_lds_state must be 0..3"); }
   D->first_lane = opts.first_tier == 1;
   psb::Caps cf, co;
   co.xcap = std::min(n, 1024); co.rcap = std::min(4 * dcap + 64, 768);
@@ -248,10 +249,12 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   cf.hcap = direct ? 0 : next_pow2(2LL * cf.xcap);
   Params& PF = D->P_fast;
   Params& PO = D->P_ovf;
-  // the wavefront first tier keeps its event cache, region bases and radius
-  // offsets in the workspace: its LDS block (about 10 KB at the default
-  // capacities) lets 16 wavefronts share a CU
-  plan_tier(PF, n, g->deg, g->n_edges, cf, D->first_lane, D->first_lane ? 0 : 2);
+  // by default the wavefront first tier keeps its event cache, region bases
+  // and radius offsets in the workspace: its LDS block (about 10 KB at the
+  // default capacities) lets 16 wavefronts share a CU.  fast_lds_state moves
+  // them into LDS (fewer wavefronts per CU, shorter dependent-load chains).
+  static const int kLean[4] = {2, 2, 1, 0};
+  plan_tier(PF, n, g->deg, g->n_edges, cf, D->first_lane, D->first_lane ? 0 : kLean[opts.fast_lds_state]);
   plan_tier(PO, n, g->deg, g->n_edges, co, false);
   for (Params* P : {&PF, &PO}) {
     P->n_levels = (int32_t)D->sched.d.size(); P->reading = opts.boundary_reading; P->mode = opts.mode;

@@ -3,7 +3,8 @@
 // and reports the fastest.  The candidates vary what changes speed but not
 // results: the first tier's shape (one shot per wavefront with the hot state
 // in LDS, or one shot per lane), its state capacity (detectors and regions
-// per shot before a shot moves to the overflow tier) and the clustering
+// per shot before a shot moves to the overflow tier), where its per-shot
+// state lives (LDS or the global workspace slot) and the clustering
 // schedule's ratio q (Methods, Algorithm "Parameter schedule"; the
 // partition-and-fuse result equals the serial MWEM for every admissible
 // schedule).  Every candidate's weights and observable flips are compared
@@ -22,13 +23,15 @@ using psb_host::fail;
 
 namespace {
 
-struct Candidate { int32_t first_tier, nodes, regions; int64_t q_num, q_den; };
+struct Candidate { int32_t first_tier, nodes, regions, lds_state; int64_t q_num, q_den; };
 
-// wave tier: hot state in LDS, so capacity trades against waves per CU
+// wave tier: its state lives in LDS, so capacity and placement trade against
+// wavefronts per CU
 constexpr Candidate kCandidates[] = {
-    {0, 320, 208, 1, 10}, {0, 480, 320, 1, 10}, {0, 640, 416, 1, 10}, {0, 896, 560, 1, 10},
-    {0, 320, 208, 1, 4},  {0, 640, 416, 1, 4},
-    {1, 320, 256, 1, 10}, {1, 640, 512, 1, 10},
+    {0, 320, 208, 0, 1, 10}, {0, 480, 320, 0, 1, 10}, {0, 640, 416, 0, 1, 10}, {0, 896, 560, 0, 1, 10},
+    {0, 320, 208, 2, 1, 10}, {0, 320, 208, 3, 1, 10}, {0, 640, 416, 3, 1, 10}, {0, 1024, 768, 3, 1, 10},
+    {0, 320, 208, 0, 1, 4},  {0, 640, 416, 0, 1, 4},
+    {1, 320, 256, 0, 1, 10}, {1, 640, 512, 0, 1, 10},
 };
 
 struct DevBuf {
@@ -69,6 +72,7 @@ extern "C" int32_t psb_autotune(const psb_graph* g, const psb_decoder_opts* base
     E.opts.first_tier = kCandidates[c].first_tier;
     E.opts.fast_max_nodes = kCandidates[c].nodes;
     E.opts.fast_max_regions = kCandidates[c].regions;
+    E.opts.fast_lds_state = kCandidates[c].lds_state;
     E.opts.q_num = kCandidates[c].q_num;
     E.opts.q_den = kCandidates[c].q_den;
     E.ms = -1.0f;

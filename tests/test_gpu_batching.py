@@ -72,7 +72,7 @@ def test_autotune_candidates_agree_and_best_matches_oracle():
     assert min(t["ms"] for t in ok) == [t for t in table if all(t[k] == best[k] for k in best)][0]["ms"]
     G.close()
     s2 = synth.sample(g, 3000, seed=81)
-    kw = {k: best[k] for k in ("fast_max_nodes", "fast_max_regions", "first_tier")}
+    kw = {k: best[k] for k in ("fast_max_nodes", "fast_max_regions", "first_tier", "fast_lds_state")}
     res = gpu_decode(g, s2.syndromes, **kw)
     bad = compare(g, s2.syndromes, res, range(0, 3000, 20))
     assert not bad, bad[:5]
@@ -93,5 +93,18 @@ def test_schedule_ratio_does_not_change_result(q):
     res = _host(out)
     res["obs"] = res["obs"].view(np.uint64)
     dec.close(); G.close()
+    bad = compare(g, s.syndromes, res, range(3000))
+    assert not bad, bad[:5]
+
+
+@pytest.mark.parametrize("lds_state,caps", [(2, (0, 0)), (3, (0, 0)), (3, (1024, 768))])
+def test_first_tier_state_placement_parity(lds_state, caps):
+    """Where the first tier keeps its per-shot state (LDS or workspace) does
+    not change results: d=13, p=0.005, every shot equals the oracle."""
+    g = synth.rotated_phenom_graph(13, 0.005)
+    s = synth.sample(g, 3000, seed=91)
+    res = gpu_decode(g, s.syndromes, fast_lds_state=lds_state, fast_max_nodes=caps[0], fast_max_regions=caps[1],
+                     want_overflow=True)
+    say(f"lds_state={lds_state} caps={caps}: {res['n_overflow']} shots in the overflow tier")
     bad = compare(g, s.syndromes, res, range(3000))
     assert not bad, bad[:5]
