@@ -225,20 +225,22 @@ int32_t psb_graph_syndrome_bytes(const psb_graph* g);
  *
  * Requests are grouped per (graph, weight set): the graph's own weights, or,
  * for requests that carry a uniform per-request weight, the graph with unit
- * weights (made on first use).  Each group holds 4 decoders built with that
- * graph's options (`opts`: NULL, or an array of n_graphs records, one per
- * graph; zeros here select edges_per_shot 1024, num_slots 1024 and
- * overflow_slots 256), each with its own stream (or `stream` for all when it
- * is not NULL) and pinned batch buffers, so up to 4 batches of one group are
- * on the device at once.  A worker thread launches the pending requests of
- * a group on any of its idle decoders as one psb_decode_batch launch (up to
- * num_slots shots, one per slot), copies results to pinned host memory and
- * completes the tickets; requests that arrive meanwhile wait for the next
- * idle decoder.  Each result is identical to psb_decode_batch on that
+ * weights (made on first use).  Batches run on a pool of 4 pipes, each a
+ * stream (its own, or `stream` for all when it is not NULL) with pinned and
+ * device batch buffers; every group holds one decoder per pipe, built with
+ * that graph's options (`opts`: NULL, or an array of n_graphs records, one
+ * per graph; zeros here select edges_per_shot 1024, num_slots 1024 and
+ * overflow_slots 256).  Whenever a pipe is idle, a worker thread gives it
+ * the group whose oldest waiting window is oldest, as one psb_decode_batch
+ * launch of up to num_slots windows (one per first-tier slot), copies the
+ * results to pinned host memory and completes the tickets.  Windows that
+ * arrive meanwhile wait for the next idle pipe; no batch is queued behind
+ * another on a stream.  Each result is identical to psb_decode_batch on that
  * window alone: a shot's decoding does not depend on the other shots of its
  * batch (Results, "Decoding task": every window is an independent MWEM).
  * device_mem_budget > 0 bounds the bytes of decoders and batch buffers
- * (batches shrink to fit; PSB_E_NOMEM if a 64-shot batch does not).
+ * (pipe buffers take at most half and shrink to fit; PSB_E_NOMEM if 64-shot
+ * batches or a group's decoders do not fit).
  * All calls are thread-safe; one server per device.
  * Errors: PSB_E_INVALID, PSB_E_NOMEM, PSB_E_DEVICE, PSB_E_UNSUPPORTED. */
 typedef struct psb_server psb_server;

@@ -1,15 +1,19 @@
-// Serving runtime: windows (shots) submitted one at a time from host threads
-// while earlier ones decode.  A worker thread groups pending requests per
-// (graph, weight class) into batches, runs each batch as one psb_decode_batch
-// launch on that group's stream (groups of different graphs run
-// concurrently), copies the results to pinned host memory and completes the
-// tickets.  A result is identical to decoding the same syndrome alone with
-// psb_decode_batch: the decoder is per graph and per weight set, and a shot's
-// result does not depend on the other shots of its batch.
+// Serving runtime: windows (shots) submitted from host threads while earlier
+// ones decode.  Requests are grouped per (graph, weight class).  A small pool
+// of pipes (a stream, pinned and device batch buffers, and one decoder per
+// group) runs batches: whenever a pipe is idle the worker thread gives it the
+// group whose oldest waiting window is oldest, as one psb_decode_batch launch,
+// copies the results to pinned host memory and completes the tickets.  A pipe
+// only ever receives work while idle, so no batch waits behind another on a
+// stream or hardware queue.  A result is identical to decoding the same
+// syndrome alone with psb_decode_batch: the decoder is per graph and per
+// weight set, and a shot's result does not depend on the other shots of its
+// batch.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -42,14 +46,17 @@ struct Request {
   Clock::time_point t_submit, t_done;
 };
 
-// One in-flight batch: a decoder of the group's graph, its stream and batch
-// buffers (two batches of one decoder would share its per-slot workspaces,
-// so concurrent batches use separate decoders).
+// Pipes (streams with batch buffers).  One per hardware queue of the default
+// HIP configuration: every pipe's stream then has a queue of its own.
+constexpr int kPipes = 4;
+
+// One stream and its batch buffers; it runs one batch at a time, of any
+// group, on that group's decoder for this pipe (two batches of one decoder
+// would share its per-slot workspaces).
 struct Pipe {
-  psb_decoder* dec = nullptr;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  int64_t max_batch = 0;
+  int64_t cap = 0;                   // shots the buffers hold
   uint8_t *h_synd = nullptr, *d_synd = nullptr;
   int32_t *d_edges = nullptr, *d_ne = nullptr, *d_st = nullptr;
   int64_t* d_w = nullptr; uint64_t* d_obs = nullptr;
@@ -57,23 +64,22 @@ struct Pipe {
   int64_t* h_w = nullptr; uint64_t* h_obs = nullptr;
   hipEvent_t done_ev = nullptr;
   std::vector<uint64_t> inflight;
-  bool busy = false;
+  int group = -1;                    // group of the batch in flight, -1 = idle
   Clock::time_point t_launch;
 };
 
-// Requests of one (graph, weight set): a FIFO and kPipes batches in flight.
+// Requests of one (graph, weight set): a FIFO and one decoder per pipe, all
+// made with the group (decoder set-up synchronises the device, so making one
+// while batches run would stall them).
 struct Group {
   int32_t graph_idx = 0;
   const psb_graph* graph = nullptr;
   psb_graph* own_graph = nullptr;    // unit-weight copy owned by the server, else null
   int32_t nbytes = 0, stride = 0;
+  int64_t max_batch = 0;             // shots per launch: one per first-tier slot
   std::deque<uint64_t> pending;
-  std::vector<std::unique_ptr<Pipe>> pipes;
+  std::vector<psb_decoder*> dec;     // [kPipes]
 };
-
-// Pipes per group, all made with the group: making one later would wait for
-// the whole device (decoder set-up synchronises), stalling every batch in flight.
-constexpr int kPipes = 4;
 
 }  // namespace
 
@@ -83,6 +89,8 @@ struct psb_server {
   std::vector<psb_decoder_opts> opts;            // per graph
   int64_t budget = 0, used = 0;
   hipStream_t user_stream = nullptr;
+  int32_t max_nbytes = 0, max_stride = 0;
+  std::vector<std::unique_ptr<Pipe>> pipes;
   std::vector<std::unique_ptr<Group>> groups;    // [2 * graph + (unit weights ? 1 : 0)]
   std::unordered_map<uint64_t, Request> reqs;
   std::deque<uint64_t> finished;                 // completion order, for psb_server_collect
@@ -113,19 +121,51 @@ static void free_pipe(Pipe* P) {
     if (p) (void)hipFree(p);
   for (void* p : {(void*)P->h_synd, (void*)P->h_edges, (void*)P->h_ne, (void*)P->h_st, (void*)P->h_w, (void*)P->h_obs})
     if (p) (void)hipHostFree(p);
-  if (P->dec) psb_decoder_destroy(P->dec);
   if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
 }
 
 static void free_group(Group* G) {
   if (!G) return;
-  for (auto& P : G->pipes) free_pipe(P.get());
-  G->pipes.clear();
+  for (psb_decoder* D : G->dec) if (D) psb_decoder_destroy(D);
+  G->dec.clear();
   if (G->own_graph) psb_graph_destroy(G->own_graph);
   G->own_graph = nullptr;
 }
 
-static int32_t add_pipe(psb_server* S, Group* G);
+// Per-shot bytes of a pipe's buffers.
+static int64_t pipe_shot_bytes(const psb_server* S) { return S->max_nbytes + 4LL * S->max_stride + 4 + 8 + 8 + 4; }
+
+// The pipes; their buffers hold `cap` shots of the largest graph.
+static int32_t make_pipes(psb_server* S, int64_t cap) {
+  for (int i = 0; i < kPipes; ++i) {
+    auto P = std::make_unique<Pipe>();
+    P->cap = cap;
+    const int64_t B = cap;
+    bool ok = hipMalloc((void**)&P->d_synd, (size_t)B * S->max_nbytes) == hipSuccess &&
+              hipMalloc((void**)&P->d_edges, (size_t)B * S->max_stride * 4) == hipSuccess &&
+              hipMalloc((void**)&P->d_ne, (size_t)B * 4) == hipSuccess &&
+              hipMalloc((void**)&P->d_st, (size_t)B * 4) == hipSuccess &&
+              hipMalloc((void**)&P->d_w, (size_t)B * 8) == hipSuccess &&
+              hipMalloc((void**)&P->d_obs, (size_t)B * 8) == hipSuccess &&
+              hipHostMalloc((void**)&P->h_synd, (size_t)B * S->max_nbytes, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void**)&P->h_edges, (size_t)B * S->max_stride * 4, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void**)&P->h_ne, (size_t)B * 4, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void**)&P->h_st, (size_t)B * 4, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void**)&P->h_w, (size_t)B * 8, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void**)&P->h_obs, (size_t)B * 8, hipHostMallocDefault) == hipSuccess &&
+              hipEventCreateWithFlags(&P->done_ev, hipEventDisableTiming) == hipSuccess;
+    if (ok && S->user_stream) {
+      P->stream = S->user_stream;
+    } else if (ok) {
+      ok = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) == hipSuccess;
+      P->own_stream = ok;
+    }
+    if (!ok) { free_pipe(P.get()); return fail(PSB_E_NOMEM, "server batch buffers"); }
+    S->used += B * pipe_shot_bytes(S);
+    S->pipes.push_back(std::move(P));
+  }
+  return PSB_OK;
+}
 
 static int32_t make_group(psb_server* S, int gi) {
   auto G = std::make_unique<Group>();
@@ -137,66 +177,40 @@ static int32_t make_group(psb_server* S, int gi) {
     G->graph = G->own_graph;
   }
   G->nbytes = psb_graph_syndrome_bytes(G->graph);
+  G->max_batch = S->pipes.empty() ? 0 : S->pipes[0]->cap;
+  int64_t added = 0;
   for (int i = 0; i < kPipes; ++i) {
-    const int32_t rc = add_pipe(S, G.get());
+    psb_decoder* D = nullptr;
+    int32_t rc = psb_decoder_create(G->graph, &S->opts[G->graph_idx], &D);
+    if (rc == PSB_OK) {
+      G->dec.push_back(D);
+      G->stride = psb_decoder_edges_per_shot(D);
+      int32_t fs = 0, os = 0, lds = 0;
+      psb_decoder_slots(D, &fs, &os, &lds);
+      if (fs > 0) G->max_batch = std::min<int64_t>(G->max_batch, fs);
+      int64_t ws = 0;
+      psb_decoder_device_bytes(D, &ws);
+      added += ws;
+      if (S->budget > 0 && S->used + added > S->budget)
+        rc = fail(PSB_E_NOMEM, "device_mem_budget too small for this group's decoders");
+      else if (G->stride > S->max_stride)
+        rc = fail(PSB_E_INTERNAL, "decoder output stride exceeds the pipe buffers");
+      else
+        rc = psb_decoder_reserve(D, std::max<int64_t>(1, S->pipes[0]->cap));
+    }
     if (rc != PSB_OK) { free_group(G.get()); return rc; }
   }
+  G->max_batch = std::max<int64_t>(1, G->max_batch);
+  S->used += added;
   S->groups[gi] = std::move(G);
   return PSB_OK;
 }
 
-// Adds a pipe (decoder, stream, buffers) to group G; lock held or before
-// the worker starts.  The pipe's decoder and buffers count against the budget.
-static int32_t add_pipe(psb_server* S, Group* G) {
-  auto P = std::make_unique<Pipe>();
-  int32_t rc = psb_decoder_create(G->graph, &S->opts[G->graph_idx], &P->dec);
-  if (rc != PSB_OK) return rc;
-  G->stride = psb_decoder_edges_per_shot(P->dec);
-  int32_t fs = 0, os = 0, lds = 0;
-  psb_decoder_slots(P->dec, &fs, &os, &lds);
-  int64_t ws = 0;
-  psb_decoder_device_bytes(P->dec, &ws);
-  // one shot per fast-tier slot: a batch finishes after one shot's decode time
-  P->max_batch = std::max<int64_t>(64, (int64_t)fs);
-  const int64_t per_shot = G->nbytes + 4LL * G->stride + 4 + 8 + 8 + 4;
-  if (S->budget > 0) {
-    const int64_t left = S->budget - S->used - ws;
-    if (left < 64 * per_shot) {
-      free_pipe(P.get());
-      return fail(PSB_E_NOMEM, "device_mem_budget too small for another decoder and a 64-shot batch");
-    }
-    P->max_batch = std::min<int64_t>(P->max_batch, left / per_shot);
-  }
-  const int64_t B = P->max_batch;
-  bool ok = hipMalloc((void**)&P->d_synd, (size_t)B * G->nbytes) == hipSuccess &&
-            hipMalloc((void**)&P->d_edges, (size_t)B * G->stride * 4) == hipSuccess &&
-            hipMalloc((void**)&P->d_ne, (size_t)B * 4) == hipSuccess &&
-            hipMalloc((void**)&P->d_st, (size_t)B * 4) == hipSuccess &&
-            hipMalloc((void**)&P->d_w, (size_t)B * 8) == hipSuccess &&
-            hipMalloc((void**)&P->d_obs, (size_t)B * 8) == hipSuccess &&
-            hipHostMalloc((void**)&P->h_synd, (size_t)B * G->nbytes, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&P->h_edges, (size_t)B * G->stride * 4, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&P->h_ne, (size_t)B * 4, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&P->h_st, (size_t)B * 4, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&P->h_w, (size_t)B * 8, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&P->h_obs, (size_t)B * 8, hipHostMallocDefault) == hipSuccess &&
-            hipEventCreateWithFlags(&P->done_ev, hipEventDisableTiming) == hipSuccess;
-  if (ok && S->user_stream) {
-    P->stream = S->user_stream;
-  } else if (ok) {
-    ok = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) == hipSuccess;
-    P->own_stream = ok;
-  }
-  if (ok) ok = psb_decoder_reserve(P->dec, B) == PSB_OK;
-  if (!ok) { free_pipe(P.get()); return fail(PSB_E_NOMEM, "server batch buffers"); }
-  S->used += ws + B * per_shot;
-  G->pipes.push_back(std::move(P));
-  return PSB_OK;
-}
-
-// Launches the next batch of group G on pipe P (lock held).
-static void launch(psb_server* S, Group* G, Pipe* P) {
-  const int64_t k = std::min<int64_t>((int64_t)G->pending.size(), P->max_batch);
+// Launches the next batch of group gi on idle pipe P (lock held).
+static void launch(psb_server* S, int gi, int pipe_idx) {
+  Group* G = S->groups[gi].get();
+  Pipe* P = S->pipes[pipe_idx].get();
+  const int64_t k = std::min<int64_t>((int64_t)G->pending.size(), G->max_batch);
   const auto t0 = Clock::now();
   P->inflight.clear();
   for (int64_t i = 0; i < k; ++i) {
@@ -208,8 +222,8 @@ static void launch(psb_server* S, Group* G, Pipe* P) {
     S->queue_ns += ns_between(R.t_submit, t0);
   }
   hipError_t e = hipMemcpyAsync(P->d_synd, P->h_synd, (size_t)k * G->nbytes, hipMemcpyHostToDevice, P->stream);
-  int32_t rc = e == hipSuccess ? psb_decode_batch(P->dec, P->d_synd, k, P->d_edges, P->d_ne, P->d_w, P->d_obs,
-                                                  P->d_st, nullptr, nullptr, nullptr, P->stream)
+  int32_t rc = e == hipSuccess ? psb_decode_batch(G->dec[pipe_idx], P->d_synd, k, P->d_edges, P->d_ne, P->d_w,
+                                                  P->d_obs, P->d_st, nullptr, nullptr, nullptr, P->stream)
                                : PSB_E_DEVICE;
   if (rc == PSB_OK) {
     e = hipMemcpyAsync(P->h_ne, P->d_ne, (size_t)k * 4, hipMemcpyDeviceToHost, P->stream);
@@ -233,16 +247,17 @@ static void launch(psb_server* S, Group* G, Pipe* P) {
     S->cv.notify_all();
     return;
   }
-  P->busy = true;
+  P->group = gi;
   P->t_launch = Clock::now();
   S->n_batches += 1;
   S->n_windows += k;
   S->launch_ns += ns_between(t0, P->t_launch);
 }
 
-// Scatters a finished batch into its requests (lock held); a batch whose
-// device work failed completes with an internal status.
-static void complete(psb_server* S, Group* G, Pipe* P, bool ok) {
+// Scatters pipe P's finished batch into its requests (lock held); a batch
+// whose device work failed completes with an internal status.
+static void complete(psb_server* S, Pipe* P, bool ok) {
+  const Group* G = S->groups[P->group].get();
   const auto now = Clock::now();
   S->run_ns += ns_between(P->t_launch, now);
   for (size_t i = 0; i < P->inflight.size(); ++i) {
@@ -259,7 +274,7 @@ static void complete(psb_server* S, Group* G, Pipe* P, bool ok) {
     S->finished.push_back(P->inflight[i]);
   }
   P->inflight.clear();
-  P->busy = false;
+  P->group = -1;
   // tickets already taken by psb_server_poll stay in the completion list
   // until psb_server_collect passes them; drop them once they dominate it
   if (S->finished.size() > 2 * S->reqs.size() + 4096) {
@@ -270,26 +285,39 @@ static void complete(psb_server* S, Group* G, Pipe* P, bool ok) {
   S->cv.notify_all();
 }
 
+// Group whose oldest waiting window is oldest, or -1 (lock held).
+static int oldest_group(const psb_server* S) {
+  int best = -1;
+  Clock::time_point tb;
+  for (size_t gi = 0; gi < S->groups.size(); ++gi) {
+    const Group* G = S->groups[gi].get();
+    if (!G || G->pending.empty()) continue;
+    const Clock::time_point t = S->reqs.at(G->pending.front()).t_submit;
+    if (best < 0 || t < tb) { best = (int)gi; tb = t; }
+  }
+  return best;
+}
+
 static void worker_main(psb_server* S) {
   (void)hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
   while (!S->stop) {
-    bool busy = false, work = false;
-    for (auto& ug : S->groups) {
-      Group* G = ug.get();
-      if (!G) continue;
-      for (auto& up : G->pipes) {
-        Pipe* P = up.get();
-        if (!P->busy) continue;
-        const hipError_t q = hipEventQuery(P->done_ev);
-        if (q == hipSuccess) complete(S, G, P, true);
-        else if (q != hipErrorNotReady) { S->worker_error = "device error while a batch ran"; complete(S, G, P, false); }
-      }
-      for (auto& up : G->pipes)
-        if (!up->busy && !G->pending.empty()) launch(S, G, up.get());
-      for (auto& up : G->pipes) busy |= up->busy;
-      work |= !G->pending.empty();
+    bool busy = false;
+    for (auto& up : S->pipes) {
+      Pipe* P = up.get();
+      if (P->group < 0) continue;
+      const hipError_t q = hipEventQuery(P->done_ev);
+      if (q == hipSuccess) complete(S, P, true);
+      else if (q != hipErrorNotReady) { S->worker_error = "device error while a batch ran"; complete(S, P, false); }
     }
+    for (size_t i = 0; i < S->pipes.size(); ++i) {
+      if (S->pipes[i]->group >= 0) continue;
+      const int gi = oldest_group(S);
+      if (gi < 0) break;
+      launch(S, gi, (int)i);
+    }
+    for (auto& up : S->pipes) busy |= up->group >= 0;
+    const bool work = oldest_group(S) >= 0;
     if (busy || work) {
       lk.unlock();
       std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -310,19 +338,33 @@ extern "C" int32_t psb_server_create(const psb_graph* const* graphs, int32_t n_g
   if (hipGetDevice(&S->device) != hipSuccess) return fail(PSB_E_DEVICE, "hipGetDevice");
   S->graphs.assign(graphs, graphs + n_graphs);
   S->opts.assign(n_graphs, psb_decoder_opts{});
+  int64_t cap = 64;
   for (int32_t i = 0; i < n_graphs; ++i) {
     psb_decoder_opts& o = S->opts[i];
     if (opts) o = opts[i];
+    if (o.edges_per_shot < 0 || o.num_slots < 0) return fail(PSB_E_INVALID, "negative edges_per_shot or num_slots");
     if (o.edges_per_shot == 0) o.edges_per_shot = 1024;       // results are copied per request
-    if (o.num_slots == 0) o.num_slots = 1024;                 // kPipes decoders of 1024 slots per group
+    if (o.num_slots == 0) o.num_slots = 1024;                 // one batch = one shot per slot
     if (o.overflow_slots == 0) o.overflow_slots = 256;
+    S->max_nbytes = std::max(S->max_nbytes, psb_graph_syndrome_bytes(graphs[i]));
+    S->max_stride = std::max(S->max_stride, o.edges_per_shot);
+    cap = std::max<int64_t>(cap, o.num_slots);
   }
   S->budget = device_mem_budget;
   S->user_stream = (hipStream_t)stream;
+  if (S->budget > 0) {
+    // pipes take at most half the budget; the decoders the rest
+    const int64_t fit = S->budget / 2 / (kPipes * pipe_shot_bytes(S.get()));
+    if (fit < 64) return fail(PSB_E_NOMEM, "device_mem_budget too small for 64-shot batches");
+    cap = std::min(cap, fit);
+  }
+  int32_t rc = make_pipes(S.get(), cap);
   S->groups.resize(2 * (size_t)n_graphs);
-  for (int32_t i = 0; i < n_graphs; ++i) {
-    const int32_t rc = make_group(S.get(), 2 * i);
-    if (rc != PSB_OK) { for (auto& G : S->groups) free_group(G.get()); return rc; }
+  for (int32_t i = 0; i < n_graphs && rc == PSB_OK; ++i) rc = make_group(S.get(), 2 * i);
+  if (rc != PSB_OK) {
+    for (auto& G : S->groups) free_group(G.get());
+    for (auto& P : S->pipes) free_pipe(P.get());
+    return rc;
   }
   psb_server* raw = S.release();
   raw->worker = std::thread(worker_main, raw);
@@ -453,6 +495,7 @@ extern "C" int32_t psb_server_destroy(psb_server* S) {
     S->cv.notify_all();
   }
   if (S->worker.joinable()) S->worker.join();
+  for (auto& P : S->pipes) free_pipe(P.get());
   for (auto& G : S->groups) free_group(G.get());
   delete S;
   return PSB_OK;
