@@ -156,6 +156,12 @@ def latency_scaling(args):
                 log(f"WARNING: d={d} shot {i} status {out.status.cpu().numpy()[0]}")
         ev_us = np.array(ev_ms) * 1e3
         dev_us = np.array(dev_us)
+        # parallel event count (E_ideal) of the same shots: one untimed batch with per-cluster accounting
+        acc = psb.Decoder(G, **dict(kw, event_accounting=1))
+        ao = acc.decode(synd, stats=True)
+        torch.cuda.synchronize()
+        ast = ao.stats.cpu().numpy()
+        acc.close()
         rows.append({"d": d, "rounds": d, "detectors": g.num_detectors, "shots": args.latency_shots,
                      "decoder": {"first_tier_state": [kw.get("fast_max_nodes", 0), kw.get("fast_max_regions", 0)],
                                  "lds_state": kw.get("fast_lds_state", 0), "q": list(kw.get("q", (1, 10)))},
@@ -165,7 +171,11 @@ def latency_scaling(args):
                      "us_per_round_launch_p50": round(float(np.percentile(ev_us, 50)) / d, 3),
                      "us_per_round_launch_p99": round(float(np.percentile(ev_us, 99)) / d, 3),
                      "us_per_round_device_p50": round(float(np.percentile(dev_us, 50)) / d, 3),
-                     "us_per_round_device_p99": round(float(np.percentile(dev_us, 99)) / d, 3)})
+                     "us_per_round_device_p99": round(float(np.percentile(dev_us, 99)) / d, 3),
+                     "events_per_round_mean": round(float(ast[:, 8].mean()) / d, 3),
+                     "e_ideal_per_round_mean": round(float(ast[:, 9].mean()) / d, 3),
+                     "e_ideal_per_round_p99": round(float(np.percentile(ast[:, 9], 99)) / d, 3),
+                     "clusters_mean": round(float(ast[:, 10].mean()), 2)})
         log(f"d={d}: {rows[-1]}")
         dec.close(); G.close()
     print(json.dumps({"metric": "one-shot-per-launch latency, us per round", "p": p, "mode": args.mode,
@@ -454,7 +464,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": measured_traffic(args.d, args.p, args.shots, kw),
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(avg_launch_s * 1e3, 3),
-                     "kernel": "psb_lane_kernel" if kw.get("first_tier", 0) else "psb_decode_kernel<0>"},
+                     "kernel": "psb_lane_kernel" if kw.get("first_tier", 0) else "psb_decode_kernel<0, 0>"},
         "work_per_shot": {"events": float(stats[:, 0].mean()), "reached": float(stats[:, 1].mean()),
                           "cluster_visits": float(stats[:, 2].mean()), "log_records": float(stats[:, 3].mean()),
                           "us_intake_cluster": float(stats[:, 4].mean()) * 1e6 / DEVICE_CLOCK_HZ,

@@ -104,6 +104,12 @@ typedef struct {
    * 3 = all per-shot state in LDS (fewest dependent global loads per event,
    * fewer wavefronts per CU).  Results do not depend on it. */
   int32_t fast_lds_state;
+  /* 1 = per-cluster event accounting (Methods, numerical evaluation: the
+   * parallel event count E_ideal of hierarchical execution): each applied
+   * event is charged to the processing cluster whose alternating tree drives
+   * it, and psb_decode_batch's stats rows grow to 12 fields (see there).
+   * Slower; results do not depend on it.  0 = off (stats rows of 8). */
+  int32_t event_accounting;
 } psb_decoder_opts;
 
 /* Builds the decoder: tie-broken weights, level parameters d_k, b_k (exact
@@ -130,10 +136,16 @@ int32_t psb_decoder_levels(const psb_decoder* d, int32_t max_levels, int64_t* d_
  *              each active detector in ascending detector order (0 = global mode);
  *   t_done     [n+1] uint64 or NULL: device clock (100 MHz) when shot i finished;
  *              t_done[n] receives the clock when the launch started;
- *   stats      [n][8] int32 or NULL: per-shot work counters (events processed,
- *              detectors reached by region growth, nodes visited by the
- *              clustering search, arrival-log records) and device-clock
- *              durations of clustering, dynamics, fuse and the whole shot.
+ *   stats      [n][8] int32 or NULL ([n][12] with event_accounting): per-shot
+ *              work counters (events processed, detectors reached by region
+ *              growth, nodes visited by the clustering search, arrival-log
+ *              records) and device-clock durations of clustering, dynamics,
+ *              fuse and the whole shot; with event_accounting also the
+ *              applied events, the parallel event count E_ideal (events on
+ *              the critical path of hierarchical execution, with each
+ *              cluster's stopping time taken as its last event), the number
+ *              of processing clusters and the highest level (all 0 for a
+ *              shot without detection events).
  * Errors: PSB_E_INVALID, PSB_E_DEVICE. */
 int32_t psb_decode_batch(psb_decoder* d, const uint8_t* syndromes, int64_t n, int32_t* edges,
                          int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,

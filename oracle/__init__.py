@@ -229,7 +229,7 @@ def schedule(w_max: int, q: Fraction = Fraction(1, 10), phi_min: Fraction = Frac
 # Processing-cluster hierarchy (Methods, Algorithm "Clustering").
 # ---------------------------------------------------------------------------
 
-def cluster_levels(D, BT, d_sched, b_sched, reading: str = "strict"):
+def cluster_levels(D, BT, d_sched, b_sched, reading: str = "strict", components: bool = False):
     """Level of every defect under the clustering algorithm.
 
     D[i][j]   exact distance between defects i and j (None = unreachable);
@@ -240,10 +240,13 @@ def cluster_levels(D, BT, d_sched, b_sched, reading: str = "strict"):
     even size or reaches a boundary vertex: under reading "strict" some
     boundary vertex lies within d_k of every member; under "loose" some
     member's exploring region (radius b_k/2) reaches a boundary vertex.
-    Returns a list of levels (1-based); 0 = never accepted within the schedule.
+    Returns a list of levels (1-based); 0 = never accepted within the schedule;
+    with components=True also the accepted components (processing clusters)
+    as (level, sorted member list) pairs.
     """
     m = len(D)
     level = [0] * m
+    clusters = []
     residual = list(range(m))
     for k in range(len(d_sched)):
         if not residual:
@@ -277,11 +280,12 @@ def cluster_levels(D, BT, d_sched, b_sched, reading: str = "strict"):
             if ok:
                 accepted.append(comp)
         for comp in accepted:
+            clusters.append((k + 1, comp))
             for x in comp:
                 level[x] = k + 1
         acc = {x for c in accepted for x in c}
         residual = [x for x in residual if x not in acc]
-    return level
+    return (level, clusters) if components else level
 
 
 # ---------------------------------------------------------------------------

@@ -40,7 +40,7 @@ class _DecoderOpts(ctypes.Structure):
                 ("edges_per_shot", ctypes.c_int32), ("num_slots", ctypes.c_int32),
                 ("fast_max_nodes", ctypes.c_int32), ("fast_max_regions", ctypes.c_int32),
                 ("overflow_slots", ctypes.c_int32), ("first_tier", ctypes.c_int32),
-                ("fast_lds_state", ctypes.c_int32)]
+                ("fast_lds_state", ctypes.c_int32), ("event_accounting", ctypes.c_int32)]
 
 
 class _TuneEntry(ctypes.Structure):
@@ -50,10 +50,10 @@ class _TuneEntry(ctypes.Structure):
 def _make_opts(tiebreak_seed: int = 0x5EED, mode: int = 0, boundary_reading: int = 0, max_defects: int = 0,
                edges_per_shot: int = 0, num_slots: int = 0, q=(1, 10), phi_min=(1, 100), fast_max_nodes: int = 0,
                fast_max_regions: int = 0, overflow_slots: int = 0, first_tier: int = 0,
-               fast_lds_state: int = 0) -> _DecoderOpts:
+               fast_lds_state: int = 0, event_accounting: int = 0) -> _DecoderOpts:
     return _DecoderOpts(q[0], q[1], phi_min[0], phi_min[1], tiebreak_seed & ((1 << 64) - 1), mode,
                         boundary_reading, max_defects, edges_per_shot, num_slots, fast_max_nodes,
-                        fast_max_regions, overflow_slots, first_tier, fast_lds_state)
+                        fast_max_regions, overflow_slots, first_tier, fast_lds_state, event_accounting)
 
 
 def _opts_kwargs(o: _DecoderOpts) -> dict:
@@ -62,7 +62,8 @@ def _opts_kwargs(o: _DecoderOpts) -> dict:
             "max_defects": o.max_defects_per_shot, "edges_per_shot": o.edges_per_shot, "num_slots": o.num_slots,
             "q": (o.q_num, o.q_den), "phi_min": (o.phi_min_num, o.phi_min_den),
             "fast_max_nodes": o.fast_max_nodes, "fast_max_regions": o.fast_max_regions,
-            "overflow_slots": o.overflow_slots, "first_tier": o.first_tier, "fast_lds_state": o.fast_lds_state}
+            "overflow_slots": o.overflow_slots, "first_tier": o.first_tier, "fast_lds_state": o.fast_lds_state,
+            "event_accounting": o.event_accounting}
 
 
 def lib():
@@ -159,10 +160,13 @@ class Decoder:
     def __init__(self, graph: Graph, tiebreak_seed: int = 0x5EED, mode: int = MODE_PARTITION,
                  boundary_reading: int = 0, max_defects: int = 0, edges_per_shot: int = 0,
                  num_slots: int = 0, q=(1, 10), phi_min=(1, 100), fast_max_nodes: int = 0,
-                 fast_max_regions: int = 0, overflow_slots: int = 0, first_tier: int = 0, fast_lds_state: int = 0):
+                 fast_max_regions: int = 0, overflow_slots: int = 0, first_tier: int = 0, fast_lds_state: int = 0,
+                 event_accounting: int = 0):
         self.graph = graph
         opts = _make_opts(tiebreak_seed, mode, boundary_reading, max_defects, edges_per_shot, num_slots, q, phi_min,
-                          fast_max_nodes, fast_max_regions, overflow_slots, first_tier, fast_lds_state)
+                          fast_max_nodes, fast_max_regions, overflow_slots, first_tier, fast_lds_state,
+                          event_accounting)
+        self.stats_width = 12 if event_accounting else 8
         h = ctypes.c_void_p()
         _check(lib().psb_decoder_create(graph._h, ctypes.byref(opts), ctypes.byref(h)), "psb_decoder_create")
         self._h = h
@@ -193,7 +197,7 @@ class Decoder:
             status=torch.empty(n, dtype=torch.int32, device=device),
             levels=torch.zeros((n, self.max_defects), dtype=torch.int8, device=device) if levels else None,
             t_done=torch.zeros(n + 1, dtype=torch.int64, device=device) if timestamps else None,
-            stats=torch.zeros((n, 8), dtype=torch.int32, device=device) if stats else None)
+            stats=torch.zeros((n, self.stats_width), dtype=torch.int32, device=device) if stats else None)
 
     def decode_into(self, syndromes, out: Batch, stream=None) -> Batch:
         """Launch psb_decode_batch on `stream` (default: torch's current stream)."""

@@ -79,6 +79,7 @@ struct Ctx {
   int64_t n_ev;
   int n_visit;                       // clustering search visits (statistics)
   uint64_t t0, t_cl, t_dyn, t_fuse;  // device clock marks (statistics)
+  char* acct;                        // event-accounting block, or null
 };
 
 // Region field f of region r: int16 storage for ids, rates and flags, int32
@@ -94,6 +95,34 @@ template <int F> PSB_DEV typename RFType<F>::T& rf_ref(const Ctx& c, int r) {
 #define CEF(c, i, f) ((c).ce[(int64_t)(i) * CE_COUNT + (f)])
 
 PSB_DEV i128 yrad(const Ctx& c, int r, i128 t) { return c.r_base[r] + (i128)RF(c, r, RF_RATE) * t; }
+
+// ---------------------------------------------------------------------------
+// parallel event count (Methods, numerical evaluation: the critical-path event
+// count of hierarchical execution, E_ideal).  Every applied event is charged
+// to the processing cluster whose alternating tree drives it; at the end of
+// each level the clusters of that level are rolled up into the critical-path
+// stopping time t_<k+1 and event count E_<k+1.
+// ---------------------------------------------------------------------------
+PSB_DEV int32_t* acct_hdr(const Ctx& c) { return (int32_t*)c.acct; }
+PSB_DEV i128* acct_tlt(const Ctx& c) { return (i128*)(c.acct + ACCT_TLT); }
+PSB_DEV int32_t* acct_cid(const Ctx& c) { return (int32_t*)(c.acct + ACCT_CID); }
+PSB_DEV int32_t* acct_cnt(const Ctx& c) { return (int32_t*)(c.acct + acct_n(c.P->cap.dcap)); }
+PSB_DEV int32_t* acct_early_n(const Ctx& c) { return (int32_t*)(c.acct + acct_early(c.P->cap.dcap)); }
+PSB_DEV i128* acct_lastt(const Ctx& c) { return (i128*)(c.acct + acct_last(c.P->cap.dcap)); }
+
+// Charges one applied event at time t to the cluster of tree `tid` (uniform).
+PSB_DEV void account_event(Ctx& c, int tid, i128 t) {
+  wave_sync();
+  int32_t* h = acct_hdr(c);
+  h[0] = uni(h[0]) + 1;
+  if (tid >= 0) {
+    const int cl = uni(acct_cid(c)[tid]);
+    acct_cnt(c)[cl] = uni(acct_cnt(c)[cl]) + 1;
+    if (t <= uni128(*acct_tlt(c))) acct_early_n(c)[cl] = uni(acct_early_n(c)[cl]) + 1;
+    acct_lastt(c)[cl] = t;
+  }
+  wave_sync();
+}
 
 // A capacity of this tier is exhausted: the fast tier hands the shot to the
 // overflow tier, the overflow tier reports it.
@@ -771,6 +800,7 @@ PSB_DEV void run_dynamics(Ctx& c) {
       const int r = code;
       if (tn < c.now) { c.status = S_INTERNAL; return; }
       c.now = tn;
+      if (c.acct) account_event(c, uni(RF(c, r, RF_TID)), tn);
       if (uni(RF(c, r, RF_BCN)) > 0) shatter(c, r); else implode(c, r);
       if (c.status) return;
       flush_changes(c);
@@ -782,6 +812,18 @@ PSB_DEV void run_dynamics(Ctx& c) {
     if (tf != tn) { wave_sync(); set_event(c, ix, tf); continue; }
     if (tf < c.now) { c.status = S_INTERNAL; return; }
     c.now = tf;
+    if (c.acct) {
+      // the event is driven by the tree of the node's region, or else (a
+      // growing region reaching a frozen one) by the tree across the edge
+      int tid = uni(RF(c, uni(c.x_top[ix]), RF_TID));
+      if (tid < 0 && kf != K_LEAVE) {
+        const int v = uni(c.nbr[(int64_t)uni(c.x_node[ix]) * c.deg + kf]);
+        const int kv = v >= 0 ? node_idx_u(c, v) : -1;
+        const int b = kv >= 0 ? uni(c.x_top[kv]) : -1;
+        if (b >= 0) tid = uni(RF(c, b, RF_TID));
+      }
+      account_event(c, tid, tf);
+    }
     node_event_apply(c, ix, kf);
   }
 }
@@ -858,7 +900,13 @@ PSB_DEV void cluster(Ctx& c) {
     if (nres == 0) return;
     const int H = uni(c.P->shmax[k]);
     if (H < 0) {
-      for (int i = lane(); i < nd; i += PSB_WAVE) if (c.level[i] == 0) c.level[i] = (int8_t)(k + 1);
+      // the final level: the remaining events form one processing cluster
+      // (the detector graphs here are connected), rooted at the first of them
+      int first = nd;
+      for (int i = lane(); i < nd; i += PSB_WAVE) if (c.level[i] == 0 && i < first) first = i;
+      first = -wave_max(-first);
+      for (int i = lane(); i < nd; i += PSB_WAVE)
+        if (c.level[i] == 0) { c.level[i] = (int8_t)(k + 1); if (c.acct) acct_cid(c)[i] = first; }
       wave_sync();
       return;
     }
@@ -978,8 +1026,14 @@ PSB_DEV void cluster(Ctx& c) {
       atom_xchg((unsigned*)&csize[i], ok ? 0xffffffffu : 0u);   // reuse as accept flag
     }
     wave_sync();
-    for (int i = lane(); i < nd; i += PSB_WAVE)
-      if (c.level[i] == 0 && atom_load(&csize[uf_find(c, i)]) == -1) c.level[i] = (int8_t)(k + 1);
+    for (int i = lane(); i < nd; i += PSB_WAVE) {
+      if (c.level[i] != 0) continue;
+      const int r = uf_find(c, i);
+      if (atom_load(&csize[r]) == -1) {
+        c.level[i] = (int8_t)(k + 1);
+        if (c.acct) acct_cid(c)[i] = r;
+      }
+    }
     wave_sync();
   }
 }
@@ -1145,6 +1199,47 @@ PSB_DEV void seed_level(Ctx& c, int lvl) {
   wave_sync();
 }
 
+// Clears the counters of the clusters of level lvl.
+PSB_DEV void account_level_start(Ctx& c, int lvl) {
+  wave_sync();
+  for (int i = lane(); i < c.nd; i += PSB_WAVE) {
+    if (c.level[i] != lvl) continue;
+    acct_cnt(c)[i] = 0; acct_early_n(c)[i] = 0; acct_lastt(c)[i] = 0;
+  }
+  wave_sync();
+}
+
+// Rolls the clusters of level lvl into the critical path: for cluster C with
+// stopping time s(C) (its last event) and E_C(t) events up to t,
+//   t(C) = max(t_<k, s(C)),  E(C) = max(E_<k, E_C(t_<k)) + E_C(s(C)) - E_C(t_<k),
+// then t_<k+1 and E_<k+1 are the maxima over the level's clusters.
+PSB_DEV void account_level_end(Ctx& c, int lvl) {
+  wave_sync();
+  const i128 tlt = uni128(*acct_tlt(c));
+  const int elt = uni(acct_hdr(c)[1]);
+  i128 neg_t = -tlt; int arg = 0;
+  int emax = elt, ncl = 0;
+  for (int i = lane(); i < c.nd; i += PSB_WAVE) {
+    if (c.level[i] != lvl || acct_cid(c)[i] != i) continue;
+    const i128 sC = acct_lastt(c)[i];
+    const int n = acct_cnt(c)[i], e = acct_early_n(c)[i];
+    const i128 tC = sC > tlt ? sC : tlt;
+    const int EC = (e > elt ? e : elt) + n - e;
+    if (-tC < neg_t) neg_t = -tC;
+    if (EC > emax) emax = EC;
+    ++ncl;
+  }
+  wave_argmin(neg_t, arg);
+  emax = wave_max(emax);
+  ncl = wave_sum(ncl);
+  wave_sync();
+  *acct_tlt(c) = -neg_t;
+  acct_hdr(c)[1] = emax;
+  acct_hdr(c)[2] = uni(acct_hdr(c)[2]) + ncl;
+  acct_hdr(c)[3] = lvl;
+  wave_sync();
+}
+
 // Single-value outputs are stored by every lane with the same value: the
 // persistent loop then has no lane-dependent branches.
 PSB_DEV void write_empty(Ctx& c, int64_t shot, int status) {
@@ -1155,7 +1250,12 @@ PSB_DEV void write_empty(Ctx& c, int64_t shot, int status) {
 PSB_DEV void cleanup(Ctx& c, int64_t shot) {
   wave_sync();
   if (c.P->out_stats && c.status != S_OVERFLOW) {
-    int32_t* st = c.P->out_stats + 8 * shot;
+    int32_t* st = c.P->out_stats + (int64_t)c.P->stats_stride * shot;
+    if (c.acct) {
+      // applied events, E_ideal, processing clusters, highest level (zeros for a shot without events)
+      const bool ran = c.nd > 0 && (c.status == S_OK || c.status == S_TRUNC);
+      for (int q = 0; q < 4; ++q) st[8 + q] = ran ? uni(acct_hdr(c)[q]) : 0;
+    }
     const uint64_t t_end = dev_clock();
     st[0] = (int32_t)c.n_ev; st[1] = uni(c.S->x_n); st[2] = c.n_visit; st[3] = c.n_log;
     st[4] = (int32_t)(c.t_cl - c.t0); st[5] = (int32_t)(c.t_dyn - c.t_cl);
@@ -1225,13 +1325,22 @@ PSB_DEV int decode_shot(Ctx& c, int64_t shot) {
     if (wave_or(miss)) c.status = S_INTERNAL;
   }
   c.t_cl = dev_clock();
+  if (c.acct) {
+    wave_sync();
+    if (c.P->mode == 1) for (int i = lane(); i < nd; i += PSB_WAVE) acct_cid(c)[i] = 0;
+    acct_hdr(c)[0] = 0; acct_hdr(c)[1] = 0; acct_hdr(c)[2] = 0; acct_hdr(c)[3] = 0;
+    *acct_tlt(c) = 0;
+    wave_sync();
+  }
   for (int lvl = 1; lvl <= max_level && !c.status; ++lvl) {
     int present = 0;
     for (int i = lane(); i < nd; i += PSB_WAVE) present |= (c.level[i] == lvl);
     if (!wave_or(present)) continue;
     c.now = 0;       // every level starts its clock at zero; stopped regions are frozen
+    if (c.acct) account_level_start(c, lvl);
     seed_level(c, lvl);
     run_dynamics(c);
+    if (c.acct && !c.status) account_level_end(c, lvl);
     if (!c.status) {
       int open = 0;
       for (int r = lane(); r < c.n_regions; r += PSB_WAVE)
@@ -1287,6 +1396,7 @@ PSB_DEV void ctx_init(Ctx& c, const Params* P, Lds* S, char* state, int64_t slot
   c.shr = (int32_t*)(base + L.shr); c.chg = (int32_t*)(base + L.chg); c.stk = (int32_t*)(base + L.stk);
   c.fin = (int32_t*)(base + L.fin); c.ebits = (uint32_t*)(base + L.ebits);
   c.dmap = P->cap.hcap == 0 ? (int16_t*)(base + L.dmap) : nullptr;
+  c.acct = (P->eacct && P->out_stats) ? base + L.acct : nullptr;
 }
 
 // Fresh state block: empty detector map or hash, zero scalars.

@@ -55,13 +55,15 @@ __global__ void psb_zero_kernel(int32_t* p, int n, uint64_t* t_start) {
 // per CU) decodes either that list (ovf_list != null) or every shot directly.
 // At most 128 VGPRs, so that four wavefronts share a SIMD (the per-shot
 // event loop is latency-bound: throughput grows with resident wavefronts).
-template <int TIER>
+// ACCT: per-cluster event accounting compiled in (ACCT = 0 removes it).
+template <int TIER, int ACCT>
 __global__ __launch_bounds__(64, 4) void psb_decode_kernel(Params P) {
   extern __shared__ __align__(16) char psb_dyn_lds[];
   ew::Lds* S = (ew::Lds*)psb_dyn_lds;
   char* state = psb_dyn_lds + 64;
   ew::Ctx c;
   ew::ctx_init(c, &P, S, state, blockIdx.x);
+  if (!ACCT) c.acct = nullptr;
   ew::state_init(c);
   for (;;) {
     // every lane takes part in the counter update (lane 0 adds 1, the others
@@ -184,6 +186,7 @@ struct psb_decoder {
   psb_decoder_opts opts{};
   int32_t edge_stride = 0, dcap = 0;
   int32_t slots_fast = 0, slots_ovf = 0;
+  bool acct = false;                 // per-cluster event accounting (kernel variant)
   size_t lds_fast = 0, lds_ovf = 0;
   bool fast_enabled = true;
   bool first_lane = true;          // first tier: one shot per lane (else one per wavefront)
@@ -234,6 +237,9 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   // overflow tier (one shot per wavefront, large LDS state)
   if (opts.first_tier != 0 && opts.first_tier != 1) { delete D; return fail(PSB_E_INVALID, "first_tier must be 0 or 1"); }
   if (opts.fast_lds_state < 0 || opts.fast_lds_state > 3) { delete D; return fail(PSB_E_INVALID, "fast_lds_state must be 0..3"); }
+  if (opts.event_accounting != 0 && opts.event_accounting != 1) { delete D; return fail(PSB_E_INVALID, "event_accounting must be 0 or 1"); }
+  const bool acct = opts.event_accounting == 1;
+  D->acct = acct;
   D->first_lane = opts.first_tier == 1;
   psb::Caps cf, co;
   co.xcap = std::min(n, 1024); co.rcap = std::min(4 * dcap + 64, 768);
@@ -254,8 +260,8 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   // default capacities) lets 16 wavefronts share a CU.  fast_lds_state moves
   // them into LDS (fewer wavefronts per CU, shorter dependent-load chains).
   static const int kLean[4] = {2, 2, 1, 0};
-  plan_tier(PF, n, g->deg, g->n_edges, cf, D->first_lane, D->first_lane ? 0 : kLean[opts.fast_lds_state]);
-  plan_tier(PO, n, g->deg, g->n_edges, co, false);
+  plan_tier(PF, n, g->deg, g->n_edges, cf, D->first_lane, D->first_lane ? 0 : kLean[opts.fast_lds_state], acct);
+  plan_tier(PO, n, g->deg, g->n_edges, co, false, 0, acct);
   for (Params* P : {&PF, &PO}) {
     P->n_levels = (int32_t)D->sched.d.size(); P->reading = opts.boundary_reading; P->mode = opts.mode;
     P->edge_stride = stride;
@@ -286,14 +292,18 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
     HIP_TRY(psb_lane_occupancy(&per_cu));
     if (per_cu < 1) D->fast_enabled = false;
   } else if (D->fast_enabled) {
-    HIP_TRY(hipFuncSetAttribute((const void*)psb_decode_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HIP_TRY(hipFuncSetAttribute(D->acct ? (const void*)psb_decode_kernel<0, 1> : (const void*)psb_decode_kernel<0, 0>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)D->lds_fast));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, psb_decode_kernel<0>, 64, D->lds_fast));
+    if (D->acct) HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, psb_decode_kernel<0, 1>, 64, D->lds_fast));
+    else HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, psb_decode_kernel<0, 0>, 64, D->lds_fast));
     if (per_cu < 1) D->fast_enabled = false;
   }
-  HIP_TRY(hipFuncSetAttribute((const void*)psb_decode_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  HIP_TRY(hipFuncSetAttribute(D->acct ? (const void*)psb_decode_kernel<1, 1> : (const void*)psb_decode_kernel<1, 0>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)D->lds_ovf));
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_o, psb_decode_kernel<1>, 64, D->lds_ovf));
+  if (D->acct) HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_o, psb_decode_kernel<1, 1>, 64, D->lds_ovf));
+  else HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_o, psb_decode_kernel<1, 0>, 64, D->lds_ovf));
   if (per_cu_o < 1) { delete D; return fail(PSB_E_UNSUPPORTED, "overflow tier does not fit on a compute unit"); }
   if (D->first_lane) {
     // lanes in flight: every wave the chip holds, at most 65536 lanes
@@ -422,6 +432,7 @@ extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, in
   for (Params* P : tiers) {
     P->n_shots = n; P->synd = syndromes; P->out_edges = edges; P->out_nedges = n_edges; P->out_weight = weight;
     P->out_obs = obs; P->out_status = status; P->out_levels = levels; P->out_tdone = t_done; P->out_stats = stats;
+    P->stats_stride = P->eacct ? 12 : 8;
     P->level_stride = D->dcap;
     P->ovf_list = D->fast_enabled ? D->d_ovf_list : nullptr;
   }
@@ -432,11 +443,13 @@ extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, in
     HIP_TRY(psb_lane_launch(D->P_fast, (unsigned)waves, s));
   } else if (D->fast_enabled) {
     const int64_t grid = std::min<int64_t>(n, D->slots_fast);
-    psb_decode_kernel<0><<<(unsigned)grid, 64, D->lds_fast, s>>>(D->P_fast);
+    if (D->acct) psb_decode_kernel<0, 1><<<(unsigned)grid, 64, D->lds_fast, s>>>(D->P_fast);
+    else psb_decode_kernel<0, 0><<<(unsigned)grid, 64, D->lds_fast, s>>>(D->P_fast);
     HIP_TRY(hipGetLastError());
   }
   const int64_t grid_o = D->fast_enabled ? D->slots_ovf : std::min<int64_t>(n, D->slots_ovf);
-  psb_decode_kernel<1><<<(unsigned)grid_o, 64, D->lds_ovf, s>>>(D->P_ovf);
+  if (D->acct) psb_decode_kernel<1, 1><<<(unsigned)grid_o, 64, D->lds_ovf, s>>>(D->P_ovf);
+  else psb_decode_kernel<1, 0><<<(unsigned)grid_o, 64, D->lds_ovf, s>>>(D->P_ovf);
   HIP_TRY(hipGetLastError());
   return PSB_OK;
 }

@@ -38,6 +38,7 @@ struct WsLayout {
                                                  // (only when the state block has no hash)
   int64_t x_ev, r_base, x_wr;                    // event cache, region bases, radius offsets, when the state block
                                                  // leaves them out (else unused)
+  int64_t acct;                                  // per-cluster event accounting block (event_accounting only)
   int64_t total;                                 // bytes per slot (multiple of 256)
 };
 
@@ -67,6 +68,17 @@ enum RegionField {
 // the two ends, -1 for the boundary.
 enum CeField { CE_E = 0, CE_A, CE_B, CE_SA, CE_SB, CE_COUNT };
 
+// Event-accounting block of a slot (dcap = d): a header (applied events,
+// critical-path event count so far, processing clusters, highest level), the
+// critical-path stopping time so far, then per detection event: its
+// processing cluster (the cluster's root event), and per cluster root: event
+// count, events up to the lower levels' critical-path time, last event time.
+constexpr int64_t ACCT_TLT = 16, ACCT_CID = 32;
+constexpr int64_t acct_n(int64_t d) { return ACCT_CID + 4 * d; }
+constexpr int64_t acct_early(int64_t d) { return ACCT_CID + 8 * d; }
+constexpr int64_t acct_last(int64_t d) { return (ACCT_CID + 12 * d + 15) & ~(int64_t)15; }
+constexpr int64_t acct_bytes(int64_t d) { return acct_last(d) + 16 * d; }
+
 struct Caps {
   int32_t xcap, hcap, rcap, dcap;                // explored nodes, hash slots (power of 2), regions, events
 };
@@ -93,15 +105,15 @@ struct Params {
   int64_t n_shots;
   const uint8_t* synd;
   int32_t* out_edges;
-  int32_t edge_stride, pad3;
+  int32_t edge_stride, stats_stride;             // stats_stride: 8, or 12 with event accounting
   int32_t* out_nedges;
   int64_t* out_weight;
   uint64_t* out_obs;
   int32_t* out_status;
   int8_t* out_levels;
-  int32_t level_stride, pad4;
+  int32_t level_stride, eacct;                   // eacct: per-cluster event accounting on
   uint64_t* out_tdone;
-  int32_t* out_stats;     // [n][8] or null
+  int32_t* out_stats;     // [n][stats_stride] or null
   int32_t* counter;       // [0] first-tier work head, [1] overflow count, [2] overflow head
   int32_t* ovf_list;      // [n_shots] shots handed to the overflow tier
   // workspace

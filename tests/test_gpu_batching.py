@@ -108,3 +108,74 @@ def test_first_tier_state_placement_parity(lds_state, caps):
     say(f"lds_state={lds_state} caps={caps}: {res['n_overflow']} shots in the overflow tier")
     bad = compare(g, s.syndromes, res, range(3000))
     assert not bad, bad[:5]
+
+
+def _accounted(g, syndromes, **kw):
+    import torch
+    import paper_2609_12262_amd as psb
+    G = psb.Graph.from_synth(g)
+    dec = psb.Decoder(G, tiebreak_seed=SEED, event_accounting=1, **kw)
+    out = dec.decode(torch.from_numpy(syndromes).cuda(), levels=True, stats=True)
+    torch.cuda.synchronize()
+    res = _host(out)
+    res["obs"] = res["obs"].view(np.uint64)
+    res["stats"] = out.stats.cpu().numpy()
+    res["levels"] = out.levels.cpu().numpy()
+    dec.close(); G.close()
+    return res
+
+
+def test_event_accounting_properties():
+    """Per-cluster event accounting (the parallel event count E_ideal of
+    hierarchical execution): results equal those without accounting; E_ideal
+    is at most the applied events, positive exactly when the shot has events;
+    the processing clusters and highest level equal the oracle's clustering
+    (one final cluster for the events left at the final level)."""
+    import oracle
+    import paper_2609_12262_amd as psb
+    g = synth.rotated_phenom_graph(11, 0.005)
+    s = synth.sample(g, 2000, seed=95)
+    acc = _accounted(g, s.syndromes)
+    plain = gpu_decode(g, s.syndromes)
+    for key in ("n_edges", "weight", "obs", "status"):
+        assert np.array_equal(acc[key], plain[key]), key
+    st = acc["stats"]
+    nd = np.array([len(synth.defects_of(r, g.num_detectors)) for r in s.syndromes])
+    assert (st[:, 9] <= st[:, 8]).all()
+    assert ((st[:, 9] > 0) == (nd > 0)).all()
+    assert ((st[:, 10] > 0) == (nd > 0)).all()
+    og = oracle.Graph(g, SEED)
+    dec = psb.Decoder(psb.Graph.from_synth(g), tiebreak_seed=SEED)
+    d_k, b_k, fin = dec.levels()
+    kf = fin.index(1) + 1
+    od, ob, _ = oracle.schedule(max(og.tiebroken_weights()), levels=max(len(d_k), 4))
+    checked = 0
+    for i in range(0, 2000, 7):
+        dd = synth.defects_of(s.syndromes[i], g.num_detectors)
+        if len(dd) == 0:
+            continue
+        D, _ = og.defect_distances(dd)
+        lv, comps = oracle.cluster_levels(D, og.boundary_table(dd), od, ob, components=True)
+        n_cl = sum(1 for k, _ in comps if k < kf) + (1 if any(x >= kf or x == 0 for x in lv) else 0)
+        top = max(min(x, kf) if x else kf for x in lv)
+        assert st[i, 10] == n_cl, (i, st[i, 10], n_cl)
+        assert st[i, 11] == top, (i, st[i, 11], top)
+        checked += 1
+    assert checked > 100
+
+
+def test_event_accounting_global_mode_and_lane_tier():
+    """Global sparse blossom is one cluster: E_ideal equals the applied
+    events.  The lane tier processes the same events: same counts."""
+    g = synth.rotated_phenom_graph(9, 0.005)
+    s = synth.sample(g, 1500, seed=96)
+    glob = _accounted(g, s.syndromes, mode=1)
+    assert np.array_equal(glob["stats"][:, 9], glob["stats"][:, 8])
+    nd = np.array([len(synth.defects_of(r, g.num_detectors)) for r in s.syndromes])
+    assert ((glob["stats"][:, 10] == 1) == (nd > 0)).all()
+    wave = _accounted(g, s.syndromes)
+    lane = _accounted(g, s.syndromes, first_tier=1)
+    for q in (8, 9, 10, 11):
+        assert np.array_equal(wave["stats"][:, q], lane["stats"][:, q]), q
+    bad = compare(g, s.syndromes, wave, range(0, 1500, 5))
+    assert not bad, bad[:5]
