@@ -57,9 +57,13 @@ def kernel_source_hash():
 
 
 def decoder_config_key(kw):
-    return (f"first_tier={kw.get('first_tier', 0)} state={kw.get('fast_max_nodes', 0)}/"
-            f"{kw.get('fast_max_regions', 0)} lds_state={kw.get('fast_lds_state', 0)} "
-            f"q={kw.get('q', (1, 10))[0]}/{kw.get('q', (1, 10))[1]}")
+    """Decoder configuration with the library's defaults filled in (0 = default)."""
+    tier = kw.get("first_tier", 0)
+    nodes = kw.get("fast_max_nodes", 0) or 320
+    regions = kw.get("fast_max_regions", 0) or (256 if tier else 208)
+    lds = kw.get("fast_lds_state", 0) or 1           # 0 and 1 are the same placement
+    q = kw.get("q", (1, 10))
+    return f"first_tier={tier} state={nodes}/{regions} lds_state={lds} q={q[0]}/{q[1]}"
 
 
 def measured_traffic(d, p, shots, kw):
