@@ -65,6 +65,7 @@ struct Ctx {
   int deg, n_det;
   // per-shot state (StateLayout)
   int32_t* x_node; int16_t *x_top, *x_reg, *x_src, *x_rec; i128 *x_wr, *x_ev;
+  int16_t* x_nb;                     // [xcap][deg] explored index of each adjacency slot's neighbour (global)
   int32_t *h_key, *h_val; uint32_t hmask; int hshift;
   int16_t* dmap;                     // direct detector -> explored index map (global), or null
   i128* r_base; int16_t* r_f16; int32_t* r_f32; int rcap, xcap;
@@ -224,12 +225,11 @@ PSB_DEV void next_event(Ctx& c, i128& t, int& code) {
 // Time of the event through adjacency slot j of explored node i (owned by
 // top region `top` with rate ra > 0 or 0 and l_u(t) = bu + ra * t); T_INF if
 // the slot gives none.
-PSB_DEV i128 slot_event(const Ctx& c, int top, int ra, i128 bu, int64_t row, int j) {
-  const int v = c.nbr[row + j];
-  if (v == NB_PAD) return T_INF;
+PSB_DEV i128 slot_event(const Ctx& c, int i, int top, int ra, i128 bu, int64_t row, int j) {
+  const int k = c.x_nb[(int64_t)i * c.deg + j];
+  if (k == XNB_PAD) return T_INF;
   const i128 W = c.wt[row + j];
-  if (v == NB_BOUNDARY) return (ra > 0) ? W - bu : T_INF;
-  const int k = node_idx(c, v);
+  if (k == XNB_BOUNDARY) return (ra > 0) ? W - bu : T_INF;
   const int vt = (k >= 0) ? c.x_top[k] : -1;
   if (vt < 0) return (ra > 0) ? W - bu : T_INF;      // ARRIVE
   if (vt == top) return T_INF;
@@ -255,7 +255,7 @@ PSB_DEV void node_event(const Ctx& c, int i, i128& tbest, int& kbest) {
   const int deg = c.deg;
   const int64_t row = (int64_t)c.x_node[i] * deg;
   for (int j = 0; j < deg; ++j) {
-    const i128 t = slot_event(c, top, ra, bu, row, j);
+    const i128 t = slot_event(c, i, top, ra, bu, row, j);
     if (t < tbest) { tbest = t; kbest = j; }
   }
 }
@@ -277,7 +277,7 @@ PSB_DEV void node_event_group(const Ctx& c, int i, int G, i128& tbest, int& kbes
       if (ra < 0) {
         if (q == 0 && c.x_reg[i] == top && !(i < c.nd && i == top)) { t = bu; k = K_LEAVE; }
       } else if (q < c.deg) {
-        t = slot_event(c, top, ra, bu, (int64_t)c.x_node[i] * c.deg, q);
+        t = slot_event(c, i, top, ra, bu, (int64_t)c.x_node[i] * c.deg, q);
         k = q;
       }
     }
@@ -305,15 +305,15 @@ PSB_DEV void node_event_u(const Ctx& c, int i, i128& t, int& k) {
 PSB_DEV void refresh_star(Ctx& c, int i) {
   wave_sync();
   const int deg = c.deg;
-  const int64_t row = (int64_t)uni(c.x_node[i]) * deg;
+  const int16_t* nb = c.x_nb + (int64_t)i * deg;
 #if PSB_WAVE > 1
   const int G = slot_group(c), per = PSB_WAVE / G;
   for (int j0 = 0; j0 <= deg; j0 += per) {
     const int j = j0 + lane() / G;
     int x = -1;
     if (j < deg) {
-      const int v = c.nbr[row + j];
-      if (v >= 0) x = node_idx(c, v);
+      const int k = nb[j];
+      if (k >= 0) x = k;
     } else if (j == deg) {
       x = i;
     }
@@ -325,9 +325,7 @@ PSB_DEV void refresh_star(Ctx& c, int i) {
   for (int j = 0; j <= deg; ++j) {
     int x = i;
     if (j < deg) {
-      const int v = c.nbr[row + j];
-      if (v < 0) continue;
-      x = node_idx(c, v);
+      x = nb[j];
       if (x < 0) continue;
     }
     i128 t; int k;
@@ -338,6 +336,29 @@ PSB_DEV void refresh_star(Ctx& c, int i) {
   wave_sync();
 }
 
+// Neighbour-table entry of an adjacency slot holding detector nbv.
+PSB_DEV int xnb_code(const Ctx& c, int nbv) {
+  if (nbv == NB_PAD) return XNB_PAD;
+  if (nbv == NB_BOUNDARY) return XNB_BOUNDARY;
+  return node_idx(c, nbv);
+}
+
+// Fills the neighbour table of explored node ix (detector v) and points the
+// slots of its explored neighbours that hold v at ix (every such slot: a
+// graph may join two detectors by several edges).  Slots are spread over lanes.
+PSB_DEV void link_neighbours(Ctx& c, int ix, int v) {
+  const int deg = c.deg;
+  for (int j = lane(); j < deg; j += PSB_WAVE) {
+    const int nbv = c.nbr[(int64_t)v * deg + j];
+    const int k = xnb_code(c, nbv);
+    c.x_nb[(int64_t)ix * deg + j] = (int16_t)k;
+    if (k >= 0) {
+      for (int j2 = 0; j2 < deg; ++j2)
+        if (c.nbr[(int64_t)nbv * deg + j2] == v) c.x_nb[(int64_t)k * deg + j2] = (int16_t)ix;
+    }
+  }
+}
+
 // Append detector v to the explored table (uniform); returns its index.
 PSB_DEV int explore(Ctx& c, int v) {
   const int ix = uni(c.S->x_n);
@@ -345,6 +366,8 @@ PSB_DEV int explore(Ctx& c, int v) {
   c.x_node[ix] = v; c.x_top[ix] = -1; c.x_reg[ix] = -1; c.x_src[ix] = -1; c.x_rec[ix] = -1;
   c.x_wr[ix] = 0; c.x_ev[ix] = T_INF;
   if (!hash_put(c, v, ix)) { cap_fail(c); return -1; }
+  wave_sync();
+  link_neighbours(c, ix, v);
   wave_sync();
   c.S->x_n = ix + 1;
   wave_sync();
@@ -767,7 +790,7 @@ PSB_DEV void node_event_apply(Ctx& c, int iu, int kind) {
     if (ce < 0) return;
     collide(c, a, -1, ce);
   } else {
-    const int kv = node_idx_u(c, v);
+    const int kv = uni(c.x_nb[(int64_t)iu * deg + kind]);
     const int b = (kv >= 0) ? uni(c.x_top[kv]) : -1;
     if (b < 0) {
       arrive(c, iu, v, e);
@@ -855,7 +878,12 @@ PSB_DEV void load_defects(Ctx& c, const uint8_t* row) {
     c.level[i] = 0;
     hash_put_atomic(c, c.x_node[i], i);
   }
-  // block minima of the blocks these entries occupy start empty
+  wave_sync();
+  // neighbour tables of the detection events (each other's entries included)
+  for (int i = lane(); i < total; i += PSB_WAVE) {
+    const int64_t row = (int64_t)c.x_node[i] * c.deg;
+    for (int j = 0; j < c.deg; ++j) c.x_nb[(int64_t)i * c.deg + j] = (int16_t)xnb_code(c, c.nbr[row + j]);
+  }
   wave_sync();
   c.S->x_n = total;
   wave_sync();
@@ -1396,6 +1424,7 @@ PSB_DEV void ctx_init(Ctx& c, const Params* P, Lds* S, char* state, int64_t slot
   c.shr = (int32_t*)(base + L.shr); c.chg = (int32_t*)(base + L.chg); c.stk = (int32_t*)(base + L.stk);
   c.fin = (int32_t*)(base + L.fin); c.ebits = (uint32_t*)(base + L.ebits);
   c.dmap = P->cap.hcap == 0 ? (int16_t*)(base + L.dmap) : nullptr;
+  c.x_nb = (int16_t*)(base + L.x_nb);
   c.acct = (P->eacct && P->out_stats) ? base + L.acct : nullptr;
 }
 

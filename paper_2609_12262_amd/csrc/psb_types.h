@@ -8,6 +8,8 @@ constexpr int K_NONE = -1;
 constexpr int K_LEAVE = 1000;
 constexpr int NB_BOUNDARY = -1;
 constexpr int NB_PAD = -2;
+// Neighbour-table codes of an adjacency slot without an explored neighbour.
+constexpr int XNB_NONE = -1, XNB_BOUNDARY = -2, XNB_PAD = -3;
 constexpr int MATE_BOUNDARY = -2;
 constexpr int MAXH = 6;           // deepest path enumeration used by clustering
 constexpr int S_OK = 0, S_CAPACITY = 1, S_INFEASIBLE = 2, S_TRUNC = 3, S_INTERNAL = 4, S_OVERFLOW = 5;
@@ -38,6 +40,8 @@ struct WsLayout {
                                                  // (only when the state block has no hash)
   int64_t x_ev, r_base, x_wr;                    // event cache, region bases, radius offsets, when the state block
                                                  // leaves them out (else unused)
+  int64_t x_nb;                                  // [xcap][deg] int16: explored index of each adjacency slot's
+                                                 // neighbour (XNB_* codes when it has none)
   int64_t acct;                                  // per-cluster event accounting block (event_accounting only)
   int64_t total;                                 // bytes per slot (multiple of 256)
 };
