@@ -95,7 +95,11 @@ template <int F> PSB_DEV typename RFType<F>::T& rf_ref(const Ctx& c, int r) {
 #define RF(c, r, f) (rf_ref<(f)>((c), (r)))
 #define CEF(c, i, f) ((c).ce[(int64_t)(i) * CE_COUNT + (f)])
 
-PSB_DEV i128 yrad(const Ctx& c, int r, i128 t) { return c.r_base[r] + (i128)RF(c, r, RF_RATE) * t; }
+// rate * t for a region rate in {-1, 0, +1}, as a select rather than a
+// 128-bit multiply.
+PSB_DEV i128 rate_times(int rate, i128 t) { return rate > 0 ? t : (rate < 0 ? -t : (i128)0); }
+
+PSB_DEV i128 yrad(const Ctx& c, int r, i128 t) { return c.r_base[r] + rate_times(RF(c, r, RF_RATE), t); }
 
 // ---------------------------------------------------------------------------
 // parallel event count (Methods, numerical evaluation: the critical-path event
@@ -394,7 +398,7 @@ PSB_DEV void note_change(Ctx& c, int r) {
 
 PSB_DEV void set_rate(Ctx& c, int r, int rate) {
   const i128 y = yrad(c, r, c.now);
-  c.r_base[r] = y - (i128)rate * c.now;
+  c.r_base[r] = y - rate_times(rate, c.now);
   RF(c, r, RF_RATE) = rate;
   if (rate < 0) c.n_shr = 1;                 // region events are possible from now on
   note_change(c, r);

@@ -70,8 +70,10 @@ constexpr int DPP_QUAD_XOR2 = 0x4E;     // quad_perm [2,3,0,1]
 constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7-i within each 8 lanes
 constexpr int DPP_MIRROR = 0x140;       // lane i <-> 15-i within each 16 lanes
 
+// Every pattern used reads a valid lane, so the destination's previous value
+// is never kept and needs no initialisation.
 template <int CTRL> PSB_DEV int dpp_mov(int v) {
-  return __builtin_amdgcn_update_dpp(0, opq(v), CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(opq(v), CTRL, 0xF, 0xF, false);
 }
 
 PSB_DEV i128 make_i128(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
@@ -79,13 +81,23 @@ PSB_DEV i128 make_i128(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
   return (i128)(((unsigned __int128)hi << 64) | lo);
 }
 
+// One step: the pair (key, arg) of the partner lane replaces this lane's if
+// it is smaller (key first, then arg).  The order is evaluated on the two
+// 64-bit halves without branches.
 template <int CTRL> PSB_DEV void argmin_step(i128& key, int& arg) {
   const unsigned __int128 u = (unsigned __int128)key;
-  const uint64_t lo = (uint64_t)u, hi = (uint64_t)(u >> 64);
-  const i128 k2 = make_i128((uint32_t)dpp_mov<CTRL>((int)(uint32_t)lo), (uint32_t)dpp_mov<CTRL>((int)(uint32_t)(lo >> 32)),
-                            (uint32_t)dpp_mov<CTRL>((int)(uint32_t)hi), (uint32_t)dpp_mov<CTRL>((int)(uint32_t)(hi >> 32)));
+  const uint64_t lo = (uint64_t)u;
+  const int64_t hi = (int64_t)(uint64_t)(u >> 64);
+  const uint64_t lo2 = ((uint64_t)(uint32_t)dpp_mov<CTRL>((int)(uint32_t)(lo >> 32)) << 32) |
+                       (uint32_t)dpp_mov<CTRL>((int)(uint32_t)lo);
+  const int64_t hi2 = (int64_t)(((uint64_t)(uint32_t)dpp_mov<CTRL>((int)(uint32_t)((uint64_t)hi >> 32)) << 32) |
+                                (uint32_t)dpp_mov<CTRL>((int)(uint32_t)(uint64_t)hi));
   const int a2 = dpp_mov<CTRL>(arg);
-  if (k2 < key || (k2 == key && a2 < arg)) { key = k2; arg = a2; }
+  const bool take = (hi2 < hi) | ((hi2 == hi) & ((lo2 < lo) | ((lo2 == lo) & (a2 < arg))));
+  const uint64_t nlo = take ? lo2 : lo;
+  const int64_t nhi = take ? hi2 : hi;
+  arg = take ? a2 : arg;
+  key = (i128)(((unsigned __int128)(uint64_t)nhi << 64) | nlo);
 }
 
 // Minimum over aligned groups of g lanes (g a power of two <= 16); ties to the
