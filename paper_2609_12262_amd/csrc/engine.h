@@ -221,6 +221,17 @@ PSB_DEV void next_event(Ctx& c, i128& t, int& code) {
 // ---------------------------------------------------------------------------
 // node-level events (flooder): ARRIVE / COLLIDE / LEAVE times at node i
 // ---------------------------------------------------------------------------
+// The wavefront tiers keep a neighbour table per explored node (the explored
+// index behind each adjacency slot); the lane tier looks neighbours up in the
+// detector map instead (with the table, lane-tier shots on the hash-map path
+// came back wrong on the device while the same code was correct on the CPU;
+// the lane tier keeps the lookups until that is explained).
+constexpr bool kNbTable = PSB_WAVE > 1;
+
+// Explored index of the neighbour behind adjacency slot j of explored node i,
+// or an XNB_* code.
+PSB_DEV int nb_index(const Ctx& c, int i, int64_t row, int j);
+
 // Earliest event seen from explored node i: returns time (T_INF = none) and
 // kind (edge slot 0..deg-1 or K_LEAVE).  The local radius of an owned node
 // is l(t) = y_top(t) + wr; an edge of weight W is crossed by one fill when
@@ -230,7 +241,7 @@ PSB_DEV void next_event(Ctx& c, i128& t, int& code) {
 // top region `top` with rate ra > 0 or 0 and l_u(t) = bu + ra * t); T_INF if
 // the slot gives none.
 PSB_DEV i128 slot_event(const Ctx& c, int i, int top, int ra, i128 bu, int64_t row, int j) {
-  const int k = c.x_nb[(int64_t)i * c.deg + j];
+  const int k = nb_index(c, i, row, j);
   if (k == XNB_PAD) return T_INF;
   const i128 W = c.wt[row + j];
   if (k == XNB_BOUNDARY) return (ra > 0) ? W - bu : T_INF;
@@ -326,10 +337,11 @@ PSB_DEV void refresh_star(Ctx& c, int i) {
     if (x >= 0 && (lane() & (G - 1)) == 0) set_event(c, x, t);
   }
 #else
+  const int64_t row = (int64_t)c.x_node[i] * deg;
   for (int j = 0; j <= deg; ++j) {
     int x = i;
     if (j < deg) {
-      x = nb[j];
+      x = nb_index(c, i, row, j);
       if (x < 0) continue;
     }
     i128 t; int k;
@@ -345,6 +357,11 @@ PSB_DEV int xnb_code(const Ctx& c, int nbv) {
   if (nbv == NB_PAD) return XNB_PAD;
   if (nbv == NB_BOUNDARY) return XNB_BOUNDARY;
   return node_idx(c, nbv);
+}
+
+PSB_DEV int nb_index(const Ctx& c, int i, int64_t row, int j) {
+  if constexpr (kNbTable) return c.x_nb[(int64_t)i * c.deg + j];
+  else return xnb_code(c, c.nbr[row + j]);
 }
 
 // Fills the neighbour table of explored node ix (detector v) and points the
@@ -371,8 +388,10 @@ PSB_DEV int explore(Ctx& c, int v) {
   c.x_wr[ix] = 0; c.x_ev[ix] = T_INF;
   if (!hash_put(c, v, ix)) { cap_fail(c); return -1; }
   wave_sync();
-  link_neighbours(c, ix, v);
-  wave_sync();
+  if constexpr (kNbTable) {
+    link_neighbours(c, ix, v);
+    wave_sync();
+  }
   c.S->x_n = ix + 1;
   wave_sync();
   return ix;
@@ -794,7 +813,7 @@ PSB_DEV void node_event_apply(Ctx& c, int iu, int kind) {
     if (ce < 0) return;
     collide(c, a, -1, ce);
   } else {
-    const int kv = uni(c.x_nb[(int64_t)iu * deg + kind]);
+    const int kv = kNbTable ? uni(c.x_nb[(int64_t)iu * deg + kind]) : node_idx_u(c, v);
     const int b = (kv >= 0) ? uni(c.x_top[kv]) : -1;
     if (b < 0) {
       arrive(c, iu, v, e);
@@ -884,7 +903,7 @@ PSB_DEV void load_defects(Ctx& c, const uint8_t* row) {
   }
   wave_sync();
   // neighbour tables of the detection events (each other's entries included)
-  for (int i = lane(); i < total; i += PSB_WAVE) {
+  for (int i = lane(); kNbTable && i < total; i += PSB_WAVE) {
     const int64_t row = (int64_t)c.x_node[i] * c.deg;
     for (int j = 0; j < c.deg; ++j) c.x_nb[(int64_t)i * c.deg + j] = (int16_t)xnb_code(c, c.nbr[row + j]);
   }

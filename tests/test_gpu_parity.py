@@ -276,6 +276,19 @@ def test_hash_map_large_graph_d41():
     assert not bad, bad[:5]
 
 
+@pytest.mark.parametrize("first_tier,lds_state,caps", [(1, 0, (0, 0)), (0, 3, (1024, 768))])
+def test_hash_map_large_graph_d41_other_first_tiers(first_tier, lds_state, caps):
+    """The hash-map path (d=41) in the lane tier and in the wavefront tier with
+    all state in LDS and large capacities: every shot equals the oracle."""
+    g = synth.rotated_phenom_graph(41, 0.001)
+    s = synth.sample(g, 32, seed=51)
+    say(f"d41 first_tier={first_tier} lds_state={lds_state} caps={caps}: decoding 32 shots")
+    res = gpu_decode(g, s.syndromes, first_tier=first_tier, fast_lds_state=lds_state, fast_max_nodes=caps[0],
+                     fast_max_regions=caps[1])
+    bad = compare_parallel(g, s.syndromes, res, range(32), chunk=2)
+    assert not bad, bad[:5]
+
+
 def test_server_windows_equal_oracle():
     """Serving: windows of three graphs, some with a uniform per-request
     weight, submitted one at a time in bursts (so several batches of one
