@@ -356,6 +356,17 @@ class Server:
         return dict(weight=w.value, obs=ob.value, edges=edges[: min(ne.value, edges_cap)].copy(), n_edges=ne.value,
                     status=st.value, latency_ns=lat.value)
 
+    def collect(self, max_n: int = 4096) -> list:
+        """Finished windows in completion order (without edge lists): dicts of ticket, weight, obs, status,
+        latency_ns; empty when none is finished."""
+        t = np.zeros(max(max_n, 1), np.uint64); w = np.zeros_like(t, dtype=np.int64)
+        ob = np.zeros_like(t); st = np.zeros(len(t), np.int32); lat = np.zeros(len(t), np.int64)
+        P = lambda a: ctypes.c_void_p(a.ctypes.data)
+        k = _check(lib().psb_server_collect(self._h, ctypes.c_int32(max_n), P(t), P(w), P(ob), P(st), P(lat)),
+                   "psb_server_collect")
+        return [dict(ticket=int(t[i]), weight=int(w[i]), obs=int(ob[i]), status=int(st[i]), latency_ns=int(lat[i]))
+                for i in range(k)]
+
     def stats(self) -> dict:
         """Running totals: batches, windows, mean submit-to-launch and launch-to-completion times."""
         v = (ctypes.c_int64 * 5)()

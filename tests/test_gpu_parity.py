@@ -337,3 +337,49 @@ def test_server_windows_equal_oracle():
         assert r["status"] == 0, (k, r)
         assert r["edges"].tolist() == ref.edges.tolist() and r["weight"] == ref.weight and r["obs"] == ref.obs
         assert r["latency_ns"] > 0
+
+
+def test_server_budget_bursts_and_collect():
+    """Serving under a device-memory budget: a budget too small for the
+    decoders is refused with PSB_E_NOMEM; under one that fits, 2,000 windows
+    of two graphs queued in bursts with per-window uniform weights
+    (psb_server_submit_many) and collected in completion order
+    (psb_server_collect) all equal the oracle with that window's weights, and
+    the running statistics count every window."""
+    import time
+    import paper_2609_12262_amd as psb
+    gs = [synth.rotated_phenom_graph(d, 0.005) for d in (7, 11)]
+    Gs = [psb.Graph.from_synth(g) for g in gs]
+    with pytest.raises(psb.PsbError, match="code -2"):
+        psb.Server(Gs, opts={"num_slots": 256}, device_mem_budget=1 << 20)
+    srv = psb.Server(Gs, opts={"num_slots": 256}, device_mem_budget=2 << 30)
+    rng = np.random.default_rng(71)
+    kinds, rows, wts, tickets = [], [], [], []
+    for j0 in range(0, 2000, 250):
+        kk = rng.integers(0, 2, 250)
+        rr = [synth.sample(gs[k], 1, seed=9000 + j0 + i).syndromes[0] for i, k in enumerate(kk)]
+        ww = [0 if (j0 + i) % 4 == 0 else synth.weight_from_p(float(rng.uniform(0.001, 0.007))) for i in range(250)]
+        tickets += srv.submit_many(kk.tolist(), rr, ww)
+        kinds += kk.tolist(); rows += rr; wts += ww
+    say("server: 2000 windows queued in bursts")
+    got = {}
+    t0 = time.time()
+    while len(got) < len(tickets) and time.time() - t0 < 60:
+        for r in srv.collect():
+            got[r["ticket"]] = r
+    st = srv.stats()
+    srv.close()
+    assert len(got) == len(tickets)
+    assert st["windows"] == len(tickets) and st["batches"] >= 1
+    oracles = {}
+    for idx in range(0, len(tickets), 5):
+        k, row, w = kinds[idx], rows[idx], wts[idx]
+        g = gs[k]
+        if w:
+            g = synth.DetectorGraph(g.num_detectors, g.u, g.v, np.full(g.num_edges, w, np.int32), g.obs_mask, g.p)
+        key = (k, w)
+        if key not in oracles:
+            oracles[key] = oracle.Graph(g, SEED)
+        ref = oracles[key].mwem(synth.defects_of(row, g.num_detectors))
+        r = got[tickets[idx]]
+        assert r["status"] == 0 and r["weight"] == ref.weight and r["obs"] == ref.obs, (idx, r, ref.weight, ref.obs)
