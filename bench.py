@@ -327,6 +327,37 @@ def serving(args):
     print(json.dumps(out), flush=True)
 
 
+def sliding_window(args):
+    """Sliding-window decoding of long streams: B shots of R rounds each, windows of W layers committing C.
+    Sustained throughput = rounds decoded per second over the whole batch."""
+    import torch
+    import synth
+    import paper_2609_12262_amd as psb
+    d, R, W, C = (int(x) for x in args.window.split(","))
+    g = synth.rotated_phenom_graph(d, args.p, rounds=R)
+    L = (d * d - 1) // 2
+    log(f"sampling {args.shots} shots d={d} rounds={R} p={args.p}")
+    shots = synth.sample(g, args.shots, seed=7)
+    plan = psb.WindowPlan(g, L, W, C, tiebreak_seed=0x5EED)
+    synd = torch.from_numpy(shots.syndromes).cuda()
+    for _ in range(args.warmup):
+        out = plan.decode(synd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = plan.decode(synd)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    st = out["status"].cpu().numpy()
+    print(json.dumps({"metric": "sliding-window decoding: rounds per second", "d": d, "rounds": R,
+                      "window_layers": W, "commit_layers": C, "p": args.p, "shots": args.shots,
+                      "windows": plan.n_windows, "window_graphs": plan.n_shapes,
+                      "value": round(args.shots * R / wall, 1), "unit": "rounds/s",
+                      "ms_per_batch": round(wall * 1e3, 3), "us_per_window_launch": round(wall * 1e6 / plan.n_windows, 1),
+                      "ok_shots": int((st == 0).sum())}), flush=True)
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,9 +389,13 @@ def main():
     ap.add_argument("--serve-dists", default="9,13,17,21,25")
     ap.add_argument("--serve-p", default="0.001,0.007", help="window noise rates drawn uniformly from this range")
     ap.add_argument("--oneshot-windows", type=int, default=3000)
+    ap.add_argument("--window", default="", help="d,rounds,W,C: sliding-window decoding of --shots long streams")
     args = ap.parse_args()
     if args.serve:
         serving(args)
+        return
+    if args.window:
+        sliding_window(args)
         return
     if args.latency:
         if args.gpus != 1:

@@ -233,6 +233,43 @@ int32_t psb_decoder_max_defects(const psb_decoder* d);
 int32_t psb_graph_syndrome_bytes(const psb_graph* g);
 
 /* ---------------------------------------------------------------------
+ * Sliding-window decoding (Introduction: decoding a long stream of rounds
+ * in overlapping windows; the MWEM of each window is the paper's problem).
+ *
+ * The graph's detectors come in num_detectors / layer_size layers (one per
+ * round, layer t = detectors t*layer_size .. (t+1)*layer_size-1).  Window k
+ * covers layers [k*commit_layers, k*commit_layers + window_layers): edges
+ * inside it are kept, an edge to a later layer becomes a boundary edge at
+ * its end in the window, an edge to an earlier layer is dropped.  Each
+ * window's MWEM is decoded with psb_decode_batch (decoders built with `opts`,
+ * NULL = defaults; windows of equal structure share one decoder); the
+ * matched edges whose lower layer is among the window's first commit_layers
+ * layers are committed (weight and observable accumulated, both endpoints
+ * flipped in a running copy of the syndrome).  The window that reaches the
+ * last layer commits everything, after which the running syndrome must be
+ * empty.  The result is a valid correction (odd degree exactly at the
+ * detection events); with window_layers >= the layer count it is the MWEM.
+ * Errors: PSB_E_INVALID (layer_size does not divide num_detectors, not
+ * 0 < commit_layers < window_layers, endpoints out of range), PSB_E_NOMEM,
+ * PSB_E_DEVICE, PSB_E_UNSUPPORTED (a window graph outside the decoder's
+ * limits). */
+typedef struct psb_window_plan psb_window_plan;
+int32_t psb_window_plan_create(const psb_graph_desc* desc, int32_t layer_size, int32_t window_layers,
+                               int32_t commit_layers, const psb_decoder_opts* opts, psb_window_plan** out);
+/* Number of windows and of distinct window graphs (decoders) of the plan. */
+int32_t psb_window_plan_info(const psb_window_plan* p, int32_t* n_windows, int32_t* n_shapes);
+/* Decodes n shots asynchronously on `stream`: syndromes [n][ceil(num_detectors/8)]
+ * uint8 (DEVICE); outputs weight [n] int64 (sum of committed caller weights),
+ * obs [n] uint64, status [n] int32 (PSB_S_OK, the first failing window's
+ * status, or PSB_S_INTERNAL if detection events were left unresolved), all
+ * DEVICE pointers owned by the caller.  Batch buffers are held by the plan
+ * and grow (after synchronising the stream) when a larger batch comes; one
+ * batch per plan at a time.  Errors: PSB_E_INVALID, PSB_E_NOMEM, PSB_E_DEVICE. */
+int32_t psb_window_decode(psb_window_plan* p, const uint8_t* syndromes, int64_t n, int64_t* weight,
+                          uint64_t* obs, int32_t* status, void* stream);
+int32_t psb_window_plan_destroy(psb_window_plan* p);
+
+/* ---------------------------------------------------------------------
  * Serving (windows arriving one at a time while others decode).
  *
  * Requests are grouped per (graph, weight set): the graph's own weights, or,

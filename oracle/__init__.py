@@ -15,6 +15,10 @@ Contents:
                            "Parameter schedule"; Supplementary S11), exact rationals.
   * ``cluster_levels``  -- processing-cluster hierarchy (Methods, Algorithm
                            "Clustering"), from exact pairwise distances.
+  * ``window_schedule``,
+    ``window_decode``   -- sliding-window decoding of a layered graph
+                           (Introduction: a stream of rounds decoded in
+                           overlapping windows), each window by ``mwem``.
   * ``brute_*``         -- brute-force pins for tiny inputs.
 """
 from __future__ import annotations
@@ -353,3 +357,94 @@ def brute_min_pairing(costs_pair, costs_bd):
         return best
 
     return rec(list(range(m)))
+
+
+# ---------------------------------------------------------------------------
+# Sliding-window decoding (Introduction: long streams of rounds decoded in
+# overlapping windows).  Parity unpinned beyond its own properties: the paper
+# fixes no window rule; this is the plain procedure the decoder implements.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class WindowGraph:
+    num_detectors: int
+    u: np.ndarray
+    v: np.ndarray
+    w: np.ndarray
+    obs_mask: np.ndarray
+
+    @property
+    def num_edges(self) -> int:
+        return int(self.u.shape[0])
+
+
+def window_schedule(g, layer_size: int, window_layers: int, commit_layers: int):
+    """Windows of `window_layers` layers advancing by `commit_layers`: list of
+    (first layer, window graph, full-graph edge id of each window edge, commit
+    flag of each window edge).  Inside window [a, b): an edge with both ends in
+    it is kept; an edge from it to a later layer ends at the boundary; an edge
+    to an earlier layer is left out.  A matched edge is committed when its
+    lower layer is below a + commit_layers, or in the last window (which
+    reaches the final layer)."""
+    L = int(layer_size)
+    n_layers = g.num_detectors // L
+    out = []
+    a = 0
+    while True:
+        last = a + window_layers >= n_layers
+        b = n_layers if last else a + window_layers
+        wu, wv, ww, wo, emap, commit = [], [], [], [], [], []
+        for e in range(g.num_edges):
+            x, y = int(g.u[e]), int(g.v[e])
+            lx = x // L
+            if y < 0:
+                if not (a <= lx < b):
+                    continue
+                ends, low = (x - a * L, -1), lx
+            else:
+                ly = y // L
+                inx, iny = a <= lx < b, a <= ly < b
+                if inx and iny:
+                    ends, low = (x - a * L, y - a * L), min(lx, ly)
+                elif inx and ly >= b:
+                    ends, low = (x - a * L, -1), lx
+                elif iny and lx >= b:
+                    ends, low = (y - a * L, -1), ly
+                else:
+                    continue
+            wu.append(ends[0]); wv.append(ends[1]); ww.append(int(g.w[e])); wo.append(int(g.obs_mask[e]))
+            emap.append(e)
+            commit.append(last or low < a + commit_layers)
+        wg = WindowGraph((b - a) * L, np.asarray(wu, np.int32), np.asarray(wv, np.int32),
+                         np.asarray(ww, np.int32), np.asarray(wo, np.uint64))
+        out.append((a, wg, emap, commit))
+        if last:
+            return out
+        a += commit_layers
+
+
+def window_decode(g, schedule, graphs, layer_size: int, defects):
+    """Decode one shot window by window.  `graphs[k]` is an oracle ``Graph`` on
+    the k-th window graph of `schedule`.  Returns (weight, obs, ok): the sum of
+    the committed edges' weights, the XOR of their observable masks, and
+    whether every detection event ended resolved and every window was
+    feasible."""
+    L = int(layer_size)
+    running = set(int(x) for x in defects)
+    weight, obs = 0, 0
+    for (a, wg, emap, commit), og in zip(schedule, graphs):
+        lo, hi = a * L, a * L + wg.num_detectors
+        local = sorted(x - lo for x in running if lo <= x < hi)
+        r = og.mwem(np.asarray(local, np.int32))
+        if r.flags & OF_INFEASIBLE:
+            return 0, 0, False
+        for e in r.edges.tolist():
+            if not commit[e]:
+                continue
+            ge = emap[e]
+            weight += int(g.w[ge])
+            obs ^= int(g.obs_mask[ge])
+            for end in (int(g.u[ge]), int(g.v[ge])):
+                if end >= 0:
+                    running ^= {end}
+    return weight, obs, not running

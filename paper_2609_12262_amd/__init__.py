@@ -80,7 +80,9 @@ def lib():
                      "psb_decoder_slots", "psb_decoder_last_overflow", "psb_decoder_device_bytes", "psb_decoder_reserve",
                      "psb_server_create", "psb_server_submit", "psb_server_submit_many", "psb_server_poll", "psb_server_collect",
                      "psb_server_stats", "psb_server_destroy", "psb_autotune", "psb_autotune_candidates",
-                     "psb_batch_graph_create", "psb_batch_graph_launch", "psb_batch_graph_destroy"):
+                     "psb_batch_graph_create", "psb_batch_graph_launch", "psb_batch_graph_destroy",
+                     "psb_window_plan_create", "psb_window_plan_info", "psb_window_decode",
+                     "psb_window_plan_destroy"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -276,6 +278,48 @@ class BatchGraph:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().psb_batch_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class WindowPlan:
+    """psb_window_plan: sliding-window decoding of a layered graph (one layer of detectors per round)."""
+
+    def __init__(self, g, layer_size: int, window_layers: int, commit_layers: int, **opts):
+        u = np.ascontiguousarray(g.u, np.int32); v = np.ascontiguousarray(g.v, np.int32)
+        w = np.ascontiguousarray(g.w, np.int32); o = np.ascontiguousarray(g.obs_mask, np.uint64)
+        desc = _GraphDesc(g.num_detectors, len(u), u.ctypes.data, v.ctypes.data, w.ctypes.data, o.ctypes.data)
+        c = _make_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().psb_window_plan_create(ctypes.byref(desc), ctypes.c_int32(layer_size),
+                                            ctypes.c_int32(window_layers), ctypes.c_int32(commit_layers),
+                                            ctypes.byref(c), ctypes.byref(h)), "psb_window_plan_create")
+        self._h = h
+        nw, ns = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().psb_window_plan_info(h, ctypes.byref(nw), ctypes.byref(ns)), "psb_window_plan_info")
+        self.n_windows, self.n_shapes = nw.value, ns.value
+
+    def decode(self, syndromes, stream=None):
+        """syndromes: uint8 CUDA tensor [n][ceil(num_detectors/8)] -> dict of weight, obs, status tensors."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        n = syndromes.shape[0]
+        out = dict(weight=torch.empty(n, dtype=torch.int64, device=syndromes.device),
+                   obs=torch.empty(n, dtype=torch.int64, device=syndromes.device),
+                   status=torch.empty(n, dtype=torch.int32, device=syndromes.device))
+        P = lambda t: ctypes.c_void_p(t.data_ptr())
+        _check(lib().psb_window_decode(self._h, P(syndromes), ctypes.c_int64(n), P(out["weight"]), P(out["obs"]),
+                                       P(out["status"]), ctypes.c_void_p(s.cuda_stream)), "psb_window_decode")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().psb_window_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):

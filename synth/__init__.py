@@ -81,8 +81,10 @@ def z_faces(d: int):
 
 
 def rotated_phenom_graph(d: int, p: float, q: float | None = None,
-                         w_spatial: int | None = None, w_time: int | None = None) -> DetectorGraph:
-    """Phenomenological rotated-code detector graph over d rounds (d+1 layers)."""
+                         w_spatial: int | None = None, w_time: int | None = None,
+                         rounds: int | None = None) -> DetectorGraph:
+    """Phenomenological rotated-code detector graph over `rounds` rounds (default d; rounds+1 layers of
+    (d*d-1)/2 detectors, layer t holding detectors (t-1)*nz .. t*nz-1)."""
     if d < 3 or d % 2 == 0:
         raise ValueError("d must be odd and >= 3")
     q = p if q is None else q
@@ -95,8 +97,11 @@ def rotated_phenom_graph(d: int, p: float, q: float | None = None,
     for fi, (_, qs) in enumerate(faces):
         for qq in qs:
             qubit_faces.setdefault(qq, []).append(fi)
+    R = d if rounds is None else int(rounds)
+    if R < 1:
+        raise ValueError("rounds must be >= 1")
     u, v, w, obs, pp = [], [], [], [], []
-    for layer in range(1, d + 1):
+    for layer in range(1, R + 1):
         base = (layer - 1) * nz
         for r in range(d):
             for c in range(d):
@@ -108,12 +113,12 @@ def rotated_phenom_graph(d: int, p: float, q: float | None = None,
                     u.append(base + fs[0]); v.append(-1)
                 w.append(ws); pp.append(p)
                 obs.append(1 if (r == 0) else 0)
-    for t in range(1, d + 1):
+    for t in range(1, R + 1):
         for fi in range(nz):
             u.append((t - 1) * nz + fi); v.append(t * nz + fi)
             w.append(wt); pp.append(q); obs.append(0)
     return DetectorGraph(
-        num_detectors=nz * (d + 1),
+        num_detectors=nz * (R + 1),
         u=np.asarray(u, np.int32), v=np.asarray(v, np.int32), w=np.asarray(w, np.int32),
         obs_mask=np.asarray(obs, np.uint64), p=np.asarray(pp, np.float64),
         name=f"rotated_phenom_d{d}_p{p}_q{q}")

@@ -179,3 +179,29 @@ def test_event_accounting_global_mode_and_lane_tier():
         assert np.array_equal(wave["stats"][:, q], lane["stats"][:, q]), q
     bad = compare(g, s.syndromes, wave, range(0, 1500, 5))
     assert not bad, bad[:5]
+
+
+@pytest.mark.parametrize("d,rounds,W,C,p", [(5, 12, 6, 3, 0.01), (9, 30, 10, 5, 0.005), (11, 44, 22, 11, 0.003)])
+def test_sliding_window_equals_oracle(d, rounds, W, C, p):
+    """Sliding-window decoding (windows of W layers committing C): every
+    shot's committed weight and observable equal the oracle's windowed
+    decode, and every detection event is resolved."""
+    import torch
+    import oracle
+    import paper_2609_12262_amd as psb
+    g = synth.rotated_phenom_graph(d, p, rounds=rounds)
+    L = (d * d - 1) // 2
+    s = synth.sample(g, 400, seed=100 + d)
+    plan = psb.WindowPlan(g, L, W, C, tiebreak_seed=SEED)
+    out = plan.decode(torch.from_numpy(s.syndromes).cuda())
+    torch.cuda.synchronize()
+    say(f"window d={d} rounds={rounds}: {plan.n_windows} windows, {plan.n_shapes} window graphs")
+    st = out["status"].cpu().numpy(); wt = out["weight"].cpu().numpy(); ob = out["obs"].cpu().numpy().view(np.uint64)
+    plan.close()
+    assert (st == 0).all(), np.bincount(st)
+    sch = oracle.window_schedule(g, L, W, C)
+    gs = [oracle.Graph(wg, SEED) for _, wg, _, _ in sch]
+    for i in range(0, 400, 2):
+        dd = synth.defects_of(s.syndromes[i], g.num_detectors)
+        w, o, ok = oracle.window_decode(g, sch, gs, L, dd)
+        assert ok and (int(wt[i]), int(ob[i])) == (w, o), (i, int(wt[i]), w, int(ob[i]), o)

@@ -358,3 +358,57 @@ def test_clustering_partition_properties():
                 for y in resid:
                     if lv[y] != k:
                         assert D[x][y] is None or D[x][y] > b[k - 1]
+
+
+# ---------------------------------------------------------------------------
+# Sliding-window decoding (oracle.window_schedule / window_decode)
+# ---------------------------------------------------------------------------
+
+def _window_setup(d, rounds, W, C, p, n, seed):
+    g = synth.rotated_phenom_graph(d, p, rounds=rounds)
+    L = (d * d - 1) // 2
+    sch = oracle.window_schedule(g, L, W, C)
+    gs = [oracle.Graph(wg, 0x5EED) for _, wg, _, _ in sch]
+    s = synth.sample(g, n, seed=seed)
+    return g, L, sch, gs, s
+
+
+def test_window_schedule_structure():
+    """Windows start every C layers; all but the last have W layers; the last
+    reaches the final layer; every window edge maps to a full-graph edge with
+    an end in the window, and the last window commits everything."""
+    g, L, sch, _, _ = _window_setup(5, 12, 6, 3, 0.01, 1, 1)
+    n_layers = g.num_detectors // L
+    assert [a for a, *_ in sch] == [0, 3, 6, 9]
+    for k, (a, wg, emap, commit) in enumerate(sch):
+        last = k == len(sch) - 1
+        assert wg.num_detectors == L * ((n_layers - a) if last else 6)
+        assert len(emap) == wg.num_edges == len(commit)
+        if last:
+            assert all(commit)
+        for e, ge in enumerate(emap):
+            ends = [x for x in (int(g.u[ge]), int(g.v[ge])) if x >= 0]
+            assert any(a * L <= x < a * L + wg.num_detectors for x in ends)
+
+
+def test_window_single_window_equals_mwem():
+    """A window covering every layer is the whole graph: the MWEM itself."""
+    g, L, sch, gs, s = _window_setup(5, 8, 100, 3, 0.01, 60, 2)
+    assert len(sch) == 1
+    full = oracle.Graph(g, 0x5EED)
+    for i in range(60):
+        d = synth.defects_of(s.syndromes[i], g.num_detectors)
+        r = full.mwem(d)
+        w, o, ok = oracle.window_decode(g, sch, gs, L, d)
+        assert ok and (w, o) == (r.weight, r.obs)
+
+
+def test_window_decode_is_a_valid_correction():
+    """Committed edges resolve every detection event (the running syndrome
+    ends empty) and weigh at least the MWEM."""
+    g, L, sch, gs, s = _window_setup(5, 16, 6, 2, 0.02, 80, 3)
+    full = oracle.Graph(g, 0x5EED)
+    for i in range(80):
+        d = synth.defects_of(s.syndromes[i], g.num_detectors)
+        w, o, ok = oracle.window_decode(g, sch, gs, L, d)
+        assert ok and w >= full.mwem(d).weight
