@@ -338,7 +338,8 @@ def sliding_window(args):
     L = (d * d - 1) // 2
     log(f"sampling {args.shots} shots d={d} rounds={R} p={args.p}")
     shots = synth.sample(g, args.shots, seed=7)
-    plan = psb.WindowPlan(g, L, W, C, tiebreak_seed=0x5EED)
+    caps = [int(x) for x in args.window_caps.split(",")] if args.window_caps else [0, 0]
+    plan = psb.WindowPlan(g, L, W, C, tiebreak_seed=0x5EED, fast_max_nodes=caps[0], fast_max_regions=caps[1])
     synd = torch.from_numpy(shots.syndromes).cuda()
     for _ in range(args.warmup):
         out = plan.decode(synd)
@@ -351,7 +352,7 @@ def sliding_window(args):
     st = out["status"].cpu().numpy()
     print(json.dumps({"metric": "sliding-window decoding: rounds per second", "d": d, "rounds": R,
                       "window_layers": W, "commit_layers": C, "p": args.p, "shots": args.shots,
-                      "windows": plan.n_windows, "window_graphs": plan.n_shapes,
+                      "windows": plan.n_windows, "window_graphs": plan.n_shapes, "first_tier_state": caps,
                       "value": round(args.shots * R / wall, 1), "unit": "rounds/s",
                       "ms_per_batch": round(wall * 1e3, 3), "us_per_window_launch": round(wall * 1e6 / plan.n_windows, 1),
                       "ok_shots": int((st == 0).sum())}), flush=True)
@@ -390,6 +391,8 @@ def main():
     ap.add_argument("--serve-p", default="0.001,0.007", help="window noise rates drawn uniformly from this range")
     ap.add_argument("--oneshot-windows", type=int, default=3000)
     ap.add_argument("--window", default="", help="d,rounds,W,C: sliding-window decoding of --shots long streams")
+    ap.add_argument("--window-caps", default="640,416",
+                    help="nodes,regions of the window decoders' first tier (the best of a sweep at d=21, W=2d)")
     args = ap.parse_args()
     if args.serve:
         serving(args)
