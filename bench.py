@@ -368,6 +368,8 @@ def main():
     ap.add_argument("--p", type=float, default=0.005)
     ap.add_argument("--shots", type=int, default=50000)
     ap.add_argument("--mode", type=int, default=0, help="0 partition-and-fuse, 1 global sparse blossom")
+    ap.add_argument("--graph", default="phenom", choices=["phenom", "circuit_x"],
+                    help="phenomenological graph, or circuit-level X-fault graph (diagonal edges, mixed weights)")
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true", help="default decoder configuration instead of the "
                                                                  "autotuner's pick")
@@ -427,8 +429,11 @@ def main():
     import paper_2609_12262_amd as psb
 
     seed_sample = {0.005: 3, 0.001: 4}.get(args.p, 3)
-    g = synth.rotated_phenom_graph(args.d, args.p)
-    log(f"sampling {args.shots} shots d={args.d} p={args.p}")
+    if args.graph == "circuit_x":
+        g = synth.rotated_circuit_x_graph(args.d, args.p)
+    else:
+        g = synth.rotated_phenom_graph(args.d, args.p)
+    log(f"sampling {args.shots} shots d={args.d} p={args.p} graph={args.graph}")
     shots = synth.sample(g, args.shots, seed=seed_sample)
     G = psb.Graph.from_synth(g)
     synd = torch.from_numpy(shots.syndromes).cuda()
@@ -485,8 +490,11 @@ def main():
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int128", "data": "synthetic",
-        "config": {"workload": f"rotated surface code memory, phenomenological noise, d={args.d}, {args.d} rounds, "
-                               f"p=q={args.p}, {args.shots} shots per step, one persistent launch",
+        "config": {"workload": (f"rotated surface code memory, phenomenological noise, d={args.d}, {args.d} rounds, "
+                                f"p=q={args.p}, {args.shots} shots per step, one persistent launch")
+                   if args.graph == "phenom" else
+                   (f"rotated surface code Z memory, circuit-level X faults (CNOT order NW,SW,NE,SE), d={args.d}, "
+                    f"{args.d} rounds, p={args.p}, {args.shots} shots per step, one persistent launch"),
                    "d": args.d, "rounds": args.d, "p": args.p, "shots_per_step": args.shots,
                    "mode": "partition-and-fuse" if args.mode == 0 else "global sparse blossom",
                    "first_tier": "one shot per lane" if kw.get("first_tier", 0) else "one shot per wavefront",
@@ -504,7 +512,7 @@ def main():
                                  "basis": "batch submission to shot completion (device clock), last step"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": measured_traffic(args.d, args.p, args.shots, kw),
+                     "traffic": measured_traffic(args.d, args.p, args.shots, kw) if args.graph == "phenom" else None,
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(avg_launch_s * 1e3, 3),
                      "kernel": "psb_lane_kernel" if kw.get("first_tier", 0) else "psb_decode_kernel<0, 0>"},
         "work_per_shot": {"events": float(stats[:, 0].mean()), "reached": float(stats[:, 1].mean()),

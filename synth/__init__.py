@@ -124,6 +124,70 @@ def rotated_phenom_graph(d: int, p: float, q: float | None = None,
         name=f"rotated_phenom_d{d}_p{p}_q{q}")
 
 
+def rotated_circuit_x_graph(d: int, p: float, rounds: int | None = None) -> DetectorGraph:
+    """Detector graph of Z-basis memory on the rotated code from X faults in the syndrome-extraction circuit.
+
+    Each round measures every Z plaquette with four CNOTs, data qubit as control and ancilla as target, in the
+    order of the plaquette's qubit list (top-left, bottom-left, top-right, bottom-right; steps 1-4; the two
+    weight-2 boundary plaquettes use steps 3-4 on the left edge and 1-2 on the right).  Fault mechanisms,
+    each of probability p:
+      * an X on a data qubit before CNOT step k+1 of round t (k = 0..3): plaquettes whose step for that
+        qubit is later than k see it in round t (detector (t, P)), the others first in round t+1;
+      * an X on a plaquette's ancilla before its measurement (a measurement error): detectors (t, P) and
+        (t+1, P).
+    Round 1 compares with the deterministic initial state and the final layer (rounds+1) with the
+    transversal data measurement.  Mechanisms with the same detector pair merge (XOR of independent events:
+    q = q1 + q2 - 2 q1 q2); weights are round(256 ln((1-q)/q)).  An X on a row-0 data qubit flips the
+    logical observable."""
+    if d < 3 or d % 2 == 0:
+        raise ValueError("d must be odd and >= 3")
+    R = d if rounds is None else int(rounds)
+    faces = z_faces(d)
+    nz = len(faces)
+    step = {}                                  # (qubit, face index) -> CNOT step 1..4
+    for fi, ((r, c), qs) in enumerate(faces):
+        steps = (1, 2, 3, 4) if len(qs) == 4 else ((3, 4) if c == -1 else (1, 2))
+        for qq, st in zip(qs, steps):
+            step[(qq, fi)] = st
+    qubit_faces: dict = {}
+    for (qq, fi) in step:
+        qubit_faces.setdefault(qq, []).append(fi)
+    mech: dict = {}                            # (u, v, obs) -> probability; v = -1 boundary
+
+    def add(dets, obs):
+        dets = sorted(set(dets))
+        if not dets:
+            return
+        if len(dets) == 1:
+            key = (dets[0], -1, obs)
+        else:
+            assert len(dets) == 2
+            key = (dets[0], dets[1], obs)
+        q0 = mech.get(key, 0.0)
+        mech[key] = q0 + p - 2 * q0 * p
+
+    for t in range(1, R + 1):
+        for r in range(d):
+            for c in range(d):
+                fs = qubit_faces[(r, c)]
+                for k in range(4):
+                    dets = []
+                    for fi in fs:
+                        layer = t if step[((r, c), fi)] > k else t + 1
+                        dets.append((layer - 1) * nz + fi)
+                    add(dets, 1 if r == 0 else 0)
+        for fi in range(nz):
+            add([(t - 1) * nz + fi, t * nz + fi], 0)
+    keys = sorted(mech)
+    u = np.asarray([k[0] for k in keys], np.int32)
+    v = np.asarray([k[1] for k in keys], np.int32)
+    obs = np.asarray([k[2] for k in keys], np.uint64)
+    pp = np.asarray([mech[k] for k in keys], np.float64)
+    w = np.asarray([weight_from_p(float(q)) for q in pp], np.int32)
+    return DetectorGraph(num_detectors=nz * (R + 1), u=u, v=v, w=w, obs_mask=obs, p=pp,
+                         name=f"rotated_circuit_x_d{d}_p{p}_r{R}")
+
+
 def repetition_graph(n_det: int, w, p: float = 0.01) -> DetectorGraph:
     """Path graph: boundary - 0 - 1 - ... - (n_det-1) - boundary (n_det+1 edges).
 

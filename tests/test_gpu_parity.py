@@ -383,3 +383,15 @@ def test_server_budget_bursts_and_collect():
         ref = oracles[key].mwem(synth.defects_of(row, g.num_detectors))
         r = got[tickets[idx]]
         assert r["status"] == 0 and r["weight"] == ref.weight and r["obs"] == ref.obs, (idx, r, ref.weight, ref.obs)
+
+
+@pytest.mark.parametrize("d,p,n,step", [(5, 0.003, 5000, 1), (9, 0.002, 3000, 1), (13, 0.002, 2000, 10)])
+def test_circuit_x_graphs_equal_oracle(d, p, n, step):
+    """Detector graphs from circuit-level X faults (diagonal spacetime edges,
+    non-uniform weights, degree up to 10): shots equal the oracle."""
+    g = synth.rotated_circuit_x_graph(d, p)
+    s = synth.sample(g, n, seed=120 + d)
+    say(f"circuit-x d={d}: decoding {n} shots")
+    res = gpu_decode(g, s.syndromes)
+    bad = compare(g, s.syndromes, res, range(0, n, step))
+    assert not bad, bad[:5]
