@@ -20,12 +20,16 @@
 // of the tie-broken even weights, so every event happens at an integer time.
 //
 // State.  Only detectors that a region has reached ("explored" nodes, the
-// detection events first, in ascending order) carry state; a hash maps a
-// detector id to its explored index.  Explored index i < nd is detection
-// event i, whose detector region is region i and whose arrival record is
-// record i.  The explored table, the hash, the event-cache block minima and
-// the region table form the StateLayout block, which lives in LDS (a small
-// block for the fast tier, a large one for the overflow tier).
+// detection events first, in ascending order) carry state; a direct map (or
+// a hash, for graphs above 32,768 detectors) takes a detector id to its
+// explored index, and in the wavefront tiers a neighbour table holds the
+// explored index behind every adjacency slot of every explored node.
+// Explored index i < nd is detection event i, whose detector region is
+// region i and whose arrival record is record i.  The explored table, the
+// region table and (per placement) the event cache, radius offsets and region
+// bases form the StateLayout block, which lives in LDS for the wavefront
+// tiers and in the slot's workspace for the lane tier; the rest of the
+// per-shot state lives in the slot's workspace.
 //
 // Code style: every function is executed by all lanes of the wavefront with
 // identical (uniform) values except inside the lane-parallel loops
@@ -320,8 +324,8 @@ PSB_DEV void node_event_u(const Ctx& c, int i, i128& t, int& k) {
 PSB_DEV void refresh_star(Ctx& c, int i) {
   wave_sync();
   const int deg = c.deg;
-  const int16_t* nb = c.x_nb + (int64_t)i * deg;
 #if PSB_WAVE > 1
+  const int16_t* nb = c.x_nb + (int64_t)i * deg;
   const int G = slot_group(c), per = PSB_WAVE / G;
   for (int j0 = 0; j0 <= deg; j0 += per) {
     const int j = j0 + lane() / G;

@@ -239,7 +239,7 @@ static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const 
   L.x_ev = lean >= 1 ? take(16LL * cap.xcap) : 0;
   L.r_base = lean >= 1 ? take(16LL * cap.rcap) : 0;
   L.x_wr = lean >= 2 ? take(16LL * cap.xcap) : 0;
-  L.x_nb = take(2LL * cap.xcap * deg);
+  L.x_nb = lane_slot ? 0 : take(2LL * cap.xcap * deg);   // the lane tier has no neighbour table
   L.acct = acct ? take(psb::acct_bytes(d)) : 0;
   P.eacct = acct ? 1 : 0;
   L.total = off;
