@@ -55,3 +55,13 @@ def test_library_rejects_bad_schedule_arguments():
         psb.schedule_levels(100, 1000, q=(2, 1))
     with pytest.raises(psb.PsbError):
         psb.schedule_levels(0, 1000)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more it exits with status 2 and a
+    message, before touching any device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
