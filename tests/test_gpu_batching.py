@@ -205,3 +205,41 @@ def test_sliding_window_equals_oracle(d, rounds, W, C, p):
         dd = synth.defects_of(s.syndromes[i], g.num_detectors)
         w, o, ok = oracle.window_decode(g, sch, gs, L, dd)
         assert ok and (int(wt[i]), int(ob[i])) == (w, o), (i, int(wt[i]), w, int(ob[i]), o)
+
+
+def test_circuit_x_graph_autotune_windows_and_accounting():
+    """The circuit-level X-fault graph (non-uniform weights, diagonal
+    spacetime edges) through the autotuner (its candidates agree), sliding
+    windows (equal to the oracle's windowed decode) and event accounting
+    (E_ideal at most the applied events, results unchanged)."""
+    import torch
+    import oracle
+    import paper_2609_12262_amd as psb
+    g = synth.rotated_circuit_x_graph(9, 0.002)
+    s = synth.sample(g, 2000, seed=130)
+    G = psb.Graph.from_synth(g)
+    best, table = psb.autotune(G, torch.from_numpy(s.syndromes).cuda(), reps=1, tiebreak_seed=SEED)
+    assert any(t["status"] == 0 for t in table)
+    acc = _accounted(g, s.syndromes)
+    plain = gpu_decode(g, s.syndromes, **{k: best[k] for k in ("fast_max_nodes", "fast_max_regions", "first_tier",
+                                                               "fast_lds_state")})
+    for key in ("n_edges", "weight", "obs", "status"):
+        assert np.array_equal(acc[key], plain[key]), key
+    assert (acc["stats"][:, 9] <= acc["stats"][:, 8]).all()
+    bad = compare(g, s.syndromes, plain, range(0, 2000, 10))
+    assert not bad, bad[:5]
+    G.close()
+    gw = synth.rotated_circuit_x_graph(7, 0.002, rounds=21)
+    L = (7 * 7 - 1) // 2
+    sw = synth.sample(gw, 300, seed=131)
+    plan = psb.WindowPlan(gw, L, 8, 4, tiebreak_seed=SEED)
+    out = plan.decode(torch.from_numpy(sw.syndromes).cuda())
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy(); wt = out["weight"].cpu().numpy(); ob = out["obs"].cpu().numpy().view(np.uint64)
+    plan.close()
+    assert (st == 0).all(), np.bincount(st)
+    sch = oracle.window_schedule(gw, L, 8, 4)
+    gs = [oracle.Graph(wg, SEED) for _, wg, _, _ in sch]
+    for i in range(0, 300, 3):
+        w, o, ok = oracle.window_decode(gw, sch, gs, L, synth.defects_of(sw.syndromes[i], gw.num_detectors))
+        assert ok and (int(wt[i]), int(ob[i])) == (w, o), i
