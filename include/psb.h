@@ -270,6 +270,36 @@ int32_t psb_window_decode(psb_window_plan* p, const uint8_t* syndromes, int64_t 
 int32_t psb_window_plan_destroy(psb_window_plan* p);
 
 /* ---------------------------------------------------------------------
+ * Complementary-gap decoding (Introduction: the weight gap between the
+ * best correction and the best one with the other value of a logical
+ * observable, a confidence measure; each is an MWEM, Results "Decoding
+ * task").  Every edge carrying observable bit `obs_bit` must be a boundary
+ * edge.  The plan rewrites the graph: observable edge j ends at a new
+ * detector x_j, consecutive x_j are joined by weight-1 chain edges, and all
+ * original weights are multiplied by S = the smallest power of two >= the
+ * number of observable edges.  Decoding with x_1 active forces the
+ * observable bit to 1, with none active to 0 (chain edges add even degree to
+ * the x_j); the chain weighs less than S, so each constrained optimum's
+ * original weight is its decoded weight / S.  The rewritten graph is decoded
+ * in global mode (opts->mode is overridden to 1): the weight-1 chain leaves
+ * the clustering no bounded path depth, and both modes return the MWEM.
+ * Errors: PSB_E_INVALID, PSB_E_UNSUPPORTED (an observable edge that is not a
+ * boundary edge, no observable edge, scaled weights beyond int32),
+ * PSB_E_NOMEM, PSB_E_DEVICE. */
+typedef struct psb_comp_plan psb_comp_plan;
+int32_t psb_comp_plan_create(const psb_graph_desc* desc, int32_t obs_bit, const psb_decoder_opts* opts,
+                             psb_comp_plan** out);
+/* n shots of the ORIGINAL graph, syndromes [n][ceil(num_detectors/8)] (DEVICE);
+ * outputs (DEVICE, caller-owned, [n] each): weight0 / weight1 = minimum
+ * weight with the observable bit 0 / 1; gap = |weight1 - weight0|; obs = the
+ * observable mask of the lighter side (ties to bit 0), i.e. the MWEM's;
+ * status (PSB_S_* of the two decodes).  Asynchronous on `stream`; batch
+ * buffers are held by the plan (grown after synchronising the stream). */
+int32_t psb_comp_decode(psb_comp_plan* p, const uint8_t* syndromes, int64_t n, int64_t* weight0, int64_t* weight1,
+                        int64_t* gap, uint64_t* obs, int32_t* status, void* stream);
+int32_t psb_comp_plan_destroy(psb_comp_plan* p);
+
+/* ---------------------------------------------------------------------
  * Serving (windows arriving one at a time while others decode).
  *
  * Requests are grouped per (graph, weight set): the graph's own weights, or,

@@ -19,6 +19,9 @@ Contents:
     ``window_decode``   -- sliding-window decoding of a layered graph
                            (Introduction: a stream of rounds decoded in
                            overlapping windows), each window by ``mwem``.
+  * ``Complementary``   -- minimum weight under each value of one logical
+                           observable and their gap (Introduction: the
+                           complementary gap), each an MWEM of a rewritten graph.
   * ``brute_*``         -- brute-force pins for tiny inputs.
 """
 from __future__ import annotations
@@ -448,3 +451,48 @@ def window_decode(g, schedule, graphs, layer_size: int, defects):
                 if end >= 0:
                     running ^= {end}
     return weight, obs, not running
+
+
+# ---------------------------------------------------------------------------
+# Complementary gap (Introduction: the gap between the best correction and the
+# best one with the other value of a logical observable).
+# ---------------------------------------------------------------------------
+
+class Complementary:
+    """The two constrained minima for observable bit `obs_bit`, whose edges
+    must all be boundary edges.  Each observable edge j is rerouted to a new
+    detector x_j, consecutive x_j are joined by weight-1 edges, and the
+    original weights are scaled by S (a power of two at least the number of
+    observable edges): an edge set with odd degree exactly at D (and at x_1
+    when asked) has observable parity equal to the number of active x_j, and
+    its chain part weighs less than S."""
+
+    def __init__(self, g, obs_bit: int, tiebreak_seed: int):
+        bit = 1 << int(obs_bit)
+        cut = [e for e in range(g.num_edges) if int(g.obs_mask[e]) & bit]
+        if not cut or any(int(g.v[e]) >= 0 for e in cut):
+            raise ValueError("the observable must be carried by boundary edges only")
+        S = 1
+        while S < len(cut):
+            S *= 2
+        n = g.num_detectors
+        u = [int(x) for x in g.u]; v = [int(x) for x in g.v]
+        w = [int(x) * S for x in g.w]; ob = [int(x) for x in g.obs_mask]
+        for j, e in enumerate(cut):
+            v[e] = n + j
+        for j in range(len(cut) - 1):
+            u.append(n + j); v.append(n + j + 1); w.append(1); ob.append(0)
+        self.n, self.S, self.bit = n, S, bit
+        self.graph = WindowGraph(n + len(cut), np.asarray(u, np.int32), np.asarray(v, np.int32),
+                                 np.asarray(w, np.int32), np.asarray(ob, np.uint64))
+        self.og = Graph(self.graph, tiebreak_seed)
+
+    def weights(self, defects):
+        """(W0, W1): minimum original weight with the observable bit 0 and 1
+        (None where no such edge set exists)."""
+        d = sorted(int(x) for x in defects)
+        out = []
+        for extra in ([], [self.n]):
+            r = self.og.mwem(np.asarray(d + extra, np.int32))
+            out.append(None if r.flags & OF_INFEASIBLE else r.weight // self.S)
+        return tuple(out)

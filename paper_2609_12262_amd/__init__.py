@@ -82,7 +82,8 @@ def lib():
                      "psb_server_stats", "psb_server_destroy", "psb_autotune", "psb_autotune_candidates",
                      "psb_batch_graph_create", "psb_batch_graph_launch", "psb_batch_graph_destroy",
                      "psb_window_plan_create", "psb_window_plan_info", "psb_window_decode",
-                     "psb_window_plan_destroy"):
+                     "psb_window_plan_destroy", "psb_comp_plan_create", "psb_comp_decode",
+                     "psb_comp_plan_destroy"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -320,6 +321,45 @@ class WindowPlan:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().psb_window_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ComplementaryPlan:
+    """psb_comp_plan: minimum weights under each value of one observable bit, and their gap."""
+
+    def __init__(self, g, obs_bit: int = 0, **opts):
+        u = np.ascontiguousarray(g.u, np.int32); v = np.ascontiguousarray(g.v, np.int32)
+        w = np.ascontiguousarray(g.w, np.int32); o = np.ascontiguousarray(g.obs_mask, np.uint64)
+        desc = _GraphDesc(g.num_detectors, len(u), u.ctypes.data, v.ctypes.data, w.ctypes.data, o.ctypes.data)
+        c = _make_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().psb_comp_plan_create(ctypes.byref(desc), ctypes.c_int32(obs_bit), ctypes.byref(c),
+                                          ctypes.byref(h)), "psb_comp_plan_create")
+        self._h = h
+
+    def decode(self, syndromes, stream=None):
+        """syndromes: uint8 CUDA tensor [n][ceil(num_detectors/8)] -> dict of weight0, weight1, gap, obs, status."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        n = syndromes.shape[0]
+        dev = syndromes.device
+        out = {k: torch.empty(n, dtype=torch.int64, device=dev) for k in ("weight0", "weight1", "gap", "obs")}
+        out["status"] = torch.empty(n, dtype=torch.int32, device=dev)
+        P = lambda t: ctypes.c_void_p(t.data_ptr())
+        _check(lib().psb_comp_decode(self._h, P(syndromes), ctypes.c_int64(n), P(out["weight0"]), P(out["weight1"]),
+                                     P(out["gap"]), P(out["obs"]), P(out["status"]), ctypes.c_void_p(s.cuda_stream)),
+               "psb_comp_decode")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().psb_comp_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):

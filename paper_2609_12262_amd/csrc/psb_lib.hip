@@ -227,7 +227,10 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   int32_t rc = build_schedule((u128)wmax, diam, opts.q_num, opts.q_den, opts.phi_min_num, opts.phi_min_den, D->sched);
   if (rc != PSB_OK) { delete D; return rc; }
   int bad_level = 0;
-  if (!level_depths(D->sched, wmin, D->hmax, bad_level)) {
+  if (opts.mode == 1) {
+    // global sparse blossom runs no clustering: no path enumeration depth applies
+    D->hmax.assign(D->sched.d.size(), -1);
+  } else if (!level_depths(D->sched, wmin, D->hmax, bad_level)) {
     delete D;
     return fail(PSB_E_UNSUPPORTED, "level " + std::to_string(bad_level) + " needs paths of more than " +
                                        std::to_string(psb::MAXH) + " edges; the clustering kernel enumerates at most that");

@@ -243,3 +243,34 @@ def test_circuit_x_graph_autotune_windows_and_accounting():
     for i in range(0, 300, 3):
         w, o, ok = oracle.window_decode(gw, sch, gs, L, synth.defects_of(sw.syndromes[i], gw.num_detectors))
         assert ok and (int(wt[i]), int(ob[i])) == (w, o), i
+
+
+@pytest.mark.parametrize("graph,d,p,n,step", [("phenom", 5, 0.01, 3000, 1), ("phenom", 11, 0.005, 2000, 4),
+                                              ("circuit_x", 7, 0.002, 1500, 3), ("phenom", 13, 0.005, 256, 2)])
+def test_complementary_gap_equals_oracle(graph, d, p, n, step):
+    """Complementary-gap decoding: both constrained minimum weights (hence the
+    gap) equal the oracle's, the reported observable is the MWEM's, and the
+    lighter side equals the MWEM weight.  d=13 (rewritten graph above 1,024
+    detectors) takes the lane-tier path."""
+    import torch
+    import oracle
+    import paper_2609_12262_amd as psb
+    g = synth.rotated_phenom_graph(d, p) if graph == "phenom" else synth.rotated_circuit_x_graph(d, p)
+    s = synth.sample(g, n, seed=140 + d)
+    plan = psb.ComplementaryPlan(g, 0, tiebreak_seed=SEED)
+    out = plan.decode(torch.from_numpy(s.syndromes).cuda())
+    torch.cuda.synchronize()
+    h = {k: v.cpu().numpy() for k, v in out.items()}
+    plan.close()
+    assert (h["status"] == 0).all(), np.bincount(h["status"])
+    co = oracle.Complementary(g, 0, SEED)
+    og = oracle.Graph(g, SEED)
+    for i in range(0, n, step):
+        dd = synth.defects_of(s.syndromes[i], g.num_detectors)
+        w0, w1 = co.weights(dd)
+        r = og.mwem(dd)
+        assert (int(h["weight0"][i]), int(h["weight1"][i])) == (w0, w1), (i, h["weight0"][i], h["weight1"][i], w0, w1)
+        assert int(h["gap"][i]) == abs(w1 - w0)
+        assert min(w0, w1) == r.weight
+        if w0 != w1:
+            assert int(h["obs"][i]) & 1 == int(r.obs) & 1

@@ -412,3 +412,62 @@ def test_window_decode_is_a_valid_correction():
         d = synth.defects_of(s.syndromes[i], g.num_detectors)
         w, o, ok = oracle.window_decode(g, sch, gs, L, d)
         assert ok and w >= full.mwem(d).weight
+
+
+# ---------------------------------------------------------------------------
+# Complementary gap (oracle.Complementary)
+# ---------------------------------------------------------------------------
+
+def _brute_constrained(g, defects, bit=1):
+    """Minimum weight over all edge subsets with odd degree exactly at the
+    defects, split by the observable bit (tiny graphs)."""
+    best = [None, None]
+    E = g.num_edges
+    want = set(int(x) for x in defects)
+    for mask in range(1 << E):
+        deg = {}
+        wsum, ob = 0, 0
+        for e in range(E):
+            if mask >> e & 1:
+                wsum += int(g.w[e]); ob ^= int(g.obs_mask[e])
+                for x in (int(g.u[e]), int(g.v[e])):
+                    if x >= 0:
+                        deg[x] = deg.get(x, 0) ^ 1
+        if {x for x, k in deg.items() if k} != want:
+            continue
+        b = 1 if ob & bit else 0
+        if best[b] is None or wsum < best[b]:
+            best[b] = wsum
+    return tuple(best)
+
+
+def test_complementary_equals_brute_force_on_small_graphs():
+    """Both constrained minima equal brute force over every edge subset: a
+    repetition code with uneven weights (observable on the left boundary) and
+    a d=3 rotated code over one round (observable on the top boundary)."""
+    rng = np.random.default_rng(5)
+    rep = synth.repetition_graph(7, rng.integers(1, 9, 8).tolist())
+    rot = synth.rotated_phenom_graph(3, 0.01, rounds=1)
+    assert rot.num_edges <= 16
+    for g in (rep, rot):
+        co = oracle.Complementary(g, 0, 0x5EED)
+        for t in range(12):
+            k = int(rng.integers(0, min(5, g.num_detectors) + 1))
+            defects = sorted(rng.choice(g.num_detectors, size=k, replace=False).tolist())
+            assert co.weights(defects) == _brute_constrained(g, defects), (g.num_detectors, defects)
+
+
+def test_complementary_minimum_is_the_mwem():
+    """The lighter constrained minimum is the MWEM weight, on the side of the
+    MWEM's observable bit."""
+    g = synth.rotated_phenom_graph(5, 0.02)
+    co = oracle.Complementary(g, 0, 0x5EED)
+    og = oracle.Graph(g, 0x5EED)
+    s = synth.sample(g, 80, seed=6)
+    for i in range(80):
+        d = synth.defects_of(s.syndromes[i], g.num_detectors)
+        w0, w1 = co.weights(d)
+        r = og.mwem(d)
+        assert min(w0, w1) == r.weight
+        if w0 != w1:
+            assert (w1 < w0) == bool(r.obs & 1)
