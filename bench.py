@@ -24,6 +24,24 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 DEVICE_CLOCK_HZ = 100e6        # wall_clock64() rate on gfx950
 
 
+GRAPHS = {
+    "phenom": "rotated surface code memory, phenomenological noise",
+    "circuit_x": "rotated surface code Z memory, circuit-level X faults (CNOT order NW,SW,NE,SE)",
+    "circuit_uniform": "rotated surface code X memory, uniform circuit-level noise (every circuit location p)",
+    "circuit_physical": "rotated surface code X memory, physical circuit-level noise (1q gates p/10, idle noiseless)",
+}
+
+
+def make_graph(kind, d, p):
+    """The detector graph of one of the workloads in GRAPHS."""
+    import synth
+    if kind == "phenom":
+        return synth.rotated_phenom_graph(d, p)
+    if kind == "circuit_x":
+        return synth.rotated_circuit_x_graph(d, p)
+    return synth.rotated_circuit_graph(d, p, kind.split("_", 1)[1])
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -364,8 +382,7 @@ def complementary(args):
     import torch
     import synth
     import paper_2609_12262_amd as psb
-    g = synth.rotated_phenom_graph(args.d, args.p) if args.graph == "phenom" else \
-        synth.rotated_circuit_x_graph(args.d, args.p)
+    g = make_graph(args.graph, args.d, args.p)
     log(f"sampling {args.shots} shots d={args.d} p={args.p} graph={args.graph}")
     shots = synth.sample(g, args.shots, seed=3)
     plan = psb.ComplementaryPlan(g, 0, tiebreak_seed=0x5EED)
@@ -399,8 +416,9 @@ def main():
     ap.add_argument("--p", type=float, default=0.005)
     ap.add_argument("--shots", type=int, default=50000)
     ap.add_argument("--mode", type=int, default=0, help="0 partition-and-fuse, 1 global sparse blossom")
-    ap.add_argument("--graph", default="phenom", choices=["phenom", "circuit_x"],
-                    help="phenomenological graph, or circuit-level X-fault graph (diagonal edges, mixed weights)")
+    ap.add_argument("--graph", default="phenom", choices=list(GRAPHS),
+                    help="phenomenological graph; circuit-level X-fault graph of Z memory (diagonal edges, mixed "
+                         "weights); or X-memory graph under the uniform or physical circuit-level noise model")
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true", help="default decoder configuration instead of the "
                                                                  "autotuner's pick")
@@ -462,10 +480,7 @@ def main():
     import paper_2609_12262_amd as psb
 
     seed_sample = {0.005: 3, 0.001: 4}.get(args.p, 3)
-    if args.graph == "circuit_x":
-        g = synth.rotated_circuit_x_graph(args.d, args.p)
-    else:
-        g = synth.rotated_phenom_graph(args.d, args.p)
+    g = make_graph(args.graph, args.d, args.p)
     log(f"sampling {args.shots} shots d={args.d} p={args.p} graph={args.graph}")
     shots = synth.sample(g, args.shots, seed=seed_sample)
     G = psb.Graph.from_synth(g)
@@ -523,11 +538,9 @@ def main():
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int128", "data": "synthetic",
-        "config": {"workload": (f"rotated surface code memory, phenomenological noise, d={args.d}, {args.d} rounds, "
-                                f"p=q={args.p}, {args.shots} shots per step, one persistent launch")
-                   if args.graph == "phenom" else
-                   (f"rotated surface code Z memory, circuit-level X faults (CNOT order NW,SW,NE,SE), d={args.d}, "
-                    f"{args.d} rounds, p={args.p}, {args.shots} shots per step, one persistent launch"),
+        "config": {"workload": (f"{GRAPHS[args.graph]}, d={args.d}, {args.d} rounds, "
+                                f"{'p=q' if args.graph == 'phenom' else 'p'}={args.p}, {args.shots} shots per step, "
+                                f"one persistent launch"),
                    "d": args.d, "rounds": args.d, "p": args.p, "shots_per_step": args.shots,
                    "mode": "partition-and-fuse" if args.mode == 0 else "global sparse blossom",
                    "first_tier": "one shot per lane" if kw.get("first_tier", 0) else "one shot per wavefront",

@@ -287,3 +287,10 @@ def defects_of(row: np.ndarray, num_detectors: int) -> np.ndarray:
     """Sorted detector ids whose bit is set in a packed syndrome row."""
     bits = np.unpackbits(row, bitorder="little")[:num_detectors]
     return np.nonzero(bits)[0].astype(np.int32)
+
+
+def rotated_circuit_graph(d: int, p: float, model: str = "uniform", rounds: int | None = None, **kw) -> DetectorGraph:
+    """Circuit-level detector graph of X-basis memory on the rotated code (uniform or physical noise
+    model); defined in synth.circuit_level."""
+    from .circuit_level import rotated_circuit_graph as _build
+    return _build(d, p, model, rounds, **kw)

@@ -395,3 +395,39 @@ def test_circuit_x_graphs_equal_oracle(d, p, n, step):
     res = gpu_decode(g, s.syndromes)
     bad = compare(g, s.syndromes, res, range(0, n, step))
     assert not bad, bad[:5]
+
+
+@pytest.mark.parametrize("model,d,p,n,step", [("uniform", 5, 0.003, 5000, 1), ("physical", 9, 0.003, 3000, 1),
+                                              ("uniform", 13, 0.003, 2000, 10), ("physical", 21, 0.002, 2000, 20)])
+def test_circuit_noise_model_graphs_equal_oracle(model, d, p, n, step):
+    """X-memory detector graphs under the two circuit-level noise models
+    (every fault of the syndrome-extraction circuit, degree up to 12, about
+    twenty distinct weights): shots equal the oracle."""
+    g = synth.rotated_circuit_graph(d, p, model)
+    s = synth.sample(g, n, seed=150 + d)
+    say(f"circuit {model} d={d} p={p}: decoding {n} shots")
+    res = gpu_decode(g, s.syndromes)
+    bad = compare(g, s.syndromes, res, range(0, n, step))
+    assert not bad, bad[:5]
+
+
+def test_circuit_uniform_d21_autotuned_graph_replay():
+    """The benchmark's circuit-level workload (uniform noise, d=21, p=0.001,
+    50,000 shots): the autotuned configuration, replayed through a captured
+    HIP graph, equals the oracle on sampled shots and is valid on all."""
+    import torch
+    import paper_2609_12262_amd as psb
+    g = synth.rotated_circuit_graph(21, 0.001, "uniform")
+    s = synth.sample(g, 50000, seed=160)
+    G = psb.Graph.from_synth(g)
+    synd = torch.from_numpy(s.syndromes).cuda()
+    say("circuit uniform d21: autotune")
+    best, table = psb.autotune(G, synd[:8192], reps=1, tiebreak_seed=SEED)
+    kw = {k: best[k] for k in ("fast_max_nodes", "fast_max_regions", "first_tier", "fast_lds_state")}
+    say(f"circuit uniform d21: decoding 50000 shots with {kw}")
+    res = gpu_decode(g, s.syndromes, **kw)
+    G.close()
+    assert (res["status"] == 0).all(), np.bincount(res["status"])
+    assert not valid_embedded(g, s.syndromes, res)
+    bad = compare_parallel(g, s.syndromes, res, range(0, 50000, 250))
+    assert not bad, bad[:5]
