@@ -997,8 +997,9 @@ PSB_DEV void cluster(Ctx& c) {
           if (q == nh) { if (nh < hitcap) { hits[2 * nh] = rj; hits[2 * nh + 1] = cl; ++nh; } else overflow = 1; }
         }
       };
-      if (H <= 2) {
-        // two rounds of independent adjacency-row loads instead of a serial walk
+      if (H <= 3) {
+        // up to three rounds of independent adjacency-row loads instead of a
+        // serial walk over a stack in scratch memory
         for (int j = 0; j < deg && H >= 1; ++j) {
           const int y = c.nbr[(int64_t)u * deg + j];
           if (y == NB_PAD) break;
@@ -1008,7 +1009,14 @@ PSB_DEV void cluster(Ctx& c) {
           for (int k2 = 0; k2 < deg; ++k2) {
             const int z = c.nbr[(int64_t)y * deg + k2];
             if (z == NB_PAD) break;
-            visit(z, c.eid[(int64_t)y * deg + k2], d1 + c.wt[(int64_t)y * deg + k2]);
+            const i128 d2 = d1 + c.wt[(int64_t)y * deg + k2];
+            visit(z, c.eid[(int64_t)y * deg + k2], d2);
+            if (H < 3 || z < 0 || d2 >= bk) continue;
+            for (int k3 = 0; k3 < deg; ++k3) {
+              const int x3 = c.nbr[(int64_t)z * deg + k3];
+              if (x3 == NB_PAD) break;
+              visit(x3, c.eid[(int64_t)z * deg + k3], d2 + c.wt[(int64_t)z * deg + k3]);
+            }
           }
         }
       } else {
