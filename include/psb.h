@@ -283,6 +283,10 @@ int32_t psb_window_plan_destroy(psb_window_plan* p);
  * original weight is its decoded weight / S.  The rewritten graph is decoded
  * in global mode (opts->mode is overridden to 1): the weight-1 chain leaves
  * the clustering no bounded path depth, and both modes return the MWEM.
+ * Tiers: unless opts sets fast_max_nodes, fast_max_regions or first_tier, a
+ * rewritten graph above 1,024 detectors is decoded by a wavefront first tier
+ * holding up to min(detectors, 8,192) explored detectors and 1,024 regions
+ * per shot (one wavefront per compute unit); smaller ones use the defaults.
  * Errors: PSB_E_INVALID, PSB_E_UNSUPPORTED (an observable edge that is not a
  * boundary edge, no observable edge, scaled weights beyond int32),
  * PSB_E_NOMEM, PSB_E_DEVICE. */

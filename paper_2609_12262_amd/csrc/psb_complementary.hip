@@ -140,18 +140,18 @@ extern "C" int32_t psb_comp_plan_create(const psb_graph_desc* desc, int32_t obs_
   if (opts) o = *opts;
   o.mode = 1;
   // once a region reaches an x_j the whole chain and the observable boundary
-  // of every round are explored.  Graphs the wavefront overflow tier holds
-  // whole (1,024 detectors) stay on the wavefront tiers; larger ones, unless
-  // the caller chose otherwise, decode in the lane tier, whose state lives in
-  // global memory, with room for every detector of the rewritten graph (up
-  // to 8,192, within the 16-bit state indices), 4,096 regions per shot and
-  // 4,096 shots in flight (slower: one shot per lane)
+  // of every round are explored, and at d = 21 most of the graph.  Graphs the
+  // wavefront overflow tier holds whole (1,024 detectors) keep the default
+  // tiers; larger ones, unless the caller chose otherwise, decode in a
+  // wavefront first tier sized to the whole rewritten graph (up to 8,192
+  // detectors) with 1,024 regions per shot: its per-shot LDS block is then
+  // about 128 KB, one wavefront per compute unit, with the event cache,
+  // region bases and radius offsets in the workspace
   const bool caller_chose = opts && (opts->fast_max_nodes != 0 || opts->fast_max_regions != 0 || opts->first_tier != 0);
   if (!caller_chose && n + nx > 1024) {
-    o.first_tier = 1;
+    o.first_tier = 0;
     o.fast_max_nodes = (int32_t)std::min<int64_t>(n + nx, 8192);
-    o.fast_max_regions = 4096;
-    if (o.num_slots == 0) o.num_slots = 4096;
+    o.fast_max_regions = 1024;
   }
   int32_t rc = psb_graph_create(&cd, &P->g);
   if (rc == PSB_OK) rc = psb_decoder_create(P->g, &o, &P->d);

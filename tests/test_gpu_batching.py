@@ -245,19 +245,27 @@ def test_circuit_x_graph_autotune_windows_and_accounting():
         assert ok and (int(wt[i]), int(ob[i])) == (w, o), i
 
 
-@pytest.mark.parametrize("graph,d,p,n,step", [("phenom", 5, 0.01, 3000, 1), ("phenom", 11, 0.005, 2000, 4),
-                                              ("circuit_x", 7, 0.002, 1500, 3), ("phenom", 13, 0.005, 256, 2)])
-def test_complementary_gap_equals_oracle(graph, d, p, n, step):
+_LANE_TIER = dict(first_tier=1, fast_max_nodes=2048, fast_max_regions=4096, num_slots=4096)
+
+
+@pytest.mark.parametrize("graph,d,p,n,step,opts", [
+    ("phenom", 5, 0.01, 3000, 1, {}), ("phenom", 11, 0.005, 2000, 4, {}), ("circuit_x", 7, 0.002, 1500, 3, {}),
+    ("phenom", 13, 0.005, 1000, 4, {}), ("phenom", 13, 0.005, 256, 4, _LANE_TIER),
+    ("circuit_uniform", 9, 0.003, 1000, 5, {}), ("phenom", 21, 0.005, 512, 8, {})])
+def test_complementary_gap_equals_oracle(graph, d, p, n, step, opts):
     """Complementary-gap decoding: both constrained minimum weights (hence the
     gap) equal the oracle's, the reported observable is the MWEM's, and the
-    lighter side equals the MWEM weight.  d=13 (rewritten graph above 1,024
-    detectors) takes the lane-tier path."""
+    lighter side equals the MWEM weight.  d=13 and d=21 (rewritten graphs
+    above 1,024 detectors) take the large wavefront first tier by default;
+    one case asks for the lane tier instead."""
     import torch
     import oracle
     import paper_2609_12262_amd as psb
-    g = synth.rotated_phenom_graph(d, p) if graph == "phenom" else synth.rotated_circuit_x_graph(d, p)
+    g = {"phenom": lambda: synth.rotated_phenom_graph(d, p), "circuit_x": lambda: synth.rotated_circuit_x_graph(d, p),
+         "circuit_uniform": lambda: synth.rotated_circuit_graph(d, p, "uniform")}[graph]()
     s = synth.sample(g, n, seed=140 + d)
-    plan = psb.ComplementaryPlan(g, 0, tiebreak_seed=SEED)
+    say(f"complementary {graph} d={d} opts={opts}: {n} shots")
+    plan = psb.ComplementaryPlan(g, 0, tiebreak_seed=SEED, **opts)
     out = plan.decode(torch.from_numpy(s.syndromes).cuda())
     torch.cuda.synchronize()
     h = {k: v.cpu().numpy() for k, v in out.items()}
