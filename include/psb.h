@@ -280,13 +280,17 @@ int32_t psb_window_plan_destroy(psb_window_plan* p);
  * number of observable edges.  Decoding with x_1 active forces the
  * observable bit to 1, with none active to 0 (chain edges add even degree to
  * the x_j); the chain weighs less than S, so each constrained optimum's
- * original weight is its decoded weight / S.  The rewritten graph is decoded
+ * original weight is its decoded weight / S.  Each shot is decoded once on the
+ * original graph (the MWEM: one of the two minima, with its observable) and
+ * once on the rewritten graph with the other value of the bit forced (x_1
+ * active exactly when the MWEM's bit is 0).  The rewritten graph is decoded
  * in global mode (opts->mode is overridden to 1): the weight-1 chain leaves
  * the clustering no bounded path depth, and both modes return the MWEM.
- * Tiers: unless opts sets fast_max_nodes, fast_max_regions or first_tier, a
- * rewritten graph above 1,024 detectors is decoded by a wavefront first tier
- * holding up to min(detectors, 8,192) explored detectors and 1,024 regions
- * per shot (one wavefront per compute unit); smaller ones use the defaults.
+ * Tiers: unless opts sets fast_max_nodes, fast_max_regions or first_tier,
+ * the first tier is a wavefront tier holding the whole rewritten graph (up
+ * to 8,192 detectors) with 208 regions per shot, or 512 above 1,024
+ * detectors; a shot beyond it ends with PSB_S_CAPACITY unless the overflow
+ * tier (1,024 detectors) holds it.
  * Errors: PSB_E_INVALID, PSB_E_UNSUPPORTED (an observable edge that is not a
  * boundary edge, no observable edge, scaled weights beyond int32),
  * PSB_E_NOMEM, PSB_E_DEVICE. */
@@ -297,7 +301,7 @@ int32_t psb_comp_plan_create(const psb_graph_desc* desc, int32_t obs_bit, const 
  * outputs (DEVICE, caller-owned, [n] each): weight0 / weight1 = minimum
  * weight with the observable bit 0 / 1; gap = |weight1 - weight0|; obs = the
  * observable mask of the lighter side (ties to bit 0), i.e. the MWEM's;
- * status (PSB_S_* of the two decodes).  Asynchronous on `stream`; batch
+ * status (PSB_S_* of the two decodes, the MWEM's first).  Asynchronous on `stream`; batch
  * buffers are held by the plan (grown after synchronising the stream). */
 int32_t psb_comp_decode(psb_comp_plan* p, const uint8_t* syndromes, int64_t n, int64_t* weight0, int64_t* weight1,
                         int64_t* gap, uint64_t* obs, int32_t* status, void* stream);

@@ -16,6 +16,8 @@
 // only x_1 forces observable bit b to 1, activating none forces it to 0.
 // The chain edges used weigh at most m - 1 < S, so the original weight of each
 // constrained optimum is its decoded weight divided by S (integer division).
+// One side is the MWEM itself: each shot is decoded once on the original graph
+// and once on the rewritten graph, with the other value of the bit forced.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -31,58 +33,67 @@ using psb_host::fail;
 
 namespace {
 
-// Rows [0, n): the original syndrome with no x_j active; rows [n, 2n): the
-// same with x_1 (detector n_orig) active.  One thread per output byte.
-__global__ void comp_expand(const uint8_t* syn, int64_t n, int32_t in_bytes, int32_t n_orig, uint8_t* out,
-                            int32_t out_bytes) {
+// Row i: the original syndrome, with x_1 (detector n_orig) active exactly
+// when the MWEM of shot i has observable bit 0, so that the rewritten graph's
+// decode returns the minimum with the other value of the bit.  One thread per
+// output byte.
+__global__ void comp_expand(const uint8_t* syn, int64_t n, int32_t in_bytes, int32_t n_orig, const uint64_t* mwem_obs,
+                            uint64_t obs_bit_mask, uint8_t* out, int32_t out_bytes) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * n * out_bytes) return;
-  const int64_t row = t / out_bytes;
+  if (t >= n * out_bytes) return;
+  const int64_t i = t / out_bytes;
   const int32_t k = (int32_t)(t % out_bytes);
-  const int64_t i = row < n ? row : row - n;
   uint32_t v = 0;
   if (k < in_bytes) {
     v = syn[i * in_bytes + k];
     if (k == in_bytes - 1 && (n_orig & 7)) v &= (1u << (n_orig & 7)) - 1u;   // bits past the original detectors
   }
-  if (row >= n && k == (n_orig >> 3)) v |= 1u << (n_orig & 7);
-  out[row * out_bytes + k] = (uint8_t)v;
+  if (k == (n_orig >> 3) && (mwem_obs[i] & obs_bit_mask) == 0) v |= 1u << (n_orig & 7);
+  out[i * out_bytes + k] = (uint8_t)v;
 }
 
-__global__ void comp_gap(int64_t n, const int64_t* wt, const uint64_t* ob, const int32_t* st, int64_t scale,
-                         uint64_t obs_bit_mask, int64_t* w0, int64_t* w1, int64_t* gap, uint64_t* obs_best,
-                         int32_t* status) {
+// a = the MWEM (original graph), b = the constrained minimum with the other
+// value of the bit (rewritten graph, scaled weights).
+__global__ void comp_gap(int64_t n, const int64_t* wa, const uint64_t* oa, const int32_t* sa, const int64_t* wb,
+                         const uint64_t* ob, const int32_t* sb, int64_t scale, uint64_t obs_bit_mask, int64_t* w0,
+                         int64_t* w1, int64_t* gap, uint64_t* obs_best, int32_t* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int32_t s = st[i] != PSB_S_OK ? st[i] : st[n + i];
+  int32_t s = sa[i] != PSB_S_OK ? sa[i] : sb[i];
   if (s == PSB_S_EDGES_TRUNCATED) s = PSB_S_OK;        // weights and observables stay valid
   status[i] = s;
-  const int64_t a = wt[i] / scale, b = wt[n + i] / scale;
-  w0[i] = a; w1[i] = b;
-  gap[i] = a > b ? a - b : b - a;
-  // the unconstrained optimum: the lighter side (ties to observable 0), with
-  // the other observable bits of that side
-  obs_best[i] = (b < a) ? ((ob[n + i] & ~obs_bit_mask) | obs_bit_mask) : (ob[i] & ~obs_bit_mask);
+  const int64_t a = wa[i], b = wb[i] / scale;
+  const bool mwem_one = (oa[i] & obs_bit_mask) != 0;
+  w0[i] = mwem_one ? b : a;
+  w1[i] = mwem_one ? a : b;
+  gap[i] = b - a;                                      // a is the minimum over both values
+  // the lighter side's observables; on a tie, the side with the bit at 0
+  obs_best[i] = (mwem_one && b == a) ? (ob[i] & ~obs_bit_mask) : oa[i];
 }
 
 }  // namespace
 
 struct psb_comp_plan {
-  psb_graph* g = nullptr;
-  psb_decoder* d = nullptr;
-  int32_t n_orig = 0, in_bytes = 0, out_bytes = 0, stride = 0, obs_bit = 0;
+  psb_graph *g = nullptr, *g0 = nullptr;        // rewritten graph, original graph
+  psb_decoder *d = nullptr, *d0 = nullptr;
+  int32_t n_orig = 0, in_bytes = 0, out_bytes = 0, stride = 0, stride0 = 0, obs_bit = 0;
   int64_t scale = 1;
   int64_t cap = 0;
   uint8_t* d_syn = nullptr;
-  int32_t *d_edges = nullptr, *d_ne = nullptr, *d_st = nullptr;
+  int32_t *d_edges = nullptr, *d_ne = nullptr, *d_st = nullptr;      // rewritten-graph decode
   int64_t* d_wt = nullptr;
   uint64_t* d_ob = nullptr;
+  int32_t *d_edges0 = nullptr, *d_ne0 = nullptr, *d_st0 = nullptr;   // MWEM decode
+  int64_t* d_wt0 = nullptr;
+  uint64_t* d_ob0 = nullptr;
 };
 
 static void comp_free_buffers(psb_comp_plan* P) {
-  for (void* p : {(void*)P->d_syn, (void*)P->d_edges, (void*)P->d_ne, (void*)P->d_st, (void*)P->d_wt, (void*)P->d_ob})
+  for (void* p : {(void*)P->d_syn, (void*)P->d_edges, (void*)P->d_ne, (void*)P->d_st, (void*)P->d_wt, (void*)P->d_ob,
+                  (void*)P->d_edges0, (void*)P->d_ne0, (void*)P->d_st0, (void*)P->d_wt0, (void*)P->d_ob0})
     if (p) (void)hipFree(p);
   P->d_syn = nullptr; P->d_edges = P->d_ne = P->d_st = nullptr; P->d_wt = nullptr; P->d_ob = nullptr;
+  P->d_edges0 = P->d_ne0 = P->d_st0 = nullptr; P->d_wt0 = nullptr; P->d_ob0 = nullptr;
   P->cap = 0;
 }
 
@@ -92,6 +103,8 @@ extern "C" int32_t psb_comp_plan_destroy(psb_comp_plan* P) {
   comp_free_buffers(P);
   if (P->d) psb_decoder_destroy(P->d);
   if (P->g) psb_graph_destroy(P->g);
+  if (P->d0) psb_decoder_destroy(P->d0);
+  if (P->g0) psb_graph_destroy(P->g0);
   delete P;
   return PSB_OK;
 }
@@ -140,24 +153,32 @@ extern "C" int32_t psb_comp_plan_create(const psb_graph_desc* desc, int32_t obs_
   if (opts) o = *opts;
   o.mode = 1;
   // once a region reaches an x_j the whole chain and the observable boundary
-  // of every round are explored, and at d = 21 most of the graph.  Graphs the
-  // wavefront overflow tier holds whole (1,024 detectors) keep the default
-  // tiers; larger ones, unless the caller chose otherwise, decode in a
-  // wavefront first tier sized to the whole rewritten graph (up to 8,192
-  // detectors) with 1,024 regions per shot: its per-shot LDS block is then
-  // about 128 KB, one wavefront per compute unit, with the event cache,
-  // region bases and radius offsets in the workspace
+  // of every round are explored, and at d = 21 most of the graph.  Unless the
+  // caller chose otherwise, the first tier is a wavefront tier sized to the
+  // whole rewritten graph (up to 8,192 detectors), with the event cache,
+  // region bases and radius offsets in the workspace (12 bytes of LDS per
+  // detector, 30 per region).  Graphs the overflow tier holds whole (1,024
+  // detectors) keep 208 regions per shot, which leaves room for several
+  // wavefronts per compute unit; larger ones get 512 (at most 512 detection
+  // events; about 79 KB of LDS at d = 21, two wavefronts per compute unit)
   const bool caller_chose = opts && (opts->fast_max_nodes != 0 || opts->fast_max_regions != 0 || opts->first_tier != 0);
-  if (!caller_chose && n + nx > 1024) {
+  if (!caller_chose) {
     o.first_tier = 0;
     o.fast_max_nodes = (int32_t)std::min<int64_t>(n + nx, 8192);
-    o.fast_max_regions = 1024;
+    o.fast_max_regions = n + nx > 1024 ? 512 : 208;
   }
   int32_t rc = psb_graph_create(&cd, &P->g);
   if (rc == PSB_OK) rc = psb_decoder_create(P->g, &o, &P->d);
+  // the MWEM itself comes from the original graph, with the library's
+  // default decoder (partition-and-fuse; the tie-break seed of opts)
+  psb_decoder_opts o0{};
+  if (opts) { o0.tiebreak_seed = opts->tiebreak_seed; o0.boundary_reading = opts->boundary_reading; }
+  if (rc == PSB_OK) rc = psb_graph_create(desc, &P->g0);
+  if (rc == PSB_OK) rc = psb_decoder_create(P->g0, &o0, &P->d0);
   if (rc != PSB_OK) return rc;
   P->n_orig = n; P->in_bytes = (n + 7) / 8; P->out_bytes = psb_graph_syndrome_bytes(P->g);
-  P->stride = psb_decoder_edges_per_shot(P->d); P->obs_bit = obs_bit; P->scale = S;
+  P->stride = psb_decoder_edges_per_shot(P->d); P->stride0 = psb_decoder_edges_per_shot(P->d0);
+  P->obs_bit = obs_bit; P->scale = S;
   *out = P.release();
   return PSB_OK;
 }
@@ -172,25 +193,36 @@ extern "C" int32_t psb_comp_decode(psb_comp_plan* P, const uint8_t* syndromes, i
   if (n > P->cap) {
     if (hipStreamSynchronize(s) != hipSuccess) return fail(PSB_E_DEVICE, "hipStreamSynchronize");
     comp_free_buffers(P);
-    const int64_t r = 2 * n;
-    bool ok = hipMalloc((void**)&P->d_syn, (size_t)r * P->out_bytes) == hipSuccess &&
-              hipMalloc((void**)&P->d_edges, (size_t)r * P->stride * 4) == hipSuccess &&
-              hipMalloc((void**)&P->d_ne, (size_t)r * 4) == hipSuccess &&
-              hipMalloc((void**)&P->d_st, (size_t)r * 4) == hipSuccess &&
-              hipMalloc((void**)&P->d_wt, (size_t)r * 8) == hipSuccess &&
-              hipMalloc((void**)&P->d_ob, (size_t)r * 8) == hipSuccess;
+    bool ok = hipMalloc((void**)&P->d_syn, (size_t)n * P->out_bytes) == hipSuccess &&
+              hipMalloc((void**)&P->d_edges, (size_t)n * P->stride * 4) == hipSuccess &&
+              hipMalloc((void**)&P->d_ne, (size_t)n * 4) == hipSuccess &&
+              hipMalloc((void**)&P->d_st, (size_t)n * 4) == hipSuccess &&
+              hipMalloc((void**)&P->d_wt, (size_t)n * 8) == hipSuccess &&
+              hipMalloc((void**)&P->d_ob, (size_t)n * 8) == hipSuccess &&
+              hipMalloc((void**)&P->d_edges0, (size_t)n * P->stride0 * 4) == hipSuccess &&
+              hipMalloc((void**)&P->d_ne0, (size_t)n * 4) == hipSuccess &&
+              hipMalloc((void**)&P->d_st0, (size_t)n * 4) == hipSuccess &&
+              hipMalloc((void**)&P->d_wt0, (size_t)n * 8) == hipSuccess &&
+              hipMalloc((void**)&P->d_ob0, (size_t)n * 8) == hipSuccess;
     if (!ok) { comp_free_buffers(P); return fail(PSB_E_NOMEM, "complementary batch buffers"); }
     P->cap = n;
   }
-  const unsigned tb = 256;
-  const int64_t nb = 2 * n * P->out_bytes;
-  comp_expand<<<(unsigned)((nb + tb - 1) / tb), tb, 0, s>>>(syndromes, n, P->in_bytes, P->n_orig, P->d_syn,
-                                                            P->out_bytes);
-  int32_t rc = psb_decode_batch(P->d, P->d_syn, 2 * n, P->d_edges, P->d_ne, P->d_wt, P->d_ob, P->d_st, nullptr,
+  // 1. the MWEM of every shot on the original graph
+  int32_t rc = psb_decode_batch(P->d0, syndromes, n, P->d_edges0, P->d_ne0, P->d_wt0, P->d_ob0, P->d_st0, nullptr,
                                 nullptr, nullptr, stream);
   if (rc != PSB_OK) return rc;
-  comp_gap<<<(unsigned)((n + tb - 1) / tb), tb, 0, s>>>(n, P->d_wt, P->d_ob, P->d_st, P->scale, 1ull << P->obs_bit,
-                                                        weight0, weight1, gap, obs, status);
+  // 2. the rewritten graph with the other value of the observable bit
+  const unsigned tb = 256;
+  const uint64_t mask = 1ull << P->obs_bit;
+  const int64_t nb = n * P->out_bytes;
+  comp_expand<<<(unsigned)((nb + tb - 1) / tb), tb, 0, s>>>(syndromes, n, P->in_bytes, P->n_orig, P->d_ob0, mask,
+                                                            P->d_syn, P->out_bytes);
+  if (hipGetLastError() != hipSuccess) return fail(PSB_E_DEVICE, "complementary kernel launch");
+  rc = psb_decode_batch(P->d, P->d_syn, n, P->d_edges, P->d_ne, P->d_wt, P->d_ob, P->d_st, nullptr, nullptr, nullptr,
+                        stream);
+  if (rc != PSB_OK) return rc;
+  comp_gap<<<(unsigned)((n + tb - 1) / tb), tb, 0, s>>>(n, P->d_wt0, P->d_ob0, P->d_st0, P->d_wt, P->d_ob, P->d_st,
+                                                        P->scale, mask, weight0, weight1, gap, obs, status);
   if (hipGetLastError() != hipSuccess) return fail(PSB_E_DEVICE, "complementary kernel launch");
   return PSB_OK;
 }

@@ -249,15 +249,16 @@ _LANE_TIER = dict(first_tier=1, fast_max_nodes=2048, fast_max_regions=4096, num_
 
 
 @pytest.mark.parametrize("graph,d,p,n,step,opts", [
-    ("phenom", 5, 0.01, 3000, 1, {}), ("phenom", 11, 0.005, 2000, 4, {}), ("circuit_x", 7, 0.002, 1500, 3, {}),
+    ("phenom", 5, 0.01, 3000, 1, {}), ("phenom", 11, 0.005, 2000, 4, {}),
+    ("phenom", 11, 0.005, 2000, 4, dict(fast_max_nodes=320, fast_max_regions=208)), ("circuit_x", 7, 0.002, 1500, 3, {}),
     ("phenom", 13, 0.005, 1000, 4, {}), ("phenom", 13, 0.005, 256, 4, _LANE_TIER),
     ("circuit_uniform", 9, 0.003, 1000, 5, {}), ("phenom", 21, 0.005, 512, 8, {})])
 def test_complementary_gap_equals_oracle(graph, d, p, n, step, opts):
     """Complementary-gap decoding: both constrained minimum weights (hence the
     gap) equal the oracle's, the reported observable is the MWEM's, and the
-    lighter side equals the MWEM weight.  d=13 and d=21 (rewritten graphs
-    above 1,024 detectors) take the large wavefront first tier by default;
-    one case asks for the lane tier instead."""
+    lighter side equals the MWEM weight.  By default the first tier holds the
+    whole rewritten graph; one case asks for the library's usual first tier
+    (with shots handed to the overflow tier), one for the lane tier."""
     import torch
     import oracle
     import paper_2609_12262_amd as psb
