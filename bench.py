@@ -148,7 +148,8 @@ def latency_scaling(args):
     p = args.p if args.p != 0.005 else 0.001
     rows = []
     for d in [int(x) for x in args.latency.split(",")]:
-        g = synth.rotated_phenom_graph(d, p)
+        log(f"latency: building the {args.graph} graph, d={d}, p={p}")
+        g = make_graph(args.graph, d, p)
         shots = synth.sample(g, args.latency_shots, seed=10 + d)
         G = psb.Graph.from_synth(g)
         synd = torch.from_numpy(shots.syndromes).cuda()
@@ -200,7 +201,8 @@ def latency_scaling(args):
                      "clusters_mean": round(float(ast[:, 10].mean()), 2)})
         log(f"d={d}: {rows[-1]}")
         dec.close(); G.close()
-    print(json.dumps({"metric": "one-shot-per-launch latency, us per round", "p": p, "mode": args.mode,
+    print(json.dumps({"metric": "one-shot-per-launch latency, us per round", "graph": GRAPHS[args.graph], "p": p,
+                      "mode": args.mode,
                       "basis": "launch = HIP events around the launch on its stream; device = kernel start stamp "
                                "to shot completion (device clock)", "per_d": rows}), flush=True)
 

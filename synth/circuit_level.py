@@ -104,11 +104,17 @@ class _Frames:
         self.z = np.zeros((nq, nrows), np.bool_)
         self.obs_row = nrows - 1
         self.mech: dict = {}
+        self.lo, self.hi = 0, nrows - 1   # detector rows that can be non-zero now (the observable row always)
+
+    def _rows(self, col):
+        r = (np.flatnonzero(col[self.lo:self.hi]) + self.lo).tolist()
+        if col[self.obs_row]:
+            r.append(self.obs_row)
+        return frozenset(r)
 
     # effects of single-qubit Pauli components at the current time
     def _hits(self, q: int):
-        return (frozenset(np.flatnonzero(self.z[q]).tolist()),   # rows an X on q flips
-                frozenset(np.flatnonzero(self.x[q]).tolist()))   # rows a Z on q flips
+        return self._rows(self.z[q]), self._rows(self.x[q])   # rows an X on q flips, rows a Z on q flips
 
     def _add(self, rows: frozenset, prob: float):
         if not rows or prob <= 0.0:
@@ -187,13 +193,16 @@ def _decompose(dets, obs, graphlike):
 
 
 def rotated_circuit_graph(d: int, p: float, model: str = "uniform", rounds: int | None = None,
-                          spec: dict | None = None, cnot_orders=(_ORDER_X, _ORDER_Z)):
+                          spec: dict | None = None, cnot_orders=(_ORDER_X, _ORDER_Z), windowed: bool = True):
     """Detector graph of the X-basis memory experiment under a circuit-level noise model.
 
     `spec` overrides the per-location probabilities ({"prep", "meas", "gate1", "idle", "cnot"}, each the
     probability of one Pauli term), for special cases.  `cnot_orders` gives the corner order of the X and
     of the Z plaquettes' CNOTs (default: the schedule in the module docstring); an order that uses a qubit
     twice in one layer raises ValueError, one whose measurements do not commute raises RuntimeError.
+    `windowed` scans, while round t is propagated, only the rows of detector layers t-1..t+2 (and the
+    observable): a layer-L detector's frame lives in rounds L-1 and L only, since every reset of the round
+    before absorbs it.  windowed=False scans every row (for checking that claim).
     Returns a DetectorGraph (synth.DetectorGraph) with two more attributes: `n_split` (faults split into
     parts) and `n_parallel` (parallel edges dropped)."""
     from . import DetectorGraph, weight_from_p
@@ -249,6 +258,8 @@ def rotated_circuit_graph(d: int, p: float, model: str = "uniform", rounds: int 
                     F.dep1(q, ns["idle"])
 
     # final X measurement of the data: include it, then the flip before it
+    if windowed:
+        F.lo = max(0, (R - 1) * nx)
     for q in data:
         rows = [R * nx + i for i in x_faces_of[q]]
         if q % d == 0:
@@ -259,6 +270,8 @@ def rotated_circuit_graph(d: int, p: float, model: str = "uniform", rounds: int 
 
     anc = xa + za
     for t in range(R, 0, -1):
+        if windowed:
+            F.lo, F.hi = max(0, (t - 2) * nx), min(nrows - 1, (t + 2) * nx)
         # moment 7: measure ancillas in Z (data idle)
         idle(anc)
         for i, a in enumerate(xa):

@@ -185,3 +185,15 @@ def test_decompose_into_graphlike_parts():
     assert cl._decompose((1, 2, 3, 4), 0, known) == [((1, 2), 0), ((3,), 0), ((4,), 0)]
     assert cl._decompose((1, 2, 5), 0, known) is None
     assert cl._decompose((2, 3, 4), 1, {(2,): (1,), (3, 4): (0,)}) == [((2,), 1), ((3, 4), 0)]
+
+
+@pytest.mark.parametrize("model", cl.NOISE_MODELS)
+@pytest.mark.parametrize("d,R", [(3, 4), (5, 5), (7, 3)])
+def test_circuit_graph_windowed_scan_equals_full_scan(model, d, R):
+    """Scanning only the detector layers near the current round gives the
+    same graph as scanning every detector row (a detector's back-propagated
+    frame lives in its own two rounds)."""
+    a = synth.rotated_circuit_graph(d, 0.002, model, rounds=R)
+    b = synth.rotated_circuit_graph(d, 0.002, model, rounds=R, windowed=False)
+    for k in ("u", "v", "w", "obs_mask", "p"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k
