@@ -245,6 +245,31 @@ def test_circuit_x_graph_autotune_windows_and_accounting():
         assert ok and (int(wt[i]), int(ob[i])) == (w, o), i
 
 
+@pytest.mark.parametrize("model", ["uniform", "physical"])
+def test_sliding_windows_on_circuit_noise_graphs(model):
+    """Sliding windows over 21 rounds of the X-memory circuit-level graphs
+    (diagonal edges between adjacent layers, degree up to 12): every stream
+    resolves and equals the oracle's windowed decode."""
+    import torch
+    import oracle
+    import paper_2609_12262_amd as psb
+    g = synth.rotated_circuit_graph(7, 0.002, model, rounds=21)
+    L = (7 * 7 - 1) // 2
+    s = synth.sample(g, 300, seed=170)
+    say(f"windows on circuit {model}: 300 streams")
+    plan = psb.WindowPlan(g, L, 8, 4, tiebreak_seed=SEED)
+    out = plan.decode(torch.from_numpy(s.syndromes).cuda())
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy(); wt = out["weight"].cpu().numpy(); ob = out["obs"].cpu().numpy().view(np.uint64)
+    plan.close()
+    assert (st == 0).all(), np.bincount(st)
+    sch = oracle.window_schedule(g, L, 8, 4)
+    gs = [oracle.Graph(wg, SEED) for _, wg, _, _ in sch]
+    for i in range(0, 300, 3):
+        w, o, ok = oracle.window_decode(g, sch, gs, L, synth.defects_of(s.syndromes[i], g.num_detectors))
+        assert ok and (int(wt[i]), int(ob[i])) == (w, o), i
+
+
 _LANE_TIER = dict(first_tier=1, fast_max_nodes=2048, fast_max_regions=4096, num_slots=4096)
 
 
