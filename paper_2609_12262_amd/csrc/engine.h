@@ -976,7 +976,8 @@ PSB_DEV void cluster(Ctx& c) {
       int nh = 0, nbd = 0, loose = 0, overflow = 0;
       int nvis = 0;
       // record one path of length nd_ from u ending at y (boundary: y < 0, edge e)
-      auto visit = [&](int y, int e, i128 nd_) {
+      // (rj_pre: the detector map's entry for y when already loaded, else -2)
+      auto visit = [&](int y, int e, i128 nd_, int rj_pre = -2) {
         ++nvis;
         if (nd_ > bk) return;
         if (y == NB_BOUNDARY) {
@@ -989,7 +990,7 @@ PSB_DEV void cluster(Ctx& c) {
           return;
         }
         if (y == u) return;
-        const int rj = node_idx(c, y);
+        const int rj = rj_pre != -2 ? rj_pre : node_idx(c, y);
         if (rj >= 0 && rj < nd && c.level[rj] == 0) {
           const int cl = (nd_ <= dk) ? 1 : 0;
           int q = 0;
@@ -997,25 +998,45 @@ PSB_DEV void cluster(Ctx& c) {
           if (q == nh) { if (nh < hitcap) { hits[2 * nh] = rj; hits[2 * nh + 1] = cl; ++nh; } else overflow = 1; }
         }
       };
+      // the last hop of a path: the adjacency row of x (reached at distance
+      // base) in chunks of four, each chunk's neighbours and their
+      // detector-map entries loaded before any of them is visited (visit
+      // order unchanged)
+      auto leaf_row = [&](int x, i128 base) {
+        const int64_t r0 = (int64_t)x * deg;
+        for (int k0 = 0; k0 < deg; k0 += 4) {
+          int zs[4], ix[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) zs[t] = k0 + t < deg ? c.nbr[r0 + k0 + t] : NB_PAD;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) ix[t] = (c.dmap && zs[t] >= 0) ? (int)c.dmap[zs[t]] : -2;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            if (zs[t] == NB_PAD) return;
+            visit(zs[t], c.eid[r0 + k0 + t], base + c.wt[r0 + k0 + t], ix[t]);
+          }
+        }
+      };
       if (H <= 3) {
         // up to three rounds of independent adjacency-row loads instead of a
         // serial walk over a stack in scratch memory
-        for (int j = 0; j < deg && H >= 1; ++j) {
-          const int y = c.nbr[(int64_t)u * deg + j];
-          if (y == NB_PAD) break;
-          const i128 d1 = c.wt[(int64_t)u * deg + j];
-          visit(y, c.eid[(int64_t)u * deg + j], d1);
-          if (H < 2 || y < 0 || d1 >= bk) continue;
-          for (int k2 = 0; k2 < deg; ++k2) {
-            const int z = c.nbr[(int64_t)y * deg + k2];
-            if (z == NB_PAD) break;
-            const i128 d2 = d1 + c.wt[(int64_t)y * deg + k2];
-            visit(z, c.eid[(int64_t)y * deg + k2], d2);
-            if (H < 3 || z < 0 || d2 >= bk) continue;
-            for (int k3 = 0; k3 < deg; ++k3) {
-              const int x3 = c.nbr[(int64_t)z * deg + k3];
-              if (x3 == NB_PAD) break;
-              visit(x3, c.eid[(int64_t)z * deg + k3], d2 + c.wt[(int64_t)z * deg + k3]);
+        if (H == 1) {
+          leaf_row(u, 0);
+        } else if (H >= 2) {
+          for (int j = 0; j < deg; ++j) {
+            const int y = c.nbr[(int64_t)u * deg + j];
+            if (y == NB_PAD) break;
+            const i128 d1 = c.wt[(int64_t)u * deg + j];
+            visit(y, c.eid[(int64_t)u * deg + j], d1);
+            if (y < 0 || d1 >= bk) continue;
+            if (H == 2) { leaf_row(y, d1); continue; }
+            for (int k2 = 0; k2 < deg; ++k2) {
+              const int z = c.nbr[(int64_t)y * deg + k2];
+              if (z == NB_PAD) break;
+              const i128 d2 = d1 + c.wt[(int64_t)y * deg + k2];
+              visit(z, c.eid[(int64_t)y * deg + k2], d2);
+              if (z < 0 || d2 >= bk) continue;
+              leaf_row(z, d2);
             }
           }
         }
