@@ -16,7 +16,8 @@ fault).  Two noise models, both parameterised by p:
     Pauli and idling is noiseless.
 
 Circuit, per round, eight moments (every qubit is acted on or idles in each):
-  0  reset every ancilla in Z (round 1: data reset in X in the same moment)
+  0  reset every ancilla in Z (in the first syndrome round the data are also
+     reset in X in this moment)
   1  H on the X ancillas
   2-5  four CNOT layers: X ancilla -> data in the order NW, NE, SW, SE;
        data -> Z ancilla in the order NW, SW, NE, SE
@@ -298,7 +299,7 @@ def rotated_circuit_graph(d: int, p: float, model: str = "uniform", rounds: int 
             F.dep1(a, ns["gate1"])
         idle(xa)
         F.h(xa)
-        # moment 0: reset ancillas (and, in round 1, the data in X)
+        # moment 0: reset ancillas (and, in the first syndrome round, the data in X)
         for a in anc:
             F.flip_x(a, ns["prep"])
         if t == 1:
