@@ -170,11 +170,19 @@ extern "C" int32_t psb_comp_plan_create(const psb_graph_desc* desc, int32_t obs_
   int32_t rc = psb_graph_create(&cd, &P->g);
   if (rc == PSB_OK) rc = psb_decoder_create(P->g, &o, &P->d);
   // the MWEM itself comes from the original graph, with the library's
-  // default decoder (partition-and-fuse; the tie-break seed of opts)
+  // default decoder (partition-and-fuse; the tie-break seed of opts).  A
+  // graph whose weight spread needs deeper clustering paths than the kernel
+  // enumerates falls back to global sparse blossom: the same MWEM (Theorem 1)
   psb_decoder_opts o0{};
   if (opts) { o0.tiebreak_seed = opts->tiebreak_seed; o0.boundary_reading = opts->boundary_reading; }
   if (rc == PSB_OK) rc = psb_graph_create(desc, &P->g0);
-  if (rc == PSB_OK) rc = psb_decoder_create(P->g0, &o0, &P->d0);
+  if (rc == PSB_OK) {
+    rc = psb_decoder_create(P->g0, &o0, &P->d0);
+    if (rc == PSB_E_UNSUPPORTED) {
+      o0.mode = 1;
+      rc = psb_decoder_create(P->g0, &o0, &P->d0);
+    }
+  }
   if (rc != PSB_OK) return rc;
   P->n_orig = n; P->in_bytes = (n + 7) / 8; P->out_bytes = psb_graph_syndrome_bytes(P->g);
   P->stride = psb_decoder_edges_per_shot(P->d); P->stride0 = psb_decoder_edges_per_shot(P->d0);

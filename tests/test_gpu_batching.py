@@ -270,6 +270,33 @@ def test_sliding_windows_on_circuit_noise_graphs(model):
         assert ok and (int(wt[i]), int(ob[i])) == (w, o), i
 
 
+def test_complementary_gap_wide_weight_range():
+    """A graph whose lightest edge is under a third of the heaviest (timelike
+    flips at q=0.2) needs level-1 search paths deeper than the clustering
+    kernel enumerates, so a partition-and-fuse decoder is refused; the
+    complementary plan then takes its MWEM side from global sparse blossom
+    and still equals the oracle."""
+    import torch
+    import oracle
+    import paper_2609_12262_amd as psb
+    g = synth.rotated_phenom_graph(5, 0.005, q=0.2)
+    G = psb.Graph.from_synth(g)
+    with pytest.raises(psb.PsbError, match="needs paths of more than"):
+        psb.Decoder(G, tiebreak_seed=SEED)
+    G.close()
+    s = synth.sample(g, 1000, seed=180)
+    plan = psb.ComplementaryPlan(g, 0, tiebreak_seed=SEED)
+    out = plan.decode(torch.from_numpy(s.syndromes).cuda())
+    torch.cuda.synchronize()
+    h = {k: v.cpu().numpy() for k, v in out.items()}
+    plan.close()
+    assert (h["status"] == 0).all(), np.bincount(h["status"])
+    co = oracle.Complementary(g, 0, SEED)
+    for i in range(0, 1000, 2):
+        w0, w1 = co.weights(synth.defects_of(s.syndromes[i], g.num_detectors))
+        assert (int(h["weight0"][i]), int(h["weight1"][i])) == (w0, w1), i
+
+
 _LANE_TIER = dict(first_tier=1, fast_max_nodes=2048, fast_max_regions=4096, num_slots=4096)
 
 
