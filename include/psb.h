@@ -281,8 +281,9 @@ int32_t psb_window_plan_destroy(psb_window_plan* p);
  * observable bit to 1, with none active to 0 (chain edges add even degree to
  * the x_j); the chain weighs less than S, so each constrained optimum's
  * original weight is its decoded weight / S.  Each shot is decoded once on the
- * original graph (the MWEM: one of the two minima, with its observable) and
- * once on the rewritten graph with the other value of the bit forced (x_1
+ * original graph (the MWEM: one of the two minima, with its observable; by
+ * partition-and-fuse, or by global sparse blossom when the clustering cannot
+ * search the graph's weight range) and once on the rewritten graph with the other value of the bit forced (x_1
  * active exactly when the MWEM's bit is 0).  The rewritten graph is decoded
  * in global mode (opts->mode is overridden to 1): the weight-1 chain leaves
  * the clustering no bounded path depth, and both modes return the MWEM.
