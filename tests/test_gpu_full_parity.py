@@ -1,0 +1,30 @@
+"""Opt-in GPU parity over every shot of the benchmark's launch shape.
+
+Set PSB_FULL_PARITY=1 to run: the oracle then decodes all 50,000 shots on the
+host cores (a few minutes at p=0.005), so the default GPU run skips it."""
+import os
+
+import pytest
+
+import synth
+from gpu_helpers import compare_parallel, gpu_decode, say
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(os.environ.get("PSB_FULL_PARITY") != "1",
+                                 reason="opt-in (PSB_FULL_PARITY=1): minutes of oracle time on the host")]
+
+
+@pytest.mark.parametrize("p,seed", [(0.005, 3), (0.001, 4)])
+def test_d21_every_shot_of_the_benchmark_launch(p, seed):
+    """d=21, 21 rounds, 50,000 shots in one launch with the library's default
+    decoder (the configuration the autotuner picks for the benchmark): the
+    edge set, weight and observable of every shot equal the oracle's."""
+    g = synth.rotated_phenom_graph(21, p)
+    s = synth.sample(g, 50000, seed=seed)
+    say(f"d21 p={p}: decoding 50000 shots")
+    res = gpu_decode(g, s.syndromes)
+    bad = []
+    for k0 in range(0, 50000, 5000):
+        bad.extend(compare_parallel(g, s.syndromes, res, range(k0, k0 + 5000), workers=16, chunk=125))
+        say(f"d21 p={p}: {k0 + 5000} shots compared, {len(bad)} differ")
+    assert not bad, bad[:5]
