@@ -28,3 +28,18 @@ def test_d21_every_shot_of_the_benchmark_launch(p, seed):
         bad.extend(compare_parallel(g, s.syndromes, res, range(k0, k0 + 5000), workers=16, chunk=125))
         say(f"d21 p={p}: {k0 + 5000} shots compared, {len(bad)} differ")
     assert not bad, bad[:5]
+
+
+def test_d21_circuit_uniform_every_shot():
+    """The paper's workload shape: X-memory graph under uniform circuit-level
+    noise, d=21, 21 rounds, p=0.001, 50,000 shots in one launch with the
+    default decoder: every shot equals the oracle."""
+    g = synth.rotated_circuit_graph(21, 0.001, "uniform")
+    s = synth.sample(g, 50000, seed=160)
+    say("d21 circuit uniform p=0.001: decoding 50000 shots")
+    res = gpu_decode(g, s.syndromes)
+    bad = []
+    for k0 in range(0, 50000, 5000):
+        bad.extend(compare_parallel(g, s.syndromes, res, range(k0, k0 + 5000), workers=16, chunk=125))
+        say(f"d21 circuit uniform: {k0 + 5000} shots compared, {len(bad)} differ")
+    assert not bad, bad[:5]
