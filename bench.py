@@ -145,7 +145,8 @@ def latency_scaling(args):
     import torch
     import synth
     import paper_2609_12262_amd as psb
-    p = args.p if args.p != 0.005 else 0.001
+    # the latency configuration's rate is 0.001 unless --latency-p (or a --p other than the headline's) is given
+    p = args.latency_p if args.latency_p is not None else (args.p if args.p != 0.005 else 0.001)
     rows = []
     for d in [int(x) for x in args.latency.split(",")]:
         log(f"latency: building the {args.graph} graph, d={d}, p={p}")
@@ -435,6 +436,8 @@ def main():
                     help="latency-scaling mode: comma-separated distances (e.g. 11,21,31,41,51); every shot is "
                          "decoded alone, one launch per shot, at p=q=--p (default 0.001 in this mode)")
     ap.add_argument("--latency-shots", type=int, default=200)
+    ap.add_argument("--latency-p", type=float, default=None,
+                    help="noise rate of --latency (default 0.001, or --p when it is not the headline's 0.005)")
     ap.add_argument("--serve", type=int, default=0,
                     help="serving mode: this many windows with d in {9,13,17,21,25} (d rounds) and p ~ U[0.001, "
                          "0.007] (uniform per-window weight), Poisson arrivals at --serve-load x the measured "
