@@ -11,6 +11,12 @@ Contents:
                            (Results, "Decoding task"): Dijkstra + Edmonds on the
                            defect graph with an LP certificate (Supplementary S1),
                            in ``mwem.c``.
+  * ``SparseBlossom``   -- serial global sparse blossom (Supplementary S1) and
+                           serial partition-and-fuse (Methods: Algorithm
+                           "Clustering", the hierarchical execution rule,
+                           Algorithm "Parallel sparse blossom") with the event
+                           counts and the parallel event count E_ideal (Methods,
+                           numerical evaluation), in ``sparse_blossom.c``.
   * ``schedule``        -- finite-size parameter schedule (Methods, Algorithm
                            "Parameter schedule"; Supplementary S11), exact rationals.
   * ``cluster_levels``  -- processing-cluster hierarchy (Methods, Algorithm
@@ -42,10 +48,13 @@ OF_TIE, OF_INFEASIBLE, OF_CERT_FAIL, OF_CAPACITY = 1, 2, 4, 8
 INF_HI = np.iinfo(np.int64).max
 
 
+_SRCS = ("mwem.c", "sparse_blossom.c")
+
+
 def build() -> None:
     """Compile the C part of the oracle (gcc, host only)."""
     tmp = _SO + f".tmp{os.getpid()}"
-    subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, os.path.join(_HERE, "mwem.c")])
+    subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, *[os.path.join(_HERE, f) for f in _SRCS]])
     os.replace(tmp, _SO)
 
 
@@ -55,15 +64,17 @@ _lib_cache = None
 def _lib():
     global _lib_cache
     if _lib_cache is None:
-        src = os.path.join(_HERE, "mwem.c")
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        if not os.path.exists(_SO) or any(os.path.getmtime(_SO) < os.path.getmtime(os.path.join(_HERE, f))
+                                          for f in _SRCS):
             build()
         lib = ctypes.CDLL(_SO)
         lib.oracle_graph_create.restype = ctypes.c_void_p
         lib.oracle_graph_destroy.argtypes = [ctypes.c_void_p]
         for name in ("oracle_mwem", "oracle_dijkstra", "oracle_defect_distances",
-                     "oracle_defect_boundary_table", "oracle_max_weight_matching"):
+                     "oracle_defect_boundary_table", "oracle_max_weight_matching", "oracle_sb_decode"):
             getattr(lib, name).restype = ctypes.c_int
+        lib.oracle_sb_graph_create.restype = ctypes.c_void_p
+        lib.oracle_sb_graph_destroy.argtypes = [ctypes.c_void_p]
         _lib_cache = lib
     return _lib_cache
 
@@ -164,6 +175,72 @@ class Graph:
                                             ctypes.c_int32(nb), _p(be), _p(hi), _p(lo))
         T = _join(hi, lo)
         return [T[i * nb:(i + 1) * nb] for i in range(m)]
+
+
+SBF_INFEASIBLE, SBF_INTERNAL, SBF_DUAL, SBF_UNCLUSTERED, SBF_REACHED_LATER, SBF_CROSS_CLUSTER = 1, 2, 4, 8, 16, 32
+
+
+@dataclass
+class SBResult:
+    edges: np.ndarray     # int32, ascending
+    weight: int           # sum of the caller's weights over edges
+    obs: int              # XOR of observable masks
+    flags: int            # SBF_* bits
+    levels: np.ndarray    # processing-cluster level of every detection event (1-based)
+    events: int           # applied flooder/matcher events (ARRIVE, LEAVE, COLLIDE, IMPLODE, shatter)
+    arrivals: int         # ARRIVE events
+    e_ideal: int          # parallel event count (Methods, numerical evaluation)
+    clusters: int         # processing clusters
+    max_level: int        # highest level holding a cluster
+    level1_search: int    # detectors inside the level-1 exploring regions, summed over events
+
+
+class SparseBlossom:
+    """Serial sparse blossom on a detector graph (``sparse_blossom.c``): global
+    (every event in one cluster) or partition-and-fuse with a given level
+    schedule.  Independent of ``Graph`` (mwem.c) and of the GPU path."""
+
+    def __init__(self, g, tiebreak_seed: int):
+        self.g = g
+        self._h = _lib().oracle_sb_graph_create(
+            ctypes.c_int32(g.num_detectors), ctypes.c_int64(g.num_edges), _p(np.ascontiguousarray(g.u, np.int32)),
+            _p(np.ascontiguousarray(g.v, np.int32)), _p(np.ascontiguousarray(g.w, np.int32)),
+            _p(np.ascontiguousarray(g.obs_mask, np.uint64)), ctypes.c_uint64(int(tiebreak_seed) & ((1 << 64) - 1)))
+        if not self._h:
+            raise ValueError("oracle: invalid graph")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib().oracle_sb_graph_destroy(ctypes.c_void_p(h))
+            self._h = None
+
+    def decode(self, defects, d_sched=(), b_sched=(), reading: str = "strict", global_mode: bool = False) -> SBResult:
+        """Decode one shot.  d_sched / b_sched: level parameters d_k, b_k
+        (index 0 = level 1, exact ints in the tie-broken units), ignored in
+        global mode."""
+        d = np.ascontiguousarray(defects, np.int32)
+        # levels whose parameters no longer fit the C side's 128-bit integers are never needed: every
+        # graph here is accepted long before (the parameters grow geometrically)
+        keep = [k for k in range(len(d_sched)) if max(int(d_sched[k]), int(b_sched[k])) < (1 << 123)]
+        d_sched = [d_sched[k] for k in keep]; b_sched = [b_sched[k] for k in keep]
+        nl = len(d_sched)
+        mask = (1 << 64) - 1
+        dh = np.asarray([int(x) >> 64 for x in d_sched] or [0], np.int64)
+        dl = np.asarray([int(x) & mask for x in d_sched] or [0], np.uint64)
+        bh = np.asarray([int(x) >> 64 for x in b_sched] or [0], np.int64)
+        bl = np.asarray([int(x) & mask for x in b_sched] or [0], np.uint64)
+        cap = max(self.g.num_edges, 1)
+        out = np.zeros(cap, np.int32)
+        lv = np.zeros(max(d.shape[0], 1), np.int8)
+        st = np.zeros(7, np.int64)
+        n = ctypes.c_int64(); wt = ctypes.c_int64(); ob = ctypes.c_uint64()
+        _lib().oracle_sb_decode(ctypes.c_void_p(self._h), ctypes.c_int32(d.shape[0]), _p(d), ctypes.c_int32(nl),
+                                _p(dh), _p(dl), _p(bh), _p(bl), ctypes.c_int32(1 if reading == "loose" else 0),
+                                ctypes.c_int32(1 if global_mode else 0), _p(out), ctypes.c_int64(cap),
+                                ctypes.byref(n), ctypes.byref(wt), ctypes.byref(ob), _p(lv), _p(st))
+        return SBResult(out[: n.value].copy(), int(wt.value), int(ob.value), int(st[6]), lv[: d.shape[0]].copy(),
+                        int(st[0]), int(st[1]), int(st[2]), int(st[3]), int(st[4]), int(st[5]))
 
 
 def max_weight_matching(W) -> tuple[list, bool]:

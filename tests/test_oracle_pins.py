@@ -331,33 +331,95 @@ def test_clustering_chain_of_three_not_level_one():
 def test_clustering_partition_properties():
     """Every accepted cluster: diameter <= d_k, separation > b_k from the
     residual of its level, parity condition (Methods, Definition of the
-    processing-cluster hierarchy; Supplementary S2 cluster condition)."""
+    processing-cluster hierarchy; Supplementary S2 cluster condition).  The
+    checks are made on the exact distance tables, independently of how
+    cluster_levels builds its components."""
     g = synth.rotated_phenom_graph(11, 0.01)
     og = oracle.Graph(g, SEED)
     wmax = max(og.tiebroken_weights())
     d, b, _ = oracle.schedule(wmax, levels=4)
     s = synth.sample(g, 40, seed=5)
+    n_odd = n_multi = 0
     for i in range(40):
         dd = synth.defects_of(s.syndromes[i], g.num_detectors)
         if len(dd) == 0:
             continue
         D, _ = og.defect_distances(dd)
         BT = og.boundary_table(dd)
-        lv = oracle.cluster_levels(D, BT, d, b)
+        lv, comps = oracle.cluster_levels(D, BT, d, b, components=True)
         m = len(dd)
-        for k in sorted(set(lv)):
-            if k == 0:
-                continue
-            resid = [x for x in range(m) if lv[x] >= k or lv[x] == 0]
-            members = [x for x in range(m) if lv[x] == k]
+        assert all(x > 0 for x in lv)
+        assert sorted(x for _, c in comps for x in c) == list(range(m))     # a partition of the events
+        for k, members in comps:
+            assert all(lv[x] == k for x in members)
+            # diameter of the event set
             for x in members:
                 for y in members:
-                    pass
-            # separation of level-k defects from level > k residual
+                    assert D[x][y] is not None and D[x][y] <= d[k - 1]
+            # parity: even, or (strict reading) one boundary vertex within d_k of every member
+            if len(members) % 2 == 1:
+                n_odd += 1
+                assert any(all(BT[x][j] is not None and BT[x][j] <= d[k - 1] for x in members)
+                           for j in range(len(BT[members[0]])))
+            n_multi += len(members) > 1
+            # separation from every event still residual at level k that is not in this cluster
             for x in members:
-                for y in resid:
-                    if lv[y] != k:
+                for y in range(m):
+                    if y not in members and lv[y] >= k:
                         assert D[x][y] is None or D[x][y] > b[k - 1]
+    assert n_odd > 0 and n_multi > 0
+
+
+def test_clustering_loose_and_strict_readings_differ_on_an_odd_cluster():
+    """A hand-built odd cluster: three events on a 60-detector path (weights
+    10, doubled 20), two adjacent (29, 30) and one two edges away (32).  All
+    three are linked at level 1 (29-30 one edge, 30-32 two edges: 40 plus
+    tie-break parts, within b_1 = 2 d_1 + 1 with d_1 = w_max + 1) but the
+    diameter (29 to 32, 60) exceeds d_1
+    (about 20), so they stay residual; at level 2 the exploring regions cover
+    the path, the diameter fits d_2 = 3 d_1 + 4 b_1 + 2 w_max (about 260) and
+    the set is odd.  Its nearest boundary vertex is 28 edges (560) from detector 32 and
+    30 edges from detector 29: beyond d_2, so the strict reading (one boundary
+    vertex within d_k of every member) rejects it until level 3, while the
+    loose reading (some member's exploring region of radius b_2/2 reaches a
+    boundary vertex) accepts it at level 2."""
+    g = synth.repetition_graph(60, 10)
+    defects = [29, 30, 32]
+    og = oracle.Graph(g, SEED)
+    d, b, _ = oracle.schedule(max(og.tiebroken_weights()), levels=4)
+    D, _ = og.defect_distances(defects)
+    BT = og.boundary_table(defects)
+    assert max(D[0][1], D[0][2], D[1][2]) >> 64 == 60 and d[0] >> 64 == 20 and D[1][2] <= b[0] and D[0][2] > d[0]
+    assert min(min(x for x in row) for row in BT) >> 64 == 560 and min(BT[2]) > d[1]
+    assert oracle.cluster_levels(D, BT, d, b, "strict") == [3, 3, 3]
+    assert oracle.cluster_levels(D, BT, d, b, "loose") == [2, 2, 2]
+
+
+def test_schedule_level_two_and_three_closed_forms():
+    """Levels 2 and 3 of the schedule (Methods, Algorithm "Parameter schedule";
+    q = 1/10, phi_min = 1/100) at w_max = 2710, 2972, 3536 and 2536 (the
+    benchmark weights doubled), derived here from the algorithm's inequalities
+    solved for b in closed form:
+      phi_2 = Phi_2(b_1) = 1 - 3 d_1 / (2 d_1 + b_1)            (phi_1 = 1),
+      Phi_3(b) >= phi_bar_3  <=>  b >= ((phi_2 + 2) d_2 / (phi_2 - phi_bar_3) - (phi_2 + 1) d_2) / phi_2,
+    and b_2 also exceeds 2 d_2 / phi_2; d_{k+1} = 3 d_k + 4 b_k + 2 w_max."""
+    import math
+    q, pm = Fraction(1, 10), Fraction(1, 100)
+    expect = {2710: (35245, 1201614, 4917611), 2972: (38651, 1317805, 5393117),
+              3536: (45983, 1567924, 6416717), 2536: (32983, 1124450, 4601821)}
+    for w, (d2_e, b2_e, d3_e) in expect.items():
+        d1 = w + 1
+        b1 = 2 * d1 + 1
+        phi2 = 1 - Fraction(3 * d1, 2 * d1 + b1)
+        d2 = 3 * d1 + 4 * b1 + 2 * w
+        target3 = pm + (1 - pm) * q ** 2
+        lo = ((phi2 + 2) * d2 / (phi2 - target3) - (phi2 + 1) * d2) / phi2
+        b2 = max(d2, math.floor(2 * d2 / phi2) + 1, math.ceil(lo))
+        d3 = 3 * d2 + 4 * b2 + 2 * w
+        assert (d2, b2, d3) == (d2_e, b2_e, d3_e)
+        od, ob, ophi = oracle.schedule(w, q, pm, levels=3)
+        assert (od[1], ob[1], od[2]) == (d2, b2, d3)
+        assert ophi[1] == phi2 and abs(float(ophi[1]) - 0.2500) < 1e-3 and abs(float(ophi[2]) - 0.0199) < 1e-4
 
 
 # ---------------------------------------------------------------------------
@@ -471,3 +533,106 @@ def test_complementary_minimum_is_the_mwem():
         assert min(w0, w1) == r.weight
         if w0 != w1:
             assert (w1 < w0) == bool(r.obs & 1)
+
+
+def _parity_search(g, bit, starts):
+    """Dijkstra over (detector, observable parity) states with the caller's
+    weights; `starts` = [(detector, parity, distance)].  Returns the distance
+    to every (detector, parity) and to every (boundary edge, parity) end."""
+    import heapq
+    adj = [[] for _ in range(g.num_detectors)]
+    for e in range(g.num_edges):
+        a, b = int(g.u[e]), int(g.v[e])
+        adj[a].append((e, b))
+        if b >= 0:
+            adj[b].append((e, a))
+    dist = {}
+    bd = {}
+    h = [(dd, x, par) for x, par, dd in starts]
+    heapq.heapify(h)
+    while h:
+        dd, x, par = heapq.heappop(h)
+        if (x, par) in dist:
+            continue
+        dist[(x, par)] = dd
+        for e, y in adj[x]:
+            np_ = par ^ (1 if int(g.obs_mask[e]) >> bit & 1 else 0)
+            nd = dd + int(g.w[e])
+            if y < 0:
+                if nd < bd.get((e, np_), 1 << 62):
+                    bd[(e, np_)] = nd
+            elif (y, np_) not in dist:
+                heapq.heappush(h, (nd, y, np_))
+    return dist, bd
+
+
+def _definition_constrained(g, defects, bit=0):
+    """(W0, W1) from the definition of the two constrained minima, without the
+    chain rewrite: an edge set with odd degree exactly at the events splits
+    into paths between events, paths from events to boundary vertices, paths
+    between two boundary vertices and cycles.  Cycles carry no observable
+    here (it sits on boundary edges only) and only add weight; two
+    boundary-to-boundary paths of odd parity cancel.  So each minimum is the
+    best pairing of the events (with each other or with the boundary) under
+    parity-tracked shortest distances, with or without one boundary-to-boundary
+    path of odd observable parity."""
+    INF = 1 << 62
+    m = len(defects)
+    pair = [[[INF, INF] for _ in range(m)] for _ in range(m)]
+    to_bd = [[INF, INF] for _ in range(m)]
+    for i, s in enumerate(defects):
+        dist, bd = _parity_search(g, bit, [(int(s), 0, 0)])
+        for j, t in enumerate(defects):
+            for par in (0, 1):
+                pair[i][j][par] = dist.get((int(t), par), INF)
+        for (e, par), dd in bd.items():
+            to_bd[i][par] = min(to_bd[i][par], dd)
+    # the cheapest boundary-to-boundary path of odd parity (two different boundary edges)
+    bb = INF
+    bedges = [e for e in range(g.num_edges) if int(g.v[e]) < 0]
+    for e1 in bedges:
+        p1 = int(g.obs_mask[e1]) >> bit & 1
+        _, bd = _parity_search(g, bit, [(int(g.u[e1]), p1, int(g.w[e1]))])
+        for (e2, par), dd in bd.items():
+            if e2 != e1 and par == 1:
+                bb = min(bb, dd)
+    from functools import lru_cache
+
+    @lru_cache(maxsize=None)
+    def best(rest, par):
+        if not rest:
+            return 0 if par == 0 else INF
+        i, others = rest[0], rest[1:]
+        out = INF
+        for q in (0, 1):
+            if to_bd[i][q] < INF:
+                out = min(out, to_bd[i][q] + best(others, par ^ q))
+            for j in others:
+                if pair[i][j][q] < INF:
+                    out = min(out, pair[i][j][q] + best(tuple(x for x in others if x != j), par ^ q))
+        return out
+
+    res = []
+    for target in (0, 1):
+        v = min(best(tuple(range(m)), target),
+                bb + best(tuple(range(m)), target ^ 1) if bb < INF else INF)
+        res.append(None if v >= INF else v)
+    return tuple(res)
+
+
+@pytest.mark.parametrize("d,rounds,p", [(3, 3, 0.05), (5, 2, 0.03), (5, 5, 0.02)])
+def test_complementary_equals_definition_without_the_rewrite(d, rounds, p):
+    """Both constrained minima on rotated codes of 39 to 185 edges equal the
+    parity-tracked pairing definition (no chain rewrite)."""
+    g = synth.rotated_phenom_graph(d, p, rounds=rounds)
+    assert g.num_edges > 16
+    co = oracle.Complementary(g, 0, 0x5EED)
+    s = synth.sample(g, 60, seed=31 + d)
+    n = 0
+    for i in range(60):
+        dd = synth.defects_of(s.syndromes[i], g.num_detectors)
+        if len(dd) > 9:
+            continue
+        n += 1
+        assert co.weights(dd) == _definition_constrained(g, dd.tolist()), (i, dd.tolist())
+    assert n >= 30
