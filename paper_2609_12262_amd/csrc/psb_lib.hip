@@ -197,6 +197,9 @@ struct psb_decoder {
   char* d_ws_ovf = nullptr;
   int32_t* d_ovf_list = nullptr;
   int64_t ovf_list_cap = 0;
+  int32_t n_graphs = 0;              // captured batch graphs whose kernel arguments hold d_ovf_list
+  int32_t* last_counter = nullptr;   // work counters of the most recent launch
+  int32_t device = 0;
   Params P_fast{}, P_ovf{};
   LevelSchedule sched;
   std::vector<int32_t> hmax;
@@ -288,6 +291,7 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   // occupancy-derived slot counts
   int dev = 0, cus = 256;
   HIP_TRY(hipGetDevice(&dev));
+  D->device = dev;
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   int per_cu = 0, per_cu_o = 0;
   if (D->lds_fast > 160 * 1024) D->fast_enabled = false;
@@ -395,6 +399,9 @@ extern "C" int32_t psb_decoder_reserve(psb_decoder* D, int64_t max_batch) {
   if (!D) return fail(PSB_E_INVALID, "null decoder");
   if (max_batch < 0 || max_batch > (int64_t)INT32_MAX) return fail(PSB_E_INVALID, "max_batch out of range");
   if (!D->fast_enabled || D->ovf_list_cap >= max_batch) return PSB_OK;
+  if (D->n_graphs > 0)
+    return fail(PSB_E_INVALID, "a captured batch graph of this decoder holds its overflow list; reserve the "
+                               "largest batch before capturing, or destroy the graphs first");
   HIP_TRY(hipDeviceSynchronize());
   if (D->d_ovf_list) (void)hipFree(D->d_ovf_list);
   D->d_ovf_list = nullptr;
@@ -414,32 +421,23 @@ extern "C" int32_t psb_decoder_slots(const psb_decoder* D, int32_t* fast_slots, 
   return PSB_OK;
 }
 
-extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, int64_t n, int32_t* edges,
-                                    int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
-                                    int8_t* levels, uint64_t* t_done, int32_t* stats, void* stream) {
-  if (!D) return fail(PSB_E_INVALID, "null decoder");
-  if (n < 0) return fail(PSB_E_INVALID, "negative batch size");
-  if (n == 0) return PSB_OK;
-  if (n > (int64_t)INT32_MAX) return fail(PSB_E_INVALID, "batch too large");
-  if (!syndromes || !edges || !n_edges || !weight || !obs || !status) return fail(PSB_E_INVALID, "null output");
-  hipStream_t s = (hipStream_t)stream;
-  if (D->fast_enabled && D->ovf_list_cap < n) {
-    // grows only between launches; the caller's stream is synchronised first
-    HIP_TRY(hipStreamSynchronize(s));
-    if (D->d_ovf_list) (void)hipFree(D->d_ovf_list);
-    D->d_ovf_list = nullptr;
-    if (hipMalloc((void**)&D->d_ovf_list, 4 * (size_t)n) != hipSuccess) return fail(PSB_E_NOMEM, "overflow list");
-    D->ovf_list_cap = n;
-  }
+// Launches one batch: the counter reset, the first tier and the overflow tier,
+// with the given work counters ([0] first-tier head, [1] overflow count, [2]
+// overflow head) and overflow list (room for n shots).
+static int32_t launch_batch(psb_decoder* D, const uint8_t* syndromes, int64_t n, int32_t* edges, int32_t* n_edges,
+                            int64_t* weight, uint64_t* obs, int32_t* status, int8_t* levels, uint64_t* t_done,
+                            int32_t* stats, int32_t* counter, int32_t* ovf_list, hipStream_t s) {
   Params* tiers[2] = {&D->P_fast, &D->P_ovf};
   for (Params* P : tiers) {
     P->n_shots = n; P->synd = syndromes; P->out_edges = edges; P->out_nedges = n_edges; P->out_weight = weight;
     P->out_obs = obs; P->out_status = status; P->out_levels = levels; P->out_tdone = t_done; P->out_stats = stats;
     P->stats_stride = P->eacct ? 12 : 8;
     P->level_stride = D->dcap;
-    P->ovf_list = D->fast_enabled ? D->d_ovf_list : nullptr;
+    P->counter = counter;
+    P->ovf_list = D->fast_enabled ? ovf_list : nullptr;
   }
-  psb_zero_kernel<<<1, 64, 0, s>>>(D->d_counter, 3, t_done ? t_done + n : nullptr);
+  D->last_counter = counter;
+  psb_zero_kernel<<<1, 64, 0, s>>>(counter, 3, t_done ? t_done + n : nullptr);
   HIP_TRY(hipGetLastError());
   if (D->fast_enabled && D->first_lane) {
     const int64_t waves = std::min<int64_t>((n + 63) / 64, D->slots_fast / 64);
@@ -457,13 +455,47 @@ extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, in
   return PSB_OK;
 }
 
+static int32_t check_batch_args(psb_decoder* D, const uint8_t* syndromes, int64_t n, int32_t* edges,
+                                int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status) {
+  if (!D) return fail(PSB_E_INVALID, "null decoder");
+  if (n < 0) return fail(PSB_E_INVALID, "negative batch size");
+  if (n > (int64_t)INT32_MAX) return fail(PSB_E_INVALID, "batch too large");
+  if (n > 0 && (!syndromes || !edges || !n_edges || !weight || !obs || !status)) return fail(PSB_E_INVALID, "null output");
+  return PSB_OK;
+}
+
+extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, int64_t n, int32_t* edges,
+                                    int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
+                                    int8_t* levels, uint64_t* t_done, int32_t* stats, void* stream) {
+  const int32_t rc = check_batch_args(D, syndromes, n, edges, n_edges, weight, obs, status);
+  if (rc != PSB_OK || n == 0) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (D->fast_enabled && D->ovf_list_cap < n) {
+    // a captured graph's kernel arguments point at the current list: it must not move
+    if (D->n_graphs > 0)
+      return fail(PSB_E_INVALID, "batch larger than the overflow list that a captured batch graph of this decoder "
+                                 "holds; reserve the largest batch before capturing");
+    // grows only between launches; the caller's stream is synchronised first
+    HIP_TRY(hipStreamSynchronize(s));
+    if (D->d_ovf_list) (void)hipFree(D->d_ovf_list);
+    D->d_ovf_list = nullptr;
+    D->ovf_list_cap = 0;
+    if (hipMalloc((void**)&D->d_ovf_list, 4 * (size_t)n) != hipSuccess) return fail(PSB_E_NOMEM, "overflow list");
+    D->ovf_list_cap = n;
+  }
+  return launch_batch(D, syndromes, n, edges, n_edges, weight, obs, status, levels, t_done, stats, D->d_counter,
+                      D->d_ovf_list, s);
+}
+
 struct psb_batch_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  psb_decoder* dec = nullptr;        // its overflow list must not move while the graph exists
 };
 
 extern "C" int32_t psb_batch_graph_destroy(psb_batch_graph* B) {
   if (!B) return PSB_OK;
+  if (B->dec) --B->dec->n_graphs;
   if (B->exec) (void)hipGraphExecDestroy(B->exec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
   delete B;
@@ -489,6 +521,8 @@ extern "C" int32_t psb_batch_graph_create(psb_decoder* D, const uint8_t* syndrom
   }
   rc = psb_decode_batch(D, syndromes, n, edges, n_edges, weight, obs, status, levels, t_done, stats, cs);
   const hipError_t e = hipStreamEndCapture(cs, &B->graph);
+  B->dec = D;
+  ++D->n_graphs;
   (void)hipStreamDestroy(cs);
   if (rc != PSB_OK || e != hipSuccess) {
     psb_batch_graph_destroy(B);
@@ -532,7 +566,7 @@ extern "C" int32_t psb_decoder_last_overflow(psb_decoder* D, void* stream, int32
   if (!D || !n_overflow) return fail(PSB_E_INVALID, "null argument");
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   int32_t v[3] = {0, 0, 0};
-  HIP_TRY(hipMemcpy(v, D->d_counter, sizeof(v), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(v, D->last_counter ? D->last_counter : D->d_counter, sizeof(v), hipMemcpyDeviceToHost));
   *n_overflow = D->fast_enabled ? v[1] : 0;
   return PSB_OK;
 }

@@ -55,6 +55,45 @@ def test_batch_graph_replays_equal_eager():
     bg.close(); dec.close(); ref.close(); G.close()
 
 
+def test_captured_graph_pins_the_overflow_list():
+    """While a captured batch graph of a decoder exists, nothing may move the
+    overflow list its kernel arguments hold: a larger batch, a larger reserve
+    and a second capture for more shots are refused with an error before
+    anything is launched.  After the graph is destroyed they succeed."""
+    import torch
+    import paper_2609_12262_amd as psb
+    g = synth.rotated_phenom_graph(9, 0.005)
+    small = torch.from_numpy(synth.sample(g, 256, seed=81).syndromes).cuda()
+    big_np = synth.sample(g, 1024, seed=82).syndromes
+    big = torch.from_numpy(big_np).cuda()
+    G = psb.Graph.from_synth(g)
+    dec = psb.Decoder(G, tiebreak_seed=SEED)
+    out = dec.alloc(256)
+    bg = dec.capture(small, out)
+    out_big = dec.alloc(1024)
+    with pytest.raises(psb.PsbError):
+        dec.decode_into(big, out_big)
+    with pytest.raises(psb.PsbError):
+        dec.reserve(1024)
+    with pytest.raises(psb.PsbError):
+        dec.capture(big, out_big)
+    bg.launch()
+    torch.cuda.synchronize()
+    got = _host(out)
+    eager = _host(dec.decode(small))
+    torch.cuda.synchronize()
+    for key in KEYS:
+        assert np.array_equal(got[key], eager[key]), key
+    bg.close()
+    dec.reserve(1024)
+    res = _host(dec.decode_into(big, out_big))
+    torch.cuda.synchronize()
+    res["obs"] = res["obs"].view(np.uint64)
+    bad = compare(g, big_np, res, range(0, 1024, 4))
+    assert not bad, bad[:5]
+    dec.close(); G.close()
+
+
 def test_autotune_candidates_agree_and_best_matches_oracle():
     """d=21, p=0.007 (some shots exceed the default first-tier state): every
     candidate that fits decodes the sample to the same weights and
