@@ -193,6 +193,8 @@ class SBResult:
     clusters: int         # processing clusters
     max_level: int        # highest level holding a cluster
     level1_search: int    # detectors inside the level-1 exploring regions, summed over events
+    tied: int             # events applied while a different event was due at the same time (the counts of
+                          # such shots can depend on the order of the simultaneous events; the result cannot)
 
 
 class SparseBlossom:
@@ -233,14 +235,14 @@ class SparseBlossom:
         cap = max(self.g.num_edges, 1)
         out = np.zeros(cap, np.int32)
         lv = np.zeros(max(d.shape[0], 1), np.int8)
-        st = np.zeros(7, np.int64)
+        st = np.zeros(8, np.int64)
         n = ctypes.c_int64(); wt = ctypes.c_int64(); ob = ctypes.c_uint64()
         _lib().oracle_sb_decode(ctypes.c_void_p(self._h), ctypes.c_int32(d.shape[0]), _p(d), ctypes.c_int32(nl),
                                 _p(dh), _p(dl), _p(bh), _p(bl), ctypes.c_int32(1 if reading == "loose" else 0),
                                 ctypes.c_int32(1 if global_mode else 0), _p(out), ctypes.c_int64(cap),
                                 ctypes.byref(n), ctypes.byref(wt), ctypes.byref(ob), _p(lv), _p(st))
         return SBResult(out[: n.value].copy(), int(wt.value), int(ob.value), int(st[6]), lv[: d.shape[0]].copy(),
-                        int(st[0]), int(st[1]), int(st[2]), int(st[3]), int(st[4]), int(st[5]))
+                        int(st[0]), int(st[1]), int(st[2]), int(st[3]), int(st[4]), int(st[5]), int(st[7]))
 
 
 def max_weight_matching(W) -> tuple[list, bool]:

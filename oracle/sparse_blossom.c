@@ -251,6 +251,7 @@ typedef struct {
   i128 now;
   int flags;
   int64_t n_events, n_arrive, max_events;
+  int64_t n_tied;            /* events applied while another, different event was due at the same time */
   /* parallel event count */
   int64_t *c_n, *c_early;
   i128* c_last;
@@ -556,7 +557,7 @@ static void collide(shot* S, int32_t a, int32_t b, int32_t c) {
 /* flooder: the next event by a plain scan                               */
 /* ------------------------------------------------------------------ */
 enum { EV_REGION = 0, EV_LEAVE = 1, EV_EDGE = 2 };
-typedef struct { i128 t; int32_t kind; int64_t key; int32_t u, x; } event;
+typedef struct { i128 t; int32_t kind; int64_t key; int32_t u, x; int32_t tied; } event;
 
 static int earlier(const event* a, const event* b) {
   if (a->t != b->t) return a->t < b->t;
@@ -582,14 +583,23 @@ static void scan_regions(shot* S) {
 
 static i128 local_radius(const shot* S, int32_t v) { return S->ysum[S->reg[v]] - S->arr[v]; }
 
+/* keeps the earliest event; `tied` records whether another, different event
+ * (not the same edge seen from its other end) is due at that same time */
 static void consider(event* best, i128 t, int32_t kind, int64_t key, int32_t u, int32_t x) {
-  event c; c.t = t; c.kind = kind; c.key = key; c.u = u; c.x = x;
-  if (earlier(&c, best)) *best = c;
+  event c; c.t = t; c.kind = kind; c.key = key; c.u = u; c.x = x; c.tied = 0;
+  const int same_time = (t == best->t);
+  const int distinct = !(kind == best->kind && key == best->key);
+  if (earlier(&c, best)) {
+    c.tied = same_time && distinct && best->t < SB_INF;
+    *best = c;
+  } else if (same_time && distinct) {
+    best->tied = 1;
+  }
 }
 
 static event next_event(shot* S) {
   const sb_graph* g = S->g;
-  event best; best.t = SB_INF; best.kind = 99; best.key = 0; best.u = -1; best.x = -1;
+  event best; best.t = SB_INF; best.kind = 99; best.key = 0; best.u = -1; best.x = -1; best.tied = 0;
   scan_regions(S);
   /* IMPLODE / shatter: an active shrinking region reaches radius zero */
   for (int64_t r = 0; r < S->nR; ++r) {
@@ -869,13 +879,16 @@ static void expand(shot* S, int32_t X, int32_t s, uint8_t* parity, int depth) {
 /* ------------------------------------------------------------------ */
 /* stats[0] applied events, [1] ARRIVE events, [2] E_ideal, [3] processing
  * clusters, [4] highest level, [5] detectors inside the level-1 exploring
- * regions (summed over events), [6] flags. */
+ * regions (summed over events), [6] flags, [7] events applied while a
+ * different event was due at the same time.  With such ties the result is
+ * unique (the MWEM), but which of the simultaneous events remain valid after
+ * the first is applied can depend on their order, and so can the counts. */
 int oracle_sb_decode(void* pg, int32_t nd, const int32_t* det, int32_t n_levels, const int64_t* d_hi,
                      const uint64_t* d_lo, const int64_t* b_hi, const uint64_t* b_lo, int32_t reading, int32_t global,
                      int32_t* out_edges, int64_t out_cap, int64_t* n_out, int64_t* weight, uint64_t* obs,
                      int8_t* levels_out, int64_t* stats) {
   const sb_graph* g = (const sb_graph*)pg;
-  for (int k = 0; k < 7; ++k) stats[k] = 0;
+  for (int k = 0; k < 8; ++k) stats[k] = 0;
   *n_out = 0; *weight = 0; *obs = 0;
   if (!g || nd < 0) return SBF_INTERNAL;
   if (nd == 0) return 0;
@@ -940,6 +953,7 @@ int oracle_sb_decode(void* pg, int32_t nd, const int32_t* det, int32_t n_levels,
       if (ev.t >= SB_INF || (S.flags & ~SBF_DUAL)) break;
       if (ev.t < S.now) { S.flags |= SBF_INTERNAL; break; }
       S.now = ev.t;
+      S.n_tied += ev.tied;
       charge(&S, driving_root(&S, &ev), ev.t);
       apply(&S, &ev);
       if (++S.n_events > S.max_events) { S.flags |= SBF_INTERNAL; break; }
@@ -992,7 +1006,7 @@ int oracle_sb_decode(void* pg, int32_t nd, const int32_t* det, int32_t n_levels,
   free(parity);
   if (levels_out) for (int32_t i = 0; i < nd; ++i) levels_out[i] = S.level[i];
   stats[0] = S.n_events; stats[1] = S.n_arrive; stats[2] = S.e_lt; stats[3] = n_clusters;
-  stats[4] = max_level; stats[5] = n_lvl1; stats[6] = S.flags;
+  stats[4] = max_level; stats[5] = n_lvl1; stats[6] = S.flags; stats[7] = S.n_tied;
   free(S.dix); free(S.level); free(S.cid); free(S.reg); free(S.arr); free(S.src); free(S.pe); free(S.pn);
   free(S.seen); free(S.reached); free(S.c_n); free(S.c_early); free(S.c_last);
   free(S.R); free(S.CE); free(S.path); free(S.cyc); free(S.ysum); free(S.top); free(dk); free(bk);

@@ -46,6 +46,14 @@
 #define PSB_ENGINE_NS engine_wave
 #endif
 
+#ifdef PSB_CHECK_INVARIANTS
+// Host builds only (the harness defines the handler): checks of properties the
+// paper proves about the dynamics.  Never compiled into a device build.
+void psb_invariant_failed(const char* what, int64_t shot, int level);
+#define PSB_INVARIANT(c, cond, what) \
+  do { if (!(cond)) psb_invariant_failed((what), (c).dbg_shot, (c).dbg_lvl); } while (0)
+#endif
+
 namespace psb {
 namespace PSB_ENGINE_NS {
 
@@ -85,6 +93,12 @@ struct Ctx {
   int n_visit;                       // clustering search visits (statistics)
   uint64_t t0, t_cl, t_dyn, t_fuse;  // device clock marks (statistics)
   char* acct;                        // event-accounting block, or null
+#ifdef PSB_CHECK_INVARIANTS
+  int64_t dbg_shot; int dbg_lvl;
+  int32_t* dbg_cfg;                  // [rcap] processing cluster whose stopped configuration holds the region
+  int32_t* dbg_touch;                // [dcap] per cluster: the cluster that touched its configuration at dbg_touch_lvl
+  int32_t* dbg_touch_lvl;            // [dcap]
+#endif
 };
 
 // Region field f of region r: int16 storage for ids, rates and flags, int32
@@ -230,7 +244,10 @@ PSB_DEV void next_event(Ctx& c, i128& t, int& code) {
 // detector map instead (with the table, lane-tier shots on the hash-map path
 // came back wrong on the device while the same code was correct on the CPU;
 // the lane tier keeps the lookups until that is explained).
-constexpr bool kNbTable = PSB_WAVE > 1;
+#ifndef PSB_NB_TABLE
+#define PSB_NB_TABLE (PSB_WAVE > 1)
+#endif
+constexpr bool kNbTable = PSB_NB_TABLE;
 
 // Explored index of the neighbour behind adjacency slot j of explored node i,
 // or an XNB_* code.
@@ -507,6 +524,9 @@ PSB_DEV void dissolve_tree(Ctx& c, int tid) {
     RF(c, r, RF_TID) = -1;
     RF(c, r, RF_TPAR) = -1;
     set_rate(c, r, 0);
+#ifdef PSB_CHECK_INVARIANTS
+    if (c.acct) c.dbg_cfg[r] = acct_cid(c)[tid];
+#endif
   }
 }
 
@@ -726,6 +746,17 @@ PSB_DEV void collide(Ctx& c, int a, int b, int ce) {
     return;
   }
   if (rb != 0) { c.status = S_INTERNAL; return; }
+#ifdef PSB_CHECK_INVARIANTS
+  // Supplementary, unique touching of inherited matching configurations: a
+  // configuration stopped at a lower level is touched by at most one
+  // processing cluster of the running level
+  if (c.acct && c.dbg_cfg[b] >= 0 && c.level[c.dbg_cfg[b]] < c.dbg_lvl) {
+    const int owner = c.dbg_cfg[b], toucher = acct_cid(c)[ta];
+    PSB_INVARIANT(c, !(c.dbg_touch_lvl[owner] == c.dbg_lvl && c.dbg_touch[owner] != toucher),
+                  "an inherited configuration touched by two clusters of one level");
+    c.dbg_touch[owner] = toucher; c.dbg_touch_lvl[owner] = c.dbg_lvl;
+  }
+#endif
   const int mb = uni(RF(c, b, RF_MATE));
   if (mb == MATE_BOUNDARY) {                                 // (g) tree hits boundary match
     augment_to_root(c, a);
@@ -857,6 +888,12 @@ PSB_DEV void run_dynamics(Ctx& c) {
       continue;
     }
     const int ix = code - EV_NODE;
+#ifdef PSB_CHECK_INVARIANTS
+    // Supplementary, persistent root: every alternating tree keeps a growing (outer) root
+    for (int r = 0; r < c.n_regions; ++r)
+      if (RF(c, r, RF_ALIVE) && RF(c, r, RF_BPAR) < 0 && RF(c, r, RF_TID) >= 0 && RF(c, r, RF_TPAR) < 0)
+        PSB_INVARIANT(c, RF(c, r, RF_RATE) == 1, "a tree root that is not growing");
+#endif
     i128 tf; int kf;
     node_event_u(c, ix, tf, kf);
     if (tf != tn) { wave_sync(); set_event(c, ix, tf); continue; }
@@ -1381,6 +1418,11 @@ PSB_DEV void cleanup(Ctx& c, int64_t shot) {
 // Decodes one shot.  Returns the status; S_OVERFLOW means nothing was
 // written and the shot must be decoded by the overflow tier.
 PSB_DEV int decode_shot(Ctx& c, int64_t shot) {
+#ifdef PSB_CHECK_INVARIANTS
+  c.dbg_shot = shot; c.dbg_lvl = 0;
+  for (int i = 0; i < c.rcap; ++i) c.dbg_cfg[i] = -1;
+  for (int i = 0; i < c.P->cap.dcap; ++i) { c.dbg_touch[i] = -1; c.dbg_touch_lvl[i] = -1; }
+#endif
   c.status = S_OK; c.n_ce = 0; c.n_bc = 0; c.n_shr = 0; c.n_chg = 0; c.stamp = 1; c.n_ev = 0;
   c.now = 0; c.n_visit = 0; c.nd = 0; c.n_log = 0; c.n_regions = 0;
   c.t0 = dev_clock(); c.t_cl = c.t0; c.t_dyn = c.t0; c.t_fuse = c.t0;
@@ -1423,7 +1465,16 @@ PSB_DEV int decode_shot(Ctx& c, int64_t shot) {
     c.now = 0;       // every level starts its clock at zero; stopped regions are frozen
     if (c.acct) account_level_start(c, lvl);
     seed_level(c, lvl);
+#ifdef PSB_CHECK_INVARIANTS
+    c.dbg_lvl = lvl;
+#endif
     run_dynamics(c);
+#ifdef PSB_CHECK_INVARIANTS
+    // Supplementary, stopping guarantee: below the final level a level-k
+    // cluster has stopped by time d_k (its diameter bound)
+    if (!c.status && c.P->shmax[lvl - 1] >= 0)
+      PSB_INVARIANT(c, c.now <= c.P->sd[lvl - 1], "a cluster ran past d_k");
+#endif
     if (c.acct && !c.status) account_level_end(c, lvl);
     if (!c.status) {
       int open = 0;
@@ -1480,7 +1531,7 @@ PSB_DEV void ctx_init(Ctx& c, const Params* P, Lds* S, char* state, int64_t slot
   c.shr = (int32_t*)(base + L.shr); c.chg = (int32_t*)(base + L.chg); c.stk = (int32_t*)(base + L.stk);
   c.fin = (int32_t*)(base + L.fin); c.ebits = (uint32_t*)(base + L.ebits);
   c.dmap = P->cap.hcap == 0 ? (int16_t*)(base + L.dmap) : nullptr;
-  c.x_nb = (int16_t*)(base + L.x_nb);
+  c.x_nb = L.x_nb >= 0 ? (int16_t*)(base + L.x_nb) : nullptr;
   c.acct = (P->eacct && P->out_stats) ? base + L.acct : nullptr;
 }
 

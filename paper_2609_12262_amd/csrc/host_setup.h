@@ -211,7 +211,7 @@ static int32_t next_pow2(int64_t x) { int32_t p = 1; while (p < x) p <<= 1; retu
 // block sit at the start of the slot, pools are sized more tightly and a shot
 // that exceeds them is handed on).
 static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const psb::Caps& cap, bool lane_slot,
-                      int lean = 0, bool acct = false) {
+                      int lean = 0, bool acct = false, bool lane_nb_table = false) {
   P.n_det = n; P.deg = deg; P.nbytes = (n + 7) / 8; P.n_edges = n_edges;
   P.cap = cap;
   const int32_t d = cap.dcap;
@@ -239,7 +239,8 @@ static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const 
   L.x_ev = lean >= 1 ? take(16LL * cap.xcap) : 0;
   L.r_base = lean >= 1 ? take(16LL * cap.rcap) : 0;
   L.x_wr = lean >= 2 ? take(16LL * cap.xcap) : 0;
-  L.x_nb = lane_slot ? 0 : take(2LL * cap.xcap * deg);   // the lane tier has no neighbour table
+  // the lane tier keeps no neighbour table (-1: none; only a host build of the engine can ask for one)
+  L.x_nb = (lane_slot && !lane_nb_table) ? -1 : take(2LL * cap.xcap * deg);
   L.acct = acct ? take(psb::acct_bytes(d)) : 0;
   P.eacct = acct ? 1 : 0;
   L.total = off;

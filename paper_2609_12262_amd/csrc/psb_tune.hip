@@ -77,6 +77,12 @@ extern "C" int32_t psb_autotune(const psb_graph* g, const psb_decoder_opts* base
     E.opts.q_den = kCandidates[c].q_den;
     E.ms = -1.0f;
     psb_decoder* D = nullptr;
+    // the lane tier is only offered on the direct detector-map path (graphs of at most 32,768 detectors):
+    // on the hash-map path a lane-tier variant once gave wrong device results whose cause was not shown
+    if (E.opts.first_tier == 1 && psb_graph_syndrome_bytes(g) > 32768 / 8) {
+      E.status = PSB_E_UNSUPPORTED;
+      continue;
+    }
     E.status = psb_decoder_create(g, &E.opts, &D);
     if (E.status != PSB_OK) continue;        // outside this graph's limits: skipped
     DevBuf d_edges;

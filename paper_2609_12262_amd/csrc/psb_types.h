@@ -41,7 +41,7 @@ struct WsLayout {
   int64_t x_ev, r_base, x_wr;                    // event cache, region bases, radius offsets, when the state block
                                                  // leaves them out (else unused)
   int64_t x_nb;                                  // [xcap][deg] int16: explored index of each adjacency slot's
-                                                 // neighbour (XNB_* codes when it has none)
+                                                 // neighbour (XNB_* codes when it has none); -1: no table
   int64_t acct;                                  // per-cluster event accounting block (event_accounting only)
   int64_t total;                                 // bytes per slot (multiple of 256)
 };

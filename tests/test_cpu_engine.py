@@ -1,0 +1,134 @@
+"""The decoder engine built for the CPU (the single-lane code of the HIP
+library, one shot at a time) under the address and undefined-behaviour
+sanitizers, with the invariant checks compiled in (a tree root keeps growing;
+below the final level a cluster stops by d_k; an inherited configuration is
+touched by at most one cluster of a level).  Results equal the MWEM oracle
+shot by shot; event counts and E_ideal equal the serial sparse-blossom oracle
+on every shot without simultaneous events."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from cpu_engine import run as ce
+
+SEED = 0x5EED
+
+
+@pytest.fixture(scope="module")
+def exe(tmp_path_factory):
+    d = tmp_path_factory.mktemp("engine_host")
+    return ce.build(str(d))
+
+
+@pytest.fixture(scope="module")
+def exe_nb(tmp_path_factory):
+    d = tmp_path_factory.mktemp("engine_host_nb")
+    return ce.build(str(d), nb_table=True)
+
+
+def _compare(g, syndromes, res, mode=0, reading="strict", counts=True):
+    og = oracle.Graph(g, SEED)
+    sb = oracle.SparseBlossom(g, SEED)
+    d, b, _ = oracle.schedule(max(og.tiebroken_weights()), levels=8)
+    bad, tied = [], 0
+    for i in range(syndromes.shape[0]):
+        dd = synth.defects_of(syndromes[i], g.num_detectors)
+        r = og.mwem(dd)
+        got = res["edges"][i, :res["n_edges"][i]].tolist()
+        if res["status"][i] != 0 or got != r.edges.tolist() or res["weight"][i] != r.weight or int(res["obs"][i]) != r.obs:
+            bad.append((i, "result", int(res["status"][i])))
+            continue
+        if not counts:
+            continue
+        s = sb.decode(dd, d, b, reading=reading, global_mode=(mode == 1))
+        if s.tied:
+            tied += 1
+            continue
+        st = res["stats"][i]
+        if (int(st[8]), int(st[9]), int(st[10])) != (s.events, s.e_ideal, s.clusters):
+            bad.append((i, "counts", tuple(int(x) for x in st[8:11]), (s.events, s.e_ideal, s.clusters)))
+    return bad, tied
+
+
+@pytest.mark.parametrize("d,p,n,seed", [(5, 0.005, 2000, 1), (11, 0.003, 600, 2), (9, 0.03, 200, 7),
+                                        (15, 0.005, 120, 12)])
+def test_cpu_engine_phenomenological(exe, d, p, n, seed):
+    g = synth.rotated_phenom_graph(d, p)
+    s = synth.sample(g, n, seed=seed)
+    res = ce.run(exe, g, s.syndromes)
+    bad, tied = _compare(g, s.syndromes, res)
+    assert not bad, bad[:5]
+    assert tied <= 0.1 * n
+
+
+def test_cpu_engine_global_mode_and_loose_reading(exe):
+    g = synth.rotated_phenom_graph(9, 0.01)
+    s = synth.sample(g, 300, seed=13)
+    for mode, reading in ((1, 0), (0, 1)):
+        res = ce.run(exe, g, s.syndromes, mode=mode, reading=reading)
+        bad, _ = _compare(g, s.syndromes, res, mode=mode, reading="loose" if reading else "strict")
+        assert not bad, (mode, reading, bad[:5])
+
+
+def test_cpu_engine_hash_map_and_small_capacities(exe):
+    """The detector -> explored-index hash (used above 32,768 detectors) and
+    tight capacities that overflow some shots (status PSB_S_CAPACITY)."""
+    g = synth.rotated_phenom_graph(11, 0.006)
+    s = synth.sample(g, 300, seed=14)
+    res = ce.run(exe, g, s.syndromes, force_hash=True)
+    bad, _ = _compare(g, s.syndromes, res)
+    assert not bad, bad[:5]
+    small = ce.run(exe, g, s.syndromes, caps=(40, 40, 40))
+    ok = small["status"] == 0
+    assert 0 < ok.sum() < 300 and set(small["status"][~ok].tolist()) == {1}
+    for k in ("weight", "n_edges"):
+        assert np.array_equal(small[k][ok], res[k][ok])
+
+
+@pytest.mark.parametrize("model", ["uniform", "physical"])
+def test_cpu_engine_circuit_level(exe, model):
+    g = synth.rotated_circuit_graph(5, 0.004, model)
+    s = synth.sample(g, 200, seed=15)
+    res = ce.run(exe, g, s.syndromes)
+    bad, _ = _compare(g, s.syndromes, res)
+    assert not bad, bad[:5]
+
+
+def test_cpu_engine_random_graphs(exe):
+    for seed in range(3):
+        g = synth.random_graph(40, 90, 6, 1, 9, seed=seed)
+        rng = np.random.default_rng(200 + seed)
+        rows = []
+        for _ in range(80):
+            row = np.zeros(g.nbytes, np.uint8)
+            for x in rng.choice(g.num_detectors, int(rng.integers(0, 14)), replace=False):
+                row[x >> 3] |= np.uint8(1 << (x & 7))
+            rows.append(row)
+        syn = np.stack(rows)
+        # weights 1..9 need clustering searches deeper than the engine's path enumeration: global mode
+        res = ce.run(exe, g, syn, mode=1)
+        # shots with an odd event count in a boundary-free part are infeasible on both sides
+        og = oracle.Graph(g, SEED)
+        for i in range(syn.shape[0]):
+            r = og.mwem(synth.defects_of(syn[i], g.num_detectors))
+            if r.flags & oracle.OF_INFEASIBLE:
+                assert res["status"][i] == 2
+                res["status"][i] = 0; res["n_edges"][i] = len(r.edges); res["weight"][i] = r.weight
+                res["obs"][i] = r.obs; res["edges"][i, :len(r.edges)] = r.edges
+        bad, _ = _compare(g, syn, res, mode=1)
+        assert not bad, (seed, bad[:5])
+
+
+def test_cpu_engine_neighbour_table_on_the_hash_map_path(exe_nb):
+    """The single-lane engine with the per-node neighbour table switched on,
+    on a d=41 graph (35,280 detectors: the hash-map path), the combination
+    whose device results came back wrong: on the CPU, under the sanitizers,
+    every shot equals the oracle."""
+    g = synth.rotated_phenom_graph(41, 0.001)
+    s = synth.sample(g, 24, seed=51)
+    res = ce.run(exe_nb, g, s.syndromes, caps=(320, 256, 320))
+    bad, _ = _compare(g, s.syndromes, res, counts=False)
+    assert not bad, bad[:5]

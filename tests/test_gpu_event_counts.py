@@ -1,7 +1,13 @@
 """GPU event counts against the serial sparse-blossom oracle, shot by shot:
 applied flooder/matcher events, the parallel event count E_ideal (Methods,
 numerical evaluation), the number of processing clusters and the highest
-level.  Exact integer comparisons."""
+level.  Exact integer comparisons.
+
+Where two different events fall due at exactly the same time, which of them
+stay valid once the first is applied can depend on the order the two are
+taken in (the decoder and the oracle use different tie orders), and with it
+the counts: the result is still the unique MWEM.  The oracle reports such
+shots (`tied`); their counts are not compared, and they must stay rare."""
 import multiprocessing as mp
 
 import numpy as np
@@ -43,7 +49,7 @@ def _oracle_chunk(idx):
     rows = []
     for i in idx:
         r = sb.decode(synth.defects_of(syndromes[i], g.num_detectors), d, b, global_mode=(mode == 1))
-        rows.append((i, r.flags, r.events, r.e_ideal, r.clusters, r.max_level))
+        rows.append((i, r.flags, r.events, r.e_ideal, r.clusters, r.max_level, r.tied))
     return rows
 
 
@@ -81,13 +87,18 @@ def test_event_counts_equal_oracle(graph, d, p, n, seed, stride, mode):
     assert (status == 0).all()
     rows = _oracle_counts(g, s.syndromes, range(0, n, stride), mode)
     bad = []
-    for i, flags, ev, e_ideal, ncl, top in rows:
+    tied = 0
+    for i, flags, ev, e_ideal, ncl, top, t in rows:
+        if t and not flags:
+            tied += 1
+            continue
         # the final cluster carries the label of the first level whose b_k spans the graph on the GPU;
         # the plain algorithm may accept the same set of events later (same dynamics, empty levels between)
         want = (ev, e_ideal, ncl, min(top, kf) if top else 0)
         got = tuple(int(x) for x in st[i, 8:12])
         if flags or got != want:
             bad.append((i, flags, got, want))
-    say(f"compared {len(rows)} shots, {len(bad)} differ; mean events {st[:, 8].mean():.2f}, "
-        f"E_ideal {st[:, 9].mean():.2f}")
+    say(f"compared {len(rows) - tied} shots ({tied} with simultaneous events left out), {len(bad)} differ; "
+        f"mean events {st[:, 8].mean():.2f}, E_ideal {st[:, 9].mean():.2f}")
     assert not bad, bad[:8]
+    assert tied <= 0.1 * len(rows)
