@@ -151,6 +151,24 @@ int32_t psb_decode_batch(psb_decoder* d, const uint8_t* syndromes, int64_t n, in
                          int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
                          int8_t* levels, uint64_t* t_done, int32_t* stats, void* stream);
 
+/* psb_decode_batch for callers that cannot allocate device memory: code
+ * being captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, outputs and errors as psb_decode_batch; the
+ * decoder itself is created beforehand (psb_decoder_create allocates).  The
+ * call allocates nothing: the batch's work counters and the list of shots the
+ * fast tier hands to the overflow tier live in a fixed device array of
+ * (64 + PSB_NOALLOC_MAX_SHOTS) int32 (about 4 MiB) that each device holds
+ * once until the process ends, so n may be at most PSB_NOALLOC_MAX_SHOTS
+ * (PSB_E_INVALID beyond).  Every call on one device shares that array: calls
+ * whose launches overlap on a device race (serialise them on one stream), and
+ * psb_decoder_last_overflow reports the most recent launch of the decoder,
+ * whichever entry point made it.  The counters are cleared by a fill kernel
+ * at the head of each launch (no memset). */
+#define PSB_NOALLOC_MAX_SHOTS (1 << 20)
+int32_t psb_decode_batch_noalloc(psb_decoder* d, const uint8_t* syndromes, int64_t n, int32_t* edges,
+                                 int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
+                                 int8_t* levels, uint64_t* t_done, int32_t* stats, void* stream);
+
 /* Host-only: the finite-size level schedule of Methods, Algorithm "Parameter
  * schedule" (Supplementary S11) for maximum edge weight w_max and target
  * diameter bound diam, both given as (hi, lo) halves of unsigned 128-bit

@@ -75,7 +75,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         L.psb_last_error.restype = ctypes.c_char_p
         for name in ("psb_graph_create", "psb_graph_destroy", "psb_decoder_create", "psb_decoder_destroy",
-                     "psb_decode_batch", "psb_decoder_levels", "psb_decoder_edges_per_shot",
+                     "psb_decode_batch", "psb_decode_batch_noalloc", "psb_decoder_levels", "psb_decoder_edges_per_shot",
                      "psb_decoder_max_defects", "psb_graph_syndrome_bytes", "psb_schedule_levels",
                      "psb_decoder_slots", "psb_decoder_last_overflow", "psb_decoder_device_bytes", "psb_decoder_reserve",
                      "psb_server_create", "psb_server_submit", "psb_server_submit_many", "psb_server_poll", "psb_server_collect",
@@ -217,6 +217,25 @@ class Decoder:
         _check(lib().psb_decode_batch(self._h, P(syndromes), ctypes.c_int64(n), P(out.edges), P(out.n_edges),
                                       P(out.weight), P(out.obs), P(out.status), P(out.levels), P(out.t_done),
                                       P(out.stats), ctypes.c_void_p(s.cuda_stream)), "psb_decode_batch")
+        return out
+
+    def decode_into_noalloc(self, syndromes, out: Batch, stream=None) -> Batch:
+        """psb_decode_batch_noalloc on `stream`: the same decode with no device allocation in the call
+        (counters and overflow list in the library's fixed per-device array; at most PSB_NOALLOC_MAX_SHOTS)."""
+        import torch
+        if not syndromes.is_cuda or syndromes.dtype != torch.uint8 or not syndromes.is_contiguous():
+            raise PsbError("syndromes must be a contiguous uint8 CUDA tensor")
+        n = syndromes.shape[0]
+        if n and syndromes.shape[1] != self.graph.syndrome_bytes:
+            raise PsbError(f"syndrome rows must have {self.graph.syndrome_bytes} bytes")
+        if out.edges.shape[0] < n:
+            raise PsbError("output batch too small")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        P = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+        _check(lib().psb_decode_batch_noalloc(self._h, P(syndromes), ctypes.c_int64(n), P(out.edges),
+                                              P(out.n_edges), P(out.weight), P(out.obs), P(out.status),
+                                              P(out.levels), P(out.t_done), P(out.stats),
+                                              ctypes.c_void_p(s.cuda_stream)), "psb_decode_batch_noalloc")
         return out
 
     def decode(self, syndromes, levels: bool = False, timestamps: bool = False, stats: bool = False) -> Batch:

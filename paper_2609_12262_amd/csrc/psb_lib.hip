@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <queue>
 #include <string>
 #include <vector>
@@ -87,6 +88,32 @@ __global__ __launch_bounds__(64, 4) void psb_decode_kernel(Params P) {
       P.out_tdone[shot] = wall_clock64();
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free batches: the work counters and the overflow list live in
+// `scratch`, one copy per device, instead of the decoder's own buffers
+// ---------------------------------------------------------------------------
+constexpr int64_t kScratchHeader = 64;   // int32 slots before the overflow list (counters in [0..2])
+static __device__ __align__(256) int32_t scratch[kScratchHeader + PSB_NOALLOC_MAX_SHOTS];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static int32_t* g_scratch_ptr[kMaxDevices];   // device address of `scratch`, per device
+
+// Called by psb_decoder_create with the decoder's device current: the device
+// address of this device's copy of `scratch` (the array's name in host code is
+// only a host-side stand-in).
+static int32_t scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(PSB_E_UNSUPPORTED, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return PSB_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return fail(PSB_E_DEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") +
+                                                         hipGetErrorString(e));
+  g_scratch_ptr[dev] = (int32_t*)ptr;
+  return PSB_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -292,6 +319,10 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   int dev = 0, cus = 256;
   HIP_TRY(hipGetDevice(&dev));
   D->device = dev;
+  {
+    const int32_t src = scratch_setup(dev);
+    if (src != PSB_OK) { delete D; return src; }
+  }
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   int per_cu = 0, per_cu_o = 0;
   if (D->lds_fast > 160 * 1024) D->fast_enabled = false;
@@ -485,6 +516,26 @@ extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, in
   }
   return launch_batch(D, syndromes, n, edges, n_edges, weight, obs, status, levels, t_done, stats, D->d_counter,
                       D->d_ovf_list, s);
+}
+
+extern "C" int32_t psb_decode_batch_noalloc(psb_decoder* D, const uint8_t* syndromes, int64_t n, int32_t* edges,
+                                            int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
+                                            int8_t* levels, uint64_t* t_done, int32_t* stats, void* stream) {
+  const int32_t rc = check_batch_args(D, syndromes, n, edges, n_edges, weight, obs, status);
+  if (rc != PSB_OK || n == 0) return rc;
+  if (n > PSB_NOALLOC_MAX_SHOTS)
+    return fail(PSB_E_INVALID, "batch of " + std::to_string(n) + " shots exceeds the allocation-free limit of " +
+                               std::to_string((long long)PSB_NOALLOC_MAX_SHOTS));
+  int32_t* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    base = g_scratch_ptr[D->device];
+  }
+  if (!base) return fail(PSB_E_INTERNAL, "no scratch address for the decoder's device");
+  // the fill kernel at the head of the launch clears the counters; the list
+  // is written before it is read
+  return launch_batch(D, syndromes, n, edges, n_edges, weight, obs, status, levels, t_done, stats, base,
+                      base + kScratchHeader, (hipStream_t)stream);
 }
 
 struct psb_batch_graph {
