@@ -110,6 +110,14 @@ typedef struct {
    * it, and psb_decode_batch's stats rows grow to 12 fields (see there).
    * Slower; results do not depend on it.  0 = off (stats rows of 8). */
   int32_t event_accounting;
+  /* Level-1 processing clusters whose own dynamics is a single event (an
+   * adjacent pair meeting halfway before anything else, or one event meeting
+   * its boundary first) are, by default, executed concurrently in one pass,
+   * one lane per cluster, before the event loop runs the rest (Methods,
+   * Algorithm "Parallel sparse blossom").  1 = send them through the event
+   * loop one event at a time instead.  Results and event counts do not
+   * depend on it. */
+  int32_t serial_level_one;
 } psb_decoder_opts;
 
 /* Builds the decoder: tie-broken weights, level parameters d_k, b_k (exact

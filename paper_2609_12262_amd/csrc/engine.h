@@ -85,6 +85,7 @@ struct Ctx {
   int32_t *ce, *bc, *lg;
   int8_t* level;
   int32_t *uf, *cl_a, *cl_b, *cl_c, *cl_d, *bdl, *hit;
+  int32_t* cid;                      // processing cluster (root event) of each detection event
   int32_t *shr, *chg, *stk, *fin; uint32_t* ebits;
   // uniform scalars
   int nd, n_regions, n_ce, n_bc, n_log, n_shr, n_chg, stamp, status;
@@ -998,7 +999,7 @@ PSB_DEV void cluster(Ctx& c) {
       for (int i = lane(); i < nd; i += PSB_WAVE) if (c.level[i] == 0 && i < first) first = i;
       first = -wave_max(-first);
       for (int i = lane(); i < nd; i += PSB_WAVE)
-        if (c.level[i] == 0) { c.level[i] = (int8_t)(k + 1); if (c.acct) acct_cid(c)[i] = first; }
+        if (c.level[i] == 0) { c.level[i] = (int8_t)(k + 1); c.cid[i] = first; if (c.acct) acct_cid(c)[i] = first; }
       wave_sync();
       return;
     }
@@ -1152,6 +1153,7 @@ PSB_DEV void cluster(Ctx& c) {
       const int r = uf_find(c, i);
       if (atom_load(&csize[r]) == -1) {
         c.level[i] = (int8_t)(k + 1);
+        c.cid[i] = r;
         if (c.acct) acct_cid(c)[i] = r;
       }
     }
@@ -1296,6 +1298,103 @@ PSB_DEV void fuse_and_write(Ctx& c, int64_t shot) {
   c.P->out_nedges[shot] = count < stride ? count : stride;
   c.P->out_weight[shot] = wsum;
   c.P->out_obs[shot] = ob;
+}
+
+// ---------------------------------------------------------------------------
+// level-1 clusters run concurrently (Methods, Algorithm "Parallel sparse
+// blossom": the active clusters of a level execute in parallel), one lane per
+// cluster, when the cluster's own dynamics is known to be a single event:
+//  - two detection events whose joining edge e is lighter than twice every
+//    other edge at either end: the two regions (radius t at time t, no
+//    lower-level configuration exists yet) meet halfway, at t = W_e / 2,
+//    before either could enter another detector or reach the boundary, and
+//    the collision matches them (event (b)) and freezes both;
+//  - one detection event whose lightest boundary edge b is lighter than
+//    every other edge at it: the region meets the boundary at t = W_b first
+//    (event (f)) and freezes.
+// No other cluster can reach them before they stop (the clusters of a level
+// are separated by more than b_1, and a level-1 cluster stops by d_1).  The
+// pass leaves exactly the state the event loop would leave: radii, matches,
+// one leaf compressed edge, empty event caches; its event is charged to the
+// cluster.  Every other level-1 cluster stays in the event loop.
+// ---------------------------------------------------------------------------
+PSB_DEV void level_one_direct(Ctx& c) {
+  const int nd = c.nd, deg = c.deg;
+  int32_t* size = c.cl_c;      // per cluster root: level-1 members
+  int32_t* other = c.cl_d;     // per cluster root: a member other than the root
+  wave_sync();
+  for (int i = lane(); i < nd; i += PSB_WAVE) { size[i] = 0; other[i] = -1; }
+  wave_sync();
+  for (int i = lane(); i < nd; i += PSB_WAVE) {
+    if (c.level[i] != 1) continue;
+    atom_add(&size[c.cid[i]], 1);
+    if (c.cid[i] != i) atom_xchg((unsigned*)&other[c.cid[i]], (unsigned)i);
+  }
+  wave_sync();
+  const int ce0 = c.n_ce;
+  int n_new = 0;
+  for (int i0 = 0; i0 < nd; i0 += PSB_WAVE) {
+    const int r = i0 + lane();
+    int kind = 0, v = -1, e = -1;     // kind 1: pair (r, v) through edge e; kind 2: boundary edge e
+    i128 t = 0;
+    if (r < nd && c.level[r] == 1 && c.cid[r] == r) {
+      const int64_t ru = (int64_t)c.x_node[r] * deg;
+      if (size[r] == 2) {
+        v = other[r];
+        const int dv = c.x_node[v];
+        int je = -1;
+        for (int j = 0; j < deg; ++j)
+          if (c.nbr[ru + j] == dv && (je < 0 || c.wt[ru + j] < c.wt[ru + je])) je = j;
+        if (je >= 0) {
+          const i128 We = c.wt[ru + je];
+          bool ok = true;
+          const int64_t rv = (int64_t)dv * deg;
+          for (int j = 0; j < deg && ok; ++j) {
+            if (j != je && c.nbr[ru + j] != NB_PAD && 2 * c.wt[ru + j] <= We) ok = false;
+            if (c.nbr[rv + j] != NB_PAD && c.eid[rv + j] != c.eid[ru + je] && 2 * c.wt[rv + j] <= We) ok = false;
+          }
+          if (ok) { kind = 1; e = c.eid[ru + je]; t = We >> 1; }
+        }
+      } else if (size[r] == 1) {
+        int jb = -1;
+        for (int j = 0; j < deg; ++j)
+          if (c.nbr[ru + j] == NB_BOUNDARY && (jb < 0 || c.wt[ru + j] < c.wt[ru + jb])) jb = j;
+        if (jb >= 0) {
+          bool ok = true;
+          for (int j = 0; j < deg && ok; ++j)
+            if (c.nbr[ru + j] >= 0 && c.wt[ru + j] <= c.wt[ru + jb]) ok = false;
+          if (ok) { kind = 2; e = c.eid[ru + jb]; t = c.wt[ru + jb]; }
+        }
+      }
+    }
+    const uint64_t mask = ballot(kind != 0);
+    if (kind) {
+      const int ce = ce0 + n_new + (int)__builtin_popcountll(mask & lanemask_lt());
+      if (ce < c.P->cecap) {
+        CEF(c, ce, CE_E) = e; CEF(c, ce, CE_A) = c.x_rec[r]; CEF(c, ce, CE_SA) = r;
+        CEF(c, ce, CE_B) = kind == 1 ? c.x_rec[v] : -1; CEF(c, ce, CE_SB) = kind == 1 ? v : -1;
+        c.r_base[r] = t; RF(c, r, RF_RATE) = 0; RF(c, r, RF_TID) = -1; RF(c, r, RF_TPAR) = -1;
+        RF(c, r, RF_MATE) = kind == 1 ? v : MATE_BOUNDARY; RF(c, r, RF_ME) = ce;
+        c.x_ev[r] = T_INF;
+        if (kind == 1) {
+          c.r_base[v] = t; RF(c, v, RF_RATE) = 0; RF(c, v, RF_TID) = -1; RF(c, v, RF_TPAR) = -1;
+          RF(c, v, RF_MATE) = r; RF(c, v, RF_ME) = ce;
+          c.x_ev[v] = T_INF;
+        }
+        if (c.acct) {
+          // one event of cluster r at time t > 0 = t_<1
+          acct_cnt(c)[r] = 1; acct_early_n(c)[r] = 0; acct_lastt(c)[r] = t;
+        }
+      }
+    }
+    n_new += (int)__builtin_popcountll(mask);
+  }
+  n_new = uni(n_new);
+  wave_sync();
+  if (ce0 + n_new > c.P->cecap) { cap_fail(c); return; }
+  c.n_ce = ce0 + n_new;
+  if (c.acct) acct_hdr(c)[0] = uni(acct_hdr(c)[0]) + n_new;
+  wave_sync();
 }
 
 // ---------------------------------------------------------------------------
@@ -1465,6 +1564,7 @@ PSB_DEV int decode_shot(Ctx& c, int64_t shot) {
     c.now = 0;       // every level starts its clock at zero; stopped regions are frozen
     if (c.acct) account_level_start(c, lvl);
     seed_level(c, lvl);
+    if (lvl == 1 && c.P->mode == 0 && c.P->direct1) level_one_direct(c);
 #ifdef PSB_CHECK_INVARIANTS
     c.dbg_lvl = lvl;
 #endif
@@ -1527,6 +1627,7 @@ PSB_DEV void ctx_init(Ctx& c, const Params* P, Lds* S, char* state, int64_t slot
   c.level = (int8_t*)(base + L.level);
   c.uf = (int32_t*)(base + L.uf); c.cl_a = (int32_t*)(base + L.cl_a); c.cl_b = (int32_t*)(base + L.cl_b);
   c.cl_c = (int32_t*)(base + L.cl_c); c.cl_d = (int32_t*)(base + L.cl_d);
+  c.cid = (int32_t*)(base + L.cid);
   c.bdl = (int32_t*)(base + L.bdl); c.hit = (int32_t*)(base + L.hit);
   c.shr = (int32_t*)(base + L.shr); c.chg = (int32_t*)(base + L.chg); c.stk = (int32_t*)(base + L.stk);
   c.fin = (int32_t*)(base + L.fin); c.ebits = (uint32_t*)(base + L.ebits);

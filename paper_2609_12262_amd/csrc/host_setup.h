@@ -232,6 +232,7 @@ static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const 
   L.ce = take(4LL * psb::CE_COUNT * P.cecap); L.bc = take(8LL * P.bccap); L.lg = take(12LL * P.lcap);
   L.level = take(d); L.uf = take(4LL * d);
   L.cl_a = take(4LL * d); L.cl_b = take(4LL * d); L.cl_c = take(4LL * d); L.cl_d = take(4LL * d);
+  L.cid = take(4LL * d);
   L.bdl = take(4LL * d * P.bdc); L.hit = take(4LL * (lane_slot ? 1 : 64) * P.hitcap * 2);
   L.shr = take(4LL * P.shrcap); L.chg = take(4LL * cap.xcap); L.stk = take(4LL * P.stkcap);
   L.fin = take(4LL * P.fincap); L.ebits = take(4 * ((n_edges + 31) / 32 + 1));

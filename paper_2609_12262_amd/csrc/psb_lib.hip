@@ -271,6 +271,7 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   if (opts.first_tier != 0 && opts.first_tier != 1) { delete D; return fail(PSB_E_INVALID, "first_tier must be 0 or 1"); }
   if (opts.fast_lds_state < 0 || opts.fast_lds_state > 3) { delete D; return fail(PSB_E_INVALID, "fast_lds_state must be 0..3"); }
   if (opts.event_accounting != 0 && opts.event_accounting != 1) { delete D; return fail(PSB_E_INVALID, "event_accounting must be 0 or 1"); }
+  if (opts.serial_level_one != 0 && opts.serial_level_one != 1) { delete D; return fail(PSB_E_INVALID, "serial_level_one must be 0 or 1"); }
   const bool acct = opts.event_accounting == 1;
   D->acct = acct;
   D->first_lane = opts.first_tier == 1;
@@ -298,6 +299,7 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   for (Params* P : {&PF, &PO}) {
     P->n_levels = (int32_t)D->sched.d.size(); P->reading = opts.boundary_reading; P->mode = opts.mode;
     P->edge_stride = stride;
+    P->direct1 = opts.serial_level_one ? 0 : 1;
   }
   PF.tier = 0; PO.tier = 1;
   for (const Params* P : {&PF, &PO}) {

@@ -35,6 +35,7 @@ struct WsLayout {
   int64_t state;                                 // lane tier: Lds header + StateLayout block; else unused
   int64_t ce, bc, lg;                            // compressed edges, blossom cycles, arrival log
   int64_t level, uf, cl_a, cl_b, cl_c, cl_d, bdl, hit;   // clustering
+  int64_t cid;                                   // processing cluster of each detection event (its root event)
   int64_t shr, chg, stk, fin, ebits;             // scratch lists, edge bitmap
   int64_t dmap;                                  // detector -> explored index [n_det] int16, -1 absent
                                                  // (only when the state block has no hash)
@@ -105,6 +106,7 @@ struct Params {
   Caps cap;
   int32_t cecap, bccap, lcap, shrcap, stkcap, fincap, hitcap, bdc;
   int64_t max_events;
+  int32_t direct1, pad1;                         // level-1 clusters of one known event applied directly
   // batch
   int64_t n_shots;
   const uint8_t* synd;

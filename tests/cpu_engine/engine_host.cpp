@@ -5,7 +5,7 @@
 // g++ and the address / undefined-behaviour sanitizers; not part of the
 // library.
 //
-// usage: engine_host <dir> <seed> <mode> <reading> <xcap> <rcap> <dcap> <hash>
+// usage: engine_host <dir> <seed> <mode> <reading> <xcap> <rcap> <dcap> <hash> <direct1>
 //   <dir>/graph.bin : int32 n, int64 m, int32 u[m], int32 v[m], int32 w[m], uint64 obs[m]
 //   <dir>/synd.bin  : int64 shots, int32 bytes per row, uint8 rows[shots][bytes]
 // writes <dir>/out.bin: per shot int32 status, int32 n_edges, int64 weight,
@@ -39,7 +39,7 @@ void psb_invariant_failed(const char* what, int64_t shot, int level) {
 template <class T> static bool rd(FILE* f, T* p, size_t n) { return fread(p, sizeof(T), n, f) == n; }
 
 int main(int argc, char** argv) {
-  if (argc != 9) { fprintf(stderr, "usage: engine_host dir seed mode reading xcap rcap dcap hash\n"); return 2; }
+  if (argc != 10) { fprintf(stderr, "usage: engine_host dir seed mode reading xcap rcap dcap hash direct1\n"); return 2; }
   const std::string dir = argv[1];
   const uint64_t seed = strtoull(argv[2], nullptr, 0);
   const int mode = atoi(argv[3]), reading = atoi(argv[4]);
@@ -90,7 +90,7 @@ int main(int argc, char** argv) {
   memset(&P, 0, sizeof(P));
   psb_host::plan_tier(P, n, deg, m, cap, /*lane_slot=*/true, 0, /*acct=*/true, /*lane_nb_table=*/PSB_NB_TABLE);
   P.nbr = ell.nbr.data(); P.eid = ell.eid.data(); P.wt = ell_w.data(); P.w = w.data(); P.obs = obs.data();
-  P.n_levels = (int32_t)S.d.size(); P.reading = reading; P.mode = mode; P.tier = 1;
+  P.n_levels = (int32_t)S.d.size(); P.reading = reading; P.mode = mode; P.tier = 1; P.direct1 = atoi(argv[9]);
   P.sd = sd.data(); P.sb = sb.data(); P.shmax = hmax.data();
 
   FILE* fs = fopen((dir + "/synd.bin").c_str(), "rb");

@@ -23,7 +23,8 @@ def build(out_dir, sanitize=True, nb_table=False):
     return exe
 
 
-def run(exe, g, syndromes, seed=0x5EED, mode=0, reading=0, caps=(1024, 768, 512), force_hash=False, log=None):
+def run(exe, g, syndromes, seed=0x5EED, mode=0, reading=0, caps=(1024, 768, 512), force_hash=False, log=None,
+        direct1=True):
     """Decodes every row of `syndromes`; returns dict of arrays (status, n_edges, weight, obs, stats, edges).
     `log`: file name that receives the program's standard error."""
     with tempfile.TemporaryDirectory() as d:
@@ -37,7 +38,8 @@ def run(exe, g, syndromes, seed=0x5EED, mode=0, reading=0, caps=(1024, 768, 512)
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                    UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
         r = subprocess.run([exe, d, str(seed), str(mode), str(reading), *[str(x) for x in caps],
-                            "1" if force_hash else "0"], capture_output=True, text=True, env=env)
+                            "1" if force_hash else "0", "1" if direct1 else "0"], capture_output=True, text=True,
+                           env=env)
         if log:
             with open(log, "w") as fh:
                 fh.write(r.stderr)

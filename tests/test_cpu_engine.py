@@ -132,3 +132,24 @@ def test_cpu_engine_neighbour_table_on_the_hash_map_path(exe_nb):
     res = ce.run(exe_nb, g, s.syndromes, caps=(320, 256, 320))
     bad, _ = _compare(g, s.syndromes, res, counts=False)
     assert not bad, bad[:5]
+
+
+@pytest.mark.parametrize("graph,d,p,n,seed", [("phenom", 21, 0.005, 40, 3), ("phenom", 11, 0.003, 600, 2),
+                                              ("phenom", 9, 0.03, 200, 7), ("circuit_uniform", 7, 0.003, 200, 16),
+                                              ("circuit_physical", 7, 0.004, 200, 17)])
+def test_cpu_engine_direct_level_one_equals_event_loop(exe, graph, d, p, n, seed):
+    """Level-1 clusters applied in one concurrent pass leave the same state as
+    the event loop: same results, same applied events, same E_ideal, same
+    clusters; and both equal the oracles."""
+    g = (synth.rotated_phenom_graph(d, p) if graph == "phenom"
+         else synth.rotated_circuit_graph(d, p, graph.split("_")[1]))
+    s = synth.sample(g, n, seed=seed)
+    a = ce.run(exe, g, s.syndromes, direct1=True)
+    b = ce.run(exe, g, s.syndromes, direct1=False)
+    for k in ("status", "n_edges", "weight", "obs"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["stats"][:, 8:12], b["stats"][:, 8:12])
+    # the pass takes loop iterations away (stats[:, 0] counts them)
+    assert a["stats"][:, 0].sum() < b["stats"][:, 0].sum()
+    bad, tied = _compare(g, s.syndromes, a)
+    assert not bad, bad[:5]

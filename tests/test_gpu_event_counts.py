@@ -102,3 +102,34 @@ def test_event_counts_equal_oracle(graph, d, p, n, seed, stride, mode):
         f"mean events {st[:, 8].mean():.2f}, E_ideal {st[:, 9].mean():.2f}")
     assert not bad, bad[:8]
     assert tied <= 0.1 * len(rows)
+
+
+@pytest.mark.parametrize("d,p,n,seed", [(21, 0.005, 4096, 3), (21, 0.001, 4096, 4), (51, 0.001, 64, 61),
+                                        (9, 0.03, 2000, 7)])
+def test_direct_level_one_equals_event_loop(d, p, n, seed):
+    """Level-1 clusters applied in one concurrent pass, against the same
+    clusters sent through the event loop: every output and every event count
+    (applied events, E_ideal, clusters, highest level) identical."""
+    import torch
+    import paper_2609_12262_amd as psb
+    g = synth.rotated_phenom_graph(d, p)
+    s = synth.sample(g, n, seed=seed)
+    G = psb.Graph.from_synth(g)
+    S = torch.from_numpy(s.syndromes).cuda()
+    outs = []
+    for serial in (0, 1):
+        dec = psb.Decoder(G, tiebreak_seed=SEED, event_accounting=1, serial_level_one=serial)
+        out = dec.decode(S, stats=True)
+        torch.cuda.synchronize()
+        h = {k: getattr(out, k).cpu().numpy() for k in ("n_edges", "weight", "obs", "status", "stats")}
+        e = out.edges.cpu().numpy()
+        h["edges"] = np.where(np.arange(e.shape[1])[None, :] < h["n_edges"][:, None], e, -1)
+        outs.append(h)
+        dec.close()
+    G.close()
+    a, b = outs
+    for k in ("edges", "n_edges", "weight", "obs", "status"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["stats"][:, 8:12], b["stats"][:, 8:12])
+    say(f"d={d} p={p}: loop iterations per shot {a['stats'][:, 0].mean():.1f} (direct) vs "
+        f"{b['stats'][:, 0].mean():.1f} (event loop only)")
