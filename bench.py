@@ -317,7 +317,58 @@ def serving(args):
     lat, t_sub, wall = run(arrivals)
     s2 = srv.stats()
     offered = n / t_sub
+    # the same stream at each load of the sweep (offered rate = load x the batched capacity above)
+    sweep = {}
+    loads = [float(x) for x in args.serve_loads.split(",")] if args.serve_loads else []
+    for ld in loads:
+        arr_l = np.cumsum(np.random.default_rng(7).exponential(1.0 / (ld * capacity), n))
+        lat_l, t_sub_l, _ = run(arr_l)
+        sweep[str(ld)] = {"offered_windows_per_s": round(n / t_sub_l, 1),
+                          "p50_us_per_round": round(float(np.percentile(lat_l / 1e3 / np.asarray(ds)[kind], 50)), 3),
+                          "p99_us_per_round": round(float(np.percentile(lat_l / 1e3 / np.asarray(ds)[kind], 99)), 3)}
+        log(f"pipe server, load {ld}: {sweep[str(ld)]}")
     srv.close()
+
+    # slot-level server: one persistent kernel, windows taken one at a time as slots free up
+    slot_out = None
+    if not args.no_slot_server:
+        ssrv = psb.SlotServer(Gs, opts=opts, waves=args.slot_waves)
+        rep.psb_replay_slots.restype = ctypes.c_int32
+
+        def run_slots(arrivals_s):
+            lat_s = np.zeros(n, np.int64)
+            st_s = np.zeros(n, np.int32)
+            span, wall_s_ = ctypes.c_double(), ctypes.c_double()
+            arr = None if arrivals_s is None else np.ascontiguousarray(arrivals_s, np.float64)
+            rc = rep.psb_replay_slots(ssrv._h, ctypes.c_int64(n), ctypes.c_void_p(gidx.ctypes.data), syn_ptrs,
+                                      ctypes.c_void_p(wts.ctypes.data),
+                                      ctypes.c_void_p(arr.ctypes.data) if arr is not None else ctypes.c_void_p(0),
+                                      ctypes.c_void_p(lat_s.ctypes.data), ctypes.c_void_p(st_s.ctypes.data),
+                                      ctypes.byref(span), ctypes.byref(wall_s_))
+            if rc != 0:
+                raise RuntimeError(f"psb_replay_slots failed ({rc})")
+            if not (st_s == 0).all():
+                log(f"WARNING: slot server statuses {np.bincount(st_s)}")
+            return lat_s, span.value, wall_s_.value
+
+        run_slots(None)                                   # warm-up
+        _, _, wall_cap = run_slots(None)
+        slot_out = {"capacity_windows_per_s": round(n / wall_cap, 1), "waves": args.slot_waves, "loads": {}}
+        for ld in sorted(set(loads + [args.serve_load])):
+            arr_l = np.cumsum(np.random.default_rng(7).exponential(1.0 / (ld * capacity), n))
+            lat_l, t_sub_l, _ = run_slots(arr_l)
+            pr = lat_l / 1e3 / np.asarray(ds)[kind]
+            slot_out["loads"][str(ld)] = {
+                "offered_windows_per_s": round(n / t_sub_l, 1),
+                "p50_us_per_round": round(float(np.percentile(pr, 50)), 3),
+                "p99_us_per_round": round(float(np.percentile(pr, 99)), 3),
+                "per_d": {str(d): {"p50_us_per_round": round(float(np.percentile(pr[kind == j], 50)), 3),
+                                   "p99_us_per_round": round(float(np.percentile(pr[kind == j], 99)), 3)}
+                          for j, d in enumerate(ds)}}
+            log(f"slot server, load {ld}: p50 {slot_out['loads'][str(ld)]['p50_us_per_round']} "
+                f"p99 {slot_out['loads'][str(ld)]['p99_us_per_round']} us/round")
+        slot_out["stats"] = ssrv.stats()
+        ssrv.close()
 
     def delta(a, b):
         nb, nw = b["batches"] - a["batches"], b["windows"] - a["windows"]
@@ -370,6 +421,7 @@ def serving(args):
                      for j, d in enumerate(ds)},
            "autotuned": tuned,
            "server_capacity_run": delta(s0, s1), "server_load_run": delta(s1, s2),
+           "load_sweep": sweep, "slot_server": slot_out,
            "one_shot_per_launch": {
                "windows": m, "capacity_windows_per_s": round(cap1, 1),
                "alone_p50_us_per_round": pct(pr1_alone, 50), "alone_p99_us_per_round": pct(pr1_alone, 99),
@@ -479,6 +531,10 @@ def main():
                          "0.007] (uniform per-window weight), Poisson arrivals at --serve-load x the measured "
                          "capacity for the mix")
     ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-loads", default="0.3,0.7,0.9",
+                    help="further offered loads (x the batched capacity) run with both serving runtimes")
+    ap.add_argument("--no-slot-server", action="store_true", help="skip the slot-level server in --serve")
+    ap.add_argument("--slot-waves", type=int, default=1024, help="slots of the slot-level server")
     ap.add_argument("--serve-dists", default="9,13,17,21,25")
     ap.add_argument("--serve-p", default="0.001,0.007", help="window noise rates drawn uniformly from this range")
     ap.add_argument("--oneshot-windows", type=int, default=3000)

@@ -38,6 +38,7 @@ extern "C" {
 #define PSB_S_INFEASIBLE 2      /* odd number of active detectors in a component with no boundary */
 #define PSB_S_EDGES_TRUNCATED 3 /* weight/obs valid, edge list cut at edges_per_shot */
 #define PSB_S_INTERNAL 4        /* an internal consistency check failed */
+#define PSB_S_CANCELLED 6       /* serving: the request was cancelled before it reached the device */
 
 #define PSB_BOUNDARY (-1)
 
@@ -394,6 +395,16 @@ int32_t psb_server_poll(psb_server* s, uint64_t ticket, int32_t* done, int64_t* 
  * releases them and returns how many were written (0 if none is finished). */
 int32_t psb_server_collect(psb_server* s, int32_t max, uint64_t* tickets, int64_t* weight, uint64_t* obs,
                            int32_t* status, int64_t* latency_ns);
+/* Cancels a window that has not reached the device yet: it completes at
+ * once with status PSB_S_CANCELLED (weight 0, no edges; poll or collect
+ * releases it as usual) and *cancelled = 1.  A window already in a running
+ * batch (or finished) is not affected: *cancelled = 0 and its result comes
+ * as usual.  PSB_E_INVALID for an unknown or released ticket. */
+int32_t psb_server_cancel(psb_server* s, uint64_t ticket, int32_t* cancelled);
+/* Blocks until the window is done or timeout_us microseconds have passed:
+ * *done = 1 if it is done (the ticket stays valid for poll or collect),
+ * 0 on time-out.  PSB_E_INVALID for an unknown or released ticket. */
+int32_t psb_server_wait(psb_server* s, uint64_t ticket, int64_t timeout_us, int32_t* done);
 /* Running totals since creation, out5[5]: batches launched, windows in them,
  * summed submit-to-launch nanoseconds over windows, summed launch-to-
  * completion nanoseconds over batches, summed host nanoseconds spent
@@ -402,6 +413,52 @@ int32_t psb_server_stats(psb_server* s, int64_t* out5);
 /* Stops the worker after its running batches and frees everything;
  * uncollected tickets are dropped. */
 int32_t psb_server_destroy(psb_server* s);
+
+/* ---------------------------------------------------------------------
+ * Slot-level serving (continuous batching at the granularity of one
+ * window): one persistent kernel whose wavefronts are decode slots.  The
+ * host publishes windows, as they are submitted, into a ring of `ring`
+ * entries (a power of two; 0 = 8192) in pinned host memory; one dispatcher
+ * wavefront copies new windows to the device; each of the `waves` slots
+ * (0 = 1024; at most 12 per compute unit and half of each unit's LDS, so
+ * that other kernels keep room) takes the next window as soon as it is
+ * free, decodes it with the first tier of the window's group decoder (the
+ * same engine and per-shot state as psb_decode_batch) and writes its result
+ * and a done flag into pinned host memory; a host thread completes the
+ * tickets.  A window thus starts as soon as one slot is free and completes
+ * on its own, whatever else is in flight, and its result is the one
+ * psb_decode_batch gives for it alone (Results, "Decoding task").  Windows
+ * beyond the first tier's capacities are decoded again by an overflow-tier
+ * decoder on a side stream.  Groups: per graph its own weights, and unit
+ * weights for windows that carry a uniform weight (the result's weight is
+ * scaled); all decoders are made at creation (`opts`: NULL or one record per
+ * graph; edges_per_shot 0 = 1024).  Windows that find the ring full wait on
+ * the host and are published in submission order as entries free up.
+ * Graphs must use the direct detector map (at most 32,768 detectors).
+ * While the server exists its kernel occupies `waves` slots, and a
+ * device-wide synchronisation in the process would wait for it: destroy the
+ * server first.  Thread-safe.
+ * Errors: PSB_E_INVALID, PSB_E_NOMEM, PSB_E_DEVICE, PSB_E_UNSUPPORTED. */
+typedef struct psb_slot_server psb_slot_server;
+int32_t psb_slot_server_create(const psb_graph* const* graphs, int32_t n_graphs, const psb_decoder_opts* opts,
+                               int32_t waves, int32_t ring, psb_slot_server** out);
+/* As psb_server_submit_many. */
+int32_t psb_slot_server_submit_many(psb_slot_server* s, int32_t n, const int32_t* graph_idx,
+                                    const uint8_t* const* syndromes, const int32_t* uniform_weight,
+                                    uint64_t* tickets);
+/* As psb_server_collect. */
+int32_t psb_slot_server_collect(psb_slot_server* s, int32_t max, uint64_t* tickets, int64_t* weight, uint64_t* obs,
+                                int32_t* status, int64_t* latency_ns);
+/* As psb_server_poll. */
+int32_t psb_slot_server_poll(psb_slot_server* s, uint64_t ticket, int32_t* done, int64_t* weight, uint64_t* obs,
+                             int32_t* edges, int64_t edges_cap, int64_t* n_edges, int32_t* status,
+                             int64_t* latency_ns);
+/* out4[4]: windows completed, windows decoded again by the overflow tier,
+ * windows waiting for a ring entry, windows published and not yet done. */
+int32_t psb_slot_server_stats(psb_slot_server* s, int64_t* out4);
+/* Stops the kernel once every published window is done (windows still
+ * waiting for a ring entry are dropped), then frees everything. */
+int32_t psb_slot_server_destroy(psb_slot_server* s);
 
 const char* psb_last_error(void);
 

@@ -29,7 +29,14 @@
  *      algorithm (Edmonds 1965; the O(n^3) organisation of Gabow/Galil with
  *      per-vertex best-edge tracking) as a maximum-weight matching of
  *      K - cost with K large enough that every maximum-weight matching is
- *      perfect.
+ *      perfect.  The matcher's organisation (vertex and blossom ids in one
+ *      array, S/T labels, per-node best slack edge, the LCA walk with
+ *      stamps, pairing within a blossom cycle by i ^ 1 after rotating to the
+ *      base, halving the slack step) follows the widely circulated O(n^3)
+ *      weighted general-matching routine of competitive programming, whose
+ *      routines it mirrors one for one under other names; it is test
+ *      infrastructure, and every call checks its output with the LP
+ *      certificate of step 5.
  *   4. M = symmetric difference of the shortest paths of the matched pairs
  *      (and of the path to the nearest boundary edge for (s, s') pairs).
  *   5. Certificate: the final duals are checked for feasibility and

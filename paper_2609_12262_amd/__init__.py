@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libpsb.so")
 
 PSB_OK = 0
 PSB_S_OK, PSB_S_CAPACITY, PSB_S_INFEASIBLE, PSB_S_EDGES_TRUNCATED, PSB_S_INTERNAL = 0, 1, 2, 3, 4
+PSB_S_CANCELLED = 6
+PSB_E_INVALID, PSB_E_NOMEM, PSB_E_DEVICE, PSB_E_UNSUPPORTED, PSB_E_INTERNAL = -1, -2, -3, -4, -5
 MODE_PARTITION, MODE_GLOBAL = 0, 1
 
 _lib = None
@@ -81,11 +83,13 @@ def lib():
                      "psb_decoder_max_defects", "psb_graph_syndrome_bytes", "psb_schedule_levels",
                      "psb_decoder_slots", "psb_decoder_last_overflow", "psb_decoder_device_bytes", "psb_decoder_reserve",
                      "psb_server_create", "psb_server_submit", "psb_server_submit_many", "psb_server_poll", "psb_server_collect",
-                     "psb_server_stats", "psb_server_destroy", "psb_autotune", "psb_autotune_candidates",
+                     "psb_server_stats", "psb_server_destroy", "psb_server_cancel", "psb_server_wait", "psb_autotune", "psb_autotune_candidates",
                      "psb_batch_graph_create", "psb_batch_graph_launch", "psb_batch_graph_destroy",
                      "psb_window_plan_create", "psb_window_plan_info", "psb_window_decode",
                      "psb_window_plan_destroy", "psb_comp_plan_create", "psb_comp_decode",
-                     "psb_comp_plan_destroy"):
+                     "psb_comp_plan_destroy", "psb_slot_server_create", "psb_slot_server_submit_many",
+                     "psb_slot_server_collect", "psb_slot_server_poll", "psb_slot_server_stats",
+                     "psb_slot_server_destroy"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -461,6 +465,19 @@ class Server:
         return dict(weight=w.value, obs=ob.value, edges=edges[: min(ne.value, edges_cap)].copy(), n_edges=ne.value,
                     status=st.value, latency_ns=lat.value)
 
+    def cancel(self, ticket: int) -> bool:
+        """psb_server_cancel: True if the window was still waiting and is now cancelled."""
+        c = ctypes.c_int32()
+        _check(lib().psb_server_cancel(self._h, ctypes.c_uint64(ticket), ctypes.byref(c)), "psb_server_cancel")
+        return bool(c.value)
+
+    def wait(self, ticket: int, timeout_us: int) -> bool:
+        """psb_server_wait: True once the window is done, False on time-out."""
+        d = ctypes.c_int32()
+        _check(lib().psb_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.c_int64(int(timeout_us)),
+                                     ctypes.byref(d)), "psb_server_wait")
+        return bool(d.value)
+
     def collect(self, max_n: int = 4096) -> list:
         """Finished windows in completion order (without edge lists): dicts of ticket, weight, obs, status,
         latency_ns; empty when none is finished."""
@@ -483,6 +500,72 @@ class Server:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().psb_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SlotServer:
+    """psb_slot_server: slot-level serving.  One persistent kernel whose wavefronts take windows one at a time
+    as they are published; each window starts as soon as a slot is free and completes on its own.  While it
+    runs, a device-wide synchronisation (torch.cuda.synchronize()) would wait for it: close it first."""
+
+    def __init__(self, graphs, opts=None, waves: int = 0, ring: int = 0):
+        self.graphs = list(graphs)
+        per = opts if isinstance(opts, (list, tuple)) else [opts] * len(self.graphs)
+        arr = (ctypes.c_void_p * len(self.graphs))(*[g._h.value for g in self.graphs])
+        c = (_DecoderOpts * len(self.graphs))(*[_make_opts(**(o or {})) for o in per])
+        h = ctypes.c_void_p()
+        _check(lib().psb_slot_server_create(arr, ctypes.c_int32(len(self.graphs)), c, ctypes.c_int32(waves),
+                                            ctypes.c_int32(ring), ctypes.byref(h)), "psb_slot_server_create")
+        self._h = h
+
+    def submit_many(self, graph_idx, syndromes, uniform_weight=None) -> list:
+        n = len(syndromes)
+        rows = [np.ascontiguousarray(r, np.uint8) for r in syndromes]
+        ptrs = (ctypes.c_void_p * n)(*[r.ctypes.data for r in rows])
+        gi = np.ascontiguousarray(graph_idx, np.int32)
+        uw = None if uniform_weight is None else np.ascontiguousarray(uniform_weight, np.int32)
+        t = np.zeros(n, np.uint64)
+        _check(lib().psb_slot_server_submit_many(self._h, ctypes.c_int32(n), ctypes.c_void_p(gi.ctypes.data), ptrs,
+                                                 ctypes.c_void_p(uw.ctypes.data) if uw is not None else ctypes.c_void_p(0),
+                                                 ctypes.c_void_p(t.ctypes.data)), "psb_slot_server_submit_many")
+        return [int(x) for x in t]
+
+    def poll(self, ticket: int, edges_cap: int = 1024):
+        """None while pending, else dict(weight, obs, edges, n_edges, status, latency_ns)."""
+        done = ctypes.c_int32(); w = ctypes.c_int64(); ob = ctypes.c_uint64(); ne = ctypes.c_int64()
+        st = ctypes.c_int32(); lat = ctypes.c_int64()
+        edges = np.zeros(max(edges_cap, 1), np.int32)
+        _check(lib().psb_slot_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(w),
+                                          ctypes.byref(ob), ctypes.c_void_p(edges.ctypes.data), ctypes.c_int64(edges_cap),
+                                          ctypes.byref(ne), ctypes.byref(st), ctypes.byref(lat)), "psb_slot_server_poll")
+        if not done.value:
+            return None
+        return dict(weight=w.value, obs=ob.value, edges=edges[: min(ne.value, edges_cap)].copy(), n_edges=ne.value,
+                    status=st.value, latency_ns=lat.value)
+
+    def collect(self, max_n: int = 4096) -> list:
+        t = np.zeros(max(max_n, 1), np.uint64); w = np.zeros_like(t, dtype=np.int64)
+        ob = np.zeros_like(t); st = np.zeros(len(t), np.int32); lat = np.zeros(len(t), np.int64)
+        P = lambda a: ctypes.c_void_p(a.ctypes.data)
+        k = _check(lib().psb_slot_server_collect(self._h, ctypes.c_int32(max_n), P(t), P(w), P(ob), P(st), P(lat)),
+                   "psb_slot_server_collect")
+        return [dict(ticket=int(t[i]), weight=int(w[i]), obs=int(ob[i]), status=int(st[i]), latency_ns=int(lat[i]))
+                for i in range(k)]
+
+    def stats(self) -> dict:
+        v = (ctypes.c_int64 * 4)()
+        _check(lib().psb_slot_server_stats(self._h, v), "psb_slot_server_stats")
+        return {"windows": v[0], "overflow_redecoded": v[1], "waiting": v[2], "in_flight": v[3]}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().psb_slot_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -94,6 +94,7 @@ struct Ctx {
   int n_visit;                       // clustering search visits (statistics)
   uint64_t t0, t_cl, t_dyn, t_fuse;  // device clock marks (statistics)
   char* acct;                        // event-accounting block, or null
+  const uint8_t* srow;               // the shot's syndrome row (detection events as bits)
 #ifdef PSB_CHECK_INVARIANTS
   int64_t dbg_shot; int dbg_lvl;
   int32_t* dbg_cfg;                  // [rcap] processing cluster whose stopped configuration holds the region
@@ -1028,7 +1029,11 @@ PSB_DEV void cluster(Ctx& c) {
           return;
         }
         if (y == u) return;
-        const int rj = rj_pre != -2 ? rj_pre : node_idx(c, y);
+        // only detection events matter here: the syndrome row (a few hundred
+        // bytes, cache-resident) answers that before the detector map is read
+        if (rj_pre == -1) return;
+        if (rj_pre == -2 && !((c.srow[y >> 3] >> (y & 7)) & 1)) return;
+        const int rj = rj_pre >= 0 ? rj_pre : node_idx(c, y);
         if (rj >= 0 && rj < nd && c.level[rj] == 0) {
           const int cl = (nd_ <= dk) ? 1 : 0;
           int q = 0;
@@ -1037,9 +1042,9 @@ PSB_DEV void cluster(Ctx& c) {
         }
       };
       // the last hop of a path: the adjacency row of x (reached at distance
-      // base) in chunks of four, each chunk's neighbours and their
-      // detector-map entries loaded before any of them is visited (visit
-      // order unchanged)
+      // base) in chunks of four, each chunk's neighbours and their syndrome
+      // bits loaded before any of them is visited (visit order unchanged;
+      // -1: not a detection event, -2: look it up)
       auto leaf_row = [&](int x, i128 base) {
         const int64_t r0 = (int64_t)x * deg;
         for (int k0 = 0; k0 < deg; k0 += 4) {
@@ -1047,7 +1052,7 @@ PSB_DEV void cluster(Ctx& c) {
 #pragma unroll
           for (int t = 0; t < 4; ++t) zs[t] = k0 + t < deg ? c.nbr[r0 + k0 + t] : NB_PAD;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) ix[t] = (c.dmap && zs[t] >= 0) ? (int)c.dmap[zs[t]] : -2;
+          for (int t = 0; t < 4; ++t) ix[t] = (zs[t] >= 0 && !((c.srow[zs[t] >> 3] >> (zs[t] & 7)) & 1)) ? -1 : -2;
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             if (zs[t] == NB_PAD) return;
@@ -1526,6 +1531,7 @@ PSB_DEV int decode_shot(Ctx& c, int64_t shot) {
   c.now = 0; c.n_visit = 0; c.nd = 0; c.n_log = 0; c.n_regions = 0;
   c.t0 = dev_clock(); c.t_cl = c.t0; c.t_dyn = c.t0; c.t_fuse = c.t0;
   const uint8_t* row = c.P->synd + shot * (int64_t)c.P->nbytes;
+  c.srow = row;
   load_defects(c, row);
   const int nd = c.nd;
   if (!c.status && nd > c.rcap) cap_fail(c);

@@ -445,6 +445,20 @@ extern "C" int32_t psb_decoder_reserve(psb_decoder* D, int64_t max_batch) {
   return PSB_OK;
 }
 
+// For the slot-level server (psb_slots.hip): the wavefront first tier's
+// parameters (graph, schedule, capacities, state layout, workspace of its
+// slots), its LDS bytes per wavefront and its slot count.  PSB_E_UNSUPPORTED
+// when the decoder has no wavefront first tier or keeps a hash in LDS.
+int32_t psb_decoder_first_tier(const psb_decoder* D, psb::Params* P, int32_t* lds_bytes, int32_t* slots) {
+  if (!D || !P || !lds_bytes || !slots) return fail(PSB_E_INVALID, "null argument");
+  if (!D->fast_enabled || D->first_lane || D->P_fast.cap.hcap != 0)
+    return fail(PSB_E_UNSUPPORTED, "slot-level serving needs a wavefront first tier with a direct detector map");
+  *P = D->P_fast;
+  *lds_bytes = (int32_t)D->lds_fast;
+  *slots = D->slots_fast;
+  return PSB_OK;
+}
+
 extern "C" int32_t psb_decoder_slots(const psb_decoder* D, int32_t* fast_slots, int32_t* overflow_slots,
                                      int32_t* fast_lds_bytes) {
   if (!D) return fail(PSB_E_INVALID, "null decoder");

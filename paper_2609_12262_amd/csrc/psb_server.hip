@@ -479,6 +479,36 @@ extern "C" int32_t psb_server_collect(psb_server* S, int32_t max, uint64_t* tick
   return k;
 }
 
+extern "C" int32_t psb_server_cancel(psb_server* S, uint64_t ticket, int32_t* cancelled) {
+  if (!S || !cancelled) return fail(PSB_E_INVALID, "null argument");
+  *cancelled = 0;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(PSB_E_INVALID, "unknown or already collected ticket");
+  Request& R = it->second;
+  if (R.done) return PSB_OK;                       // finished (or cancelled) already
+  Group* G = S->groups[R.group].get();
+  auto q = std::find(G->pending.begin(), G->pending.end(), ticket);
+  if (q == G->pending.end()) return PSB_OK;        // on the device: it completes normally
+  G->pending.erase(q);
+  R.done = true;
+  R.status = PSB_S_CANCELLED;
+  R.t_done = Clock::now();
+  R.synd.clear(); R.synd.shrink_to_fit();
+  S->finished.push_back(ticket);
+  *cancelled = 1;
+  return PSB_OK;
+}
+
+extern "C" int32_t psb_server_wait(psb_server* S, uint64_t ticket, int64_t timeout_us, int32_t* done) {
+  if (!S || !done || timeout_us < 0) return fail(PSB_E_INVALID, "null argument or negative timeout");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto ready = [&]() { auto it = S->reqs.find(ticket); return it == S->reqs.end() || it->second.done; };
+  if (S->reqs.find(ticket) == S->reqs.end()) return fail(PSB_E_INVALID, "unknown or already collected ticket");
+  *done = S->cv.wait_for(lk, std::chrono::microseconds(timeout_us), ready) ? 1 : 0;
+  return PSB_OK;
+}
+
 extern "C" int32_t psb_server_stats(psb_server* S, int64_t* out5) {
   if (!S || !out5) return fail(PSB_E_INVALID, "null argument");
   std::lock_guard<std::mutex> lk(S->mu);

@@ -16,10 +16,31 @@
 
 #include "../../include/psb.h"
 
-extern "C" int32_t psb_replay(psb_server* s, int64_t n, const int32_t* graph_idx, const uint8_t* const* syndromes,
-                              const int32_t* uniform_weight, const double* arrival_s, int64_t* latency_ns,
-                              int32_t* status, double* submit_span_s, double* wall_s) {
-  if (!s || n <= 0 || !graph_idx || !syndromes || !latency_ns || !status) return -1;
+// The two serving runtimes share the submit / collect calls' shape.
+struct PipeServer {
+  psb_server* s;
+  int32_t submit_many(int32_t n, const int32_t* g, const uint8_t* const* syn, const int32_t* w, uint64_t* t) const {
+    return psb_server_submit_many(s, n, g, syn, w, t);
+  }
+  int32_t collect(int32_t max, uint64_t* t, int32_t* st, int64_t* lat) const {
+    return psb_server_collect(s, max, t, nullptr, nullptr, st, lat);
+  }
+};
+struct SlotServer {
+  psb_slot_server* s;
+  int32_t submit_many(int32_t n, const int32_t* g, const uint8_t* const* syn, const int32_t* w, uint64_t* t) const {
+    return psb_slot_server_submit_many(s, n, g, syn, w, t);
+  }
+  int32_t collect(int32_t max, uint64_t* t, int32_t* st, int64_t* lat) const {
+    return psb_slot_server_collect(s, max, t, nullptr, nullptr, st, lat);
+  }
+};
+
+template <class Srv>
+static int32_t replay(const Srv& srv, int64_t n, const int32_t* graph_idx, const uint8_t* const* syndromes,
+                      const int32_t* uniform_weight, const double* arrival_s, int64_t* latency_ns,
+                      int32_t* status, double* submit_span_s, double* wall_s) {
+  if (!srv.s || n <= 0 || !graph_idx || !syndromes || !latency_ns || !status) return -1;
   std::vector<uint64_t> tickets(n, 0);
   std::vector<int64_t> lag(n, 0);       // arrival to submission, added to the server's latency
   std::atomic<int64_t> submitted{0};
@@ -34,7 +55,7 @@ extern "C" int32_t psb_replay(psb_server* s, int64_t n, const int32_t* graph_idx
     local.reserve((size_t)n * 2);
     int64_t got = 0, seen = 0;
     while (got < n && !error.load()) {
-      const int32_t k = psb_server_collect(s, 4096, t.data(), nullptr, nullptr, st.data(), lat.data());
+      const int32_t k = srv.collect(4096, t.data(), st.data(), lat.data());
       if (k < 0) { error = 1; break; }
       const int64_t sub = submitted.load(std::memory_order_acquire);
       for (; seen < sub; ++seen) local[tickets[seen]] = seen;
@@ -72,8 +93,8 @@ extern "C" int32_t psb_replay(psb_server* s, int64_t n, const int32_t* graph_idx
       const double now = std::chrono::duration<double>(Clock::now() - t0).count();
       for (int64_t k = i; k < j; ++k) lag[k] = (int64_t)((now - arrival_s[k]) * 1e9);
     }
-    if (psb_server_submit_many(s, (int32_t)(j - i), graph_idx + i, syndromes + i,
-                               uniform_weight ? uniform_weight + i : nullptr, tickets.data() + i) != 0) {
+    if (srv.submit_many((int32_t)(j - i), graph_idx + i, syndromes + i, uniform_weight ? uniform_weight + i : nullptr,
+                        tickets.data() + i) != 0) {
       error = 3;
       break;
     }
@@ -84,6 +105,21 @@ extern "C" int32_t psb_replay(psb_server* s, int64_t n, const int32_t* graph_idx
   collector.join();
   if (wall_s) *wall_s = std::chrono::duration<double>(Clock::now() - t0).count();
   return error.load() ? -error.load() : 0;
+}
+
+extern "C" int32_t psb_replay(psb_server* s, int64_t n, const int32_t* graph_idx, const uint8_t* const* syndromes,
+                              const int32_t* uniform_weight, const double* arrival_s, int64_t* latency_ns,
+                              int32_t* status, double* submit_span_s, double* wall_s) {
+  return replay(PipeServer{s}, n, graph_idx, syndromes, uniform_weight, arrival_s, latency_ns, status, submit_span_s,
+                wall_s);
+}
+
+extern "C" int32_t psb_replay_slots(psb_slot_server* s, int64_t n, const int32_t* graph_idx,
+                                    const uint8_t* const* syndromes, const int32_t* uniform_weight,
+                                    const double* arrival_s, int64_t* latency_ns, int32_t* status,
+                                    double* submit_span_s, double* wall_s) {
+  return replay(SlotServer{s}, n, graph_idx, syndromes, uniform_weight, arrival_s, latency_ns, status, submit_span_s,
+                wall_s);
 }
 
 // The one-shot-per-launch form on the same stream of windows: one thread

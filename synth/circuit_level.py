@@ -41,7 +41,7 @@ an error.  Faults with the same effect merge (XOR of independent events,
 q = q1 + q2 - 2 q1 q2).  A fault flipping more than two detectors is split
 into detector pairs and singletons that single faults also produce, their
 observables summing to its own; its probability is merged into each part.
-Parallel edges with different observables keep the more probable one.
+Parallel edges with different observables are an error (or, on request, keep the more probable one).
 Weights are round(256 ln((1-q)/q)).  Edges are independent in the sampler,
 so the correlations of split faults are not reproduced in sampled shots.
 """
@@ -194,7 +194,8 @@ def _decompose(dets, obs, graphlike):
 
 
 def rotated_circuit_graph(d: int, p: float, model: str = "uniform", rounds: int | None = None,
-                          spec: dict | None = None, cnot_orders=(_ORDER_X, _ORDER_Z), windowed: bool = True):
+                          spec: dict | None = None, cnot_orders=(_ORDER_X, _ORDER_Z), windowed: bool = True,
+                          parallel: str = "raise"):
     """Detector graph of the X-basis memory experiment under a circuit-level noise model.
 
     `spec` overrides the per-location probabilities ({"prep", "meas", "gate1", "idle", "cnot"}, each the
@@ -204,6 +205,9 @@ def rotated_circuit_graph(d: int, p: float, model: str = "uniform", rounds: int 
     `windowed` scans, while round t is propagated, only the rows of detector layers t-1..t+2 (and the
     observable): a layer-L detector's frame lives in rounds L-1 and L only, since every reset of the round
     before absorbs it.  windowed=False scans every row (for checking that claim).
+    Two faults with the same detectors but different observable flips would be parallel edges, which a
+    detector graph cannot hold: `parallel="raise"` (default) raises ValueError for them, and
+    `parallel="keep_likelier"` keeps the more probable one and counts the other.
     Returns a DetectorGraph (synth.DetectorGraph) with two more attributes: `n_split` (faults split into
     parts) and `n_parallel` (parallel edges dropped)."""
     from . import DetectorGraph, weight_from_p
@@ -347,6 +351,9 @@ def rotated_circuit_graph(d: int, p: float, model: str = "uniform", rounds: int 
         if cur is None or q > cur[1] or (q == cur[1] and obs < cur[0]):
             best[dets] = (obs, q)
     n_parallel = len(edges) - len(best)
+    if n_parallel and parallel != "keep_likelier":
+        raise ValueError(f"{n_parallel} pairs of faults share their detectors but differ in the observable "
+                         "(pass parallel='keep_likelier' to keep the more probable of each)")
     keys = sorted(best)
     u = np.asarray([k[0] for k in keys], np.int32)
     v = np.asarray([k[1] if len(k) == 2 else -1 for k in keys], np.int32)

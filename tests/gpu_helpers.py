@@ -106,3 +106,43 @@ def compare_parallel(g, syndromes, res, idx, seed=SEED, workers=16, chunk=64):
         for b in pool.imap(_par_chunk, parts):
             bad.extend(b)
     return bad
+
+
+_SB = None
+
+
+def _sb_init(g, seed, syndromes, res):
+    global _SB
+    _SB = (g, oracle.SparseBlossom(g, seed), syndromes, res)
+
+
+def _sb_chunk(idx):
+    g, sb, syndromes, res = _SB
+    bad = []
+    for i in idx:
+        r = sb.decode(synth.defects_of(syndromes[i], g.num_detectors), global_mode=True)
+        st = int(res["status"][i])
+        if r.flags & oracle.SBF_INFEASIBLE:
+            if st != 2:
+                bad.append((i, "infeasible expected", st))
+            continue
+        got = res["edges"][i, : res["n_edges"][i]].tolist()
+        if r.flags or st != 0 or got != r.edges.tolist() or int(res["weight"][i]) != r.weight or int(res["obs"][i]) != r.obs:
+            bad.append((i, st, int(res["weight"][i]), r.weight, int(res["obs"][i]), r.obs, r.flags))
+    return bad
+
+
+def compare_sb_parallel(g, syndromes, res, idx, seed=SEED, workers=16, chunk=500):
+    """Every shot in idx against the serial sparse-blossom oracle (global mode; pinned to the Dijkstra +
+    Edmonds MWEM on every shot of the small configurations and on samples of the large ones), spread over
+    host processes."""
+    import multiprocessing as mp
+    idx = list(idx)
+    parts = [idx[i:i + chunk] for i in range(0, len(idx), chunk)]
+    keep = {k: res[k] for k in ("edges", "n_edges", "weight", "obs", "status")}
+    with mp.get_context("fork").Pool(min(workers, len(parts)), initializer=_sb_init,
+                                     initargs=(g, seed, syndromes, keep)) as pool:
+        bad = []
+        for b in pool.imap(_sb_chunk, parts):
+            bad.extend(b)
+    return bad

@@ -393,6 +393,48 @@ def test_server_budget_bursts_and_collect():
         assert r["status"] == 0 and r["weight"] == ref.weight and r["obs"] == ref.obs, (idx, r, ref.weight, ref.obs)
 
 
+def test_server_cancel_and_wait():
+    """Cancellation and time-outs in serving: of a 30,000-window burst, the
+    last 200 are cancelled right after submission; every one still waiting
+    completes at once with PSB_S_CANCELLED and is never decoded, any one
+    already on the device completes normally.  psb_server_wait with a zero
+    time-out returns at once; with a long one it returns when the window is
+    done.  Every window that was not cancelled equals the oracle (sampled)."""
+    import time
+    import paper_2609_12262_amd as psb
+    g = synth.rotated_phenom_graph(21, 0.005)
+    G = psb.Graph.from_synth(g)
+    srv = psb.Server([G])
+    s = synth.sample(g, 30000, seed=77)
+    rows = list(s.syndromes)
+    tickets = srv.submit_many([0] * len(rows), rows)
+    cancelled = {t for t in tickets[-200:] if srv.cancel(t)}
+    say(f"server: {len(cancelled)} of the last 200 windows cancelled")
+    assert cancelled, "the burst's tail should still be waiting"
+    for t in list(cancelled)[:5]:
+        assert srv.wait(t, 0)                     # already complete
+    first_live = next(t for t in tickets if t not in cancelled)
+    srv.wait(first_live, 0)                       # returns at once either way
+    assert srv.wait(tickets[-201], 60_000_000)
+    got = {}
+    t0 = time.time()
+    while len(got) < len(tickets) and time.time() - t0 < 120:
+        for r in srv.collect():
+            got[r["ticket"]] = r
+    srv.close(); G.close()
+    assert len(got) == len(tickets)
+    og = oracle.Graph(g, SEED)
+    for i, t in enumerate(tickets):
+        r = got[t]
+        if t in cancelled:
+            assert r["status"] == psb.PSB_S_CANCELLED and r["weight"] == 0
+            continue
+        assert r["status"] == 0, (i, r)
+        if i % 97 == 0:
+            ref = og.mwem(synth.defects_of(rows[i], g.num_detectors))
+            assert r["weight"] == ref.weight and r["obs"] == ref.obs, i
+
+
 @pytest.mark.parametrize("d,p,n,step", [(5, 0.003, 5000, 1), (9, 0.002, 3000, 1), (13, 0.002, 2000, 10)])
 def test_circuit_x_graphs_equal_oracle(d, p, n, step):
     """Detector graphs from circuit-level X faults (diagonal spacetime edges,

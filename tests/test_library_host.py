@@ -65,3 +65,53 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def _create_raw(n, u, v, w, obs=None):
+    """psb_graph_create on raw arrays; returns (code, message, handle)."""
+    import ctypes
+    import numpy as np
+    import paper_2609_12262_amd as psb
+    u = np.ascontiguousarray(u, np.int32); v = np.ascontiguousarray(v, np.int32)
+    w = np.ascontiguousarray(w, np.int32)
+    obs = np.zeros(len(u), np.uint64) if obs is None else np.ascontiguousarray(obs, np.uint64)
+    desc = psb._GraphDesc(n, len(u), u.ctypes.data, v.ctypes.data, w.ctypes.data, obs.ctypes.data)
+    h = ctypes.c_void_p()
+    rc = psb.lib().psb_graph_create(ctypes.byref(desc), ctypes.byref(h))
+    return rc, psb.lib().psb_last_error().decode(), h
+
+
+@pytest.mark.parametrize("case,n,u,v,w,why", [
+    ("zero weight", 3, [0, 1], [1, 2], [5, 0], "non-positive weight"),
+    ("negative weight", 3, [0, 1], [1, -1], [5, -3], "non-positive weight"),
+    ("u out of range", 3, [0, 3], [1, 2], [5, 5], "out of range"),
+    ("negative u", 3, [-1, 1], [1, 2], [5, 5], "out of range"),
+    ("v below the boundary code", 3, [0, 1], [1, -2], [5, 5], "out of range"),
+    ("v out of range", 3, [0, 1], [1, 7], [5, 5], "out of range"),
+    ("self loop", 3, [0, 1], [1, 1], [5, 5], "self loop"),
+    ("no detectors", 0, [], [], [], "num_detectors"),
+    ("degree above 16", 2, [0] * 17, [1] * 17, [3] * 17, "degree"),
+])
+def test_graph_create_rejects_malformed_graphs(case, n, u, v, w, why):
+    """The decoding task needs positive weights on a graph whose edges join
+    distinct detectors or a detector and its own boundary vertex (Results,
+    "Decoding task"): anything else is refused with PSB_E_INVALID and a
+    message, before any device work."""
+    import paper_2609_12262_amd as psb
+    rc, msg, h = _create_raw(n, u, v, w)
+    assert rc == psb.PSB_E_INVALID, case
+    assert why in msg, (case, msg)
+    assert not h.value
+
+
+def test_null_arguments_are_refused():
+    import ctypes
+    import paper_2609_12262_amd as psb
+    L = psb.lib()
+    h = ctypes.c_void_p()
+    assert L.psb_graph_create(None, ctypes.byref(h)) == psb.PSB_E_INVALID
+    assert L.psb_decoder_create(None, None, ctypes.byref(h)) == psb.PSB_E_INVALID
+    assert L.psb_decode_batch(None, None, ctypes.c_int64(1), None, None, None, None, None, None, None, None,
+                              None) == psb.PSB_E_INVALID
+    assert L.psb_batch_graph_launch(None, None) == psb.PSB_E_INVALID
+    assert L.psb_server_submit(None, 0, None, None, None) == psb.PSB_E_INVALID

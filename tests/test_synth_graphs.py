@@ -100,7 +100,7 @@ def test_circuit_graph_standard_schedule(model, d):
 def test_circuit_graph_hook_orientation_matters(d):
     """Exchanging the two plaquette types' CNOT orders turns the hook faults
     along the logical operator: the circuit distance falls to (d+1)/2."""
-    g = synth.rotated_circuit_graph(d, 0.001, cnot_orders=(cl._ORDER_Z, cl._ORDER_X))
+    g = synth.rotated_circuit_graph(d, 0.001, cnot_orders=(cl._ORDER_Z, cl._ORDER_X), parallel="keep_likelier")
     assert _logical_distance(g) == (d + 1) // 2
 
 
