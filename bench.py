@@ -353,7 +353,7 @@ def serving(args):
 
         run_slots(None)                                   # warm-up
         _, _, wall_cap = run_slots(None)
-        slot_out = {"capacity_windows_per_s": round(n / wall_cap, 1), "waves": args.slot_waves, "loads": {}}
+        slot_out = {"capacity_windows_per_s": round(n / wall_cap, 1), "waves": args.slot_waves or "auto", "loads": {}}
         for ld in sorted(set(loads + [args.serve_load])):
             arr_l = np.cumsum(np.random.default_rng(7).exponential(1.0 / (ld * capacity), n))
             lat_l, t_sub_l, _ = run_slots(arr_l)
@@ -534,7 +534,7 @@ def main():
     ap.add_argument("--serve-loads", default="0.3,0.7,0.9",
                     help="further offered loads (x the batched capacity) run with both serving runtimes")
     ap.add_argument("--no-slot-server", action="store_true", help="skip the slot-level server in --serve")
-    ap.add_argument("--slot-waves", type=int, default=1024, help="slots of the slot-level server")
+    ap.add_argument("--slot-waves", type=int, default=0, help="slots of the slot-level server (0 = as many as fit)")
     ap.add_argument("--serve-dists", default="9,13,17,21,25")
     ap.add_argument("--serve-p", default="0.001,0.007", help="window noise rates drawn uniformly from this range")
     ap.add_argument("--oneshot-windows", type=int, default=3000)

@@ -420,8 +420,9 @@ int32_t psb_server_destroy(psb_server* s);
  * host publishes windows, as they are submitted, into a ring of `ring`
  * entries (a power of two; 0 = 8192) in pinned host memory; one dispatcher
  * wavefront copies new windows to the device; each of the `waves` slots
- * (0 = 1024; at most 12 per compute unit and half of each unit's LDS, so
- * that other kernels keep room) takes the next window as soon as it is
+ * (at most 12 per compute unit and half of each unit's LDS, so that other
+ * kernels keep room; 0 = as many as that allows, up to 1024) takes the next
+ * window as soon as it is
  * free, decodes it with the first tier of the window's group decoder (the
  * same engine and per-shot state as psb_decode_batch) and writes its result
  * and a done flag into pinned host memory; a host thread completes the

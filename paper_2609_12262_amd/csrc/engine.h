@@ -94,7 +94,6 @@ struct Ctx {
   int n_visit;                       // clustering search visits (statistics)
   uint64_t t0, t_cl, t_dyn, t_fuse;  // device clock marks (statistics)
   char* acct;                        // event-accounting block, or null
-  const uint8_t* srow;               // the shot's syndrome row (detection events as bits)
 #ifdef PSB_CHECK_INVARIANTS
   int64_t dbg_shot; int dbg_lvl;
   int32_t* dbg_cfg;                  // [rcap] processing cluster whose stopped configuration holds the region
@@ -979,6 +978,10 @@ PSB_DEV void uf_union(Ctx& c, int a, int b) {
 // events or satisfies the boundary condition.  At the first level whose b_k
 // exceeds the diameter bound, every remaining event is in the component of
 // its connected part of the graph: these form the final clusters.
+// DEEP = 0 compiles only the enumeration of paths of up to three edges (the
+// generic deeper walk holds enough registers to make the whole kernel spill);
+// the host picks DEEP = 1 for graphs whose levels need deeper paths.
+template <int DEEP = 1>
 PSB_DEV void cluster(Ctx& c) {
   const int nd = c.nd;
   const int deg = c.deg;
@@ -1029,11 +1032,7 @@ PSB_DEV void cluster(Ctx& c) {
           return;
         }
         if (y == u) return;
-        // only detection events matter here: the syndrome row (a few hundred
-        // bytes, cache-resident) answers that before the detector map is read
-        if (rj_pre == -1) return;
-        if (rj_pre == -2 && !((c.srow[y >> 3] >> (y & 7)) & 1)) return;
-        const int rj = rj_pre >= 0 ? rj_pre : node_idx(c, y);
+        const int rj = rj_pre != -2 ? rj_pre : node_idx(c, y);
         if (rj >= 0 && rj < nd && c.level[rj] == 0) {
           const int cl = (nd_ <= dk) ? 1 : 0;
           int q = 0;
@@ -1042,9 +1041,9 @@ PSB_DEV void cluster(Ctx& c) {
         }
       };
       // the last hop of a path: the adjacency row of x (reached at distance
-      // base) in chunks of four, each chunk's neighbours and their syndrome
-      // bits loaded before any of them is visited (visit order unchanged;
-      // -1: not a detection event, -2: look it up)
+      // base) in chunks of four, each chunk's neighbours and their
+      // detector-map entries loaded before any of them is visited (visit
+      // order unchanged)
       auto leaf_row = [&](int x, i128 base) {
         const int64_t r0 = (int64_t)x * deg;
         for (int k0 = 0; k0 < deg; k0 += 4) {
@@ -1052,7 +1051,7 @@ PSB_DEV void cluster(Ctx& c) {
 #pragma unroll
           for (int t = 0; t < 4; ++t) zs[t] = k0 + t < deg ? c.nbr[r0 + k0 + t] : NB_PAD;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) ix[t] = (zs[t] >= 0 && !((c.srow[zs[t] >> 3] >> (zs[t] & 7)) & 1)) ? -1 : -2;
+          for (int t = 0; t < 4; ++t) ix[t] = (c.dmap && zs[t] >= 0) ? (int)c.dmap[zs[t]] : -2;
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             if (zs[t] == NB_PAD) return;
@@ -1083,6 +1082,9 @@ PSB_DEV void cluster(Ctx& c) {
             }
           }
         }
+      } else if constexpr (!DEEP) {
+        overflow = 1;                    // never reached: the host builds DEEP kernels for such graphs
+        c.status = S_INTERNAL;
       } else {
         int st_node[MAXH + 1], st_slot[MAXH + 1];
         i128 st_dist[MAXH + 1];
@@ -1521,6 +1523,7 @@ PSB_DEV void cleanup(Ctx& c, int64_t shot) {
 
 // Decodes one shot.  Returns the status; S_OVERFLOW means nothing was
 // written and the shot must be decoded by the overflow tier.
+template <int DEEP = 1>
 PSB_DEV int decode_shot(Ctx& c, int64_t shot) {
 #ifdef PSB_CHECK_INVARIANTS
   c.dbg_shot = shot; c.dbg_lvl = 0;
@@ -1531,7 +1534,6 @@ PSB_DEV int decode_shot(Ctx& c, int64_t shot) {
   c.now = 0; c.n_visit = 0; c.nd = 0; c.n_log = 0; c.n_regions = 0;
   c.t0 = dev_clock(); c.t_cl = c.t0; c.t_dyn = c.t0; c.t_fuse = c.t0;
   const uint8_t* row = c.P->synd + shot * (int64_t)c.P->nbytes;
-  c.srow = row;
   load_defects(c, row);
   const int nd = c.nd;
   if (!c.status && nd > c.rcap) cap_fail(c);
@@ -1549,7 +1551,7 @@ PSB_DEV int decode_shot(Ctx& c, int64_t shot) {
     for (int i = lane(); i < nd; i += PSB_WAVE) c.level[i] = 1;
     wave_sync();
   } else {
-    cluster(c);
+    cluster<DEEP>(c);
     int mx = 0, miss = 0;
     for (int i = lane(); i < nd; i += PSB_WAVE) { mx = c.level[i] > mx ? c.level[i] : mx; miss |= (c.level[i] == 0); }
     max_level = wave_max(mx);

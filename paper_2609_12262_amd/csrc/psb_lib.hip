@@ -57,7 +57,9 @@ __global__ void psb_zero_kernel(int32_t* p, int n, uint64_t* t_start) {
 // At most 128 VGPRs, so that four wavefronts share a SIMD (the per-shot
 // event loop is latency-bound: throughput grows with resident wavefronts).
 // ACCT: per-cluster event accounting compiled in (ACCT = 0 removes it).
-template <int TIER, int ACCT>
+// DEEP: the clustering search's generic walk for paths of more than three
+// edges compiled in (only graphs whose levels need it get it).
+template <int TIER, int ACCT, int DEEP>
 __global__ __launch_bounds__(64, 4) void psb_decode_kernel(Params P) {
   extern __shared__ __align__(16) char psb_dyn_lds[];
   ew::Lds* S = (ew::Lds*)psb_dyn_lds;
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(64, 4) void psb_decode_kernel(Params P) {
       if (k >= lim) break;
       shot = uni(P.ovf_list[k]);
     }
-    const int st = ew::decode_shot(c, shot);
+    const int st = ew::decode_shot<DEEP>(c, shot);
     if (st == psb::S_OVERFLOW) {
       const int q = lane0(atomicAdd(&P.counter[1], lane() == 0 ? 1 : 0));
       P.ovf_list[q] = (int32_t)shot;               // same value from every lane
@@ -88,6 +90,22 @@ __global__ __launch_bounds__(64, 4) void psb_decode_kernel(Params P) {
       P.out_tdone[shot] = wall_clock64();
     }
   }
+}
+
+// The decode kernel instantiation for a tier, accounting and search depth.
+static const void* decode_kernel_fn(int tier, bool acct, bool deep) {
+  const void* k[2][2][2] = {
+      {{(const void*)psb_decode_kernel<0, 0, 0>, (const void*)psb_decode_kernel<0, 0, 1>},
+       {(const void*)psb_decode_kernel<0, 1, 0>, (const void*)psb_decode_kernel<0, 1, 1>}},
+      {{(const void*)psb_decode_kernel<1, 0, 0>, (const void*)psb_decode_kernel<1, 0, 1>},
+       {(const void*)psb_decode_kernel<1, 1, 0>, (const void*)psb_decode_kernel<1, 1, 1>}}};
+  return k[tier][acct ? 1 : 0][deep ? 1 : 0];
+}
+
+static hipError_t launch_decode_kernel(int tier, bool acct, bool deep, unsigned grid, size_t lds, hipStream_t s,
+                                       const Params& P) {
+  void* args[] = {(void*)&P};
+  return hipLaunchKernel(decode_kernel_fn(tier, acct, deep), dim3(grid), dim3(64), args, lds, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -214,6 +232,7 @@ struct psb_decoder {
   int32_t edge_stride = 0, dcap = 0;
   int32_t slots_fast = 0, slots_ovf = 0;
   bool acct = false;                 // per-cluster event accounting (kernel variant)
+  bool deep = false;                 // a level's clustering search needs paths of more than three edges
   size_t lds_fast = 0, lds_ovf = 0;
   bool fast_enabled = true;
   bool first_lane = true;          // first tier: one shot per lane (else one per wavefront)
@@ -265,6 +284,7 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
     return fail(PSB_E_UNSUPPORTED, "level " + std::to_string(bad_level) + " needs paths of more than " +
                                        std::to_string(psb::MAXH) + " edges; the clustering kernel enumerates at most that");
   }
+  for (int32_t h : D->hmax) D->deep |= h > 3;
   // tier capacities: the first tier (one shot per lane, state in its global
   // workspace slot; or one shot per wavefront, state in LDS) and the
   // overflow tier (one shot per wavefront, large LDS state)
@@ -332,18 +352,14 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
     HIP_TRY(psb_lane_occupancy(&per_cu));
     if (per_cu < 1) D->fast_enabled = false;
   } else if (D->fast_enabled) {
-    HIP_TRY(hipFuncSetAttribute(D->acct ? (const void*)psb_decode_kernel<0, 1> : (const void*)psb_decode_kernel<0, 0>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
+    HIP_TRY(hipFuncSetAttribute(decode_kernel_fn(0, D->acct, D->deep), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)D->lds_fast));
-    if (D->acct) HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, psb_decode_kernel<0, 1>, 64, D->lds_fast));
-    else HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, psb_decode_kernel<0, 0>, 64, D->lds_fast));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_kernel_fn(0, D->acct, D->deep), 64, D->lds_fast));
     if (per_cu < 1) D->fast_enabled = false;
   }
-  HIP_TRY(hipFuncSetAttribute(D->acct ? (const void*)psb_decode_kernel<1, 1> : (const void*)psb_decode_kernel<1, 0>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
+  HIP_TRY(hipFuncSetAttribute(decode_kernel_fn(1, D->acct, D->deep), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)D->lds_ovf));
-  if (D->acct) HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_o, psb_decode_kernel<1, 1>, 64, D->lds_ovf));
-  else HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_o, psb_decode_kernel<1, 0>, 64, D->lds_ovf));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_o, decode_kernel_fn(1, D->acct, D->deep), 64, D->lds_ovf));
   if (per_cu_o < 1) { delete D; return fail(PSB_E_UNSUPPORTED, "overflow tier does not fit on a compute unit"); }
   if (D->first_lane) {
     // lanes in flight: every wave the chip holds, at most 65536 lanes
@@ -491,14 +507,10 @@ static int32_t launch_batch(psb_decoder* D, const uint8_t* syndromes, int64_t n,
     HIP_TRY(psb_lane_launch(D->P_fast, (unsigned)waves, s));
   } else if (D->fast_enabled) {
     const int64_t grid = std::min<int64_t>(n, D->slots_fast);
-    if (D->acct) psb_decode_kernel<0, 1><<<(unsigned)grid, 64, D->lds_fast, s>>>(D->P_fast);
-    else psb_decode_kernel<0, 0><<<(unsigned)grid, 64, D->lds_fast, s>>>(D->P_fast);
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_decode_kernel(0, D->acct, D->deep, (unsigned)grid, D->lds_fast, s, D->P_fast));
   }
   const int64_t grid_o = D->fast_enabled ? D->slots_ovf : std::min<int64_t>(n, D->slots_ovf);
-  if (D->acct) psb_decode_kernel<1, 1><<<(unsigned)grid_o, 64, D->lds_ovf, s>>>(D->P_ovf);
-  else psb_decode_kernel<1, 0><<<(unsigned)grid_o, 64, D->lds_ovf, s>>>(D->P_ovf);
-  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_decode_kernel(1, D->acct, D->deep, (unsigned)grid_o, D->lds_ovf, s, D->P_ovf));
   return PSB_OK;
 }
 

@@ -106,7 +106,9 @@ PSB_DEV void dispatch(const SlotArgs& A) {
 }  // namespace
 
 // Block 0 dispatches; block s >= 1 is slot s - 1 of every group's first-tier
-// workspace.  At most 128 VGPRs (four wavefronts per SIMD), as the batch kernel.
+// workspace.  At most 128 VGPRs (four wavefronts per SIMD), as the batch
+// kernel; DEEP as there (the clustering search's generic walk compiled in).
+template <int DEEP>
 __global__ __launch_bounds__(64, 4) void psb_slot_kernel(SlotArgs A) {
   extern __shared__ __align__(16) char psb_dyn_lds[];
   if (blockIdx.x == 0) { dispatch(A); return; }
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(64, 4) void psb_slot_kernel(SlotArgs A) {
     const int64_t e = (int64_t)(k & (uint64_t)A.mask);
     const int g = uni(A.d_group[e]);
     es::ctx_init(c, &A.params[g], S, state, slot);
-    const int st = es::decode_shot(c, e);
+    const int st = es::decode_shot<DEEP>(c, e);
     __threadfence_system();                       // the result reaches host memory before its flag
     const uint64_t flag = (k + 1) | (st == psb::S_OVERFLOW ? kOverflowFlag : 0);
     __hip_atomic_store(&A.h_done[e], flag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -168,6 +170,7 @@ struct SlotGroup {
 struct psb_slot_server {
   int device = 0;
   int32_t waves = 0, ring = 0, max_stride = 0, synd_words = 0, lds = 0;
+  bool deep = false;                                // some group's clustering search needs paths of > 3 edges
   std::vector<std::unique_ptr<SlotGroup>> groups;   // [2 * graph + (unit weights ? 1 : 0)]
   int32_t n_graphs = 0;
   hipStream_t stream = nullptr, side = nullptr;
@@ -303,7 +306,8 @@ extern "C" int32_t psb_slot_server_create(const psb_graph* const* graphs, int32_
   *out = nullptr;
   for (int32_t i = 0; i < n_graphs; ++i) if (!graphs[i]) return fail(PSB_E_INVALID, "null graph");
   if (waves < 0 || ring < 0) return fail(PSB_E_INVALID, "negative waves or ring");
-  if (waves == 0) waves = 1024;
+  const bool auto_waves = waves == 0;
+  if (auto_waves) waves = 1024;          // decoders are sized for this many; the launch may use fewer (below)
   if (ring == 0) ring = 8192;
   if (ring & (ring - 1)) return fail(PSB_E_INVALID, "ring entries must be a power of two");
   auto S = std::make_unique<psb_slot_server>();
@@ -330,6 +334,13 @@ extern "C" int32_t psb_slot_server_create(const psb_graph* const* graphs, int32_
     rc = psb_decoder_create(G->graph, &o, &G->dec);
     int32_t lds = 0, slots = 0;
     if (rc == PSB_OK) rc = psb_decoder_first_tier(G->dec, &params[gi], &lds, &slots);
+    if (rc == PSB_OK) {
+      // the search depth of each level is in the parameters' device copy; read it back once
+      std::vector<int32_t> h(params[gi].n_levels);
+      if (!h.empty() && hipMemcpy(h.data(), params[gi].shmax, 4 * h.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = fail(PSB_E_DEVICE, "level depths");
+      for (int32_t x : h) S->deep |= x > 3;
+    }
     if (rc == PSB_OK && slots < waves) rc = fail(PSB_E_INTERNAL, "first tier has fewer slots than waves");
     psb_decoder_opts oo = o;
     oo.fast_max_nodes = -1;                         // overflow tier only
@@ -349,6 +360,11 @@ extern "C" int32_t psb_slot_server_create(const psb_graph* const* graphs, int32_
   // room while the persistent kernel runs
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device);
+  if (auto_waves) {
+    const int64_t fit = std::min<int64_t>(12LL * cus, (int64_t)cus * 80 * 1024 / std::max(1, S->lds));
+    waves = (int32_t)std::max<int64_t>(1, std::min<int64_t>(waves, fit));
+    S->waves = waves;
+  }
   if ((int64_t)waves * S->lds > (int64_t)cus * 80 * 1024 || waves > 12 * cus) {
     slot_free(S.get());
     return fail(PSB_E_UNSUPPORTED, "too many slots: they must leave half of each compute unit's LDS free");
@@ -383,7 +399,8 @@ extern "C" int32_t psb_slot_server_create(const psb_graph* const* graphs, int32_
       hipMemset(S->d_ctl, 0, 64) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
       hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking) != hipSuccess ||
-      hipFuncSetAttribute((const void*)psb_slot_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, S->lds) != hipSuccess) {
+      hipFuncSetAttribute(S->deep ? (const void*)psb_slot_kernel<1> : (const void*)psb_slot_kernel<0>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, S->lds) != hipSuccess) {
     slot_free(S.get());
     return fail(PSB_E_DEVICE, "slot server set-up");
   }
@@ -399,7 +416,8 @@ extern "C" int32_t psb_slot_server_create(const psb_graph* const* graphs, int32_
     slot_free(S.get());
     return fail(PSB_E_DEVICE, "device addresses of the pinned ring");
   }
-  psb_slot_kernel<<<(unsigned)(waves + 1), 64, S->lds, S->stream>>>(A);
+  if (S->deep) psb_slot_kernel<1><<<(unsigned)(waves + 1), 64, S->lds, S->stream>>>(A);
+  else psb_slot_kernel<0><<<(unsigned)(waves + 1), 64, S->lds, S->stream>>>(A);
   if (hipGetLastError() != hipSuccess) { slot_free(S.get()); return fail(PSB_E_DEVICE, "slot kernel launch"); }
   S->running = true;
   psb_slot_server* raw = S.release();

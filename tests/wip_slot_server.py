@@ -34,19 +34,23 @@ def test_slot_server_windows_equal_oracle_alone():
     gs = [synth.rotated_phenom_graph(d, 0.006) for d in (5, 9, 13)]
     Gs = [psb.Graph.from_synth(g) for g in gs]
     opts = [{}, {}, {"fast_max_nodes": 28, "fast_max_regions": 28}]
-    srv = psb.SlotServer(Gs, opts=opts, waves=128, ring=512)
     rng = np.random.default_rng(81)
-    kinds, rows, wts, tickets = [], [], [], []
+    kinds, rows, wts = [], [], []
     for j0 in range(0, 3000, 250):
         kk = rng.integers(0, 3, 250)
-        rr = [synth.sample(gs[k], 1, seed=12000 + j0 + i).syndromes[0] for i, k in enumerate(kk)]
-        ww = [0 if (j0 + i) % 3 == 0 else synth.weight_from_p(float(rng.uniform(0.001, 0.007))) for i in range(250)]
-        tickets += srv.submit_many(kk.tolist(), rr, ww)
-        kinds += kk.tolist(); rows += rr; wts += ww
-    say("slot server: 3000 windows submitted")
-    got = _collect_all(srv, len(tickets))
-    st = srv.stats()
-    srv.close()
+        kinds += kk.tolist()
+        rows += [synth.sample(gs[k], 1, seed=12000 + j0 + i).syndromes[0] for i, k in enumerate(kk)]
+        wts += [0 if (j0 + i) % 3 == 0 else synth.weight_from_p(float(rng.uniform(0.001, 0.007))) for i in range(250)]
+    srv = psb.SlotServer(Gs, opts=opts, waves=128, ring=512)
+    try:
+        tickets = []
+        for j0 in range(0, 3000, 250):
+            tickets += srv.submit_many(kinds[j0:j0 + 250], rows[j0:j0 + 250], wts[j0:j0 + 250])
+        say("slot server: 3000 windows submitted")
+        got = _collect_all(srv, len(tickets))
+        st = srv.stats()
+    finally:
+        srv.close()
     for G in Gs:
         G.close()
     say(f"slot server stats: {st}")
@@ -73,16 +77,24 @@ def test_slot_server_edges_and_single_windows():
     import paper_2609_12262_amd as psb
     g = synth.rotated_phenom_graph(21, 0.005)
     G = psb.Graph.from_synth(g)
-    srv = psb.SlotServer([G], waves=64, ring=64)
     s = synth.sample(g, 40, seed=83)
     og = oracle.Graph(g, SEED)
-    for i in range(40):
-        t = srv.submit_many([0], [s.syndromes[i]])[0]
-        r = None
-        t0 = time.time()
-        while r is None and time.time() - t0 < 30:
-            r = srv.poll(t, edges_cap=2048)
+    got = []
+    srv = psb.SlotServer([G], waves=64, ring=64)
+    try:
+        for i in range(40):
+            t = srv.submit_many([0], [s.syndromes[i]])[0]
+            r = None
+            t0 = time.time()
+            while r is None and time.time() - t0 < 30:
+                r = srv.poll(t, edges_cap=2048)
+            got.append(r)
+            if r is None:
+                break
+    finally:
+        srv.close()
+    G.close()
+    for i, r in enumerate(got):
         assert r is not None, i
         ref = og.mwem(synth.defects_of(s.syndromes[i], g.num_detectors))
         assert r["status"] == 0 and r["edges"].tolist() == ref.edges.tolist() and r["weight"] == ref.weight, i
-    srv.close(); G.close()
