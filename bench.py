@@ -353,7 +353,7 @@ def serving(args):
 
         run_slots(None)                                   # warm-up
         _, _, wall_cap = run_slots(None)
-        slot_out = {"capacity_windows_per_s": round(n / wall_cap, 1), "waves": args.slot_waves or "auto", "loads": {}}
+        slot_out = {"capacity_windows_per_s": round(n / wall_cap, 1), "slots": ssrv.stats()["slots"], "loads": {}}
         for ld in sorted(set(loads + [args.serve_load])):
             arr_l = np.cumsum(np.random.default_rng(7).exponential(1.0 / (ld * capacity), n))
             lat_l, t_sub_l, _ = run_slots(arr_l)

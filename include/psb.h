@@ -424,9 +424,9 @@ int32_t psb_server_destroy(psb_server* s);
  * kernels keep room; 0 = as many as that allows, up to 1024) takes the next
  * window as soon as it is
  * free, decodes it with the first tier of the window's group decoder (the
- * same engine and per-shot state as psb_decode_batch) and writes its result
- * and a done flag into pinned host memory; a host thread completes the
- * tickets.  A window thus starts as soon as one slot is free and completes
+ * same engine and per-shot state as psb_decode_batch), writes its result
+ * into pinned host memory and appends the window to a completion queue
+ * there, which a host thread reads in order to complete the tickets.  A window thus starts as soon as one slot is free and completes
  * on its own, whatever else is in flight, and its result is the one
  * psb_decode_batch gives for it alone (Results, "Decoding task").  Windows
  * beyond the first tier's capacities are decoded again by an overflow-tier
@@ -454,9 +454,10 @@ int32_t psb_slot_server_collect(psb_slot_server* s, int32_t max, uint64_t* ticke
 int32_t psb_slot_server_poll(psb_slot_server* s, uint64_t ticket, int32_t* done, int64_t* weight, uint64_t* obs,
                              int32_t* edges, int64_t edges_cap, int64_t* n_edges, int32_t* status,
                              int64_t* latency_ns);
-/* out4[4]: windows completed, windows decoded again by the overflow tier,
- * windows waiting for a ring entry, windows published and not yet done. */
-int32_t psb_slot_server_stats(psb_slot_server* s, int64_t* out4);
+/* out5[5]: windows completed, windows decoded again by the overflow tier,
+ * windows waiting for a ring entry, windows published and not yet done,
+ * decode slots (wavefronts) of the kernel. */
+int32_t psb_slot_server_stats(psb_slot_server* s, int64_t* out5);
 /* Stops the kernel once every published window is done (windows still
  * waiting for a ring entry are dropped), then frees everything. */
 int32_t psb_slot_server_destroy(psb_slot_server* s);

@@ -559,9 +559,9 @@ class SlotServer:
                 for i in range(k)]
 
     def stats(self) -> dict:
-        v = (ctypes.c_int64 * 4)()
+        v = (ctypes.c_int64 * 5)()
         _check(lib().psb_slot_server_stats(self._h, v), "psb_slot_server_stats")
-        return {"windows": v[0], "overflow_redecoded": v[1], "waiting": v[2], "in_flight": v[3]}
+        return {"windows": v[0], "overflow_redecoded": v[1], "waiting": v[2], "in_flight": v[3], "slots": v[4]}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -1,16 +1,19 @@
 // Slot-level serving (continuous batching per slot): one persistent kernel
 // whose wavefronts are decode slots.  The host publishes decode windows, as
 // they arrive, into a ring in pinned host memory; one dispatcher wavefront
-// copies newly published windows into device memory; every other wavefront
-// takes the next window as soon as it is free, decodes it with the same
-// engine and the same per-slot state layout as psb_decode_batch (the first
-// tier of the decoder of the window's graph and weight class), writes the
-// result into pinned host memory and raises the window's done flag.  A window
-// therefore starts as soon as one slot is free and completes on its own,
-// whatever else is in flight; its result is the one psb_decode_batch gives
-// for it alone (Results, "Decoding task": every window is an independent
-// MWEM).  Windows that exceed the first tier's per-shot capacities are
-// decoded again, on the host's side stream, by an overflow-only decoder.
+// watches the ring's tail and passes it on in device memory; every other
+// wavefront takes the next window as soon as it is free, fetches that
+// window's syndrome row across the bus itself (all of its loads in flight at
+// once), decodes it with the same engine and the same per-slot state layout
+// as psb_decode_batch (the first tier of the decoder of the window's graph
+// and weight class), writes the result into pinned host memory and appends
+// the window to a completion queue in pinned host memory, which the host
+// reads in order.  A window therefore starts as soon as one slot is free and
+// completes on its own, whatever else is in flight; its result is the one
+// psb_decode_batch gives for it alone (Results, "Decoding task": every window
+// is an independent MWEM).  Windows that exceed the first tier's per-shot
+// capacities are decoded again, on the host's side stream, by an
+// overflow-only decoder.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -44,7 +47,11 @@ int64_t psb_graph_edges(const psb_graph* g);
 
 namespace {
 
+// A completion queue entry: bit 63 = the first tier handed the window on,
+// bits 32..62 = (completion number + 1) mod 2^31 (tells a fresh entry from
+// the one a lap before), bits 0..31 = the window's ring entry.
 constexpr uint64_t kOverflowFlag = 1ull << 63;
+constexpr uint64_t kTagMask = 0x7fffffffull;
 
 struct SlotArgs {
   const psb::Params* params;      // [n_groups] first-tier parameters of each group (device memory)
@@ -56,10 +63,9 @@ struct SlotArgs {
   const int32_t* h_group;         // [ring] group of each window
   const uint32_t* h_synd;         // [ring][synd_words] syndrome rows
   // pinned host memory written by the device
-  uint64_t* h_done;               // [ring] window sequence number + 1 once its result is written
+  uint64_t* h_cq;                 // [ring] completion queue
   // device memory
-  uint64_t* d_ctl;                // [0] slots' reservations, [1] windows copied to the device, [2] stop
-  int32_t* d_group;               // [ring]
+  uint64_t* d_ctl;                // [0] slots' reservations, [1] windows published, [2] stop, [3] completions
 };
 
 PSB_DEV uint64_t lane0_u64(uint64_t v) {
@@ -67,39 +73,52 @@ PSB_DEV uint64_t lane0_u64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// The dispatcher: copies published windows (group and syndrome row) from the
-// pinned ring into device memory, then advances the device-side count; on
-// the stop request, once everything published is copied, raises the device
-// stop flag.  Every lane runs it with the same values.
+PSB_DEV uint64_t load_sys(const uint64_t* p) {
+  return (uint64_t)uni64((int64_t)__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
+}
+
+// The dispatcher: passes the host's count of published windows on to the
+// slots in device memory.  On the stop request it reads the count once more
+// (the host publishes before it asks to stop), passes that on, and only then
+// raises the device stop flag, so that no published window is left behind.
+// Every lane runs it with the same values.
 PSB_DEV void dispatch(const SlotArgs& A) {
-  uint64_t copied = uni64((int64_t)__hip_atomic_load(&A.d_ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  uint64_t seen = load_sys(&A.d_ctl[1]);
   for (;;) {
-    const uint64_t pub = (uint64_t)uni64((int64_t)__hip_atomic_load(A.h_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
-    if (pub > copied) {
-      for (uint64_t k = copied; k < pub; ++k) {
-        const int64_t e = (int64_t)(k & (uint64_t)A.mask);
-        const int g = uni(__hip_atomic_load(&A.h_group[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
-        const psb::Params* P = &A.params[g];
-        const int nb = uni(P->nbytes);
-        uint8_t* dst = const_cast<uint8_t*>(P->synd) + e * (int64_t)nb;
-        const uint32_t* src = A.h_synd + e * (int64_t)A.synd_words;
-        for (int w = lane(); 4 * w < nb; w += PSB_WAVE) {
-          const uint32_t x = __hip_atomic_load(src + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-          for (int b = 0; b < 4; ++b)
-            if (4 * w + b < nb) dst[4 * w + b] = (uint8_t)(x >> (8 * b));
-        }
-        A.d_group[e] = g;
-      }
-      __threadfence();
+    const uint64_t pub = load_sys(A.h_tail);
+    if (pub > seen) {
       __hip_atomic_store(&A.d_ctl[1], pub, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      copied = pub;
+      seen = pub;
       continue;
     }
     if (uni((int)__hip_atomic_load(A.h_stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM))) {
+      const uint64_t last = load_sys(A.h_tail);
+      __hip_atomic_store(&A.d_ctl[1], last, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&A.d_ctl[2], (uint64_t)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
-    __builtin_amdgcn_s_sleep(32);
+    __builtin_amdgcn_s_sleep(16);
+  }
+}
+
+// Copies ring row e (nb bytes, from pinned host memory) to dst in device
+// memory: each lane issues up to four word loads before it stores any, so a
+// row of up to 1 KiB costs one bus round trip.
+PSB_DEV void fetch_row(const uint32_t* src, uint8_t* dst, int nb) {
+  const int nw = (nb + 3) >> 2;
+  for (int w0 = 0; w0 < nw; w0 += 4 * PSB_WAVE) {
+    uint32_t x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int w = w0 + j * PSB_WAVE + lane();
+      x[j] = w < nw ? __hip_atomic_load(src + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int w = w0 + j * PSB_WAVE + lane();
+      for (int b = 0; b < 4; ++b)
+        if (w < nw && 4 * w + b < nb) dst[4 * w + b] = (uint8_t)(x[j] >> (8 * b));
+    }
   }
 }
 
@@ -108,16 +127,19 @@ PSB_DEV void dispatch(const SlotArgs& A) {
 // Block 0 dispatches; block s >= 1 is slot s - 1 of every group's first-tier
 // workspace.  At most 128 VGPRs (four wavefronts per SIMD), as the batch
 // kernel; DEEP as there (the clustering search's generic walk compiled in).
+// `params` (= A.params) is its own restrict argument: the table is written
+// once before the launch and only read here, which lets the compiler keep the
+// decode context built from it per window in scalar registers.
 template <int DEEP>
-__global__ __launch_bounds__(64, 4) void psb_slot_kernel(SlotArgs A) {
+__global__ __launch_bounds__(64, 4) void psb_slot_kernel(SlotArgs A, const psb::Params* __restrict__ params) {
   extern __shared__ __align__(16) char psb_dyn_lds[];
   if (blockIdx.x == 0) { dispatch(A); return; }
   es::Lds* S = (es::Lds*)psb_dyn_lds;
   char* state = psb_dyn_lds + 64;
   const int64_t slot = (int64_t)blockIdx.x - 1;
-  es::Ctx c;
   for (int g = 0; g < A.n_groups; ++g) {          // every group's detector map of this slot starts empty
-    es::ctx_init(c, &A.params[g], S, state, slot);
+    es::Ctx c;
+    es::ctx_init(c, params + g, S, state, slot);
     es::state_init(c);
   }
   for (;;) {
@@ -126,16 +148,34 @@ __global__ __launch_bounds__(64, 4) void psb_slot_kernel(SlotArgs A) {
     for (;;) {
       const uint64_t t = (uint64_t)uni64((int64_t)__hip_atomic_load(&A.d_ctl[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
       if (k < t) break;
-      if (uni((int)__hip_atomic_load(&A.d_ctl[2], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT))) return;
-      __builtin_amdgcn_s_sleep(8);
+      if (uni((int)__hip_atomic_load(&A.d_ctl[2], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT))) {
+        // the final count was passed on before the stop flag: windows below it are still this slot's
+        if (k < (uint64_t)uni64((int64_t)__hip_atomic_load(&A.d_ctl[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)))
+          break;
+        return;
+      }
+      // idle slots poll one counter: the slot next in line polls most often,
+      // one m windows further back m + 1 times less often (at most 32 times),
+      // so that the polling leaves the busy slots' memory traffic alone
+      const int naps = (int)std::min<uint64_t>(k - t + 1, 32);
+      for (int i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(8);
     }
     const int64_t e = (int64_t)(k & (uint64_t)A.mask);
-    const int g = uni(A.d_group[e]);
-    es::ctx_init(c, &A.params[g], S, state, slot);
+    const int g = uni(__hip_atomic_load(&A.h_group[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+    const psb::Params* P = params + g;
+    const int nb = uni(P->nbytes);
+    fetch_row(A.h_synd + e * (int64_t)A.synd_words, const_cast<uint8_t*>(P->synd) + e * (int64_t)nb, nb);
+    __threadfence();                              // the row is in device memory before the engine reads it
+    es::Ctx c;
+    es::ctx_init(c, P, S, state, slot);
+    c.acct = nullptr;                             // no event accounting in serving
     const int st = es::decode_shot<DEEP>(c, e);
-    __threadfence_system();                       // the result reaches host memory before its flag
-    const uint64_t flag = (k + 1) | (st == psb::S_OVERFLOW ? kOverflowFlag : 0);
-    __hip_atomic_store(&A.h_done[e], flag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();                       // the result reaches host memory before its queue entry
+    const uint64_t n = lane0_u64(atomicAdd((unsigned long long*)&A.d_ctl[3], lane() == 0 ? 1ull : 0ull));
+    if (lane() == 0) {
+      const uint64_t v = (((n + 1) & kTagMask) << 32) | (uint64_t)e | (st == psb::S_OVERFLOW ? kOverflowFlag : 0);
+      __hip_atomic_store(&A.h_cq[n & (uint64_t)A.mask], v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
@@ -176,19 +216,22 @@ struct psb_slot_server {
   hipStream_t stream = nullptr, side = nullptr;
   // pinned host memory
   uint64_t* h_tail = nullptr; uint32_t* h_stop = nullptr; int32_t* h_group = nullptr; uint32_t* h_synd = nullptr;
-  uint64_t* h_done = nullptr;
+  uint64_t* h_cq = nullptr;
   int32_t *h_edges = nullptr, *h_ne = nullptr, *h_st = nullptr; int64_t* h_w = nullptr; uint64_t* h_obs = nullptr;
   // device memory
-  psb::Params* d_params = nullptr; uint64_t* d_ctl = nullptr; int32_t* d_group = nullptr; uint8_t* d_synd = nullptr;
+  psb::Params* d_params = nullptr; uint64_t* d_ctl = nullptr; uint8_t* d_synd = nullptr;
   uint8_t* d_ovf_synd = nullptr; int32_t *d_ovf_edges = nullptr, *d_ovf_small = nullptr; int64_t* d_ovf_w = nullptr;
   uint64_t* d_ovf_obs = nullptr;
   bool running = false;
   // host bookkeeping
   std::mutex mu;
+  std::condition_variable cv;                       // wakes an idle completer when windows are published
   std::thread completer;
   bool stop = false;
   uint64_t next_ticket = 1, published = 0;          // ticket t has sequence number t - 1
+  std::atomic<uint64_t> n_published{0};             // = published, read by the completer without the lock
   std::unordered_map<uint64_t, SlotRequest> reqs;
+  std::vector<uint64_t> entry_ticket;               // [ring] ticket of the window published in each entry
   std::deque<uint64_t> waiting;                     // submitted, not yet published (ring full)
   std::deque<uint64_t> inflight;                    // published, in publication order
   std::deque<uint64_t> finished;
@@ -197,10 +240,10 @@ struct psb_slot_server {
 };
 
 static void slot_free(psb_slot_server* S) {
-  for (void* p : {(void*)S->h_tail, (void*)S->h_stop, (void*)S->h_group, (void*)S->h_synd, (void*)S->h_done,
+  for (void* p : {(void*)S->h_tail, (void*)S->h_stop, (void*)S->h_group, (void*)S->h_synd, (void*)S->h_cq,
                   (void*)S->h_edges, (void*)S->h_ne, (void*)S->h_st, (void*)S->h_w, (void*)S->h_obs})
     if (p) (void)hipHostFree(p);
-  for (void* p : {(void*)S->d_params, (void*)S->d_ctl, (void*)S->d_group, (void*)S->d_synd, (void*)S->d_ovf_synd,
+  for (void* p : {(void*)S->d_params, (void*)S->d_ctl, (void*)S->d_synd, (void*)S->d_ovf_synd,
                   (void*)S->d_ovf_edges, (void*)S->d_ovf_small, (void*)S->d_ovf_w, (void*)S->d_ovf_obs})
     if (p) (void)hipFree(p);
   for (auto& G : S->groups) {
@@ -225,6 +268,7 @@ static void publish(psb_slot_server* S) {
     const int64_t e = (int64_t)(R.seq & (uint64_t)(S->ring - 1));
     S->h_group[e] = R.group;
     memcpy(S->h_synd + e * S->synd_words, R.synd.data(), R.synd.size());
+    S->entry_ticket[e] = t;
     R.synd.clear(); R.synd.shrink_to_fit();
     R.published = true;
     S->inflight.push_back(t);
@@ -233,14 +277,19 @@ static void publish(psb_slot_server* S) {
   }
   if (n) {
     S->published += n;
+    S->n_published.store(S->published, std::memory_order_release);
     __atomic_store_n(S->h_tail, S->published, __ATOMIC_RELEASE);
+    S->cv.notify_one();
   }
 }
 
-// Decodes window R again with the group's overflow-only decoder on the side stream.
-static int32_t redo_overflow(psb_slot_server* S, SlotRequest& R, const std::vector<uint8_t>& row, int64_t e) {
-  SlotGroup* G = S->groups[R.group].get();
-  bool ok = hipMemcpyAsync(S->d_ovf_synd, row.data(), row.size(), hipMemcpyHostToDevice, S->side) == hipSuccess &&
+// Decodes the window in ring entry e again with its group's overflow-only
+// decoder on the side stream; the results replace the first tier's in the
+// entry's result rows.
+static int32_t redo_overflow(psb_slot_server* S, int64_t e) {
+  SlotGroup* G = S->groups[S->h_group[e]].get();
+  const uint8_t* row = (const uint8_t*)(S->h_synd + e * S->synd_words);
+  bool ok = hipMemcpyAsync(S->d_ovf_synd, row, (size_t)G->nbytes, hipMemcpyHostToDevice, S->side) == hipSuccess &&
             psb_decode_batch(G->ovf, S->d_ovf_synd, 1, S->d_ovf_edges, S->d_ovf_small, S->d_ovf_w, S->d_ovf_obs,
                              S->d_ovf_small + 1, nullptr, nullptr, nullptr, S->side) == PSB_OK &&
             hipMemcpyAsync(S->h_ne + e, S->d_ovf_small, 4, hipMemcpyDeviceToHost, S->side) == hipSuccess &&
@@ -253,25 +302,48 @@ static int32_t redo_overflow(psb_slot_server* S, SlotRequest& R, const std::vect
   return ok ? PSB_OK : PSB_E_DEVICE;
 }
 
+// The completer reads the completion queue in order.  While windows are in
+// flight it polls closely (a window decodes in tens of microseconds); when
+// none are, it waits for the next publication.
 static void completer_main(psb_slot_server* S) {
   (void)hipSetDevice(S->device);
-  std::vector<uint8_t> row;
-  std::unique_lock<std::mutex> lk(S->mu);
-  while (!S->stop || !S->inflight.empty()) {
-    bool any = false;
-    for (size_t q = 0; q < S->inflight.size(); ++q) {
-      auto it = S->reqs.find(S->inflight[q]);
-      if (it == S->reqs.end() || it->second.done) continue;     // finished (and perhaps already released)
-      SlotRequest& R = it->second;
-      const int64_t e = (int64_t)(R.seq & (uint64_t)(S->ring - 1));
-      const uint64_t f = __atomic_load_n(S->h_done + e, __ATOMIC_ACQUIRE);
-      if ((f & ~kOverflowFlag) != R.seq + 1) continue;
-      if (f & kOverflowFlag) {
-        const SlotGroup* G = S->groups[R.group].get();
-        row.assign((const uint8_t*)(S->h_synd + e * S->synd_words), (const uint8_t*)(S->h_synd + e * S->synd_words) + G->nbytes);
-        ++S->n_overflow;
-        if (redo_overflow(S, R, row, e) != PSB_OK) { S->error = "overflow re-decode failed"; S->h_st[e] = PSB_S_INTERNAL; }
+  struct Ready { int64_t e; bool ovf; };
+  std::vector<Ready> ready;
+  const uint64_t mask = (uint64_t)S->ring - 1;
+  uint64_t next = 0;                                // completions read so far
+  for (;;) {
+    ready.clear();
+    for (;;) {                                      // only this thread reads the queue: no lock needed
+      const uint64_t v = __atomic_load_n(S->h_cq + (next & mask), __ATOMIC_ACQUIRE);
+      if (((v >> 32) & kTagMask) != ((next + 1) & kTagMask)) break;
+      ready.push_back({(int64_t)(v & 0xffffffffull), (v & kOverflowFlag) != 0});
+      ++next;
+    }
+    if (ready.empty()) {
+      if (next < S->n_published.load(std::memory_order_acquire)) {
+        std::this_thread::yield();
+        continue;
       }
+      std::unique_lock<std::mutex> lk(S->mu);
+      if (next >= S->published) {
+        if (S->stop) return;
+        S->cv.wait_for(lk, std::chrono::milliseconds(1));
+      }
+      continue;
+    }
+    // an entry stays its window's until that window is done, so the
+    // overflow re-decode may run without the lock
+    int32_t redo_rc = PSB_OK;
+    for (const Ready& r : ready)
+      if (r.ovf && redo_overflow(S, r.e) != PSB_OK) { S->h_st[r.e] = PSB_S_INTERNAL; redo_rc = PSB_E_DEVICE; }
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (redo_rc != PSB_OK) S->error = "overflow re-decode failed";
+    const auto now = Clock::now();
+    for (const Ready& r : ready) {
+      const int64_t e = r.e;
+      const uint64_t t = S->entry_ticket[e];
+      SlotRequest& R = S->reqs[t];
+      S->n_overflow += r.ovf;
       R.status = S->h_st[e];
       R.weight = S->h_w[e] * R.scale;
       R.obs = S->h_obs[e];
@@ -279,23 +351,16 @@ static void completer_main(psb_slot_server* S) {
       const int64_t m = std::min<int64_t>(R.n_edges, S->max_stride);
       R.edges.assign(S->h_edges + e * (int64_t)S->max_stride, S->h_edges + e * (int64_t)S->max_stride + m);
       R.done = true;
-      R.t_done = Clock::now();
-      S->finished.push_back(S->inflight[q]);
+      R.t_done = now;
+      S->finished.push_back(t);
       ++S->n_windows;
-      any = true;
     }
-    if (any) {
-      while (!S->inflight.empty()) {
-        auto it = S->reqs.find(S->inflight.front());
-        if (it != S->reqs.end() && !it->second.done) break;
-        S->inflight.pop_front();
-      }
-      publish(S);
-      continue;
+    while (!S->inflight.empty()) {
+      auto it = S->reqs.find(S->inflight.front());
+      if (it != S->reqs.end() && !it->second.done) break;
+      S->inflight.pop_front();
     }
-    lk.unlock();
-    std::this_thread::sleep_for(std::chrono::microseconds(5));
-    lk.lock();
+    publish(S);
   }
 }
 
@@ -373,18 +438,19 @@ extern "C" int32_t psb_slot_server_create(const psb_graph* const* graphs, int32_
   const size_t R = (size_t)ring, st = (size_t)S->max_stride;
   auto hm = [&](void** p, size_t bytes) { return hipHostMalloc(p, bytes, hipHostMallocCoherent) == hipSuccess; };
   bool ok = hm((void**)&S->h_tail, 64) && hm((void**)&S->h_stop, 64) && hm((void**)&S->h_group, 4 * R) &&
-            hm((void**)&S->h_synd, 4 * R * S->synd_words) && hm((void**)&S->h_done, 8 * R) &&
+            hm((void**)&S->h_synd, 4 * R * S->synd_words) && hm((void**)&S->h_cq, 8 * R) &&
             hm((void**)&S->h_edges, 4 * R * st) && hm((void**)&S->h_ne, 4 * R) && hm((void**)&S->h_st, 4 * R) &&
             hm((void**)&S->h_w, 8 * R) && hm((void**)&S->h_obs, 8 * R);
   ok = ok && hipMalloc((void**)&S->d_params, sizeof(psb::Params) * params.size()) == hipSuccess &&
-       hipMalloc((void**)&S->d_ctl, 64) == hipSuccess && hipMalloc((void**)&S->d_group, 4 * R) == hipSuccess &&
+       hipMalloc((void**)&S->d_ctl, 64) == hipSuccess &&
        hipMalloc((void**)&S->d_synd, R * (size_t)max_nbytes * params.size()) == hipSuccess &&
        hipMalloc((void**)&S->d_ovf_synd, (size_t)max_nbytes) == hipSuccess &&
        hipMalloc((void**)&S->d_ovf_edges, 4 * st) == hipSuccess && hipMalloc((void**)&S->d_ovf_small, 16) == hipSuccess &&
        hipMalloc((void**)&S->d_ovf_w, 8) == hipSuccess && hipMalloc((void**)&S->d_ovf_obs, 8) == hipSuccess;
   if (!ok) { slot_free(S.get()); return fail(PSB_E_NOMEM, "slot server buffers"); }
   *S->h_tail = 0; *S->h_stop = 0;
-  memset(S->h_done, 0, 8 * R);
+  memset(S->h_cq, 0, 8 * R);
+  S->entry_ticket.assign(R, 0);
   // every group reads its syndromes from its own device pool and writes the shared pinned result rows
   for (size_t gi = 0; gi < params.size(); ++gi) {
     psb::Params& P = params[gi];
@@ -410,14 +476,14 @@ extern "C" int32_t psb_slot_server_create(const psb_graph* const* graphs, int32_
   auto dev = [&](void* h) { dp = nullptr; (void)hipHostGetDevicePointer(&dp, h, 0); return dp; };
   A.h_tail = (const uint64_t*)dev(S->h_tail); A.h_stop = (const uint32_t*)dev(S->h_stop);
   A.h_group = (const int32_t*)dev(S->h_group); A.h_synd = (const uint32_t*)dev(S->h_synd);
-  A.h_done = (uint64_t*)dev(S->h_done);
-  A.d_ctl = S->d_ctl; A.d_group = S->d_group;
-  if (!A.h_tail || !A.h_stop || !A.h_group || !A.h_synd || !A.h_done) {
+  A.h_cq = (uint64_t*)dev(S->h_cq);
+  A.d_ctl = S->d_ctl;
+  if (!A.h_tail || !A.h_stop || !A.h_group || !A.h_synd || !A.h_cq) {
     slot_free(S.get());
     return fail(PSB_E_DEVICE, "device addresses of the pinned ring");
   }
-  if (S->deep) psb_slot_kernel<1><<<(unsigned)(waves + 1), 64, S->lds, S->stream>>>(A);
-  else psb_slot_kernel<0><<<(unsigned)(waves + 1), 64, S->lds, S->stream>>>(A);
+  if (S->deep) psb_slot_kernel<1><<<(unsigned)(waves + 1), 64, S->lds, S->stream>>>(A, A.params);
+  else psb_slot_kernel<0><<<(unsigned)(waves + 1), 64, S->lds, S->stream>>>(A, A.params);
   if (hipGetLastError() != hipSuccess) { slot_free(S.get()); return fail(PSB_E_DEVICE, "slot kernel launch"); }
   S->running = true;
   psb_slot_server* raw = S.release();
@@ -500,11 +566,11 @@ extern "C" int32_t psb_slot_server_poll(psb_slot_server* S, uint64_t ticket, int
   return PSB_OK;
 }
 
-extern "C" int32_t psb_slot_server_stats(psb_slot_server* S, int64_t* out4) {
-  if (!S || !out4) return fail(PSB_E_INVALID, "null argument");
+extern "C" int32_t psb_slot_server_stats(psb_slot_server* S, int64_t* out5) {
+  if (!S || !out5) return fail(PSB_E_INVALID, "null argument");
   std::lock_guard<std::mutex> lk(S->mu);
-  out4[0] = S->n_windows; out4[1] = S->n_overflow; out4[2] = (int64_t)S->waiting.size();
-  out4[3] = (int64_t)S->inflight.size();
+  out5[0] = S->n_windows; out5[1] = S->n_overflow; out5[2] = (int64_t)S->waiting.size();
+  out5[3] = (int64_t)S->inflight.size(); out5[4] = S->waves;
   return PSB_OK;
 }
 
@@ -517,6 +583,7 @@ extern "C" int32_t psb_slot_server_destroy(psb_slot_server* S) {
     for (uint64_t t : S->waiting) S->reqs.erase(t);
     S->waiting.clear();
     __atomic_store_n(S->h_stop, 1u, __ATOMIC_RELEASE);
+    S->cv.notify_one();
   }
   if (S->completer.joinable()) S->completer.join();
   if (S->running) (void)hipStreamSynchronize(S->stream);
