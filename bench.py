@@ -667,7 +667,7 @@ def main():
     roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
             "traffic": measured_traffic(args.d, args.p, args.shots, kw) if args.graph == "phenom" else None,
             "avg_launch_ms": round(avg_launch_s * 1e3, 3),
-            "kernel": "psb_lane_kernel" if kw.get("first_tier", 0) else "psb_decode_kernel<0, 0>",
+            "kernel": "psb_lane_kernel" if kw.get("first_tier", 0) else "psb_decode_kernel<0, 0, 0>",
             "alg_bytes_per_launch_kernel_counts": kern_bytes,
             "achieved_kernel_counts": round(kern_bytes / avg_launch_s / 1e9, 2)}
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:

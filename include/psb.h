@@ -228,7 +228,9 @@ int32_t psb_decoder_reserve(psb_decoder* d, int64_t max_batch);
  * candidate to entries[0 .. psb_autotune_candidates()-1]: its options, the
  * fastest launch in milliseconds (-1 if skipped) and its status (PSB_OK, or
  * the error that skipped it, e.g. PSB_E_UNSUPPORTED when its state does not
- * fit).  *best_index = the fastest candidate.  These options change speed
+ * fit).  *best_index = the fastest candidate, where a later candidate must
+ * be at least 2 % faster than an earlier one to replace it (within timing
+ * noise the earlier stays; the library default comes first).  These options change speed
  * only: the partition-and-fuse result is the serial MWEM for every
  * admissible schedule (Methods, "Parallel sparse blossom"), and every
  * candidate's weights and observables are checked against the first one's

@@ -117,7 +117,9 @@ extern "C" int32_t psb_autotune(const psb_graph* g, const psb_decoder_opts* base
       continue;
     }
     E.ms = best_ms;
-    if (best < 0 || best_ms < entries[best].ms) best = c;
+    // a later candidate must be at least 2 % faster to replace an earlier one:
+    // within timing noise the earlier (the library default comes first) stays
+    if (best < 0 || best_ms < 0.98f * entries[best].ms) best = c;
   }
   (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
   if (rc_out != PSB_OK) return fail(rc_out, err);
