@@ -86,6 +86,8 @@ struct Ctx {
   int8_t* level;
   int32_t *uf, *cl_a, *cl_b, *cl_c, *cl_d, *bdl, *hit;
   int32_t* cid;                      // processing cluster (root event) of each detection event
+  NearEntry* near;                   // clustering near-list entries, or null (WsLayout::near)
+  int32_t* ehead;                    // near-list head of each detection event
   int32_t *shr, *chg, *stk, *fin; uint32_t* ebits;
   // uniform scalars
   int nd, n_regions, n_ce, n_bc, n_log, n_shr, n_chg, stamp, status;
@@ -970,6 +972,61 @@ PSB_DEV void uf_union(Ctx& c, int a, int b) {
   }
 }
 
+// Near lists of the clustering search (direct detector map only).  For a
+// level's search every unresolved detection event i puts, for each adjacency
+// slot j of its row that leads to a detector x, the entry i * deg + j on x's
+// list: x's detector-map cell holds -2 - (head entry) while the search runs
+// (-1 stays "no list"), and an event's own list head is ehead[i].  A path of
+// the search whose last edge leaves detector x then reaches exactly the
+// unresolved events on x's list (with the weight of that edge) and the
+// boundary edges of x, so the last hop reads the list and, only if x has a
+// boundary edge, x's row for its boundary slots.  Entries of one event never
+// move; heads are swapped in with a compare-and-swap on the 32-bit word that
+// holds the 16-bit cell.
+PSB_DEV void near_push_cell(Ctx& c, int x, int e) {
+  int16_t* cell = c.dmap + x;
+  int* word = (int*)((uintptr_t)cell & ~(uintptr_t)3);
+  const int sh = ((uintptr_t)cell & 2) ? 16 : 0;
+  for (int guard = 0; guard < 1 << 20; ++guard) {
+    const int old = atom_load(word);
+    const int cur = (int)(int16_t)(uint16_t)((uint32_t)old >> sh);
+    c.near[e].next = (int16_t)(cur <= -2 ? -2 - cur : -1);
+    const uint32_t code = (uint32_t)(uint16_t)(int16_t)(-2 - e);
+    const int nw = (int)(((uint32_t)old & ~(0xffffu << sh)) | (code << sh));
+    if (atom_cas(word, old, nw) == old) return;
+  }
+}
+
+// set = 1: builds the level's near lists (event heads already -1); set = 0:
+// takes them out of the detector map again (before anything else reads it).
+PSB_DEV void near_lists(Ctx& c, int set) {
+  const int deg = c.deg;
+  for (int i = lane(); i < c.nd; i += PSB_WAVE) {
+    if (c.level[i] != 0) continue;
+    const int64_t r0 = (int64_t)c.x_node[i] * deg;
+    for (int j = 0; j < deg; ++j) {
+      const int y = c.nbr[r0 + j];
+      if (y == NB_PAD) break;
+      if (y < 0) continue;
+      if (!set) {
+        if (c.dmap[y] <= -2) c.dmap[y] = -1;
+        continue;
+      }
+      const int e = i * deg + j;
+      c.near[e].widx = (int32_t)(r0 + j);
+      c.near[e].ev = (int16_t)i;
+      const int rj = c.dmap[y];
+      if (rj >= 0) {
+        c.near[e].next = (int16_t)atom_xchg((unsigned*)&c.ehead[rj], (unsigned)e);
+      } else {
+        near_push_cell(c, y, e);
+      }
+    }
+  }
+}
+
+PSB_DEV bool has_boundary_edge(const Ctx& c, int x) { return (c.P->bndb[x >> 5] >> (x & 31)) & 1u; }
+
 // Level of every detection event.  For each level k with b_k below the graph's
 // diameter bound, the exploring region of radius b_k/2 around event u touches
 // that of event v iff d(u, v) <= b_k; all such pairs are found by enumerating
@@ -978,10 +1035,11 @@ PSB_DEV void uf_union(Ctx& c, int a, int b) {
 // events or satisfies the boundary condition.  At the first level whose b_k
 // exceeds the diameter bound, every remaining event is in the component of
 // its connected part of the graph: these form the final clusters.
-// DEEP = 0 compiles only the enumeration of paths of up to three edges (the
-// generic deeper walk holds enough registers to make the whole kernel spill);
-// the host picks DEEP = 1 for graphs whose levels need deeper paths.
-template <int DEEP = 1>
+// DEEP, the deepest search compiled in (the deeper ones hold registers that
+// make the whole kernel spill more, so the host picks the least that the
+// graph's levels need): 0 = paths of up to two edges; 1 = up to three, with
+// near lists; 2 = the generic walk of up to MAXH edges as well.
+template <int DEEP = 2>
 PSB_DEV void cluster(Ctx& c) {
   const int nd = c.nd;
   const int deg = c.deg;
@@ -1009,7 +1067,18 @@ PSB_DEV void cluster(Ctx& c) {
     }
     const i128 bk = uni128(c.P->sb[k]), dk = uni128(c.P->sd[k]);
     int visits = 0;
-    for (int i = lane(); i < nd; i += PSB_WAVE) { c.uf[i] = i; close_cnt[i] = 0; bcount[i] = 0; csize[i] = 0; cclose[i] = 0; }
+    // near lists pay from three edges on: shallower searches read each last
+    // hop's row in chunks of independent loads, which is faster than a chain
+    // of list entries
+    const bool use_near = DEEP >= 1 && c.near && H >= 3;
+    for (int i = lane(); i < nd; i += PSB_WAVE) {
+      c.uf[i] = i; close_cnt[i] = 0; bcount[i] = 0; csize[i] = 0; cclose[i] = 0;
+      if (use_near) c.ehead[i] = -1;
+    }
+    if (use_near) {
+      wave_sync();
+      near_lists(c, 1);
+    }
     wave_sync();
     for (int i = lane(); i < nd; i += PSB_WAVE) {
       if (c.level[i] != 0) continue;
@@ -1046,6 +1115,24 @@ PSB_DEV void cluster(Ctx& c) {
       // order unchanged)
       auto leaf_row = [&](int x, i128 base) {
         const int64_t r0 = (int64_t)x * deg;
+        if (use_near) {
+          // the events next to x, from its near list, then x's boundary slots
+          const int h = c.dmap[x];
+          int e = h >= 0 ? c.ehead[h] : (h <= -2 ? -2 - h : -1);
+          while (e >= 0) {
+            const NearEntry ne = c.near[e];
+            e = ne.next;
+            if (ne.ev == i) { ++nvis; continue; }
+            visit(c.x_node[ne.ev], -1, base + c.wt[ne.widx], ne.ev);
+          }
+          if (!has_boundary_edge(c, x)) return;
+          for (int k0 = 0; k0 < deg; ++k0) {
+            const int z = c.nbr[r0 + k0];
+            if (z == NB_PAD) return;
+            if (z == NB_BOUNDARY) visit(NB_BOUNDARY, c.eid[r0 + k0], base + c.wt[r0 + k0]);
+          }
+          return;
+        }
         for (int k0 = 0; k0 < deg; k0 += 4) {
           int zs[4], ix[4];
 #pragma unroll
@@ -1059,7 +1146,7 @@ PSB_DEV void cluster(Ctx& c) {
           }
         }
       };
-      if (H <= 3) {
+      if (H <= (DEEP >= 1 ? 3 : 2)) {
         // up to three rounds of independent adjacency-row loads instead of a
         // serial walk over a stack in scratch memory
         if (H == 1) {
@@ -1071,7 +1158,7 @@ PSB_DEV void cluster(Ctx& c) {
             const i128 d1 = c.wt[(int64_t)u * deg + j];
             visit(y, c.eid[(int64_t)u * deg + j], d1);
             if (y < 0 || d1 >= bk) continue;
-            if (H == 2) { leaf_row(y, d1); continue; }
+            if (DEEP == 0 || H == 2) { leaf_row(y, d1); continue; }
             for (int k2 = 0; k2 < deg; ++k2) {
               const int z = c.nbr[(int64_t)y * deg + k2];
               if (z == NB_PAD) break;
@@ -1082,8 +1169,8 @@ PSB_DEV void cluster(Ctx& c) {
             }
           }
         }
-      } else if constexpr (!DEEP) {
-        overflow = 1;                    // never reached: the host builds DEEP kernels for such graphs
+      } else if constexpr (DEEP < 2) {
+        overflow = 1;                    // never reached: the host builds deeper kernels for such graphs
         c.status = S_INTERNAL;
       } else {
         int st_node[MAXH + 1], st_slot[MAXH + 1];
@@ -1093,6 +1180,7 @@ PSB_DEV void cluster(Ctx& c) {
         while (dep >= 0) {
           if (st_slot[dep] >= deg || dep >= H) { --dep; continue; }
           const int x = st_node[dep];
+          if (dep == H - 1 && use_near) { leaf_row(x, st_dist[dep]); --dep; continue; }
           const int j = st_slot[dep]++;
           const int y = c.nbr[(int64_t)x * deg + j];
           if (y == NB_PAD) { st_slot[dep] = deg; continue; }
@@ -1114,6 +1202,10 @@ PSB_DEV void cluster(Ctx& c) {
     }
     c.n_visit += wave_sum(visits);
     wave_sync();
+    if (use_near) {
+      near_lists(c, 0);
+      wave_sync();
+    }
     for (int i = lane(); i < nd; i += PSB_WAVE) {
       if (c.level[i] != 0) continue;
       const int r = uf_find(c, i);
@@ -1523,7 +1615,7 @@ PSB_DEV void cleanup(Ctx& c, int64_t shot) {
 
 // Decodes one shot.  Returns the status; S_OVERFLOW means nothing was
 // written and the shot must be decoded by the overflow tier.
-template <int DEEP = 1>
+template <int DEEP = 2>
 PSB_DEV int decode_shot(Ctx& c, int64_t shot) {
 #ifdef PSB_CHECK_INVARIANTS
   c.dbg_shot = shot; c.dbg_lvl = 0;
@@ -1636,6 +1728,8 @@ PSB_DEV void ctx_init(Ctx& c, const Params* P, Lds* S, char* state, int64_t slot
   c.uf = (int32_t*)(base + L.uf); c.cl_a = (int32_t*)(base + L.cl_a); c.cl_b = (int32_t*)(base + L.cl_b);
   c.cl_c = (int32_t*)(base + L.cl_c); c.cl_d = (int32_t*)(base + L.cl_d);
   c.cid = (int32_t*)(base + L.cid);
+  c.near = P->near_on ? (NearEntry*)(base + L.near) : nullptr;
+  c.ehead = (int32_t*)(base + L.ehead);
   c.bdl = (int32_t*)(base + L.bdl); c.hit = (int32_t*)(base + L.hit);
   c.shr = (int32_t*)(base + L.shr); c.chg = (int32_t*)(base + L.chg); c.stk = (int32_t*)(base + L.stk);
   c.fin = (int32_t*)(base + L.fin); c.ebits = (uint32_t*)(base + L.ebits);

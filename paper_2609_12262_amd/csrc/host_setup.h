@@ -243,6 +243,9 @@ static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const 
   // the lane tier keeps no neighbour table (-1: none; only a host build of the engine can ask for one)
   L.x_nb = (lane_slot && !lane_nb_table) ? -1 : take(2LL * cap.xcap * deg);
   L.acct = acct ? take(psb::acct_bytes(d)) : 0;
+  P.near_on = (cap.hcap == 0 && (int64_t)d * deg <= 32766) ? 1 : 0;
+  L.near = P.near_on ? take((int64_t)sizeof(psb::NearEntry) * d * deg) : 0;
+  L.ehead = P.near_on ? take(4LL * d) : 0;
   P.eacct = acct ? 1 : 0;
   L.total = off;
 }

@@ -92,17 +92,22 @@ __global__ __launch_bounds__(64, 4) void psb_decode_kernel(Params P) {
   }
 }
 
-// The decode kernel instantiation for a tier, accounting and search depth.
-static const void* decode_kernel_fn(int tier, bool acct, bool deep) {
-  const void* k[2][2][2] = {
-      {{(const void*)psb_decode_kernel<0, 0, 0>, (const void*)psb_decode_kernel<0, 0, 1>},
-       {(const void*)psb_decode_kernel<0, 1, 0>, (const void*)psb_decode_kernel<0, 1, 1>}},
-      {{(const void*)psb_decode_kernel<1, 0, 0>, (const void*)psb_decode_kernel<1, 0, 1>},
-       {(const void*)psb_decode_kernel<1, 1, 0>, (const void*)psb_decode_kernel<1, 1, 1>}}};
-  return k[tier][acct ? 1 : 0][deep ? 1 : 0];
+// The decode kernel instantiation for a tier, accounting and search depth
+// class (0: paths of up to two edges, 1: three, 2: the generic walk).
+static const void* decode_kernel_fn(int tier, bool acct, int deep) {
+  const void* k[2][2][3] = {
+      {{(const void*)psb_decode_kernel<0, 0, 0>, (const void*)psb_decode_kernel<0, 0, 1>,
+        (const void*)psb_decode_kernel<0, 0, 2>},
+       {(const void*)psb_decode_kernel<0, 1, 0>, (const void*)psb_decode_kernel<0, 1, 1>,
+        (const void*)psb_decode_kernel<0, 1, 2>}},
+      {{(const void*)psb_decode_kernel<1, 0, 0>, (const void*)psb_decode_kernel<1, 0, 1>,
+        (const void*)psb_decode_kernel<1, 0, 2>},
+       {(const void*)psb_decode_kernel<1, 1, 0>, (const void*)psb_decode_kernel<1, 1, 1>,
+        (const void*)psb_decode_kernel<1, 1, 2>}}};
+  return k[tier][acct ? 1 : 0][deep];
 }
 
-static hipError_t launch_decode_kernel(int tier, bool acct, bool deep, unsigned grid, size_t lds, hipStream_t s,
+static hipError_t launch_decode_kernel(int tier, bool acct, int deep, unsigned grid, size_t lds, hipStream_t s,
                                        const Params& P) {
   void* args[] = {(void*)&P};
   return hipLaunchKernel(decode_kernel_fn(tier, acct, deep), dim3(grid), dim3(64), args, lds, s);
@@ -145,6 +150,7 @@ struct psb_graph {
   std::vector<int32_t> nbr, eid;     // host ELL
   int32_t *d_nbr = nullptr, *d_eid = nullptr, *d_w = nullptr;
   uint64_t* d_obs = nullptr;
+  uint32_t* d_bndb = nullptr;        // bit per detector: it has a boundary edge
 };
 
 extern "C" int32_t psb_graph_create(const psb_graph_desc* desc, psb_graph** out) {
@@ -191,7 +197,11 @@ extern "C" int32_t psb_graph_create(const psb_graph_desc* desc, psb_graph** out)
   hipError_t e2 = up((void**)&g->d_eid, g->eid.data(), g->eid.size() * 4);
   hipError_t e3 = up((void**)&g->d_w, g->w.data(), g->w.size() * 4);
   hipError_t e4 = up((void**)&g->d_obs, g->obs.data(), g->obs.size() * 8);
-  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+  std::vector<uint32_t> bndb(((size_t)n + 31) / 32, 0u);
+  for (int64_t k = 0; k < (int64_t)g->nbr.size(); ++k)
+    if (g->nbr[k] == psb::NB_BOUNDARY) bndb[(size_t)(k / deg) >> 5] |= 1u << ((k / deg) & 31);
+  hipError_t e5 = up((void**)&g->d_bndb, bndb.data(), bndb.size() * 4);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess) {
     psb_graph_destroy(g);
     return fail(PSB_E_DEVICE, "graph upload failed");
   }
@@ -205,6 +215,7 @@ extern "C" int32_t psb_graph_destroy(psb_graph* g) {
   if (g->d_eid) (void)hipFree(g->d_eid);
   if (g->d_w) (void)hipFree(g->d_w);
   if (g->d_obs) (void)hipFree(g->d_obs);
+  if (g->d_bndb) (void)hipFree(g->d_bndb);
   delete g;
   return PSB_OK;
 }
@@ -232,7 +243,7 @@ struct psb_decoder {
   int32_t edge_stride = 0, dcap = 0;
   int32_t slots_fast = 0, slots_ovf = 0;
   bool acct = false;                 // per-cluster event accounting (kernel variant)
-  bool deep = false;                 // a level's clustering search needs paths of more than three edges
+  int deep = 0;                      // search depth class the levels need: 0 (<= 2 edges), 1 (3), 2 (deeper)
   size_t lds_fast = 0, lds_ovf = 0;
   bool fast_enabled = true;
   bool first_lane = true;          // first tier: one shot per lane (else one per wavefront)
@@ -284,7 +295,7 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
     return fail(PSB_E_UNSUPPORTED, "level " + std::to_string(bad_level) + " needs paths of more than " +
                                        std::to_string(psb::MAXH) + " edges; the clustering kernel enumerates at most that");
   }
-  for (int32_t h : D->hmax) D->deep |= h > 3;
+  for (int32_t h : D->hmax) D->deep = std::max(D->deep, h > 3 ? 2 : h == 3 ? 1 : 0);
   // tier capacities: the first tier (one shot per lane, state in its global
   // workspace slot; or one shot per wavefront, state in LDS) and the
   // overflow tier (one shot per wavefront, large LDS state)
@@ -395,7 +406,7 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   HIP_TRY(hipMemset(D->d_ws_ovf, 0, (size_t)PO.L.total * D->slots_ovf));
   HIP_TRY(hipDeviceSynchronize());
   for (Params* P : {&PF, &PO}) {
-    P->nbr = g->d_nbr; P->eid = g->d_eid; P->wt = D->d_wt; P->w = g->d_w; P->obs = g->d_obs;
+    P->nbr = g->d_nbr; P->eid = g->d_eid; P->wt = D->d_wt; P->w = g->d_w; P->obs = g->d_obs; P->bndb = g->d_bndb;
     P->sd = D->d_sd; P->sb = D->d_sb; P->shmax = D->d_shmax;
     P->counter = D->d_counter;
   }

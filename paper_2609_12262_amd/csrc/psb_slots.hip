@@ -126,7 +126,7 @@ PSB_DEV void fetch_row(const uint32_t* src, uint8_t* dst, int nb) {
 
 // Block 0 dispatches; block s >= 1 is slot s - 1 of every group's first-tier
 // workspace.  At most 128 VGPRs (four wavefronts per SIMD), as the batch
-// kernel; DEEP as there (the clustering search's generic walk compiled in).
+// kernel; DEEP as there (the search depth class compiled in).
 // `params` (= A.params) is its own restrict argument: the table is written
 // once before the launch and only read here, which lets the compiler keep the
 // decode context built from it per window in scalar registers.
@@ -210,7 +210,7 @@ struct SlotGroup {
 struct psb_slot_server {
   int device = 0;
   int32_t waves = 0, ring = 0, max_stride = 0, synd_words = 0, lds = 0;
-  bool deep = false;                                // some group's clustering search needs paths of > 3 edges
+  int deep = 0;                                     // search depth class the groups need (as psb_decode_kernel)
   std::vector<std::unique_ptr<SlotGroup>> groups;   // [2 * graph + (unit weights ? 1 : 0)]
   int32_t n_graphs = 0;
   hipStream_t stream = nullptr, side = nullptr;
@@ -404,7 +404,7 @@ extern "C" int32_t psb_slot_server_create(const psb_graph* const* graphs, int32_
       std::vector<int32_t> h(params[gi].n_levels);
       if (!h.empty() && hipMemcpy(h.data(), params[gi].shmax, 4 * h.size(), hipMemcpyDeviceToHost) != hipSuccess)
         rc = fail(PSB_E_DEVICE, "level depths");
-      for (int32_t x : h) S->deep |= x > 3;
+      for (int32_t x : h) S->deep = std::max(S->deep, x > 3 ? 2 : x == 3 ? 1 : 0);
     }
     if (rc == PSB_OK && slots < waves) rc = fail(PSB_E_INTERNAL, "first tier has fewer slots than waves");
     psb_decoder_opts oo = o;
@@ -465,7 +465,8 @@ extern "C" int32_t psb_slot_server_create(const psb_graph* const* graphs, int32_
       hipMemset(S->d_ctl, 0, 64) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
       hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking) != hipSuccess ||
-      hipFuncSetAttribute(S->deep ? (const void*)psb_slot_kernel<1> : (const void*)psb_slot_kernel<0>,
+      hipFuncSetAttribute(S->deep == 2 ? (const void*)psb_slot_kernel<2>
+                          : S->deep == 1 ? (const void*)psb_slot_kernel<1> : (const void*)psb_slot_kernel<0>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, S->lds) != hipSuccess) {
     slot_free(S.get());
     return fail(PSB_E_DEVICE, "slot server set-up");
@@ -482,7 +483,8 @@ extern "C" int32_t psb_slot_server_create(const psb_graph* const* graphs, int32_
     slot_free(S.get());
     return fail(PSB_E_DEVICE, "device addresses of the pinned ring");
   }
-  if (S->deep) psb_slot_kernel<1><<<(unsigned)(waves + 1), 64, S->lds, S->stream>>>(A, A.params);
+  if (S->deep == 2) psb_slot_kernel<2><<<(unsigned)(waves + 1), 64, S->lds, S->stream>>>(A, A.params);
+  else if (S->deep == 1) psb_slot_kernel<1><<<(unsigned)(waves + 1), 64, S->lds, S->stream>>>(A, A.params);
   else psb_slot_kernel<0><<<(unsigned)(waves + 1), 64, S->lds, S->stream>>>(A, A.params);
   if (hipGetLastError() != hipSuccess) { slot_free(S.get()); return fail(PSB_E_DEVICE, "slot kernel launch"); }
   S->running = true;

@@ -44,6 +44,9 @@ struct WsLayout {
   int64_t x_nb;                                  // [xcap][deg] int16: explored index of each adjacency slot's
                                                  // neighbour (XNB_* codes when it has none); -1: no table
   int64_t acct;                                  // per-cluster event accounting block (event_accounting only)
+  int64_t near, ehead;                           // clustering search, direct detector map only: near-list
+                                                 // entries [dcap*deg] (NearEntry) and the list head of each
+                                                 // detection event [dcap] int32 (-1 empty)
   int64_t total;                                 // bytes per slot (multiple of 256)
 };
 
@@ -84,6 +87,14 @@ constexpr int64_t acct_early(int64_t d) { return ACCT_CID + 8 * d; }
 constexpr int64_t acct_last(int64_t d) { return (ACCT_CID + 12 * d + 15) & ~(int64_t)15; }
 constexpr int64_t acct_bytes(int64_t d) { return acct_last(d) + 16 * d; }
 
+// Near-list entry of the clustering search: the adjacency slot (row * deg +
+// slot, so the weight is wt[widx]) joining a detector to the unresolved
+// detection event ev, and the next entry of the detector's list (-1 ends it).
+struct NearEntry {
+  int32_t widx;
+  int16_t ev, next;
+};
+
 struct Caps {
   int32_t xcap, hcap, rcap, dcap;                // explored nodes, hash slots (power of 2), regions, events
 };
@@ -97,6 +108,7 @@ struct Params {
   const __int128* wt;     // [n_det*deg]: tie-broken even weight of each adjacency slot
   const int32_t* w;       // [n_edges]: caller weights
   const uint64_t* obs;    // [n_edges]
+  const uint32_t* bndb;   // [ceil(n_det/32)]: detector has a boundary edge
   // schedule
   int32_t n_levels, reading, mode, tier;         // tier: 0 first tier (wave or lane), 1 overflow tier
   const __int128* sd;     // [n_levels] d_k
@@ -106,7 +118,9 @@ struct Params {
   Caps cap;
   int32_t cecap, bccap, lcap, shrcap, stkcap, fincap, hitcap, bdc;
   int64_t max_events;
-  int32_t direct1, pad1;                         // level-1 clusters of one known event applied directly
+  int32_t direct1;                               // level-1 clusters of one known event applied directly
+  int32_t near_on;                               // clustering search ends paths through near lists (needs the
+                                                 // direct detector map and dcap*deg <= 32766)
   // batch
   int64_t n_shots;
   const uint8_t* synd;

@@ -89,7 +89,11 @@ int main(int argc, char** argv) {
   psb::Params P;
   memset(&P, 0, sizeof(P));
   psb_host::plan_tier(P, n, deg, m, cap, /*lane_slot=*/true, 0, /*acct=*/true, /*lane_nb_table=*/PSB_NB_TABLE);
+  std::vector<uint32_t> bndb(((size_t)n + 31) / 32, 0u);
+  for (size_t k = 0; k < ell.nbr.size(); ++k)
+    if (ell.nbr[k] == psb::NB_BOUNDARY) bndb[(k / deg) >> 5] |= 1u << ((k / deg) & 31);
   P.nbr = ell.nbr.data(); P.eid = ell.eid.data(); P.wt = ell_w.data(); P.w = w.data(); P.obs = obs.data();
+  P.bndb = bndb.data();
   P.n_levels = (int32_t)S.d.size(); P.reading = reading; P.mode = mode; P.tier = 1; P.direct1 = atoi(argv[9]);
   P.sd = sd.data(); P.sb = sb.data(); P.shmax = hmax.data();
 

@@ -64,6 +64,20 @@ def test_cpu_engine_phenomenological(exe, d, p, n, seed):
     assert tied <= 0.1 * n
 
 
+@pytest.mark.parametrize("q,reading", [(0.1, 0), (0.1, 1), (0.05, 0)])
+def test_cpu_engine_deep_clustering_search(exe, q, reading):
+    """Cheap timelike edges (q above p) make the level-1 search need paths of
+    four (q = 0.05) or five (q = 0.1) edges: the generic walk, whose last hop
+    reads the near lists.  Results, event counts, E_ideal and the number of
+    processing clusters equal the oracles on every shot."""
+    g = synth.rotated_phenom_graph(7, 0.003, q=q)
+    s = synth.sample(g, 300, seed=16)
+    res = ce.run(exe, g, s.syndromes, reading=reading)
+    bad, tied = _compare(g, s.syndromes, res, reading="loose" if reading else "strict")
+    assert not bad, bad[:5]
+    assert tied <= 30
+
+
 def test_cpu_engine_global_mode_and_loose_reading(exe):
     g = synth.rotated_phenom_graph(9, 0.01)
     s = synth.sample(g, 300, seed=13)
