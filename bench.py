@@ -466,6 +466,59 @@ def sliding_window(args):
     plan.close()
 
 
+def streaming(args):
+    """Sliding windows fed by the serving loop: --streams streams of R rounds each, every stream's rounds pushed
+    at the syndrome rate (one round per --round-us microseconds) and decoded window by window through the slot
+    server as they complete.  Per rate: offered and sustained rounds/s over all streams, the lag of the last
+    commit behind the last round, each window's latency from its last round's arrival to its commit, and its
+    decode time (submission to the slot server to its decoded result)."""
+    import ctypes
+    import synth
+    import paper_2609_12262_amd as psb
+    d, R, W, C = (int(x) for x in args.stream.split(","))
+    g = synth.rotated_phenom_graph(d, args.p, rounds=R)
+    L = (d * d - 1) // 2
+    n = args.streams
+    log(f"sampling {n} streams d={d} rounds={R} p={args.p}")
+    rows = synth.sample(g, n, seed=9).syndromes
+    caps = [int(x) for x in args.window_caps.split(",")] if args.window_caps else [0, 0]
+    srv = psb.StreamServer(g, L, W, C, n, tiebreak_seed=0x5EED, fast_max_nodes=caps[0], fast_max_regions=caps[1],
+                           fast_lds_state=args.lds_state)
+    rep = ctypes.CDLL(os.path.join(ROOT, "paper_2609_12262_amd", "libpsb_replay.so"))
+    rep.psb_stream_replay.restype = ctypes.c_int32
+    keep = [np.ascontiguousarray(r) for r in rows]
+    ptrs = (ctypes.c_void_p * n)(*[r.ctypes.data for r in keep])
+    out = {"metric": "streaming sliding-window decoding: sustained rounds/s against the syndrome rate",
+           "d": d, "rounds": R, "window_layers": W, "commit_layers": C, "p": args.p, "streams": n,
+           "windows_per_stream": srv.n_windows, "first_tier_state": caps, "lds_state": args.lds_state, "rates": {}}
+    for ru in [float(x) for x in args.round_us.split(",")] + [float(args.round_us.split(",")[0])]:
+        for i in range(n):
+            srv.reset(i)
+        wall, span = ctypes.c_double(), ctypes.c_double()
+        rc = rep.psb_stream_replay(srv._h, ctypes.c_int32(n), ptrs, ctypes.c_int32(srv.n_layers),
+                                   ctypes.c_int32(args.layers_per_push), ctypes.c_double(ru * 1e-6),
+                                   ctypes.c_double(120.0), ctypes.byref(wall), ctypes.byref(span))
+        if rc != 0:
+            raise RuntimeError(f"psb_stream_replay failed ({rc})")
+        res = [srv.poll(i) for i in range(n)]
+        ld = [srv.latencies(i, decode=True) for i in range(n)]
+        lat = np.concatenate([x[0] for x in ld]) / 1e3
+        dec = np.concatenate([x[1] for x in ld]) / 1e3
+        ok = sum(1 for r in res if r["done"] and r["status"] == 0)
+        rec = {"round_us": ru, "offered_rounds_per_s": round(n * 1e6 / ru, 1) if ru > 0 else None,
+               "pushed_rounds_per_s": round(n * srv.n_layers / span.value, 1),
+               "sustained_rounds_per_s": round(n * srv.n_layers / wall.value, 1),
+               "lag_after_last_round_us": round((wall.value - span.value) * 1e6, 1),
+               "window_latency_us_p50": round(float(np.percentile(lat, 50)), 1),
+               "window_latency_us_p99": round(float(np.percentile(lat, 99)), 1),
+               "window_decode_us_p50": round(float(np.percentile(dec, 50)), 1),
+               "window_decode_us_p99": round(float(np.percentile(dec, 99)), 1), "ok_streams": ok}
+        log(f"round every {ru} us: {rec}")
+        out["rates"][str(ru)] = rec          # the first rate runs twice; the second run (warm) is kept
+    srv.close()
+    print(json.dumps(out), flush=True)
+
+
 def complementary(args):
     """Complementary-gap decoding of a batch: two constrained MWEM decodes per shot (observable 0 and 1)."""
     import torch
@@ -539,6 +592,13 @@ def main():
     ap.add_argument("--serve-p", default="0.001,0.007", help="window noise rates drawn uniformly from this range")
     ap.add_argument("--oneshot-windows", type=int, default=3000)
     ap.add_argument("--window", default="", help="d,rounds,W,C: sliding-window decoding of --shots long streams")
+    ap.add_argument("--stream", default="", help="d,rounds,W,C: sliding windows fed by the serving loop")
+    ap.add_argument("--streams", type=int, default=64, help="streams for --stream")
+    ap.add_argument("--round-us", default="0", help="--stream: microseconds per syndrome round (list; 0 = as fast "
+                                                   "as the pushes go)")
+    ap.add_argument("--layers-per-push", type=int, default=1)
+    ap.add_argument("--lds-state", type=int, default=3, help="--stream: first-tier state placement of the window "
+                                                             "decoders (fast_lds_state; 3 = all per-shot state in LDS)")
     ap.add_argument("--complementary", action="store_true",
                     help="complementary-gap decoding (both values of the logical observable) of --shots shots")
     ap.add_argument("--window-caps", default="640,416",
@@ -553,6 +613,9 @@ def main():
         return
     if args.window:
         sliding_window(args)
+        return
+    if args.stream:
+        streaming(args)
         return
     if args.complementary:
         complementary(args)

@@ -452,6 +452,14 @@ int32_t psb_slot_server_submit_many(psb_slot_server* s, int32_t n, const int32_t
 /* As psb_server_collect. */
 int32_t psb_slot_server_collect(psb_slot_server* s, int32_t max, uint64_t* tickets, int64_t* weight, uint64_t* obs,
                                 int32_t* status, int64_t* latency_ns);
+/* As psb_slot_server_collect, also writing each window's matched edges:
+ * edges[k * edges_stride ..] receives up to edges_stride edge ids of the k-th
+ * ticket and n_edges[k] its edge count (status PSB_S_EDGES_TRUNCATED when
+ * that exceeds edges_stride).  edges and n_edges are host arrays of at least
+ * max * edges_stride and max entries. */
+int32_t psb_slot_server_collect_edges(psb_slot_server* s, int32_t max, uint64_t* tickets, int64_t* weight,
+                                      uint64_t* obs, int32_t* status, int64_t* latency_ns, int32_t* edges,
+                                      int64_t edges_stride, int64_t* n_edges);
 /* As psb_server_poll. */
 int32_t psb_slot_server_poll(psb_slot_server* s, uint64_t ticket, int32_t* done, int64_t* weight, uint64_t* obs,
                              int32_t* edges, int64_t edges_cap, int64_t* n_edges, int32_t* status,
@@ -463,6 +471,51 @@ int32_t psb_slot_server_stats(psb_slot_server* s, int64_t* out5);
 /* Stops the kernel once every published window is done (windows still
  * waiting for a ring entry are dropped), then frees everything. */
 int32_t psb_slot_server_destroy(psb_slot_server* s);
+
+/* Streaming sliding-window decoding fed by the serving loop (Introduction:
+ * streaming decoding of syndrome-extraction rounds; the window rule of
+ * psb_window_plan_create).  `desc` is one run of a layered detector graph
+ * (layers of layer_size detectors, one per round); the server keeps
+ * n_streams independent streams of it.  Callers push each stream's layers as
+ * they arrive; window k of a stream (layers [k*C, k*C + W), the last window to
+ * the final layer) is decoded as soon as its last layer has arrived and
+ * window k - 1 has committed, by a slot server (psb_slot_server_create with
+ * `slots`, 0 = as many as fit) whose groups are the window shapes, so windows
+ * of different streams share the GPU.  A host thread commits each decoded
+ * window on its stream's running syndrome (weights and observable masks of the
+ * committed edges accumulate; their endpoints flip).  A finished stream's
+ * weight, observable and status are what psb_window_decode gives for its
+ * syndrome; status PSB_S_INTERNAL if a detection event was left unresolved.
+ * While the server exists its kernel occupies the slots (see
+ * psb_slot_server_create).  Thread-safe.
+ * Errors: PSB_E_INVALID, PSB_E_NOMEM, PSB_E_DEVICE, PSB_E_UNSUPPORTED. */
+typedef struct psb_stream_server psb_stream_server;
+int32_t psb_stream_server_create(const psb_graph_desc* desc, int32_t layer_size, int32_t window_layers,
+                                 int32_t commit_layers, const psb_decoder_opts* opts, int32_t n_streams,
+                                 int32_t slots, psb_stream_server** out);
+/* Layers [first_layer, first_layer + n_layers) of `stream` have arrived.
+ * bits: a host row packed LSB-first over the whole graph's detectors (as a
+ * psb_decode_batch syndrome row); only the bits of those layers are read.
+ * Layers arrive in order, each once (PSB_E_INVALID otherwise). */
+int32_t psb_stream_push(psb_stream_server* s, int32_t stream, int32_t first_layer, int32_t n_layers,
+                        const uint8_t* bits);
+/* *done = 1 once every window of the stream has committed (or one failed:
+ * *status); committed_layers: layers whose corrections are final; weight and
+ * obs: of the committed edges so far (any output but done may be NULL). */
+int32_t psb_stream_poll(psb_stream_server* s, int32_t stream, int32_t* done, int32_t* committed_layers,
+                        int64_t* weight, uint64_t* obs, int32_t* status);
+/* Per committed window of the stream, in window order: ns = nanoseconds from
+ * the arrival of the window's last layer to its commit (waiting for the
+ * previous window included); decode_ns (may be NULL) = from its submission to
+ * the slot server to its decoded result.  *n = windows committed; up to max
+ * are written. */
+int32_t psb_stream_latencies(psb_stream_server* s, int32_t stream, int32_t max, int64_t* ns, int64_t* decode_ns,
+                             int32_t* n);
+/* Clears a stream that has no window in flight, for a new run. */
+int32_t psb_stream_reset(psb_stream_server* s, int32_t stream);
+int32_t psb_stream_server_info(const psb_stream_server* s, int32_t* n_windows, int32_t* n_shapes, int32_t* n_layers);
+/* Waits for the windows in flight, then frees everything. */
+int32_t psb_stream_server_destroy(psb_stream_server* s);
 
 const char* psb_last_error(void);
 

@@ -88,8 +88,10 @@ def lib():
                      "psb_window_plan_create", "psb_window_plan_info", "psb_window_decode",
                      "psb_window_plan_destroy", "psb_comp_plan_create", "psb_comp_decode",
                      "psb_comp_plan_destroy", "psb_slot_server_create", "psb_slot_server_submit_many",
-                     "psb_slot_server_collect", "psb_slot_server_poll", "psb_slot_server_stats",
-                     "psb_slot_server_destroy"):
+                     "psb_slot_server_collect", "psb_slot_server_collect_edges", "psb_slot_server_poll",
+                     "psb_slot_server_stats", "psb_slot_server_destroy", "psb_stream_server_create", "psb_stream_push",
+                     "psb_stream_poll", "psb_stream_latencies", "psb_stream_reset", "psb_stream_server_info",
+                     "psb_stream_server_destroy"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -566,6 +568,67 @@ class SlotServer:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().psb_slot_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class StreamServer:
+    """psb_stream_server: sliding-window decoding of live syndrome streams through the slot server.  Each of
+    n_streams streams is one run of the layered graph `g`; push its layers as they arrive, poll for the
+    committed result.  Close it before any device-wide synchronisation (its slot kernel keeps running)."""
+
+    def __init__(self, g, layer_size: int, window_layers: int, commit_layers: int, n_streams: int, slots: int = 0,
+                 **opts):
+        u = np.ascontiguousarray(g.u, np.int32); v = np.ascontiguousarray(g.v, np.int32)
+        w = np.ascontiguousarray(g.w, np.int32); o = np.ascontiguousarray(g.obs_mask, np.uint64)
+        desc = _GraphDesc(g.num_detectors, len(u), u.ctypes.data, v.ctypes.data, w.ctypes.data, o.ctypes.data)
+        c = _make_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().psb_stream_server_create(ctypes.byref(desc), ctypes.c_int32(layer_size),
+                                              ctypes.c_int32(window_layers), ctypes.c_int32(commit_layers),
+                                              ctypes.byref(c), ctypes.c_int32(n_streams), ctypes.c_int32(slots),
+                                              ctypes.byref(h)), "psb_stream_server_create")
+        self._h = h
+        nw, ns, nl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().psb_stream_server_info(h, ctypes.byref(nw), ctypes.byref(ns), ctypes.byref(nl)),
+               "psb_stream_server_info")
+        self.n_windows, self.n_shapes, self.n_layers = nw.value, ns.value, nl.value
+
+    def push(self, stream: int, first_layer: int, n_layers: int, row):
+        """row: the stream's packed syndrome row over the whole graph (only the pushed layers' bits are read)."""
+        r = np.ascontiguousarray(row, np.uint8)
+        _check(lib().psb_stream_push(self._h, ctypes.c_int32(stream), ctypes.c_int32(first_layer),
+                                     ctypes.c_int32(n_layers), ctypes.c_void_p(r.ctypes.data)), "psb_stream_push")
+
+    def poll(self, stream: int) -> dict:
+        done, cl, st = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        w, ob = ctypes.c_int64(), ctypes.c_uint64()
+        _check(lib().psb_stream_poll(self._h, ctypes.c_int32(stream), ctypes.byref(done), ctypes.byref(cl),
+                                     ctypes.byref(w), ctypes.byref(ob), ctypes.byref(st)), "psb_stream_poll")
+        return dict(done=bool(done.value), committed_layers=cl.value, weight=w.value, obs=ob.value, status=st.value)
+
+    def latencies(self, stream: int, decode: bool = False):
+        """Nanoseconds from each committed window's last layer arriving to its commit; with decode=True also
+        (second array) from its submission to the slot server to its decoded result."""
+        n = ctypes.c_int32()
+        buf = np.zeros(max(self.n_windows, 1), np.int64)
+        dec = np.zeros_like(buf)
+        _check(lib().psb_stream_latencies(self._h, ctypes.c_int32(stream), ctypes.c_int32(len(buf)),
+                                          ctypes.c_void_p(buf.ctypes.data), ctypes.c_void_p(dec.ctypes.data),
+                                          ctypes.byref(n)), "psb_stream_latencies")
+        return (buf[: n.value].copy(), dec[: n.value].copy()) if decode else buf[: n.value].copy()
+
+    def reset(self, stream: int):
+        _check(lib().psb_stream_reset(self._h, ctypes.c_int32(stream)), "psb_stream_reset")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().psb_stream_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

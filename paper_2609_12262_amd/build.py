@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libpsb.so")
 REPLAY = os.path.join(HERE, "libpsb_replay.so")
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("psb_lib.hip", "psb_lane.hip", "psb_server.hip", "psb_tune.hip", "psb_window.hip", "psb_complementary.hip", "psb_slots.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("psb_lib.hip", "psb_lane.hip", "psb_server.hip", "psb_tune.hip", "psb_window.hip", "psb_complementary.hip", "psb_slots.hip", "psb_stream.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

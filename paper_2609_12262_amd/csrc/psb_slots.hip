@@ -522,9 +522,9 @@ extern "C" int32_t psb_slot_server_submit_many(psb_slot_server* S, int32_t n, co
   return PSB_OK;
 }
 
-extern "C" int32_t psb_slot_server_collect(psb_slot_server* S, int32_t max, uint64_t* tickets, int64_t* weight,
-                                           uint64_t* obs, int32_t* status, int64_t* latency_ns) {
-  if (!S || max < 0 || (max > 0 && !tickets)) return fail(PSB_E_INVALID, "null argument");
+static int32_t collect_common(psb_slot_server* S, int32_t max, uint64_t* tickets, int64_t* weight, uint64_t* obs,
+                              int32_t* status, int64_t* latency_ns, int32_t* edges, int64_t edges_stride,
+                              int64_t* n_edges) {
   std::lock_guard<std::mutex> lk(S->mu);
   int32_t k = 0;
   while (k < max && !S->finished.empty()) {
@@ -536,12 +536,31 @@ extern "C" int32_t psb_slot_server_collect(psb_slot_server* S, int32_t max, uint
     tickets[k] = t;
     if (weight) weight[k] = R.weight;
     if (obs) obs[k] = R.obs;
-    if (status) status[k] = R.status;
+    if (status) status[k] = (edges && R.n_edges > edges_stride && R.status == PSB_S_OK) ? PSB_S_EDGES_TRUNCATED : R.status;
     if (latency_ns) latency_ns[k] = std::chrono::duration_cast<std::chrono::nanoseconds>(R.t_done - R.t_submit).count();
+    if (edges) {
+      const int64_t m = std::min<int64_t>((int64_t)R.edges.size(), edges_stride);
+      if (m > 0) memcpy(edges + (int64_t)k * edges_stride, R.edges.data(), (size_t)m * 4);
+      n_edges[k] = R.n_edges;
+    }
     S->reqs.erase(it);
     ++k;
   }
   return k;
+}
+
+extern "C" int32_t psb_slot_server_collect(psb_slot_server* S, int32_t max, uint64_t* tickets, int64_t* weight,
+                                           uint64_t* obs, int32_t* status, int64_t* latency_ns) {
+  if (!S || max < 0 || (max > 0 && !tickets)) return fail(PSB_E_INVALID, "null argument");
+  return collect_common(S, max, tickets, weight, obs, status, latency_ns, nullptr, 0, nullptr);
+}
+
+extern "C" int32_t psb_slot_server_collect_edges(psb_slot_server* S, int32_t max, uint64_t* tickets, int64_t* weight,
+                                                 uint64_t* obs, int32_t* status, int64_t* latency_ns, int32_t* edges,
+                                                 int64_t edges_stride, int64_t* n_edges) {
+  if (!S || max < 0 || edges_stride < 0 || (max > 0 && (!tickets || !edges || !n_edges)))
+    return fail(PSB_E_INVALID, "null argument or negative stride");
+  return collect_common(S, max, tickets, weight, obs, status, latency_ns, edges, edges_stride, n_edges);
 }
 
 extern "C" int32_t psb_slot_server_poll(psb_slot_server* S, uint64_t ticket, int32_t* done, int64_t* weight,

@@ -1,21 +1,13 @@
-// Sliding-window decoding of a layered detector graph (Introduction: decoding
-// a stream of syndrome-extraction rounds in overlapping windows, committing
-// the corrections of the oldest rounds).  The detectors come in layers of
-// equal size (one layer per round).  Window k covers layers
-// [k*C, k*C + W); inside it:
-//   * edges with both ends in the window are kept;
-//   * an edge from the window to a later layer becomes a boundary edge at its
-//     window end (the future is open);
-//   * an edge to an earlier layer is dropped (the past is committed; its
-//     effect is already in the running syndrome).
-// The window's MWEM is decoded with psb_decode_batch.  The matched edges whose
-// lower layer lies in the window's first C layers are committed: their
-// weights and observable masks are accumulated and both of their endpoints
-// are flipped in the running syndrome, which resolves every detector of the
-// committed layers (all of their edges in the window are committed) and
-// carries the flips of edges into the next window's first layer.  The last
-// window reaches the final layer and commits everything; afterwards the
-// running syndrome must be empty.
+// Sliding-window decoding of a batch of layered detector graphs' syndrome
+// streams (Introduction: decoding a stream of syndrome-extraction rounds in
+// overlapping windows, committing the corrections of the oldest rounds).  The
+// window rule is in window_rule.h.  Each window's MWEM is decoded with
+// psb_decode_batch; its committed edges' weights and observable masks are
+// accumulated and both of their endpoints are flipped in the running
+// syndrome, which resolves every detector of the committed layers and carries
+// the flips of edges into the next window's first layer.  The last window
+// reaches the final layer and commits everything; afterwards the running
+// syndrome must be empty.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -26,6 +18,7 @@
 #include <vector>
 
 #include "../../include/psb.h"
+#include "window_rule.h"
 
 namespace psb_host { int32_t fail(int32_t code, const std::string& msg); }
 using psb_host::fail;
@@ -173,72 +166,34 @@ extern "C" int32_t psb_window_plan_create(const psb_graph_desc* desc, int32_t la
   auto P = std::unique_ptr<psb_window_plan, int32_t (*)(psb_window_plan*)>(new psb_window_plan(), psb_window_plan_destroy);
   P->n_det = n; P->layer = layer_size; P->n_layers = n / layer_size; P->W = window_layers; P->C = commit_layers;
   P->m = m; P->run_bytes = (n + 7) / 8;
-  const int32_t L = layer_size;
-  std::map<std::vector<int64_t>, int32_t> shape_of;   // window structure -> shape index
-  for (int32_t a = 0;; a += commit_layers) {
-    const bool last = a + window_layers >= P->n_layers;
-    const int32_t b = last ? P->n_layers : a + window_layers;
-    std::vector<int32_t> lu, lv, lw, map;
-    std::vector<uint64_t> lo;
-    std::vector<uint8_t> commit;
-    for (int64_t e = 0; e < m; ++e) {
-      const int32_t u = desc->u[e], v = desc->v[e];
-      const int32_t la = u / L;
-      const bool in_u = la >= a && la < b;
-      int32_t x = -1, y = PSB_BOUNDARY, low = -1;
-      if (v < 0) {
-        if (!in_u) continue;
-        x = u - a * L; low = la;
-      } else {
-        const int32_t lb = v / L;
-        const bool in_v = lb >= a && lb < b;
-        if (in_u && in_v) { x = u - a * L; y = v - a * L; low = std::min(la, lb); }
-        else if (in_u && lb >= b) { x = u - a * L; low = la; }
-        else if (in_v && la >= b) { x = v - a * L; low = lb; }
-        else continue;                                   // outside, or reaching into the committed past
-      }
-      lu.push_back(x); lv.push_back(y); lw.push_back(desc->w[e]); lo.push_back(desc->obs_mask[e]);
-      map.push_back((int32_t)e);
-      commit.push_back((uint8_t)(last || low < a + commit_layers));
+  std::vector<psb_host::WindowShape> hs;
+  std::vector<psb_host::WindowSpan> spans;
+  psb_host::build_windows(desc, layer_size, window_layers, commit_layers, hs, spans);
+  for (const psb_host::WindowShape& H : hs) {
+    Shape S;
+    psb_graph_desc wd{};
+    wd.num_detectors = H.n_det; wd.num_edges = (int64_t)H.u.size();
+    wd.u = H.u.data(); wd.v = H.v.data(); wd.w = H.w.data(); wd.obs_mask = H.obs.data();
+    int32_t rc = psb_graph_create(&wd, &S.g);
+    if (rc == PSB_OK) rc = psb_decoder_create(S.g, opts, &S.d);
+    if (rc == PSB_OK && !dev_copy(&S.d_commit, H.commit)) rc = fail(PSB_E_NOMEM, "commit flags");
+    if (rc != PSB_OK) {
+      if (S.d) psb_decoder_destroy(S.d);
+      if (S.g) psb_graph_destroy(S.g);
+      if (S.d_commit) (void)hipFree(S.d_commit);
+      return rc;
     }
-    std::vector<int64_t> key;
-    key.reserve(5 * lu.size() + 1);
-    key.push_back(b - a);
-    for (size_t k = 0; k < lu.size(); ++k) {
-      key.push_back(lu[k]); key.push_back(lv[k]); key.push_back(lw[k]); key.push_back((int64_t)lo[k]);
-      key.push_back(commit[k]);
-    }
-    auto it = shape_of.find(key);
-    int32_t si;
-    if (it != shape_of.end()) {
-      si = it->second;
-    } else {
-      Shape S;
-      psb_graph_desc wd{};
-      wd.num_detectors = (b - a) * L; wd.num_edges = (int64_t)lu.size();
-      wd.u = lu.data(); wd.v = lv.data(); wd.w = lw.data(); wd.obs_mask = lo.data();
-      int32_t rc = psb_graph_create(&wd, &S.g);
-      if (rc == PSB_OK) rc = psb_decoder_create(S.g, opts, &S.d);
-      if (rc == PSB_OK && !dev_copy(&S.d_commit, commit)) rc = fail(PSB_E_NOMEM, "commit flags");
-      if (rc != PSB_OK) {
-        if (S.d) psb_decoder_destroy(S.d);
-        if (S.g) psb_graph_destroy(S.g);
-        if (S.d_commit) (void)hipFree(S.d_commit);
-        return rc;
-      }
-      S.n_det = wd.num_detectors; S.nbytes = psb_graph_syndrome_bytes(S.g); S.m = wd.num_edges;
-      S.stride = psb_decoder_edges_per_shot(S.d);
-      si = (int32_t)P->shapes.size();
-      P->shapes.push_back(S);
-      shape_of.emplace(std::move(key), si);
-      P->max_win_bytes = std::max(P->max_win_bytes, S.nbytes);
-      P->max_stride = std::max(P->max_stride, S.stride);
-    }
+    S.n_det = wd.num_detectors; S.nbytes = psb_graph_syndrome_bytes(S.g); S.m = wd.num_edges;
+    S.stride = psb_decoder_edges_per_shot(S.d);
+    P->shapes.push_back(S);
+    P->max_win_bytes = std::max(P->max_win_bytes, S.nbytes);
+    P->max_stride = std::max(P->max_stride, S.stride);
+  }
+  for (const psb_host::WindowSpan& sp : spans) {
     Window w;
-    w.first_layer = a; w.shape = si;
-    if (!dev_copy(&w.d_map, map)) return fail(PSB_E_NOMEM, "edge map");
+    w.first_layer = sp.first_layer; w.shape = sp.shape;
+    if (!dev_copy(&w.d_map, sp.map)) return fail(PSB_E_NOMEM, "edge map");
     P->windows.push_back(w);
-    if (last) break;
   }
   std::vector<int32_t> u(desc->u, desc->u + m), v(desc->v, desc->v + m), wv(desc->w, desc->w + m);
   std::vector<uint64_t> ob(desc->obs_mask, desc->obs_mask + m);
