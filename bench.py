@@ -32,11 +32,11 @@ GRAPHS = {
 }
 
 
-def make_graph(kind, d, p):
-    """The detector graph of one of the workloads in GRAPHS."""
+def make_graph(kind, d, p, q=None):
+    """The detector graph of one of the workloads in GRAPHS (q: the phenomenological timelike rate, default p)."""
     import synth
     if kind == "phenom":
-        return synth.rotated_phenom_graph(d, p)
+        return synth.rotated_phenom_graph(d, p, q=q)
     if kind == "circuit_x":
         return synth.rotated_circuit_x_graph(d, p)
     return synth.rotated_circuit_graph(d, p, kind.split("_", 1)[1])
@@ -524,7 +524,7 @@ def complementary(args):
     import torch
     import synth
     import paper_2609_12262_amd as psb
-    g = make_graph(args.graph, args.d, args.p)
+    g = make_graph(args.graph, args.d, args.p, args.q)
     log(f"sampling {args.shots} shots d={args.d} p={args.p} graph={args.graph}")
     shots = synth.sample(g, args.shots, seed=3)
     plan = psb.ComplementaryPlan(g, 0, tiebreak_seed=0x5EED)
@@ -556,6 +556,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--d", type=int, default=21)
     ap.add_argument("--p", type=float, default=0.005)
+    ap.add_argument("--q", type=float, default=None, help="phenomenological graphs: timelike rate (default p)")
     ap.add_argument("--shots", type=int, default=50000)
     ap.add_argument("--mode", type=int, default=0, help="0 partition-and-fuse, 1 global sparse blossom")
     ap.add_argument("--graph", default="phenom", choices=list(GRAPHS),
@@ -640,7 +641,7 @@ def main():
     import paper_2609_12262_amd as psb
 
     seed_sample = {0.005: 3, 0.001: 4}.get(args.p, 3)
-    g = make_graph(args.graph, args.d, args.p)
+    g = make_graph(args.graph, args.d, args.p, args.q)
     log(f"sampling {args.shots} shots d={args.d} p={args.p} graph={args.graph}")
     shots = synth.sample(g, args.shots, seed=seed_sample)
     G = psb.Graph.from_synth(g)
@@ -701,7 +702,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int128", "data": "synthetic",
         "config": {"workload": (f"{GRAPHS[args.graph]}, d={args.d}, {args.d} rounds, "
-                                f"{'p=q' if args.graph == 'phenom' else 'p'}={args.p}, {args.shots} shots per step, "
+                                f"{('p=q' if args.q is None else 'p') if args.graph == 'phenom' else 'p'}={args.p}"
+                                f"{'' if args.q is None else f', q={args.q}'}, {args.shots} shots per step, "
                                 f"one persistent launch"),
                    "d": args.d, "rounds": args.d, "p": args.p, "shots_per_step": args.shots,
                    "mode": "partition-and-fuse" if args.mode == 0 else "global sparse blossom",

@@ -11,7 +11,11 @@ constexpr int NB_PAD = -2;
 // Neighbour-table codes of an adjacency slot without an explored neighbour.
 constexpr int XNB_NONE = -1, XNB_BOUNDARY = -2, XNB_PAD = -3;
 constexpr int MATE_BOUNDARY = -2;
-constexpr int MAXH = 6;           // deepest path enumeration used by clustering
+// Deepest path walk of the clustering search.  The hop bound floor(b_k/w_min)
+// assumes every edge is the lightest; the walk itself is cut by distance, so
+// even graphs whose light edges allow 7-9 hops (timelike q = 0.2 against
+// spatial p = 0.001-0.005) walk only a few hundred paths per event.
+constexpr int MAXH = 16;
 constexpr int S_OK = 0, S_CAPACITY = 1, S_INFEASIBLE = 2, S_TRUNC = 3, S_INTERNAL = 4, S_OVERFLOW = 5;
 
 // Byte offsets of the per-shot state that the event loop touches on every

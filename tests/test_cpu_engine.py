@@ -64,12 +64,13 @@ def test_cpu_engine_phenomenological(exe, d, p, n, seed):
     assert tied <= 0.1 * n
 
 
-@pytest.mark.parametrize("q,reading", [(0.1, 0), (0.1, 1), (0.05, 0)])
+@pytest.mark.parametrize("q,reading", [(0.1, 0), (0.1, 1), (0.05, 0), (0.2, 0), (0.3, 1)])
 def test_cpu_engine_deep_clustering_search(exe, q, reading):
     """Cheap timelike edges (q above p) make the level-1 search need paths of
-    four (q = 0.05) or five (q = 0.1) edges: the generic walk, whose last hop
-    reads the near lists.  Results, event counts, E_ideal and the number of
-    processing clusters equal the oracles on every shot."""
+    four (q = 0.05), five (q = 0.1), eight (q = 0.2) or twelve (q = 0.3)
+    edges: the generic walk, whose last hop reads the near lists.  Results,
+    event counts, E_ideal and the number of processing clusters equal the
+    oracles on every shot."""
     g = synth.rotated_phenom_graph(7, 0.003, q=q)
     s = synth.sample(g, 300, seed=16)
     res = ce.run(exe, g, s.syndromes, reading=reading)

@@ -310,15 +310,15 @@ def test_sliding_windows_on_circuit_noise_graphs(model):
 
 
 def test_complementary_gap_wide_weight_range():
-    """A graph whose lightest edge is under a third of the heaviest (timelike
-    flips at q=0.2) needs level-1 search paths deeper than the clustering
-    kernel enumerates, so a partition-and-fuse decoder is refused; the
+    """A graph whose lightest edge is under a tenth of the heaviest (timelike
+    flips at q=0.4) needs level-1 search paths deeper than the clustering
+    kernel walks, so a partition-and-fuse decoder is refused; the
     complementary plan then takes its MWEM side from global sparse blossom
     and still equals the oracle."""
     import torch
     import oracle
     import paper_2609_12262_amd as psb
-    g = synth.rotated_phenom_graph(5, 0.005, q=0.2)
+    g = synth.rotated_phenom_graph(5, 0.005, q=0.4)
     G = psb.Graph.from_synth(g)
     with pytest.raises(psb.PsbError, match="needs paths of more than"):
         psb.Decoder(G, tiebreak_seed=SEED)

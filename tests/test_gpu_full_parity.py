@@ -105,3 +105,20 @@ def test_d5_config_one_launch_per_shot():
     bad = compare(g, s.syndromes, res, range(n))
     say(f"d5 one launch per shot: {n} shots, {len(bad)} differ")
     assert not bad, bad[:5]
+
+
+def test_d21_timelike_q02_partition_mode_every_shot():
+    """Decoding weights for timelike flips at q = 0.2 against spatial
+    p = 0.005 (d=21, 21 rounds): the level-1 clustering search needs paths of
+    up to seven edges (the generic walk with near lists).  The syndromes are
+    sampled at p = q = 0.005 on the same edges (at q = 0.2 itself about 40 %
+    of the detectors fire, beyond every tier's capacity); 20,000 shots in one
+    launch with the default partition-and-fuse decoder, every one equal to
+    the oracle on the q = 0.2 weights."""
+    g = synth.rotated_phenom_graph(21, 0.005, q=0.2)
+    gs = synth.rotated_phenom_graph(21, 0.005)
+    assert np.array_equal(g.u, gs.u) and np.array_equal(g.v, gs.v)
+    s = synth.sample(gs, 20000, seed=170)
+    say("d21 q=0.2 weights: decoding 20000 shots")
+    res = gpu_decode(g, s.syndromes)
+    _every_shot(g, s.syndromes, res, "d21 q=0.2 weights")

@@ -92,7 +92,7 @@ def test_random_and_repetition_graphs():
     assert not compare(g, s.syndromes, res, range(500))
 
 
-@pytest.mark.parametrize("graph", ["phenom", "circuit_uniform", "circuit_physical"])
+@pytest.mark.parametrize("graph", ["phenom", "circuit_uniform", "circuit_physical", "phenom_q02"])
 def test_cluster_levels_equal_oracle_clustering(graph):
     """Processing-cluster levels (Methods, Algorithm "Clustering") against the
     oracle's plain construction: identical below the final level; at the
@@ -100,10 +100,13 @@ def test_cluster_levels_equal_oracle_clustering(graph):
     a later level to the same, single remaining component).  The level-1
     search enumerates paths of up to floor(b_1 / w_min) edges: 2 on the
     phenomenological and physical-noise graphs, 3 on the uniform-noise graph
-    (its lightest edges are about 0.55 of the heaviest).  The final MWEM does
-    not depend on the clusters (Theorem 1), so only this test checks them."""
+    (its lightest edges are about 0.55 of the heaviest), 8 on a graph with
+    timelike flips at q = 0.2 (the generic walk).  The final MWEM does not
+    depend on the clusters (Theorem 1), so only this test checks them."""
     if graph == "phenom":
         g = synth.rotated_phenom_graph(11, 0.003)
+    elif graph == "phenom_q02":
+        g = synth.rotated_phenom_graph(11, 0.003, q=0.2)
     else:
         g = synth.rotated_circuit_graph(11, 0.003, graph.split("_")[1])
     s = synth.sample(g, 300, seed=14)
