@@ -103,7 +103,10 @@ typedef struct {
    * global workspace slot, the rest in LDS (default; most wavefronts per CU);
    * 2 = radius offsets in the workspace, event cache and region bases in LDS;
    * 3 = all per-shot state in LDS (fewest dependent global loads per event,
-   * fewer wavefronts per CU).  Results do not depend on it. */
+   * fewer wavefronts per CU); 4 = all per-shot state in the workspace, no LDS
+   * (for whole-graph capacities, whose LDS block would allow few wavefronts
+   * per CU; not with event_accounting, and not for the slot-level server).
+   * Results do not depend on it. */
   int32_t fast_lds_state;
   /* 1 = per-cluster event accounting (Methods, numerical evaluation: the
    * parallel event count E_ideal of hierarchical execution): each applied

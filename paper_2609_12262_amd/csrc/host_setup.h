@@ -205,7 +205,8 @@ static void plan_state(psb::StateLayout& SL, const psb::Caps& cap, int lean) {
 
 static int32_t next_pow2(int64_t x) { int32_t p = 1; while (p < x) p <<= 1; return p; }
 
-// Capacities and global workspace layout for one slot of a tier.  A slot is
+// Capacities and global workspace layout for one slot of a tier.  lean >= 3
+// (wavefront tiers): as lean 2, and the state block itself in the workspace.  A slot is
 // one wavefront (wavefront tiers: per-shot state in LDS, 64 lanes share the
 // clustering hit buffers) or one lane (lane tier: the Lds header and the state
 // block sit at the start of the slot, pools are sized more tightly and a shot
@@ -224,11 +225,12 @@ static void plan_tier(Params& P, int32_t n, int32_t deg, int64_t n_edges, const 
   P.hitcap = 32;
   P.bdc = 8;
   P.max_events = (int64_t)64 * ((int64_t)cap.xcap + 64 * (int64_t)d);
-  plan_state(P.SL, cap, lean);
+  plan_state(P.SL, cap, lean >= 3 ? 2 : lean);
+  P.state_ws = (!lane_slot && lean >= 3) ? 1 : 0;
   WsLayout& L = P.L;
   int64_t off = 0;
   auto take = [&](int64_t bytes) { int64_t o = off; off = align256(off + bytes); return o; };
-  L.state = lane_slot ? take(64 + P.SL.total) : 0;
+  L.state = (lane_slot || P.state_ws) ? take(64 + P.SL.total) : 0;
   L.ce = take(4LL * psb::CE_COUNT * P.cecap); L.bc = take(8LL * P.bccap); L.lg = take(12LL * P.lcap);
   L.level = take(d); L.uf = take(4LL * d);
   L.cl_a = take(4LL * d); L.cl_b = take(4LL * d); L.cl_c = take(4LL * d); L.cl_d = take(4LL * d);

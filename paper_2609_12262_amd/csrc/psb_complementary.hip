@@ -155,17 +155,20 @@ extern "C" int32_t psb_comp_plan_create(const psb_graph_desc* desc, int32_t obs_
   // once a region reaches an x_j the whole chain and the observable boundary
   // of every round are explored, and at d = 21 most of the graph.  Unless the
   // caller chose otherwise, the first tier is a wavefront tier sized to the
-  // whole rewritten graph (up to 8,192 detectors), with the event cache,
-  // region bases and radius offsets in the workspace (12 bytes of LDS per
-  // detector, 30 per region).  Graphs the overflow tier holds whole (1,024
-  // detectors) keep 208 regions per shot, which leaves room for several
-  // wavefronts per compute unit; larger ones get 512 (at most 512 detection
-  // events; about 79 KB of LDS at d = 21, two wavefronts per compute unit)
-  const bool caller_chose = opts && (opts->fast_max_nodes != 0 || opts->fast_max_regions != 0 || opts->first_tier != 0);
+  // whole rewritten graph (up to 8,192 detectors).  Graphs the overflow tier
+  // holds whole (1,024 detectors) keep 208 regions per shot and the usual
+  // placement (event cache, region bases and radius offsets in the workspace,
+  // the rest in LDS); larger ones get 512 regions (at most 512 detection
+  // events) and keep the whole per-shot state in the workspace: in LDS it
+  // would take about 79 KB at d = 21 and leave room for two wavefronts per
+  // compute unit instead of sixteen
+  const bool caller_chose = opts && (opts->fast_max_nodes != 0 || opts->fast_max_regions != 0 ||
+                                     opts->first_tier != 0 || opts->fast_lds_state != 0);
   if (!caller_chose) {
     o.first_tier = 0;
     o.fast_max_nodes = (int32_t)std::min<int64_t>(n + nx, 8192);
     o.fast_max_regions = n + nx > 1024 ? 512 : 208;
+    if (n + nx > 1024) o.fast_lds_state = 4;
   }
   int32_t rc = psb_graph_create(&cd, &P->g);
   if (rc == PSB_OK) rc = psb_decoder_create(P->g, &o, &P->d);

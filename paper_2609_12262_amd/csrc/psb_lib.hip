@@ -59,11 +59,14 @@ __global__ void psb_zero_kernel(int32_t* p, int n, uint64_t* t_start) {
 // ACCT: per-cluster event accounting compiled in (ACCT = 0 removes it).
 // DEEP: the clustering search's generic walk for paths of more than three
 // edges compiled in (only graphs whose levels need it get it).
-template <int TIER, int ACCT, int DEEP>
+// WS: the Lds header and state block sit in the slot's workspace instead of
+// LDS (first tier only, Params::state_ws).
+template <int TIER, int ACCT, int DEEP, int WS = 0>
 __global__ __launch_bounds__(64, 4) void psb_decode_kernel(Params P) {
   extern __shared__ __align__(16) char psb_dyn_lds[];
-  ew::Lds* S = (ew::Lds*)psb_dyn_lds;
-  char* state = psb_dyn_lds + 64;
+  char* base = WS ? P.ws + (int64_t)blockIdx.x * P.L.total + P.L.state : psb_dyn_lds;
+  ew::Lds* S = (ew::Lds*)base;
+  char* state = base + 64;
   ew::Ctx c;
   ew::ctx_init(c, &P, S, state, blockIdx.x);
   if (!ACCT) c.acct = nullptr;
@@ -94,7 +97,12 @@ __global__ __launch_bounds__(64, 4) void psb_decode_kernel(Params P) {
 
 // The decode kernel instantiation for a tier, accounting and search depth
 // class (0: paths of up to two edges, 1: three, 2: the generic walk).
-static const void* decode_kernel_fn(int tier, bool acct, int deep) {
+static const void* decode_kernel_fn(int tier, bool acct, int deep, bool ws = false) {
+  if (ws) {                                       // first tier without accounting only (host-checked)
+    const void* kw[3] = {(const void*)psb_decode_kernel<0, 0, 0, 1>, (const void*)psb_decode_kernel<0, 0, 1, 1>,
+                         (const void*)psb_decode_kernel<0, 0, 2, 1>};
+    return kw[deep];
+  }
   const void* k[2][2][3] = {
       {{(const void*)psb_decode_kernel<0, 0, 0>, (const void*)psb_decode_kernel<0, 0, 1>,
         (const void*)psb_decode_kernel<0, 0, 2>},
@@ -110,7 +118,7 @@ static const void* decode_kernel_fn(int tier, bool acct, int deep) {
 static hipError_t launch_decode_kernel(int tier, bool acct, int deep, unsigned grid, size_t lds, hipStream_t s,
                                        const Params& P) {
   void* args[] = {(void*)&P};
-  return hipLaunchKernel(decode_kernel_fn(tier, acct, deep), dim3(grid), dim3(64), args, lds, s);
+  return hipLaunchKernel(decode_kernel_fn(tier, acct, deep, P.state_ws != 0), dim3(grid), dim3(64), args, lds, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,7 +308,11 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   // workspace slot; or one shot per wavefront, state in LDS) and the
   // overflow tier (one shot per wavefront, large LDS state)
   if (opts.first_tier != 0 && opts.first_tier != 1) { delete D; return fail(PSB_E_INVALID, "first_tier must be 0 or 1"); }
-  if (opts.fast_lds_state < 0 || opts.fast_lds_state > 3) { delete D; return fail(PSB_E_INVALID, "fast_lds_state must be 0..3"); }
+  if (opts.fast_lds_state < 0 || opts.fast_lds_state > 4) { delete D; return fail(PSB_E_INVALID, "fast_lds_state must be 0..4"); }
+  if (opts.fast_lds_state == 4 && opts.event_accounting) {
+    delete D;
+    return fail(PSB_E_UNSUPPORTED, "fast_lds_state 4 has no event-accounting kernel");
+  }
   if (opts.event_accounting != 0 && opts.event_accounting != 1) { delete D; return fail(PSB_E_INVALID, "event_accounting must be 0 or 1"); }
   if (opts.serial_level_one != 0 && opts.serial_level_one != 1) { delete D; return fail(PSB_E_INVALID, "serial_level_one must be 0 or 1"); }
   const bool acct = opts.event_accounting == 1;
@@ -324,7 +336,7 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   // and radius offsets in the workspace: its LDS block (about 10 KB at the
   // default capacities) lets 16 wavefronts share a CU.  fast_lds_state moves
   // them into LDS (fewer wavefronts per CU, shorter dependent-load chains).
-  static const int kLean[4] = {2, 2, 1, 0};
+  static const int kLean[5] = {2, 2, 1, 0, 3};
   plan_tier(PF, n, g->deg, g->n_edges, cf, D->first_lane, D->first_lane ? 0 : kLean[opts.fast_lds_state], acct);
   plan_tier(PO, n, g->deg, g->n_edges, co, false, 0, acct);
   for (Params* P : {&PF, &PO}) {
@@ -342,7 +354,7 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
                                      "fast_max_regions / max_defects_per_shot)");
     }
   }
-  D->lds_fast = D->first_lane ? 0 : 64 + (size_t)PF.SL.total;
+  D->lds_fast = (D->first_lane || PF.state_ws) ? 0 : 64 + (size_t)PF.SL.total;
   D->lds_ovf = 64 + (size_t)PO.SL.total;
   if (D->lds_ovf > 160 * 1024) {
     delete D;
@@ -363,9 +375,9 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
     HIP_TRY(psb_lane_occupancy(&per_cu));
     if (per_cu < 1) D->fast_enabled = false;
   } else if (D->fast_enabled) {
-    HIP_TRY(hipFuncSetAttribute(decode_kernel_fn(0, D->acct, D->deep), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)D->lds_fast));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_kernel_fn(0, D->acct, D->deep), 64, D->lds_fast));
+    const void* kf = decode_kernel_fn(0, D->acct, D->deep, PF.state_ws != 0);
+    HIP_TRY(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)D->lds_fast));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf, 64, D->lds_fast));
     if (per_cu < 1) D->fast_enabled = false;
   }
   HIP_TRY(hipFuncSetAttribute(decode_kernel_fn(1, D->acct, D->deep), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -478,8 +490,9 @@ extern "C" int32_t psb_decoder_reserve(psb_decoder* D, int64_t max_batch) {
 // when the decoder has no wavefront first tier or keeps a hash in LDS.
 int32_t psb_decoder_first_tier(const psb_decoder* D, psb::Params* P, int32_t* lds_bytes, int32_t* slots) {
   if (!D || !P || !lds_bytes || !slots) return fail(PSB_E_INVALID, "null argument");
-  if (!D->fast_enabled || D->first_lane || D->P_fast.cap.hcap != 0)
-    return fail(PSB_E_UNSUPPORTED, "slot-level serving needs a wavefront first tier with a direct detector map");
+  if (!D->fast_enabled || D->first_lane || D->P_fast.cap.hcap != 0 || D->P_fast.state_ws)
+    return fail(PSB_E_UNSUPPORTED, "slot-level serving needs a wavefront first tier with its state in LDS and a "
+                                   "direct detector map");
   *P = D->P_fast;
   *lds_bytes = (int32_t)D->lds_fast;
   *slots = D->slots_fast;

@@ -36,7 +36,8 @@ struct StateLayout {
 // Byte offsets of the per-slot global workspace (pools touched per matcher
 // event or once per shot).
 struct WsLayout {
-  int64_t state;                                 // lane tier: Lds header + StateLayout block; else unused
+  int64_t state;                                 // lane tier, or a wavefront tier with Params::state_ws: Lds
+                                                 // header + StateLayout block; else unused
   int64_t ce, bc, lg;                            // compressed edges, blossom cycles, arrival log
   int64_t level, uf, cl_a, cl_b, cl_c, cl_d, bdl, hit;   // clustering
   int64_t cid;                                   // processing cluster of each detection event (its root event)
@@ -105,7 +106,8 @@ struct Caps {
 
 struct Params {
   // graph (device pointers)
-  int32_t n_det, deg, nbytes, pad0;
+  int32_t n_det, deg, nbytes;
+  int32_t state_ws;       // wavefront tier: the Lds header and state block sit in the slot's workspace (at L.state)
   int64_t n_edges;
   const int32_t* nbr;     // [n_det*deg]: neighbour detector, -1 boundary, -2 padding
   const int32_t* eid;     // [n_det*deg]: edge id

@@ -136,10 +136,12 @@ def test_schedule_ratio_does_not_change_result(q):
     assert not bad, bad[:5]
 
 
-@pytest.mark.parametrize("lds_state,caps", [(2, (0, 0)), (3, (0, 0)), (3, (1024, 768))])
+@pytest.mark.parametrize("lds_state,caps", [(2, (0, 0)), (3, (0, 0)), (3, (1024, 768)), (4, (0, 0)),
+                                            (4, (2048, 1024))])
 def test_first_tier_state_placement_parity(lds_state, caps):
-    """Where the first tier keeps its per-shot state (LDS or workspace) does
-    not change results: d=13, p=0.005, every shot equals the oracle."""
+    """Where the first tier keeps its per-shot state (LDS, workspace, or all
+    of it in the workspace with no LDS) does not change results: d=13,
+    p=0.005, every shot equals the oracle."""
     g = synth.rotated_phenom_graph(13, 0.005)
     s = synth.sample(g, 3000, seed=91)
     res = gpu_decode(g, s.syndromes, fast_lds_state=lds_state, fast_max_nodes=caps[0], fast_max_regions=caps[1],
