@@ -1113,11 +1113,12 @@ PSB_DEV void cluster(Ctx& c) {
       // base) in chunks of four, each chunk's neighbours and their
       // detector-map entries loaded before any of them is visited (visit
       // order unchanged)
-      auto leaf_row = [&](int x, i128 base) {
+      // (hpre: x's detector-map cell when the caller has loaded it, else -3)
+      auto leaf_row = [&](int x, i128 base, int hpre = -3) {
         const int64_t r0 = (int64_t)x * deg;
         if (use_near) {
           // the events next to x, from its near list, then x's boundary slots
-          const int h = c.dmap[x];
+          const int h = hpre != -3 ? hpre : c.dmap[x];
           int e = h >= 0 ? c.ehead[h] : (h <= -2 ? -2 - h : -1);
           while (e >= 0) {
             const NearEntry ne = c.near[e];
@@ -1159,6 +1160,34 @@ PSB_DEV void cluster(Ctx& c) {
             visit(y, c.eid[(int64_t)u * deg + j], d1);
             if (y < 0 || d1 >= bk) continue;
             if (DEEP == 0 || H == 2) { leaf_row(y, d1); continue; }
+            if (use_near) {
+              // the second hop four neighbours at a time: their ids, detector-map
+              // cells (event index, or near-list head) and weights are loaded
+              // before any of them is visited (visit order unchanged); an edge
+              // id is read only for a boundary slot
+              const int64_t r1 = (int64_t)y * deg;
+              for (int k0 = 0; k0 < deg; k0 += 4) {
+                int zs[4], hs[4];
+                i128 ds[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) zs[t] = k0 + t < deg ? c.nbr[r1 + k0 + t] : NB_PAD;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                  hs[t] = zs[t] >= 0 ? (int)c.dmap[zs[t]] : -1;
+                  ds[t] = zs[t] != NB_PAD ? d1 + c.wt[r1 + k0 + t] : (i128)0;
+                }
+                bool end = false;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                  if (end || zs[t] == NB_PAD) { end = true; continue; }
+                  visit(zs[t], zs[t] == NB_BOUNDARY ? c.eid[r1 + k0 + t] : -1, ds[t], hs[t] >= 0 ? hs[t] : -1);
+                  if (zs[t] < 0 || ds[t] >= bk) continue;
+                  leaf_row(zs[t], ds[t], hs[t]);
+                }
+                if (end) break;
+              }
+              continue;
+            }
             for (int k2 = 0; k2 < deg; ++k2) {
               const int z = c.nbr[(int64_t)y * deg + k2];
               if (z == NB_PAD) break;
