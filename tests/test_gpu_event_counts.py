@@ -75,11 +75,12 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("graph,d,p,n,seed,stride", CASES)
-@pytest.mark.parametrize("mode", [0, 1])
+# every workload in partition-and-fuse mode, three of them in global mode as well
+RUNS = [c + (0,) for c in CASES] + [c + (1,) for c in CASES if (c[1], c[2]) in ((21, 0.005), (11, 0.003), (9, 0.03))]
+
+
+@pytest.mark.parametrize("graph,d,p,n,seed,stride,mode", RUNS)
 def test_event_counts_equal_oracle(graph, d, p, n, seed, stride, mode):
-    if mode == 1 and (d, p) not in ((21, 0.005), (11, 0.003), (9, 0.03)):
-        pytest.skip("global mode is compared on three of the workloads")
     g = synth.rotated_phenom_graph(d, p) if graph == "phenom" else synth.rotated_circuit_graph(d, p, "uniform")
     s = synth.sample(g, n, seed=seed)
     say(f"{graph} d={d} p={p} mode={mode}: {n} shots on the GPU")
