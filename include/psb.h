@@ -502,6 +502,11 @@ int32_t psb_stream_server_create(const psb_graph_desc* desc, int32_t layer_size,
  * Layers arrive in order, each once (PSB_E_INVALID otherwise). */
 int32_t psb_stream_push(psb_stream_server* s, int32_t stream, int32_t first_layer, int32_t n_layers,
                         const uint8_t* bits);
+/* psb_stream_push for n streams (streams[i] with rows[i]) that all deliver
+ * the same layer range, under one lock.  Stops at the first refused push
+ * (the earlier ones stand). */
+int32_t psb_stream_push_many(psb_stream_server* s, int32_t n, const int32_t* streams, int32_t first_layer,
+                             int32_t n_layers, const uint8_t* const* rows);
 /* *done = 1 once every window of the stream has committed (or one failed:
  * *status); committed_layers: layers whose corrections are final; weight and
  * obs: of the committed edges so far (any output but done may be NULL). */

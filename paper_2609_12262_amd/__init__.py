@@ -89,7 +89,7 @@ def lib():
                      "psb_window_plan_destroy", "psb_comp_plan_create", "psb_comp_decode",
                      "psb_comp_plan_destroy", "psb_slot_server_create", "psb_slot_server_submit_many",
                      "psb_slot_server_collect", "psb_slot_server_collect_edges", "psb_slot_server_poll",
-                     "psb_slot_server_stats", "psb_slot_server_destroy", "psb_stream_server_create", "psb_stream_push",
+                     "psb_slot_server_stats", "psb_slot_server_destroy", "psb_stream_server_create", "psb_stream_push", "psb_stream_push_many",
                      "psb_stream_poll", "psb_stream_latencies", "psb_stream_reset", "psb_stream_server_info",
                      "psb_stream_server_destroy"):
             getattr(L, name).restype = ctypes.c_int32
@@ -604,6 +604,15 @@ class StreamServer:
         r = np.ascontiguousarray(row, np.uint8)
         _check(lib().psb_stream_push(self._h, ctypes.c_int32(stream), ctypes.c_int32(first_layer),
                                      ctypes.c_int32(n_layers), ctypes.c_void_p(r.ctypes.data)), "psb_stream_push")
+
+    def push_many(self, streams, first_layer: int, n_layers: int, rows):
+        """The same layer range of several streams in one call (rows[i] for streams[i])."""
+        ids = np.ascontiguousarray(streams, np.int32)
+        keep = [np.ascontiguousarray(r, np.uint8) for r in rows]
+        ptrs = (ctypes.c_void_p * len(keep))(*[r.ctypes.data for r in keep])
+        _check(lib().psb_stream_push_many(self._h, ctypes.c_int32(len(ids)), ctypes.c_void_p(ids.ctypes.data),
+                                          ctypes.c_int32(first_layer), ctypes.c_int32(n_layers), ptrs),
+               "psb_stream_push_many")
 
     def poll(self, stream: int) -> dict:
         done, cl, st = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -81,12 +81,18 @@ static void maybe_submit(psb_stream_server* S, int32_t i) {
   const psb_host::WindowSpan& sp = S->spans[T.next];
   if (T.layers < sp.end_layer) return;
   const psb_host::WindowShape& sh = S->shapes[sp.shape];
-  std::vector<uint8_t> row(((size_t)sh.n_det + 7) / 8, 0);
+  // the window's bits [lo, lo + n_det) of the running syndrome, a byte at a time
+  const int32_t nb = (sh.n_det + 7) / 8;
+  std::vector<uint8_t> row(nb, 0);
   const int64_t lo = (int64_t)sp.first_layer * S->L;
-  for (int32_t j = 0; j < sh.n_det; ++j) {
-    const int64_t p = lo + j;
-    if ((T.run[p >> 3] >> (p & 7)) & 1) row[j >> 3] |= (uint8_t)(1u << (j & 7));
+  const int64_t b0 = lo >> 3;
+  const int sh8 = (int)(lo & 7);
+  for (int32_t j = 0; j < nb; ++j) {
+    const uint32_t a = T.run[b0 + j];
+    const uint32_t b = b0 + j + 1 < (int64_t)T.run.size() ? T.run[b0 + j + 1] : 0u;
+    row[j] = (uint8_t)((a >> sh8) | (b << (8 - sh8)));
   }
+  if (sh.n_det & 7) row[nb - 1] &= (uint8_t)((1u << (sh.n_det & 7)) - 1);
   const uint8_t* rp = row.data();
   const int32_t g = sp.shape;
   uint64_t ticket = 0;
@@ -216,21 +222,46 @@ extern "C" int32_t psb_stream_server_create(const psb_graph_desc* desc, int32_t 
   return PSB_OK;
 }
 
+// Takes layers [first_layer, first_layer + n_layers) of one stream (lock held).
+static int32_t push_locked(psb_stream_server* S, int32_t stream, int32_t first_layer, int32_t n_layers,
+                           const uint8_t* bits, Clock::time_point now) {
+  if (!bits) return fail(PSB_E_INVALID, "null syndrome row");
+  if (stream < 0 || stream >= (int32_t)S->streams.size()) return fail(PSB_E_INVALID, "stream out of range");
+  StreamState& T = S->streams[stream];
+  if (first_layer != T.layers) return fail(PSB_E_INVALID, "layers must arrive in order, each once");
+  if (n_layers <= 0 || first_layer + n_layers > S->n_layers) return fail(PSB_E_INVALID, "layer range out of bounds");
+  // XOR bits [lo, hi) of the row into the running syndrome, a byte at a time
+  const int64_t lo = (int64_t)first_layer * S->L, hi = (int64_t)(first_layer + n_layers) * S->L;
+  const int64_t b_lo = lo >> 3, b_hi = (hi - 1) >> 3;
+  for (int64_t b = b_lo; b <= b_hi; ++b) {
+    uint32_t mask = 0xffu;
+    if (b == b_lo) mask &= 0xffu << (lo & 7);
+    if (b == b_hi) mask &= 0xffu >> (7 - ((hi - 1) & 7));
+    T.run[b] ^= (uint8_t)(bits[b] & mask);
+  }
+  for (int32_t l = first_layer; l < first_layer + n_layers; ++l) T.layer_t[l] = now;
+  T.layers += n_layers;
+  maybe_submit(S, stream);
+  return PSB_OK;
+}
+
 extern "C" int32_t psb_stream_push(psb_stream_server* S, int32_t stream, int32_t first_layer, int32_t n_layers,
                                    const uint8_t* bits) {
   if (!S || !bits) return fail(PSB_E_INVALID, "null argument");
   const auto now = Clock::now();
   std::lock_guard<std::mutex> lk(S->mu);
-  if (stream < 0 || stream >= (int32_t)S->streams.size()) return fail(PSB_E_INVALID, "stream out of range");
-  StreamState& T = S->streams[stream];
-  if (first_layer != T.layers) return fail(PSB_E_INVALID, "layers must arrive in order, each once");
-  if (n_layers <= 0 || first_layer + n_layers > S->n_layers) return fail(PSB_E_INVALID, "layer range out of bounds");
-  const int64_t lo = (int64_t)first_layer * S->L, hi = (int64_t)(first_layer + n_layers) * S->L;
-  for (int64_t p = lo; p < hi; ++p)
-    if ((bits[p >> 3] >> (p & 7)) & 1) T.run[p >> 3] ^= (uint8_t)(1u << (p & 7));
-  for (int32_t l = first_layer; l < first_layer + n_layers; ++l) T.layer_t[l] = now;
-  T.layers += n_layers;
-  maybe_submit(S, stream);
+  return push_locked(S, stream, first_layer, n_layers, bits, now);
+}
+
+extern "C" int32_t psb_stream_push_many(psb_stream_server* S, int32_t n, const int32_t* streams, int32_t first_layer,
+                                        int32_t n_layers, const uint8_t* const* rows) {
+  if (!S || n < 0 || (n > 0 && (!streams || !rows))) return fail(PSB_E_INVALID, "null argument");
+  const auto now = Clock::now();
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t rc = push_locked(S, streams[i], first_layer, n_layers, rows[i], now);
+    if (rc != PSB_OK) return rc;
+  }
   return PSB_OK;
 }
 

@@ -190,13 +190,15 @@ extern "C" int32_t psb_replay_oneshot(psb_decoder* const* decs, int32_t n_dec, i
 // Streaming windows at a syndrome rate: layer group g (layers_per_push layers)
 // of every stream is pushed once its last round has been measured, at
 // (g + 1) * layers_per_push * round_s after the start (round_s = 0: as fast as
-// the pushes go), stream after stream; then waits until every stream is done
+// the pushes go), all streams in one call; then waits until every stream is done
 // (at most timeout_s).  The server records each layer's actual arrival.
 extern "C" int32_t psb_stream_replay(psb_stream_server* s, int32_t n_streams, const uint8_t* const* rows,
                                      int32_t n_layers, int32_t layers_per_push, double round_s, double timeout_s,
                                      double* wall_s, double* push_span_s) {
   if (!s || n_streams <= 0 || !rows || n_layers <= 0 || layers_per_push <= 0) return -1;
   using Clock = std::chrono::steady_clock;
+  std::vector<int32_t> ids(n_streams);
+  for (int32_t i = 0; i < n_streams; ++i) ids[i] = i;
   const auto t0 = Clock::now();
   auto since = [&] { return std::chrono::duration<double>(Clock::now() - t0).count(); };
   for (int32_t l0 = 0; l0 < n_layers; l0 += layers_per_push) {
@@ -205,8 +207,7 @@ extern "C" int32_t psb_stream_replay(psb_stream_server* s, int32_t n_streams, co
       const double due = (l0 + n) * round_s;
       while (since() < due) {}
     }
-    for (int32_t i = 0; i < n_streams; ++i)
-      if (psb_stream_push(s, i, l0, n, rows[i]) != 0) return -2;
+    if (psb_stream_push_many(s, n_streams, ids.data(), l0, n, rows) != 0) return -2;
   }
   if (push_span_s) *push_span_s = since();
   for (;;) {

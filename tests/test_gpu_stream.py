@@ -15,11 +15,17 @@ from gpu_helpers import SEED, say
 pytestmark = pytest.mark.gpu
 
 
-def _run_streams(srv, rows, rng, limit_s=120):
-    """Pushes every stream's layers in random chunks, streams interleaved at random; waits for all."""
+def _run_streams(srv, rows, rng, limit_s=120, lockstep=False):
+    """Pushes every stream's layers in random chunks, streams interleaved at random (or, lockstep, the same
+    random chunk of every stream in one push_many call); waits for all."""
     n = len(rows)
     nxt = [0] * n
     while any(x < srv.n_layers for x in nxt):
+        if lockstep:
+            k = int(min(rng.integers(1, 5), srv.n_layers - nxt[0]))
+            srv.push_many(list(range(n)), nxt[0], k, rows)
+            nxt = [x + k for x in nxt]
+            continue
         i = int(rng.integers(0, n))
         if nxt[i] >= srv.n_layers:
             continue
@@ -38,10 +44,11 @@ def _run_streams(srv, rows, rng, limit_s=120):
 
 @pytest.mark.parametrize("d,rounds,W,C,p,n", [(5, 20, 6, 3, 0.01, 60), (9, 27, 12, 6, 0.006, 40)])
 def test_streams_equal_oracle_window_decode(d, rounds, W, C, p, n):
-    """Two runs over the same streams (reset in between), layers pushed in
-    random chunks of 1-4 with the streams interleaved: each stream ends done,
-    with status OK and the oracle's committed weight and observable; every
-    window has a latency record."""
+    """Two runs over the same streams (reset in between): layers pushed in
+    random chunks of 1-4 with the streams interleaved at random, then in
+    lockstep chunks through push_many.  Each stream ends done, with status OK
+    and the oracle's committed weight and observable; every window has a
+    latency record."""
     import paper_2609_12262_amd as psb
     g = synth.rotated_phenom_graph(d, p, rounds=rounds)
     L = (d * d - 1) // 2
@@ -56,7 +63,7 @@ def test_streams_equal_oracle_window_decode(d, rounds, W, C, p, n):
             if run:
                 for i in range(n):
                     srv.reset(i)
-            res = _run_streams(srv, rows, np.random.default_rng(run))
+            res = _run_streams(srv, rows, np.random.default_rng(run), lockstep=run == 1)
             lats = [srv.latencies(i) for i in range(n)]
             say(f"d={d} run {run}: {sum(r['done'] for r in res)} of {n} streams done, "
                 f"window latency p50 {np.median(np.concatenate(lats)) / 1e3:.1f} us")
