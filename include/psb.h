@@ -138,8 +138,11 @@ int32_t psb_decoder_levels(const psb_decoder* d, int32_t max_levels, int64_t* d_
                            int64_t* b_hi, uint64_t* b_lo, int32_t* final_level);
 
 /* Decodes n shots in one persistent launch, asynchronously on `stream`
- * (a hipStream_t; NULL = the default stream).  All array arguments are
- * DEVICE pointers owned by the caller:
+ * (a hipStream_t; NULL = the default stream).  The first tier takes the shots
+ * in descending order of their detection-event counts (three small kernels
+ * sort them first), so that short shots are the last ones; results do not
+ * depend on the order.  All array arguments are DEVICE pointers owned by the
+ * caller:
  *   syndromes  [n][ceil(num_detectors/8)] uint8, detector j = bit (j&7) of byte (j>>3);
  *   edges      [n][edges_per_shot] int32, MWEM edge ids in ascending order;
  *   n_edges    [n] int32;  weight [n] int64 (sum of caller weights);
@@ -175,7 +178,8 @@ int32_t psb_decode_batch(psb_decoder* d, const uint8_t* syndromes, int64_t n, in
  * whose launches overlap on a device race (serialise them on one stream), and
  * psb_decoder_last_overflow reports the most recent launch of the decoder,
  * whichever entry point made it.  The counters are cleared by a fill kernel
- * at the head of each launch (no memset). */
+ * at the head of each launch (no memset).  Its first tier takes the shots in
+ * index order (no room for the largest-first ordering). */
 #define PSB_NOALLOC_MAX_SHOTS (1 << 20)
 int32_t psb_decode_batch_noalloc(psb_decoder* d, const uint8_t* syndromes, int64_t n, int32_t* edges,
                                  int32_t* n_edges, int64_t* weight, uint64_t* obs, int32_t* status,
@@ -198,8 +202,8 @@ int32_t psb_schedule_levels(uint64_t wmax_hi, uint64_t wmax_lo, uint64_t diam_hi
 int32_t psb_decoder_device_bytes(const psb_decoder* d, int64_t* bytes);
 
 /* A psb_decode_batch call captured once into a HIP graph and replayed with
- * one launch: the counter reset and both tiers' persistent kernels (a fill
- * kernel clears the counters, no memset node).  The arguments are those of
+ * one launch: the counter reset, the shot ordering and both tiers'
+ * persistent kernels (fill kernels clear the counters, no memset node).  The arguments are those of
  * psb_decode_batch and are fixed at capture (the caller refills
  * `syndromes` in place between launches); all pointers are DEVICE memory
  * owned by the caller and must outlive the graph.  Creation reserves the

@@ -22,8 +22,9 @@ __global__ __launch_bounds__(64) void psb_lane_kernel(psb::Params P) {
   el::ctx_init(c, &P, S, base + 64, slot);
   el::state_init(c);
   for (;;) {
-    const int k = atomicAdd(&P.counter[0], 1);
-    if (k >= P.n_shots) break;
+    const int j = atomicAdd(&P.counter[0], 1);
+    if (j >= P.n_shots) break;
+    const int k = P.order ? P.order[j] : j;
     const int st = el::decode_shot(c, k);
     if (st == psb::S_OVERFLOW) {
       const int q = atomicAdd(&P.counter[1], 1);

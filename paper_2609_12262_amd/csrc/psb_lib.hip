@@ -50,6 +50,54 @@ __global__ void psb_zero_kernel(int32_t* p, int n, uint64_t* t_start) {
   if (i == 0 && t_start) *t_start = wall_clock64();
 }
 
+// Largest shots first: the first tier takes shots in descending order of
+// their detection-event counts (a count predicts a shot's decode time), so
+// the shots left when wavefronts start to run out of work are the short ones
+// and the launch's idle tail shrinks.  Counts above kOrderBuckets - 1 share
+// the first bucket; order within a bucket is whatever the atomics give (the
+// results do not depend on the order).  Three kernels, no memset: count and
+// bucket every shot (one wavefront per shot), scan the bucket sizes (one
+// block), scatter.
+constexpr int kOrderBuckets = 1024;
+
+__global__ __launch_bounds__(64) void psb_order_count(const uint8_t* synd, int32_t nbytes, int64_t n, int32_t* bkt,
+                                                      int32_t* hist) {
+  const int64_t i = blockIdx.x;
+  if (i >= n) return;
+  const uint8_t* row = synd + i * (int64_t)nbytes;
+  int cnt = 0;
+  for (int b = threadIdx.x; b < nbytes; b += 64) cnt += __builtin_popcount((unsigned)row[b]);
+  for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
+  if (threadIdx.x == 0) {
+    const int b = kOrderBuckets - 1 - min(cnt, kOrderBuckets - 1);
+    bkt[i] = b;
+    atomicAdd(&hist[b], 1);
+  }
+}
+
+// hist[b] -> the first position of bucket b (exclusive prefix sum), one block
+// of kOrderBuckets threads
+__global__ __launch_bounds__(kOrderBuckets) void psb_order_scan(int32_t* hist) {
+  __shared__ int32_t buf[kOrderBuckets];
+  const int t = threadIdx.x;
+  const int32_t v = hist[t];
+  buf[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kOrderBuckets; off <<= 1) {
+    const int32_t add = t >= off ? buf[t - off] : 0;
+    __syncthreads();
+    buf[t] += add;
+    __syncthreads();
+  }
+  hist[t] = buf[t] - v;
+}
+
+__global__ void psb_order_scatter(int64_t n, const int32_t* bkt, int32_t* hist, int32_t* order) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  order[atomicAdd(&hist[bkt[i]], 1)] = (int32_t)i;
+}
+
 // Persistent decode kernel, one wavefront per shot, per-shot state in LDS.
 // TIER 0 (small capacities, many waves per CU) hands shots that exceed its
 // capacities to the overflow list; TIER 1 (large capacities, a few waves
@@ -79,7 +127,7 @@ __global__ __launch_bounds__(64, 4) void psb_decode_kernel(Params P) {
     int64_t shot;
     if (TIER == 0 || P.ovf_list == nullptr) {
       if (k >= P.n_shots) break;
-      shot = k;
+      shot = (TIER == 0 && P.order) ? uni(P.order[k]) : k;
     } else {
       const int lim = uni(__hip_atomic_load(&P.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
       if (k >= lim) break;
@@ -260,7 +308,7 @@ struct psb_decoder {
   int32_t* d_counter = nullptr;
   char* d_ws_fast = nullptr;
   char* d_ws_ovf = nullptr;
-  int32_t* d_ovf_list = nullptr;
+  int32_t* d_ovf_list = nullptr;     // [cap] overflow list, then [2 cap + kOrderBuckets] the shot order's buffers
   int64_t ovf_list_cap = 0;
   int32_t n_graphs = 0;              // captured batch graphs whose kernel arguments hold d_ovf_list
   int32_t* last_counter = nullptr;   // work counters of the most recent launch
@@ -461,7 +509,7 @@ extern "C" int32_t psb_decoder_device_bytes(const psb_decoder* D, int64_t* bytes
   if (!D || !bytes) return fail(PSB_E_INVALID, "null argument");
   int64_t b = (int64_t)D->P_ovf.L.total * D->slots_ovf + 16LL * D->g->n_det * D->g->deg + 256;
   if (D->fast_enabled) b += (int64_t)D->P_fast.L.total * D->slots_fast;
-  b += 4 * D->ovf_list_cap;
+  if (D->ovf_list_cap > 0) b += 4 * (3 * D->ovf_list_cap + kOrderBuckets);
   *bytes = b;
   return PSB_OK;
 }
@@ -478,7 +526,7 @@ extern "C" int32_t psb_decoder_reserve(psb_decoder* D, int64_t max_batch) {
   if (D->d_ovf_list) (void)hipFree(D->d_ovf_list);
   D->d_ovf_list = nullptr;
   D->ovf_list_cap = 0;
-  if (hipMalloc((void**)&D->d_ovf_list, 4 * (size_t)std::max<int64_t>(max_batch, 1)) != hipSuccess)
+  if (hipMalloc((void**)&D->d_ovf_list, 4 * (3 * (size_t)std::max<int64_t>(max_batch, 1) + kOrderBuckets)) != hipSuccess)
     return fail(PSB_E_NOMEM, "overflow list");
   D->ovf_list_cap = max_batch;
   return PSB_OK;
@@ -511,9 +559,12 @@ extern "C" int32_t psb_decoder_slots(const psb_decoder* D, int32_t* fast_slots, 
 // Launches one batch: the counter reset, the first tier and the overflow tier,
 // with the given work counters ([0] first-tier head, [1] overflow count, [2]
 // overflow head) and overflow list (room for n shots).
+// order_buf (room for 2 n + kOrderBuckets int32, or null for the identity
+// order): the largest-first shot order is built there first.
 static int32_t launch_batch(psb_decoder* D, const uint8_t* syndromes, int64_t n, int32_t* edges, int32_t* n_edges,
                             int64_t* weight, uint64_t* obs, int32_t* status, int8_t* levels, uint64_t* t_done,
-                            int32_t* stats, int32_t* counter, int32_t* ovf_list, hipStream_t s) {
+                            int32_t* stats, int32_t* counter, int32_t* ovf_list, int32_t* order_buf,
+                            hipStream_t s) {
   Params* tiers[2] = {&D->P_fast, &D->P_ovf};
   for (Params* P : tiers) {
     P->n_shots = n; P->synd = syndromes; P->out_edges = edges; P->out_nedges = n_edges; P->out_weight = weight;
@@ -526,6 +577,18 @@ static int32_t launch_batch(psb_decoder* D, const uint8_t* syndromes, int64_t n,
   D->last_counter = counter;
   psb_zero_kernel<<<1, 64, 0, s>>>(counter, 3, t_done ? t_done + n : nullptr);
   HIP_TRY(hipGetLastError());
+  D->P_fast.order = nullptr; D->P_ovf.order = nullptr;
+  if (order_buf && D->fast_enabled && n > 1) {
+    int32_t* order = order_buf;
+    int32_t* bkt = order_buf + n;
+    int32_t* hist = order_buf + 2 * n;
+    psb_zero_kernel<<<kOrderBuckets / 64, 64, 0, s>>>(hist, kOrderBuckets, nullptr);
+    psb_order_count<<<(unsigned)n, 64, 0, s>>>(syndromes, D->P_fast.nbytes, n, bkt, hist);
+    psb_order_scan<<<1, kOrderBuckets, 0, s>>>(hist);
+    psb_order_scatter<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, bkt, hist, order);
+    HIP_TRY(hipGetLastError());
+    D->P_fast.order = order;
+  }
   if (D->fast_enabled && D->first_lane) {
     const int64_t waves = std::min<int64_t>((n + 63) / 64, D->slots_fast / 64);
     HIP_TRY(psb_lane_launch(D->P_fast, (unsigned)waves, s));
@@ -563,11 +626,12 @@ extern "C" int32_t psb_decode_batch(psb_decoder* D, const uint8_t* syndromes, in
     if (D->d_ovf_list) (void)hipFree(D->d_ovf_list);
     D->d_ovf_list = nullptr;
     D->ovf_list_cap = 0;
-    if (hipMalloc((void**)&D->d_ovf_list, 4 * (size_t)n) != hipSuccess) return fail(PSB_E_NOMEM, "overflow list");
+    if (hipMalloc((void**)&D->d_ovf_list, 4 * (3 * (size_t)n + kOrderBuckets)) != hipSuccess)
+      return fail(PSB_E_NOMEM, "overflow list");
     D->ovf_list_cap = n;
   }
   return launch_batch(D, syndromes, n, edges, n_edges, weight, obs, status, levels, t_done, stats, D->d_counter,
-                      D->d_ovf_list, s);
+                      D->d_ovf_list, D->fast_enabled ? D->d_ovf_list + D->ovf_list_cap : nullptr, s);
 }
 
 extern "C" int32_t psb_decode_batch_noalloc(psb_decoder* D, const uint8_t* syndromes, int64_t n, int32_t* edges,
@@ -587,7 +651,7 @@ extern "C" int32_t psb_decode_batch_noalloc(psb_decoder* D, const uint8_t* syndr
   // the fill kernel at the head of the launch clears the counters; the list
   // is written before it is read
   return launch_batch(D, syndromes, n, edges, n_edges, weight, obs, status, levels, t_done, stats, base,
-                      base + kScratchHeader, (hipStream_t)stream);
+                      base + kScratchHeader, nullptr, (hipStream_t)stream);
 }
 
 struct psb_batch_graph {

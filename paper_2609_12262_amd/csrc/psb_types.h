@@ -142,6 +142,7 @@ struct Params {
   int32_t* out_stats;     // [n][stats_stride] or null
   int32_t* counter;       // [0] first-tier work head, [1] overflow count, [2] overflow head
   int32_t* ovf_list;      // [n_shots] shots handed to the overflow tier
+  const int32_t* order;   // [n_shots] the order in which the first tier takes shots (null: 0, 1, 2, ...)
   // workspace
   char* ws;
   WsLayout L;
