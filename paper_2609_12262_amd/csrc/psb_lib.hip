@@ -56,23 +56,36 @@ __global__ void psb_zero_kernel(int32_t* p, int n, uint64_t* t_start) {
 // and the launch's idle tail shrinks.  Counts above kOrderBuckets - 1 share
 // the first bucket; order within a bucket is whatever the atomics give (the
 // results do not depend on the order).  Three kernels, no memset: count and
-// bucket every shot (one wavefront per shot), scan the bucket sizes (one
-// block), scatter.
+// bucket every shot, scan the bucket sizes, scatter.  The count and scatter
+// kernels run kOrderBlocks blocks of 1,024 threads over contiguous chunks of
+// shots with histograms in LDS, so each block adds to a global bucket once
+// (thousands of shots in a handful of buckets would otherwise queue on the
+// same few atomic counters).
 constexpr int kOrderBuckets = 1024;
+constexpr int kOrderBlocks = 256;
 
-__global__ __launch_bounds__(64) void psb_order_count(const uint8_t* synd, int32_t nbytes, int64_t n, int32_t* bkt,
-                                                      int32_t* hist) {
-  const int64_t i = blockIdx.x;
-  if (i >= n) return;
-  const uint8_t* row = synd + i * (int64_t)nbytes;
-  int cnt = 0;
-  for (int b = threadIdx.x; b < nbytes; b += 64) cnt += __builtin_popcount((unsigned)row[b]);
-  for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
-  if (threadIdx.x == 0) {
-    const int b = kOrderBuckets - 1 - min(cnt, kOrderBuckets - 1);
-    bkt[i] = b;
-    atomicAdd(&hist[b], 1);
+__global__ __launch_bounds__(1024) void psb_order_count(const uint8_t* synd, int32_t nbytes, int64_t n,
+                                                        int32_t* bkt, int32_t* hist) {
+  __shared__ int32_t lh[kOrderBuckets];
+  for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) lh[b] = 0;
+  __syncthreads();
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63, waves = blockDim.x >> 6;
+  for (int64_t i = lo + wave; i < hi; i += waves) {           // one wavefront per shot, lanes over its bytes
+    const uint8_t* row = synd + i * (int64_t)nbytes;
+    int cnt = 0;
+    for (int b = ln; b < nbytes; b += 64) cnt += __builtin_popcount((unsigned)row[b]);
+    for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
+    if (ln == 0) {
+      const int b = kOrderBuckets - 1 - min(cnt, kOrderBuckets - 1);
+      bkt[i] = b;
+      atomicAdd(&lh[b], 1);
+    }
   }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x)
+    if (lh[b]) atomicAdd(&hist[b], lh[b]);
 }
 
 // hist[b] -> the first position of bucket b (exclusive prefix sum), one block
@@ -92,10 +105,26 @@ __global__ __launch_bounds__(kOrderBuckets) void psb_order_scan(int32_t* hist) {
   hist[t] = buf[t] - v;
 }
 
-__global__ void psb_order_scatter(int64_t n, const int32_t* bkt, int32_t* hist, int32_t* order) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  order[atomicAdd(&hist[bkt[i]], 1)] = (int32_t)i;
+// Each block reserves, per bucket, a range for its chunk's shots (one global
+// atomic per bucket it uses), then places them with LDS atomics.
+__global__ __launch_bounds__(1024) void psb_order_scatter(int64_t n, const int32_t* bkt, int32_t* hist,
+                                                          int32_t* order) {
+  __shared__ int32_t cnt[kOrderBuckets], base[kOrderBuckets];
+  for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&cnt[bkt[i]], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) {
+    base[b] = cnt[b] ? atomicAdd(&hist[b], cnt[b]) : 0;
+    cnt[b] = 0;
+  }
+  __syncthreads();
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const int b = bkt[i];
+    order[base[b] + atomicAdd(&cnt[b], 1)] = (int32_t)i;
+  }
 }
 
 // Persistent decode kernel, one wavefront per shot, per-shot state in LDS.
@@ -583,9 +612,10 @@ static int32_t launch_batch(psb_decoder* D, const uint8_t* syndromes, int64_t n,
     int32_t* bkt = order_buf + n;
     int32_t* hist = order_buf + 2 * n;
     psb_zero_kernel<<<kOrderBuckets / 64, 64, 0, s>>>(hist, kOrderBuckets, nullptr);
-    psb_order_count<<<(unsigned)n, 64, 0, s>>>(syndromes, D->P_fast.nbytes, n, bkt, hist);
+    const unsigned blocks = (unsigned)std::min<int64_t>(kOrderBlocks, (n + 63) / 64);
+    psb_order_count<<<blocks, 1024, 0, s>>>(syndromes, D->P_fast.nbytes, n, bkt, hist);
     psb_order_scan<<<1, kOrderBuckets, 0, s>>>(hist);
-    psb_order_scatter<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, bkt, hist, order);
+    psb_order_scatter<<<blocks, 1024, 0, s>>>(n, bkt, hist, order);
     HIP_TRY(hipGetLastError());
     D->P_fast.order = order;
   }
