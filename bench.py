@@ -188,7 +188,8 @@ def latency_scaling(args):
         shots = synth.sample(g, args.latency_shots, seed=10 + d)
         G = psb.Graph.from_synth(g)
         synd = torch.from_numpy(shots.syndromes).cuda()
-        kw = dict(tiebreak_seed=0x5EED, mode=args.mode, serial_level_one=1 if args.serial_level_one else 0)
+        kw = dict(tiebreak_seed=0x5EED, mode=args.mode, serial_level_one=1 if args.serial_level_one else 0,
+                  cluster_walk=1 if args.cluster_walk else 0)
         if not args.no_autotune:
             # a batch of 64 shots, one per wavefront on an otherwise idle device, lasts about as long as its
             # slowest shot alone: the tuner's proxy for one-shot latency
@@ -565,6 +566,8 @@ def main():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--serial-level-one", action="store_true",
                     help="send every level-1 processing cluster through the event loop (no concurrent level-1 pass)")
+    ap.add_argument("--cluster-walk", action="store_true",
+                    help="the clustering search walks its paths at every level (no ball tables)")
     ap.add_argument("--no-autotune", action="store_true", help="default decoder configuration instead of the "
                                                                  "autotuner's pick")
     ap.add_argument("--no-graph", action="store_true", help="eager psb_decode_batch launches instead of a "
@@ -647,7 +650,7 @@ def main():
     G = psb.Graph.from_synth(g)
     synd = torch.from_numpy(shots.syndromes).cuda()
     base = dict(tiebreak_seed=0x5EED, mode=args.mode, num_slots=args.slots,
-                serial_level_one=1 if args.serial_level_one else 0)
+                serial_level_one=1 if args.serial_level_one else 0, cluster_walk=1 if args.cluster_walk else 0)
     tune_table = None
     if args.no_autotune:
         kw = base
@@ -709,6 +712,8 @@ def main():
                    "mode": "partition-and-fuse" if args.mode == 0 else "global sparse blossom",
                    "level_one": ("event loop" if args.serial_level_one else
                                  "single-event clusters in one concurrent pass, the rest in the event loop"),
+                   "cluster_search": ("walks its paths" if args.cluster_walk else
+                                      "ball tables for levels of at most two edges, else walks"),
                    "first_tier": "one shot per lane" if kw.get("first_tier", 0) else "one shot per wavefront",
                    "first_tier_state": [kw.get("fast_max_nodes", 0), kw.get("fast_max_regions", 0)],
                    "first_tier_lds_state": kw.get("fast_lds_state", 0),

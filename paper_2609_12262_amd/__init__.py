@@ -43,7 +43,7 @@ class _DecoderOpts(ctypes.Structure):
                 ("fast_max_nodes", ctypes.c_int32), ("fast_max_regions", ctypes.c_int32),
                 ("overflow_slots", ctypes.c_int32), ("first_tier", ctypes.c_int32),
                 ("fast_lds_state", ctypes.c_int32), ("event_accounting", ctypes.c_int32),
-                ("serial_level_one", ctypes.c_int32)]
+                ("serial_level_one", ctypes.c_int32), ("cluster_walk", ctypes.c_int32)]
 
 
 class _TuneEntry(ctypes.Structure):
@@ -53,11 +53,12 @@ class _TuneEntry(ctypes.Structure):
 def _make_opts(tiebreak_seed: int = 0x5EED, mode: int = 0, boundary_reading: int = 0, max_defects: int = 0,
                edges_per_shot: int = 0, num_slots: int = 0, q=(1, 10), phi_min=(1, 100), fast_max_nodes: int = 0,
                fast_max_regions: int = 0, overflow_slots: int = 0, first_tier: int = 0,
-               fast_lds_state: int = 0, event_accounting: int = 0, serial_level_one: int = 0) -> _DecoderOpts:
+               fast_lds_state: int = 0, event_accounting: int = 0, serial_level_one: int = 0,
+               cluster_walk: int = 0) -> _DecoderOpts:
     return _DecoderOpts(q[0], q[1], phi_min[0], phi_min[1], tiebreak_seed & ((1 << 64) - 1), mode,
                         boundary_reading, max_defects, edges_per_shot, num_slots, fast_max_nodes,
                         fast_max_regions, overflow_slots, first_tier, fast_lds_state, event_accounting,
-                        serial_level_one)
+                        serial_level_one, cluster_walk)
 
 
 def _opts_kwargs(o: _DecoderOpts) -> dict:
@@ -67,7 +68,8 @@ def _opts_kwargs(o: _DecoderOpts) -> dict:
             "q": (o.q_num, o.q_den), "phi_min": (o.phi_min_num, o.phi_min_den),
             "fast_max_nodes": o.fast_max_nodes, "fast_max_regions": o.fast_max_regions,
             "overflow_slots": o.overflow_slots, "first_tier": o.first_tier, "fast_lds_state": o.fast_lds_state,
-            "event_accounting": o.event_accounting, "serial_level_one": o.serial_level_one}
+            "event_accounting": o.event_accounting, "serial_level_one": o.serial_level_one,
+            "cluster_walk": o.cluster_walk}
 
 
 def lib():
@@ -172,11 +174,11 @@ class Decoder:
                  boundary_reading: int = 0, max_defects: int = 0, edges_per_shot: int = 0,
                  num_slots: int = 0, q=(1, 10), phi_min=(1, 100), fast_max_nodes: int = 0,
                  fast_max_regions: int = 0, overflow_slots: int = 0, first_tier: int = 0, fast_lds_state: int = 0,
-                 event_accounting: int = 0, serial_level_one: int = 0):
+                 event_accounting: int = 0, serial_level_one: int = 0, cluster_walk: int = 0):
         self.graph = graph
         opts = _make_opts(tiebreak_seed, mode, boundary_reading, max_defects, edges_per_shot, num_slots, q, phi_min,
                           fast_max_nodes, fast_max_regions, overflow_slots, first_tier, fast_lds_state,
-                          event_accounting, serial_level_one)
+                          event_accounting, serial_level_one, cluster_walk)
         self.stats_width = 12 if event_accounting else 8
         h = ctypes.c_void_p()
         _check(lib().psb_decoder_create(graph._h, ctypes.byref(opts), ctypes.byref(h)), "psb_decoder_create")

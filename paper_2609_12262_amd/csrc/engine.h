@@ -1071,6 +1071,8 @@ PSB_DEV void cluster(Ctx& c) {
     // hop's row in chunks of independent loads, which is faster than a chain
     // of list entries
     const bool use_near = DEEP >= 1 && c.near && H >= 3;
+    // levels whose paths have at most two edges read their ball table
+    const int bt = c.P->ball_slot ? uni(c.P->ball_slot[k]) : -1;
     for (int i = lane(); i < nd; i += PSB_WAVE) {
       c.uf[i] = i; close_cnt[i] = 0; bcount[i] = 0; csize[i] = 0; cclose[i] = 0;
       if (use_near) c.ehead[i] = -1;
@@ -1147,7 +1149,36 @@ PSB_DEV void cluster(Ctx& c) {
           }
         }
       };
-      if (H <= (DEEP >= 1 ? 3 : 2)) {
+      if (bt >= 0) {
+        // the detectors and boundary edges that the level's paths reach, with
+        // the flags their least distances decide; partners four at a time, all
+        // loads of a chunk issued before any of them is used
+        const int32_t* row = c.P->ball_off + (int64_t)bt * (2 * (int64_t)c.n_det + 1) + 2 * (int64_t)u;
+        const int a0 = row[0], a1 = row[1], a2 = row[2];
+        const int32_t* ent = c.P->ball_ent;
+        nvis += a2 - a0;
+        for (int q0 = a0; q0 < a1; q0 += 4) {
+          int ys[4], ix[4], lv[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) ys[t] = q0 + t < a1 ? ent[q0 + t] : -1;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) ix[t] = ys[t] >= 0 ? node_idx(c, ys[t] & BALL_ID) : -1;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) lv[t] = (ix[t] >= 0 && ix[t] < nd) ? (int)c.level[ix[t]] : 1;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            if (lv[t] != 0) continue;
+            // the row's detectors are distinct: no partner repeats
+            if (nh < hitcap) { hits[2 * nh] = ix[t]; hits[2 * nh + 1] = (ys[t] & BALL_CLOSE) ? 1 : 0; ++nh; }
+            else overflow = 1;
+          }
+        }
+        for (int q0 = a1; q0 < a2; ++q0) {
+          const int v = ent[q0];
+          if (v & BALL_LOOSE) loose = 1;
+          if (v & BALL_CLOSE) { if (nbd < bdc) c.bdl[(int64_t)i * bdc + nbd] = v & BALL_ID; ++nbd; }
+        }
+      } else if (H <= (DEEP >= 1 ? 3 : 2)) {
         // up to three rounds of independent adjacency-row loads instead of a
         // serial walk over a stack in scratch memory
         if (H == 1) {

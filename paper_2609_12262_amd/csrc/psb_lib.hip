@@ -334,6 +334,8 @@ struct psb_decoder {
   bool first_lane = true;          // first tier: one shot per lane (else one per wavefront)
   __int128* d_wt = nullptr;
   __int128* d_sd = nullptr; __int128* d_sb = nullptr; int32_t* d_shmax = nullptr;
+  int32_t* d_ball = nullptr;         // ball tables: [levels] slot, then the offsets, then the entries
+  int64_t ball_bytes = 0;
   int32_t* d_counter = nullptr;
   char* d_ws_fast = nullptr;
   char* d_ws_ovf = nullptr;
@@ -392,6 +394,7 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   }
   if (opts.event_accounting != 0 && opts.event_accounting != 1) { delete D; return fail(PSB_E_INVALID, "event_accounting must be 0 or 1"); }
   if (opts.serial_level_one != 0 && opts.serial_level_one != 1) { delete D; return fail(PSB_E_INVALID, "serial_level_one must be 0 or 1"); }
+  if (opts.cluster_walk != 0 && opts.cluster_walk != 1) { delete D; return fail(PSB_E_INVALID, "cluster_walk must be 0 or 1"); }
   const bool acct = opts.event_accounting == 1;
   D->acct = acct;
   D->first_lane = opts.first_tier == 1;
@@ -471,16 +474,33 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   D->slots_ovf = opts.overflow_slots > 0 ? opts.overflow_slots : per_cu_o * cus;
   // device buffers
   auto fail_dev = [&](const char* what) { psb_decoder_destroy(D); return fail(PSB_E_NOMEM, std::string("device allocation failed: ") + what); };
+  const size_t nl = D->sched.d.size();
+  std::vector<__int128> sd(nl), sb(nl);
+  for (size_t k = 0; k < nl; ++k) { sd[k] = (__int128)D->sched.d[k]; sb[k] = (__int128)D->sched.b[k]; }
   {
     // weights laid out like the adjacency rows, so a row is read in one pass
     std::vector<__int128> ell_w((size_t)n * g->deg, 0);
     for (size_t k = 0; k < ell_w.size(); ++k) if (g->eid[k] >= 0) ell_w[k] = wt[g->eid[k]];
     if (hipMalloc((void**)&D->d_wt, 16 * ell_w.size()) != hipSuccess) return fail_dev("weights");
     HIP_TRY(hipMemcpy(D->d_wt, ell_w.data(), 16 * ell_w.size(), hipMemcpyHostToDevice));
+    // the levels whose search walks at most two edges read ball tables
+    // instead (at most 2^28 entries; beyond that, or with cluster_walk, they walk)
+    BallTables T;
+    if (opts.cluster_walk == 0 && opts.mode == 0 &&
+        build_ball_tables(ell, ell_w, sb, sd, D->hmax, (int64_t)1 << 28, T) && !T.off.empty()) {
+      const size_t words = T.slot.size() + T.off.size() + T.ent.size();
+      T.slot.insert(T.slot.end(), T.off.begin(), T.off.end());
+      T.slot.insert(T.slot.end(), T.ent.begin(), T.ent.end());
+      if (hipMalloc((void**)&D->d_ball, 4 * words) != hipSuccess) return fail_dev("ball tables");
+      HIP_TRY(hipMemcpy(D->d_ball, T.slot.data(), 4 * words, hipMemcpyHostToDevice));
+      D->ball_bytes = 4 * (int64_t)words;
+      for (Params* P : {&PF, &PO}) {
+        P->ball_slot = D->d_ball;
+        P->ball_off = D->d_ball + nl;
+        P->ball_ent = D->d_ball + nl + T.off.size();
+      }
+    }
   }
-  const size_t nl = D->sched.d.size();
-  std::vector<__int128> sd(nl), sb(nl);
-  for (size_t k = 0; k < nl; ++k) { sd[k] = (__int128)D->sched.d[k]; sb[k] = (__int128)D->sched.b[k]; }
   if (hipMalloc((void**)&D->d_sd, 16 * nl) != hipSuccess || hipMalloc((void**)&D->d_sb, 16 * nl) != hipSuccess ||
       hipMalloc((void**)&D->d_shmax, 4 * nl) != hipSuccess || hipMalloc((void**)&D->d_counter, 256) != hipSuccess)
     return fail_dev("schedule");
@@ -510,6 +530,7 @@ extern "C" int32_t psb_decoder_destroy(psb_decoder* D) {
   if (D->d_sd) (void)hipFree(D->d_sd);
   if (D->d_sb) (void)hipFree(D->d_sb);
   if (D->d_shmax) (void)hipFree(D->d_shmax);
+  if (D->d_ball) (void)hipFree(D->d_ball);
   if (D->d_counter) (void)hipFree(D->d_counter);
   if (D->d_ws_fast) (void)hipFree(D->d_ws_fast);
   if (D->d_ws_ovf) (void)hipFree(D->d_ws_ovf);

@@ -16,6 +16,10 @@ constexpr int MATE_BOUNDARY = -2;
 // even graphs whose light edges allow 7-9 hops (timelike q = 0.2 against
 // spatial p = 0.001-0.005) walk only a few hundred paths per event.
 constexpr int MAXH = 16;
+// Ball-table entry flags: within d_k of the detector (a close partner, or a
+// boundary edge for the boundary condition), within b_k / 2 (a boundary edge
+// for the loose reading); the id sits in the low 29 bits.
+constexpr int BALL_CLOSE = 1 << 30, BALL_LOOSE = 1 << 29, BALL_ID = (1 << 29) - 1;
 constexpr int S_OK = 0, S_CAPACITY = 1, S_INFEASIBLE = 2, S_TRUNC = 3, S_INTERNAL = 4, S_OVERFLOW = 5;
 
 // Byte offsets of the per-shot state that the event loop touches on every
@@ -120,6 +124,14 @@ struct Params {
   const __int128* sd;     // [n_levels] d_k
   const __int128* sb;     // [n_levels] b_k
   const int32_t* shmax;   // [n_levels] path-enumeration depth, -1 = final level
+  // ball tables of the levels whose search walks at most two edges: level k
+  // reads table ball_slot[k] (-1: it walks its paths), whose row for detector
+  // u is ball_ent[off[2u] .. off[2u+1]) = the detectors within b_k of u, then
+  // [off[2u+1] .. off[2u+2]) = the boundary edges that matter (off = ball_off +
+  // table * (2 n_det + 1)); flags in the high bits of each entry (BALL_*)
+  const int32_t* ball_slot;
+  const int32_t* ball_off;
+  const int32_t* ball_ent;
   // capacities (this tier)
   Caps cap;
   int32_t cecap, bccap, lcap, shrcap, stkcap, fincap, hitcap, bdc;

@@ -5,7 +5,9 @@
 // g++ and the address / undefined-behaviour sanitizers; not part of the
 // library.
 //
-// usage: engine_host <dir> <seed> <mode> <reading> <xcap> <rcap> <dcap> <hash> <direct1>
+// usage: engine_host <dir> <seed> <mode> <reading> <xcap> <rcap> <dcap> <hash> <direct1> [<walk>]
+//   (walk = 1: the clustering search walks its paths at every level; 0, the
+//   default: levels of at most two edges read the library's ball tables)
 //   <dir>/graph.bin : int32 n, int64 m, int32 u[m], int32 v[m], int32 w[m], uint64 obs[m]
 //   <dir>/synd.bin  : int64 shots, int32 bytes per row, uint8 rows[shots][bytes]
 // writes <dir>/out.bin: per shot int32 status, int32 n_edges, int64 weight,
@@ -39,7 +41,11 @@ void psb_invariant_failed(const char* what, int64_t shot, int level) {
 template <class T> static bool rd(FILE* f, T* p, size_t n) { return fread(p, sizeof(T), n, f) == n; }
 
 int main(int argc, char** argv) {
-  if (argc != 10) { fprintf(stderr, "usage: engine_host dir seed mode reading xcap rcap dcap hash direct1\n"); return 2; }
+  if (argc != 10 && argc != 11) {
+    fprintf(stderr, "usage: engine_host dir seed mode reading xcap rcap dcap hash direct1 [walk]\n");
+    return 2;
+  }
+  const int walk = argc == 11 ? atoi(argv[10]) : 0;
   const std::string dir = argv[1];
   const uint64_t seed = strtoull(argv[2], nullptr, 0);
   const int mode = atoi(argv[3]), reading = atoi(argv[4]);
@@ -96,6 +102,11 @@ int main(int argc, char** argv) {
   P.bndb = bndb.data();
   P.n_levels = (int32_t)S.d.size(); P.reading = reading; P.mode = mode; P.tier = 1; P.direct1 = atoi(argv[9]);
   P.sd = sd.data(); P.sb = sb.data(); P.shmax = hmax.data();
+  psb_host::BallTables balls;
+  if (!walk && mode == 0 && psb_host::build_ball_tables(ell, ell_w, sb, sd, hmax, (int64_t)1 << 28, balls) &&
+      !balls.off.empty()) {
+    P.ball_slot = balls.slot.data(); P.ball_off = balls.off.data(); P.ball_ent = balls.ent.data();
+  }
 
   FILE* fs = fopen((dir + "/synd.bin").c_str(), "rb");
   if (!fs) return 2;

@@ -24,9 +24,10 @@ def build(out_dir, sanitize=True, nb_table=False):
 
 
 def run(exe, g, syndromes, seed=0x5EED, mode=0, reading=0, caps=(1024, 768, 512), force_hash=False, log=None,
-        direct1=True):
+        direct1=True, walk=False):
     """Decodes every row of `syndromes`; returns dict of arrays (status, n_edges, weight, obs, stats, edges).
-    `log`: file name that receives the program's standard error."""
+    `log`: file name that receives the program's standard error; `walk`: the clustering search walks its
+    paths at every level (else levels of at most two edges read the ball tables)."""
     with tempfile.TemporaryDirectory() as d:
         with open(os.path.join(d, "graph.bin"), "wb") as f:
             f.write(np.int32(g.num_detectors).tobytes()); f.write(np.int64(g.num_edges).tobytes())
@@ -38,7 +39,8 @@ def run(exe, g, syndromes, seed=0x5EED, mode=0, reading=0, caps=(1024, 768, 512)
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                    UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
         r = subprocess.run([exe, d, str(seed), str(mode), str(reading), *[str(x) for x in caps],
-                            "1" if force_hash else "0", "1" if direct1 else "0"], capture_output=True, text=True,
+                            "1" if force_hash else "0", "1" if direct1 else "0", "1" if walk else "0"],
+                           capture_output=True, text=True,
                            env=env)
         if log:
             with open(log, "w") as fh:
