@@ -269,11 +269,11 @@ static bool level_depths(const LevelSchedule& S, __int128 wmin, std::vector<int3
 }
 
 // Ball tables of the clustering levels whose search walks paths of at most
-// two edges (shmax 1 or 2), each path cut at length b_k and extended only while
-// shorter than b_k.  Row u of a level's table lists every detector x != u at
-// the end of such a path, flagged BALL_CLOSE when its least such length is at
-// most d_k, then every boundary edge ending such a path whose least length is
-// at most d_k (BALL_CLOSE) or at most b_k / 2 (BALL_LOOSE).  Reading the row
+// three edges (shmax 1 to 3), each path cut at length b_k and extended only
+// while shorter than b_k.  Row u of a level's table lists every detector x != u
+// at the end of such a path, flagged BALL_CLOSE when its least such length is
+// at most d_k, then every boundary edge ending such a path whose least length
+// is at most d_k (BALL_CLOSE) or at most b_k / 2 (BALL_LOOSE).  Reading the row
 // gives the search exactly the partners, close pairs, boundary edges within d_k
 // and loose flag that walking the paths gives, in one pass of independent
 // loads.  Returns false (and no tables) when ids do not fit the entries or the
@@ -287,51 +287,43 @@ static bool build_ball_tables(const Ell& g, const std::vector<__int128>& ell_w, 
                               BallTables& T) {
   const int32_t n = g.n_det, deg = g.deg;
   T.slot.assign(hmax.size(), -1); T.off.clear(); T.ent.clear();
-  if (n > psb::BALL_ID || g.n_edges > psb::BALL_ID) { T.slot.assign(hmax.size(), -1); return false; }
+  if (n > psb::BALL_ID || g.n_edges > psb::BALL_ID) return false;
   std::vector<std::pair<int32_t, __int128>> cand, bc;
-  auto keep_min = [](std::vector<std::pair<int32_t, __int128>>& v) {
-    std::sort(v.begin(), v.end());
-    size_t m = 0;
-    for (size_t k = 0; k < v.size(); ++k)
-      if (m == 0 || v[m - 1].first != v[k].first) v[m++] = v[k];
-    v.resize(m);
-  };
   int32_t tables = 0;
   for (size_t k = 0; k < hmax.size(); ++k) {
     const int hops = hmax[k];
-    if (hops != 1 && hops != 2) continue;
+    if (hops < 1 || hops > 3) continue;
     const __int128 b = sb[k], d = sd[k];
     T.slot[k] = tables++;
     const size_t base = T.off.size();
     T.off.resize(base + 2 * (size_t)n + 1);
     for (int32_t u = 0; u < n; ++u) {
       cand.clear(); bc.clear();
-      for (int32_t j = 0; j < deg; ++j) {
-        const int64_t a = (int64_t)u * deg + j;
-        const int32_t y = g.nbr[a];
-        if (y == psb::NB_PAD) break;
-        const __int128 w1 = ell_w[a];
-        if (w1 > b) continue;
-        if (y == psb::NB_BOUNDARY) { bc.push_back({g.eid[a], w1}); continue; }
-        if (y != u) cand.push_back({y, w1});
-        if (hops < 2 || w1 >= b) continue;
-        for (int32_t t = 0; t < deg; ++t) {
-          const int64_t c = (int64_t)y * deg + t;
-          const int32_t z = g.nbr[c];
-          if (z == psb::NB_PAD) break;
-          const __int128 w2 = w1 + ell_w[c];
-          if (w2 > b) continue;
-          if (z == psb::NB_BOUNDARY) bc.push_back({g.eid[c], w2});
-          else if (z != u) cand.push_back({z, w2});
+      // the paths in the walk's order (depth first, adjacency slots in row
+      // order), returns to u included: the order decides which boundary edges
+      // a full list keeps
+      auto walk = [&](auto&& self, int32_t x, __int128 base_w, int depth) -> void {
+        for (int32_t j = 0; j < deg; ++j) {
+          const int64_t a = (int64_t)x * deg + j;
+          const int32_t y = g.nbr[a];
+          if (y == psb::NB_PAD) break;
+          const __int128 w = base_w + ell_w[a];
+          if (w > b) continue;
+          if (y == psb::NB_BOUNDARY) { bc.push_back({g.eid[a], w}); continue; }
+          if (y != u) cand.push_back({y, w});
+          if (depth + 1 < hops && w < b) self(self, y, w, depth + 1);
         }
-      }
-      keep_min(cand);
+      };
+      walk(walk, u, 0, 0);
+      std::sort(cand.begin(), cand.end());
       T.off[base + 2 * (size_t)u] = (int32_t)T.ent.size();
-      for (const auto& e : cand) T.ent.push_back(e.first | (e.second <= d ? psb::BALL_CLOSE : 0));
+      for (size_t q = 0; q < cand.size(); ++q)
+        if (q == 0 || cand[q - 1].first != cand[q].first)   // least length of each detector
+          T.ent.push_back(cand[q].first | (cand[q].second <= d ? psb::BALL_CLOSE : 0));
       T.off[base + 2 * (size_t)u + 1] = (int32_t)T.ent.size();
       // boundary edges: those within d_k in the order of the walk's first path
-      // within d_k (the order in which the walk lists them, which decides the
-      // kept ones when a list is full), then those only within b_k / 2
+      // within d_k (the order in which the walk lists them), then those only
+      // within b_k / 2
       for (int pass = 0; pass < 2; ++pass)
         for (size_t k2 = 0; k2 < bc.size(); ++k2) {
           const int32_t e = bc[k2].first;

@@ -382,7 +382,23 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
     return fail(PSB_E_UNSUPPORTED, "level " + std::to_string(bad_level) + " needs paths of more than " +
                                        std::to_string(psb::MAXH) + " edges; the clustering kernel enumerates at most that");
   }
-  for (int32_t h : D->hmax) D->deep = std::max(D->deep, h > 3 ? 2 : h == 3 ? 1 : 0);
+  // weights laid out like the adjacency rows, so a row is read in one pass
+  std::vector<__int128> ell_w((size_t)n * g->deg, 0);
+  for (size_t k = 0; k < ell_w.size(); ++k) if (g->eid[k] >= 0) ell_w[k] = wt[g->eid[k]];
+  const size_t nl = D->sched.d.size();
+  std::vector<__int128> sd(nl), sb(nl);
+  for (size_t k = 0; k < nl; ++k) { sd[k] = (__int128)D->sched.d[k]; sb[k] = (__int128)D->sched.b[k]; }
+  // the levels whose search walks at most three edges read ball tables instead
+  // (at most 2^28 entries; beyond that, or with cluster_walk, they walk)
+  BallTables balls;
+  const bool use_balls = opts.cluster_walk == 0 && opts.mode == 0 &&
+                         build_ball_tables(ell, ell_w, sb, sd, D->hmax, (int64_t)1 << 28, balls) && !balls.off.empty();
+  // the search depth class that the walking levels need
+  for (size_t k = 0; k < nl; ++k) {
+    const int32_t h = D->hmax[k];
+    if (use_balls && balls.slot[k] >= 0) continue;
+    D->deep = std::max(D->deep, h > 3 ? 2 : h == 3 ? 1 : 0);
+  }
   // tier capacities: the first tier (one shot per lane, state in its global
   // workspace slot; or one shot per wavefront, state in LDS) and the
   // overflow tier (one shot per wavefront, large LDS state)
@@ -474,20 +490,11 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   D->slots_ovf = opts.overflow_slots > 0 ? opts.overflow_slots : per_cu_o * cus;
   // device buffers
   auto fail_dev = [&](const char* what) { psb_decoder_destroy(D); return fail(PSB_E_NOMEM, std::string("device allocation failed: ") + what); };
-  const size_t nl = D->sched.d.size();
-  std::vector<__int128> sd(nl), sb(nl);
-  for (size_t k = 0; k < nl; ++k) { sd[k] = (__int128)D->sched.d[k]; sb[k] = (__int128)D->sched.b[k]; }
   {
-    // weights laid out like the adjacency rows, so a row is read in one pass
-    std::vector<__int128> ell_w((size_t)n * g->deg, 0);
-    for (size_t k = 0; k < ell_w.size(); ++k) if (g->eid[k] >= 0) ell_w[k] = wt[g->eid[k]];
     if (hipMalloc((void**)&D->d_wt, 16 * ell_w.size()) != hipSuccess) return fail_dev("weights");
     HIP_TRY(hipMemcpy(D->d_wt, ell_w.data(), 16 * ell_w.size(), hipMemcpyHostToDevice));
-    // the levels whose search walks at most two edges read ball tables
-    // instead (at most 2^28 entries; beyond that, or with cluster_walk, they walk)
-    BallTables T;
-    if (opts.cluster_walk == 0 && opts.mode == 0 &&
-        build_ball_tables(ell, ell_w, sb, sd, D->hmax, (int64_t)1 << 28, T) && !T.off.empty()) {
+    if (use_balls) {
+      BallTables& T = balls;
       const size_t words = T.slot.size() + T.off.size() + T.ent.size();
       T.slot.insert(T.slot.end(), T.off.begin(), T.off.end());
       T.slot.insert(T.slot.end(), T.ent.begin(), T.ent.end());

@@ -400,11 +400,16 @@ extern "C" int32_t psb_slot_server_create(const psb_graph* const* graphs, int32_
     int32_t lds = 0, slots = 0;
     if (rc == PSB_OK) rc = psb_decoder_first_tier(G->dec, &params[gi], &lds, &slots);
     if (rc == PSB_OK) {
-      // the search depth of each level is in the parameters' device copy; read it back once
-      std::vector<int32_t> h(params[gi].n_levels);
+      // the search depth of each level, and whether it reads a ball table,
+      // are in the parameters' device copies; read them back once
+      std::vector<int32_t> h(params[gi].n_levels), bt(params[gi].n_levels, -1);
       if (!h.empty() && hipMemcpy(h.data(), params[gi].shmax, 4 * h.size(), hipMemcpyDeviceToHost) != hipSuccess)
         rc = fail(PSB_E_DEVICE, "level depths");
-      for (int32_t x : h) S->deep = std::max(S->deep, x > 3 ? 2 : x == 3 ? 1 : 0);
+      if (!bt.empty() && params[gi].ball_slot &&
+          hipMemcpy(bt.data(), params[gi].ball_slot, 4 * bt.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = fail(PSB_E_DEVICE, "ball tables");
+      for (size_t k = 0; k < h.size(); ++k)
+        if (bt[k] < 0) S->deep = std::max(S->deep, h[k] > 3 ? 2 : h[k] == 3 ? 1 : 0);
     }
     if (rc == PSB_OK && slots < waves) rc = fail(PSB_E_INTERNAL, "first tier has fewer slots than waves");
     psb_decoder_opts oo = o;

@@ -17,14 +17,14 @@ def say(msg):
 
 def gpu_decode(g, syndromes, mode=0, reading=0, max_defects=0, edges_per_shot=0, num_slots=0,
                levels=False, seed=SEED, timestamps=False, fast_max_nodes=0, fast_max_regions=0,
-               overflow_slots=0, want_overflow=False, first_tier=0, fast_lds_state=0):
+               overflow_slots=0, want_overflow=False, first_tier=0, fast_lds_state=0, cluster_walk=0):
     import torch
     import paper_2609_12262_amd as psb
     G = psb.Graph.from_synth(g)
     dec = psb.Decoder(G, tiebreak_seed=seed, mode=mode, boundary_reading=reading, max_defects=max_defects,
                       edges_per_shot=edges_per_shot, num_slots=num_slots, fast_max_nodes=fast_max_nodes,
                       fast_max_regions=fast_max_regions, overflow_slots=overflow_slots, first_tier=first_tier,
-                      fast_lds_state=fast_lds_state)
+                      fast_lds_state=fast_lds_state, cluster_walk=cluster_walk)
     synd = torch.from_numpy(np.ascontiguousarray(syndromes)).to("cuda")
     out = dec.decode(synd, levels=levels, timestamps=timestamps)
     torch.cuda.synchronize()

@@ -178,8 +178,8 @@ def test_cpu_engine_ball_tables_equal_the_walk(exe, graph, d, p, q, reading):
     tables built with the decoder: same results, same processing clusters,
     applied events and E_ideal as walking the paths, on every shot, and both
     equal the oracles; the tables read fewer entries than the walk visits
-    (the circuit-level graph with uniform noise needs three edges at level 1:
-    it walks either way)."""
+    (the circuit-level graph with uniform noise needs three edges at level 1,
+    the others two)."""
     g = (synth.rotated_phenom_graph(d, p, q=q) if graph == "phenom"
          else synth.rotated_circuit_graph(d, p, graph.split("_")[1]))
     s = synth.sample(g, 300, seed=41)
@@ -188,9 +188,6 @@ def test_cpu_engine_ball_tables_equal_the_walk(exe, graph, d, p, q, reading):
     for k in ("status", "n_edges", "weight", "obs"):
         assert np.array_equal(a[k], b[k]), k
     assert np.array_equal(a["stats"][:, 8:12], b["stats"][:, 8:12])
-    if graph == "circuit_uniform":
-        assert np.array_equal(a["stats"][:, 2], b["stats"][:, 2])
-    else:
-        assert a["stats"][:, 2].sum() < b["stats"][:, 2].sum()
+    assert a["stats"][:, 2].sum() < b["stats"][:, 2].sum()
     bad, tied = _compare(g, s.syndromes, a, reading="loose" if reading else "strict")
     assert not bad, bad[:5]

@@ -92,8 +92,9 @@ def test_random_and_repetition_graphs():
     assert not compare(g, s.syndromes, res, range(500))
 
 
-@pytest.mark.parametrize("graph", ["phenom", "circuit_uniform", "circuit_physical", "phenom_q02"])
-def test_cluster_levels_equal_oracle_clustering(graph):
+@pytest.mark.parametrize("graph,walk", [("phenom", 0), ("circuit_uniform", 0), ("circuit_physical", 0),
+                                        ("phenom_q02", 0), ("phenom", 1), ("circuit_uniform", 1)])
+def test_cluster_levels_equal_oracle_clustering(graph, walk):
     """Processing-cluster levels (Methods, Algorithm "Clustering") against the
     oracle's plain construction: identical below the final level; at the
     final level every remaining event is placed there (the oracle may assign
@@ -101,8 +102,11 @@ def test_cluster_levels_equal_oracle_clustering(graph):
     search enumerates paths of up to floor(b_1 / w_min) edges: 2 on the
     phenomenological and physical-noise graphs, 3 on the uniform-noise graph
     (its lightest edges are about 0.55 of the heaviest), 8 on a graph with
-    timelike flips at q = 0.2 (the generic walk).  The final MWEM does not
-    depend on the clusters (Theorem 1), so only this test checks them."""
+    timelike flips at q = 0.2 (the generic walk).  Levels of at most three
+    edges read the decoder's ball tables; walk = 1 makes them walk their
+    paths (rows read in chunks, near lists at three edges).  The final MWEM
+    does not depend on the clusters (Theorem 1), so only this test checks
+    them, and the results are compared with the oracle as well."""
     if graph == "phenom":
         g = synth.rotated_phenom_graph(11, 0.003)
     elif graph == "phenom_q02":
@@ -110,7 +114,8 @@ def test_cluster_levels_equal_oracle_clustering(graph):
     else:
         g = synth.rotated_circuit_graph(11, 0.003, graph.split("_")[1])
     s = synth.sample(g, 300, seed=14)
-    res = gpu_decode(g, s.syndromes, levels=True)
+    res = gpu_decode(g, s.syndromes, levels=True, cluster_walk=walk)
+    assert not compare(g, s.syndromes, res, range(0, 300, 3))
     og = oracle.Graph(g, SEED)
     import paper_2609_12262_amd as psb
     dec = psb.Decoder(psb.Graph.from_synth(g), tiebreak_seed=SEED)
