@@ -224,9 +224,19 @@ PSB_DEV void next_event(Ctx& c, i128& t, int& code) {
   wave_sync();
   const int xn = uni(c.S->x_n);
   i128 key = T_INF; int arg = 0x7fffffff;
-  for (int i = lane(); i < xn; i += PSB_WAVE) {
-    const i128 k = c.x_ev[i];
-    if (k < key) { key = k; arg = EV_NODE + i; }
+  // up to four entries per lane loaded before any is compared (one round trip
+  // for up to 4 * PSB_WAVE explored nodes); each lane still takes its entries
+  // in ascending index order, so ties go to the smaller index as before
+  for (int i0 = 0; i0 < xn; i0 += 4 * PSB_WAVE) {
+    i128 k[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * PSB_WAVE + lane();
+      k[u] = i < xn ? c.x_ev[i] : T_INF;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k[u] < key) { key = k[u]; arg = EV_NODE + i0 + u * PSB_WAVE + lane(); }
   }
   // regions: only once some region has been inner in this shot
   for (int x = lane(); c.n_shr > 0 && x < c.n_regions; x += PSB_WAVE) {
