@@ -274,8 +274,8 @@ PSB_DEV int nb_index(const Ctx& c, int i, int64_t row, int j);
 // Time of the event through adjacency slot j of explored node i (owned by
 // top region `top` with rate ra > 0 or 0 and l_u(t) = bu + ra * t); T_INF if
 // the slot gives none.
-PSB_DEV i128 slot_event(const Ctx& c, int i, int top, int ra, i128 bu, int64_t row, int j) {
-  const int k = nb_index(c, i, row, j);
+// (k: the slot's neighbour-table entry, already loaded)
+PSB_DEV i128 slot_event_k(const Ctx& c, int top, int ra, i128 bu, int64_t row, int j, int k) {
   if (k == XNB_PAD) return T_INF;
   const i128 W = c.wt[row + j];
   if (k == XNB_BOUNDARY) return (ra > 0) ? W - bu : T_INF;
@@ -286,6 +286,10 @@ PSB_DEV i128 slot_event(const Ctx& c, int i, int top, int ra, i128 bu, int64_t r
   if (rs <= 0) return T_INF;
   const i128 num = W - bu - (c.r_base[vt] + c.x_wr[k]);
   return (rs == 1) ? num : (num >> 1);               // COLLIDE (num even when rs == 2)
+}
+
+PSB_DEV i128 slot_event(const Ctx& c, int i, int top, int ra, i128 bu, int64_t row, int j) {
+  return slot_event_k(c, top, ra, bu, row, j, nb_index(c, i, row, j));
 }
 
 // Earliest event seen from explored node i, evaluated by one lane.
@@ -303,9 +307,17 @@ PSB_DEV void node_event(const Ctx& c, int i, i128& tbest, int& kbest) {
   }
   const int deg = c.deg;
   const int64_t row = (int64_t)c.x_node[i] * deg;
-  for (int j = 0; j < deg; ++j) {
-    const i128 t = slot_event(c, i, top, ra, bu, row, j);
-    if (t < tbest) { tbest = t; kbest = j; }
+  // four slots at a time: their neighbour entries are loaded before any slot
+  // is evaluated (slots still taken in order, ties to the smaller slot)
+  for (int j0 = 0; j0 < deg; j0 += 4) {
+    int ks[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ks[u] = j0 + u < deg ? nb_index(c, i, row, j0 + u) : XNB_PAD;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const i128 t = slot_event_k(c, top, ra, bu, row, j0 + u, ks[u]);
+      if (t < tbest) { tbest = t; kbest = j0 + u; }
+    }
   }
 }
 
@@ -1508,32 +1520,65 @@ PSB_DEV void level_one_direct(Ctx& c) {
     i128 t = 0;
     if (r < nd && c.level[r] == 1 && c.cid[r] == r) {
       const int64_t ru = (int64_t)c.x_node[r] * deg;
-      if (size[r] == 2) {
-        v = other[r];
-        const int dv = c.x_node[v];
-        int je = -1;
-        for (int j = 0; j < deg; ++j)
-          if (c.nbr[ru + j] == dv && (je < 0 || c.wt[ru + j] < c.wt[ru + je])) je = j;
-        if (je >= 0) {
-          const i128 We = c.wt[ru + je];
-          bool ok = true;
-          const int64_t rv = (int64_t)dv * deg;
-          for (int j = 0; j < deg && ok; ++j) {
-            if (j != je && c.nbr[ru + j] != NB_PAD && 2 * c.wt[ru + j] <= We) ok = false;
-            if (c.nbr[rv + j] != NB_PAD && c.eid[rv + j] != c.eid[ru + je] && 2 * c.wt[rv + j] <= We) ok = false;
+      // the rows are read in chunks whose loads are all issued before any
+      // value is tested (no early exit: every slot is checked)
+      const int target = size[r] == 2 ? c.x_node[other[r]] : NB_BOUNDARY;
+      int jm = -1;                     // lightest slot of r's row to the partner (or the boundary)
+      i128 Wm = 0;
+      if (size[r] == 1 || size[r] == 2) {
+        for (int j0 = 0; j0 < deg; j0 += 4) {
+          int nb4[4];
+          i128 w4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int j = j0 + u < deg ? j0 + u : deg - 1;
+            nb4[u] = c.nbr[ru + j]; w4[u] = c.wt[ru + j];
           }
-          if (ok) { kind = 1; e = c.eid[ru + je]; t = We >> 1; }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (j0 + u < deg && nb4[u] == target && (jm < 0 || w4[u] < Wm)) { jm = j0 + u; Wm = w4[u]; }
         }
-      } else if (size[r] == 1) {
-        int jb = -1;
-        for (int j = 0; j < deg; ++j)
-          if (c.nbr[ru + j] == NB_BOUNDARY && (jb < 0 || c.wt[ru + j] < c.wt[ru + jb])) jb = j;
-        if (jb >= 0) {
-          bool ok = true;
-          for (int j = 0; j < deg && ok; ++j)
-            if (c.nbr[ru + j] >= 0 && c.wt[ru + j] <= c.wt[ru + jb]) ok = false;
-          if (ok) { kind = 2; e = c.eid[ru + jb]; t = c.wt[ru + jb]; }
+      }
+      if (size[r] == 2 && jm >= 0) {
+        // an adjacent pair meets halfway (at W/2) before either reaches
+        // anything else: every other slot of both rows is heavier than W/2
+        v = other[r];
+        const int64_t rv = (int64_t)target * deg;
+        const int em = c.eid[ru + jm];
+        bool ok = true;
+        for (int j0 = 0; j0 < deg; j0 += 2) {
+          int na[2], nv[2], ev[2];
+          i128 wa[2], wv[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int j = j0 + u < deg ? j0 + u : deg - 1;
+            na[u] = c.nbr[ru + j]; wa[u] = c.wt[ru + j];
+            nv[u] = c.nbr[rv + j]; wv[u] = c.wt[rv + j]; ev[u] = c.eid[rv + j];
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (j0 + u >= deg) continue;
+            if (j0 + u != jm && na[u] != NB_PAD && 2 * wa[u] <= Wm) ok = false;
+            if (nv[u] != NB_PAD && ev[u] != em && 2 * wv[u] <= Wm) ok = false;
+          }
         }
+        if (ok) { kind = 1; e = em; t = Wm >> 1; }
+      } else if (size[r] == 1 && jm >= 0) {
+        // a lone event reaches its lightest boundary edge before any neighbour
+        bool ok = true;
+        for (int j0 = 0; j0 < deg; j0 += 4) {
+          int nb4[4];
+          i128 w4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int j = j0 + u < deg ? j0 + u : deg - 1;
+            nb4[u] = c.nbr[ru + j]; w4[u] = c.wt[ru + j];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (j0 + u < deg && nb4[u] >= 0 && w4[u] <= Wm) ok = false;
+        }
+        if (ok) { kind = 2; e = c.eid[ru + jm]; t = Wm; }
       }
     }
     const uint64_t mask = ballot(kind != 0);
