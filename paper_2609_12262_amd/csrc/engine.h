@@ -947,17 +947,30 @@ PSB_DEV void load_defects(Ctx& c, const uint8_t* row) {
   const int nb = c.P->nbytes;
   const int lim = c.xcap < c.P->cap.dcap ? c.xcap : c.P->cap.dcap;
   int total = 0;
-  for (int b0 = 0; b0 < nb; b0 += PSB_WAVE) {
-    int cnt = 0, byte = 0;
-    const int i = b0 + lane();
-    if (i < nb) { byte = row[i]; cnt = __builtin_popcount(byte); }
-    int pos = total + wave_prefix(cnt);
-    for (int k = 0; k < 8; ++k) if (byte >> k & 1) {
-      const int d = 8 * i + k;
-      if (d < c.n_det && pos < lim) c.x_node[pos] = d;
-      ++pos;
+  // eight bytes per lane loaded before any is used; bytes are still taken in
+  // ascending order, a wavefront-wide chunk at a time, skipping empty chunks
+  constexpr int PER = 8;
+  for (int b0 = 0; b0 < nb; b0 += PER * PSB_WAVE) {
+    int bytes[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = b0 + u * PSB_WAVE + lane();
+      bytes[u] = i < nb ? row[i] : 0;
     }
-    total += wave_sum(cnt);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = b0 + u * PSB_WAVE + lane();
+      const int byte = bytes[u];
+      const int cnt = __builtin_popcount(byte);
+      if (ballot(cnt != 0) == 0) continue;
+      int pos = total + wave_prefix(cnt);
+      for (int k = 0; k < 8; ++k) if (byte >> k & 1) {
+        const int d = 8 * i + k;
+        if (d < c.n_det && pos < lim) c.x_node[pos] = d;
+        ++pos;
+      }
+      total += wave_sum(cnt);
+    }
   }
   wave_sync();
   c.nd = total;
@@ -969,9 +982,19 @@ PSB_DEV void load_defects(Ctx& c, const uint8_t* row) {
   }
   wave_sync();
   // neighbour tables of the detection events (each other's entries included)
+  // (a row's neighbours four at a time, their lookups issued together)
   for (int i = lane(); kNbTable && i < total; i += PSB_WAVE) {
-    const int64_t row = (int64_t)c.x_node[i] * c.deg;
-    for (int j = 0; j < c.deg; ++j) c.x_nb[(int64_t)i * c.deg + j] = (int16_t)xnb_code(c, c.nbr[row + j]);
+    const int deg = c.deg;
+    const int64_t row = (int64_t)c.x_node[i] * deg;
+    for (int j0 = 0; j0 < deg; j0 += 4) {
+      int nb4[4], k4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) nb4[u] = j0 + u < deg ? c.nbr[row + j0 + u] : NB_PAD;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) k4[u] = xnb_code(c, nb4[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) if (j0 + u < deg) c.x_nb[(int64_t)i * deg + j0 + u] = (int16_t)k4[u];
+    }
   }
   wave_sync();
   c.S->x_n = total;
