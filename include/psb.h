@@ -122,13 +122,15 @@ typedef struct {
    * loop one event at a time instead.  Results and event counts do not
    * depend on it. */
   int32_t serial_level_one;
-  /* The clustering search of a level whose paths have at most two edges
-   * (Methods, Algorithm "Clustering": H_k = floor(b_k / w_min) <= 2) reads, by
-   * default, a table built with the decoder: for every detector, the detectors
-   * and boundary edges within b_k along such paths, flagged by whether their
-   * least distance is within d_k (and, for boundary edges, b_k / 2).  The
-   * tables take about 4 bytes per such pair of device memory.  1 = walk the
-   * paths at every level instead.  Results do not depend on it. */
+  /* The clustering search of a level below the final one (Methods, Algorithm
+   * "Clustering": paths of at most H_k = floor(b_k / w_min) edges within b_k)
+   * reads, by default, a table built with the decoder: for every detector, the
+   * detectors and boundary edges within b_k along such paths, flagged by
+   * whether their least distance is within d_k (and, for boundary edges,
+   * b_k / 2).  The tables take about 4 bytes per such pair of device memory; a
+   * level whose paths are too many to replay on the host (more than about 2048
+   * walk steps per detector) walks them on the device instead.  1 = walk the paths at every level.
+   * Results do not depend on it. */
   int32_t cluster_walk;
 } psb_decoder_opts;
 

@@ -268,42 +268,48 @@ static bool level_depths(const LevelSchedule& S, __int128 wmin, std::vector<int3
   return true;
 }
 
-// Ball tables of the clustering levels whose search walks paths of at most
-// three edges (shmax 1 to 3), each path cut at length b_k and extended only
-// while shorter than b_k.  Row u of a level's table lists every detector x != u
+// Ball tables of the clustering levels below the final one (shmax >= 1): the
+// search walks paths of at most shmax edges, each cut at length b_k and
+// extended only while shorter than b_k.  Row u of a level's table lists every detector x != u
 // at the end of such a path, flagged BALL_CLOSE when its least such length is
 // at most d_k, then every boundary edge ending such a path whose least length
 // is at most d_k (BALL_CLOSE) or at most b_k / 2 (BALL_LOOSE).  Reading the row
 // gives the search exactly the partners, close pairs, boundary edges within d_k
 // and loose flag that walking the paths gives, in one pass of independent
-// loads.  Returns false (and no tables) when ids do not fit the entries or the
-// tables would exceed max_entries.
+// loads.  A level whose walks, replayed here for every detector, take more
+// than max_paths steps in all (default 2048 per detector) gets no table (its
+// search walks on the device).
+// Returns false (and no tables) when ids do not fit the entries or the tables
+// would exceed max_entries.
 struct BallTables {
   std::vector<int32_t> slot, off, ent;
 };
 
 static bool build_ball_tables(const Ell& g, const std::vector<__int128>& ell_w, const std::vector<__int128>& sb,
                               const std::vector<__int128>& sd, const std::vector<int32_t>& hmax, int64_t max_entries,
-                              BallTables& T) {
+                              BallTables& T, int64_t max_paths = -1) {
   const int32_t n = g.n_det, deg = g.deg;
+  if (max_paths < 0) max_paths = 2048 * (int64_t)n + (1 << 20);
   T.slot.assign(hmax.size(), -1); T.off.clear(); T.ent.clear();
   if (n > psb::BALL_ID || g.n_edges > psb::BALL_ID) return false;
   std::vector<std::pair<int32_t, __int128>> cand, bc;
   int32_t tables = 0;
   for (size_t k = 0; k < hmax.size(); ++k) {
     const int hops = hmax[k];
-    if (hops < 1 || hops > 3) continue;
+    if (hops < 1) continue;
     const __int128 b = sb[k], d = sd[k];
-    T.slot[k] = tables++;
-    const size_t base = T.off.size();
+    const size_t base = T.off.size(), ebase = T.ent.size();
     T.off.resize(base + 2 * (size_t)n + 1);
-    for (int32_t u = 0; u < n; ++u) {
+    int64_t steps = 0;
+    bool over = false;
+    for (int32_t u = 0; u < n && !over; ++u) {
       cand.clear(); bc.clear();
       // the paths in the walk's order (depth first, adjacency slots in row
       // order), returns to u included: the order decides which boundary edges
       // a full list keeps
       auto walk = [&](auto&& self, int32_t x, __int128 base_w, int depth) -> void {
-        for (int32_t j = 0; j < deg; ++j) {
+        for (int32_t j = 0; j < deg && !over; ++j) {
+          if (++steps > max_paths) { over = true; return; }
           const int64_t a = (int64_t)x * deg + j;
           const int32_t y = g.nbr[a];
           if (y == psb::NB_PAD) break;
@@ -342,7 +348,13 @@ static bool build_ball_tables(const Ell& g, const std::vector<__int128>& ell_w, 
         }
       if ((int64_t)T.ent.size() > max_entries) { T.slot.assign(hmax.size(), -1); T.off.clear(); T.ent.clear(); return false; }
     }
+    if (over) {                          // this level walks: drop its partial table
+      T.off.resize(base);
+      T.ent.resize(ebase);
+      continue;
+    }
     T.off[base + 2 * (size_t)n] = (int32_t)T.ent.size();
+    T.slot[k] = tables++;
   }
   return true;
 }

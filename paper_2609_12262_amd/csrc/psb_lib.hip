@@ -388,8 +388,9 @@ extern "C" int32_t psb_decoder_create(const psb_graph* g, const psb_decoder_opts
   const size_t nl = D->sched.d.size();
   std::vector<__int128> sd(nl), sb(nl);
   for (size_t k = 0; k < nl; ++k) { sd[k] = (__int128)D->sched.d[k]; sb[k] = (__int128)D->sched.b[k]; }
-  // the levels whose search walks at most three edges read ball tables instead
-  // (at most 2^28 entries; beyond that, or with cluster_walk, they walk)
+  // the levels below the final one read ball tables instead of walking (at most
+  // 2^28 entries in all and about 2048 replayed walk steps per detector and
+  // level; beyond that, or with cluster_walk, they walk)
   BallTables balls;
   const bool use_balls = opts.cluster_walk == 0 && opts.mode == 0 &&
                          build_ball_tables(ell, ell_w, sb, sd, D->hmax, (int64_t)1 << 28, balls) && !balls.off.empty();

@@ -124,7 +124,7 @@ struct Params {
   const __int128* sd;     // [n_levels] d_k
   const __int128* sb;     // [n_levels] b_k
   const int32_t* shmax;   // [n_levels] path-enumeration depth, -1 = final level
-  // ball tables of the levels whose search walks at most two edges: level k
+  // ball tables of the clustering levels (those that have one): level k
   // reads table ball_slot[k] (-1: it walks its paths), whose row for detector
   // u is ball_ent[off[2u] .. off[2u+1]) = the detectors within b_k of u, then
   // [off[2u+1] .. off[2u+2]) = the boundary edges that matter (off = ball_off +

@@ -172,14 +172,16 @@ def test_cpu_engine_direct_level_one_equals_event_loop(exe, graph, d, p, n, seed
 
 @pytest.mark.parametrize("graph,d,p,q,reading", [("phenom", 11, 0.005, None, 0), ("phenom", 9, 0.01, None, 1),
                                                  ("phenom", 7, 0.003, 0.002, 0), ("circuit_uniform", 5, 0.004, None, 0),
-                                                 ("circuit_physical", 5, 0.004, None, 1)])
+                                                 ("circuit_physical", 5, 0.004, None, 1), ("phenom", 7, 0.003, 0.05, 0),
+                                                 ("phenom", 7, 0.003, 0.2, 1)])
 def test_cpu_engine_ball_tables_equal_the_walk(exe, graph, d, p, q, reading):
     """Levels whose clustering search walks at most two edges read the ball
     tables built with the decoder: same results, same processing clusters,
     applied events and E_ideal as walking the paths, on every shot, and both
     equal the oracles; the tables read fewer entries than the walk visits
     (the circuit-level graph with uniform noise needs three edges at level 1,
-    the others two)."""
+    the timelike-light graphs four (q = 0.05) and eight (q = 0.2), the others
+    two)."""
     g = (synth.rotated_phenom_graph(d, p, q=q) if graph == "phenom"
          else synth.rotated_circuit_graph(d, p, graph.split("_")[1]))
     s = synth.sample(g, 300, seed=41)

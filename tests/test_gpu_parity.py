@@ -93,7 +93,8 @@ def test_random_and_repetition_graphs():
 
 
 @pytest.mark.parametrize("graph,walk", [("phenom", 0), ("circuit_uniform", 0), ("circuit_physical", 0),
-                                        ("phenom_q02", 0), ("phenom", 1), ("circuit_uniform", 1)])
+                                        ("phenom_q02", 0), ("phenom", 1), ("circuit_uniform", 1),
+                                        ("phenom_q02", 1)])
 def test_cluster_levels_equal_oracle_clustering(graph, walk):
     """Processing-cluster levels (Methods, Algorithm "Clustering") against the
     oracle's plain construction: identical below the final level; at the
@@ -102,9 +103,9 @@ def test_cluster_levels_equal_oracle_clustering(graph, walk):
     search enumerates paths of up to floor(b_1 / w_min) edges: 2 on the
     phenomenological and physical-noise graphs, 3 on the uniform-noise graph
     (its lightest edges are about 0.55 of the heaviest), 8 on a graph with
-    timelike flips at q = 0.2 (the generic walk).  Levels of at most three
-    edges read the decoder's ball tables; walk = 1 makes them walk their
-    paths (rows read in chunks, near lists at three edges).  The final MWEM
+    timelike flips at q = 0.2.  The levels read the decoder's ball tables;
+    walk = 1 makes them walk their paths (rows read in chunks, near lists from
+    three edges on, the generic walk beyond three).  The final MWEM
     does not depend on the clusters (Theorem 1), so only this test checks
     them, and the results are compared with the oracle as well."""
     if graph == "phenom":
