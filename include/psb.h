@@ -208,7 +208,8 @@ int32_t psb_schedule_levels(uint64_t wmax_hi, uint64_t wmax_lo, uint64_t diam_hi
                             int32_t max_levels, uint64_t* d_hi, uint64_t* d_lo, uint64_t* b_hi,
                             uint64_t* b_lo, int32_t* final_level);
 
-/* Device memory the decoder holds (workspaces, weights, schedule), in bytes. */
+/* Device memory the decoder holds (workspaces, weights, schedule, ball tables, shot-order and overflow
+ * buffers), in bytes. */
 int32_t psb_decoder_device_bytes(const psb_decoder* d, int64_t* bytes);
 
 /* A psb_decode_batch call captured once into a HIP graph and replayed with

@@ -568,6 +568,7 @@ extern "C" int32_t psb_decoder_device_bytes(const psb_decoder* D, int64_t* bytes
   int64_t b = (int64_t)D->P_ovf.L.total * D->slots_ovf + 16LL * D->g->n_det * D->g->deg + 256;
   if (D->fast_enabled) b += (int64_t)D->P_fast.L.total * D->slots_fast;
   if (D->ovf_list_cap > 0) b += 4 * (3 * D->ovf_list_cap + kOrderBuckets);
+  b += D->ball_bytes;
   *bytes = b;
   return PSB_OK;
 }
