@@ -420,8 +420,16 @@ PSB_DEV void link_neighbours(Ctx& c, int ix, int v) {
     const int k = xnb_code(c, nbv);
     c.x_nb[(int64_t)ix * deg + j] = (int16_t)k;
     if (k >= 0) {
-      for (int j2 = 0; j2 < deg; ++j2)
-        if (c.nbr[(int64_t)nbv * deg + j2] == v) c.x_nb[(int64_t)k * deg + j2] = (int16_t)ix;
+      // the neighbour's row four slots at a time, loaded before any is tested
+      const int64_t r2 = (int64_t)nbv * deg;
+      for (int j0 = 0; j0 < deg; j0 += 4) {
+        int n4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) n4[u] = j0 + u < deg ? c.nbr[r2 + j0 + u] : NB_PAD;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (n4[u] == v) c.x_nb[(int64_t)k * deg + j0 + u] = (int16_t)ix;
+      }
     }
   }
 }
