@@ -1093,7 +1093,7 @@ PSB_DEV bool has_boundary_edge(const Ctx& c, int x) { return (c.P->bndb[x >> 5] 
 // graph's levels need): 0 = paths of up to two edges; 1 = up to three, with
 // near lists; 2 = the generic walk of up to MAXH edges as well.
 template <int DEEP = 2>
-PSB_DEV void cluster(Ctx& c) {
+PSB_DEV void cluster_levels(Ctx& c) {
   const int nd = c.nd;
   const int deg = c.deg;
   const int hitcap = c.P->hitcap, bdc = c.P->bdc;
@@ -1371,6 +1371,26 @@ PSB_DEV void cluster(Ctx& c) {
     }
     wave_sync();
   }
+}
+
+// The clustering's union-find and per-root sizes use the two int32 region
+// stamp arrays (in the state block: LDS on the wavefront tiers) instead of the
+// workspace, so that its chains of atomics stay on chip: the stamps are not
+// read before the dynamics, and the detection-event regions' stamps are set
+// back to zero (region_init's value) afterwards.
+template <int DEEP = 2>
+PSB_DEV void cluster(Ctx& c) {
+  int32_t* const uf_ws = c.uf;
+  int32_t* const size_ws = c.cl_c;
+  c.uf = &rf_ref<RF_MARK>(c, 0);
+  c.cl_c = &rf_ref<RF_CHGM>(c, 0);
+  wave_sync();
+  cluster_levels<DEEP>(c);
+  wave_sync();
+  for (int i = lane(); i < c.nd; i += PSB_WAVE) { RF(c, i, RF_MARK) = 0; RF(c, i, RF_CHGM) = 0; }
+  wave_sync();
+  c.uf = uf_ws;
+  c.cl_c = size_ws;
 }
 
 // ---------------------------------------------------------------------------
