@@ -1204,22 +1204,22 @@ PSB_DEV void cluster_levels(Ctx& c) {
       };
       if (bt >= 0) {
         // the detectors and boundary edges that the level's paths reach, with
-        // the flags their least distances decide; partners four at a time, all
+        // the flags their least distances decide; partners eight at a time, all
         // loads of a chunk issued before any of them is used
         const int32_t* row = c.P->ball_off + (int64_t)bt * (2 * (int64_t)c.n_det + 1) + 2 * (int64_t)u;
         const int a0 = row[0], a1 = row[1], a2 = row[2];
         const int32_t* ent = c.P->ball_ent;
         nvis += a2 - a0;
-        for (int q0 = a0; q0 < a1; q0 += 4) {
-          int ys[4], ix[4], lv[4];
+        for (int q0 = a0; q0 < a1; q0 += 8) {
+          int ys[8], ix[8], lv[8];
 #pragma unroll
-          for (int t = 0; t < 4; ++t) ys[t] = q0 + t < a1 ? ent[q0 + t] : -1;
+          for (int t = 0; t < 8; ++t) ys[t] = q0 + t < a1 ? ent[q0 + t] : -1;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) ix[t] = ys[t] >= 0 ? node_idx(c, ys[t] & BALL_ID) : -1;
+          for (int t = 0; t < 8; ++t) ix[t] = ys[t] >= 0 ? node_idx(c, ys[t] & BALL_ID) : -1;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) lv[t] = (ix[t] >= 0 && ix[t] < nd) ? (int)c.level[ix[t]] : 1;
+          for (int t = 0; t < 8; ++t) lv[t] = (ix[t] >= 0 && ix[t] < nd) ? (int)c.level[ix[t]] : 1;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
+          for (int t = 0; t < 8; ++t) {
             if (lv[t] != 0) continue;
             // the row's detectors are distinct: no partner repeats
             if (nh < hitcap) { hits[2 * nh] = ix[t]; hits[2 * nh + 1] = (ys[t] & BALL_CLOSE) ? 1 : 0; ++nh; }
