@@ -1087,11 +1087,13 @@ PSB_DEV bool has_boundary_edge(const Ctx& c, int x) { return (c.P->bndb[x >> 5] 
 // every pair in it is within d_k (its diameter) and it has an even number of
 // events or satisfies the boundary condition.  At the first level whose b_k
 // exceeds the diameter bound, every remaining event is in the component of
-// its connected part of the graph: these form the final clusters.
-// DEEP, the deepest search compiled in (the deeper ones hold registers that
+// its connected part of the graph: these form the final clusters.  A level
+// with a ball table (built with the decoder) reads each event's partners and
+// boundary edges from it instead of walking the paths.
+// DEEP, the deepest walk compiled in (the deeper ones hold registers that
 // make the whole kernel spill more, so the host picks the least that the
-// graph's levels need): 0 = paths of up to two edges; 1 = up to three, with
-// near lists; 2 = the generic walk of up to MAXH edges as well.
+// levels without a table need): 0 = paths of up to two edges; 1 = up to
+// three, with near lists; 2 = the generic walk of up to MAXH edges as well.
 template <int DEEP = 2>
 PSB_DEV void cluster_levels(Ctx& c) {
   const int nd = c.nd;
@@ -1124,7 +1126,7 @@ PSB_DEV void cluster_levels(Ctx& c) {
     // hop's row in chunks of independent loads, which is faster than a chain
     // of list entries
     const bool use_near = DEEP >= 1 && c.near && H >= 3;
-    // levels whose paths have at most two edges read their ball table
+    // the level's ball table, if the decoder built one (else it walks)
     const int bt = c.P->ball_slot ? uni(c.P->ball_slot[k]) : -1;
     for (int i = lane(); i < nd; i += PSB_WAVE) {
       c.uf[i] = i; close_cnt[i] = 0; bcount[i] = 0; csize[i] = 0; cclose[i] = 0;

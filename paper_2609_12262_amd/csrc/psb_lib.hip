@@ -173,7 +173,8 @@ __global__ __launch_bounds__(64, 4) void psb_decode_kernel(Params P) {
 }
 
 // The decode kernel instantiation for a tier, accounting and search depth
-// class (0: paths of up to two edges, 1: three, 2: the generic walk).
+// class of the walking levels (0: paths of up to two edges, 1: three, 2: the
+// generic walk).
 static const void* decode_kernel_fn(int tier, bool acct, int deep, bool ws = false) {
   if (ws) {                                       // first tier without accounting only (host-checked)
     const void* kw[3] = {(const void*)psb_decode_kernel<0, 0, 0, 1>, (const void*)psb_decode_kernel<0, 0, 1, 1>,
